@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the far-field Stokeslet sum on one MI355X.
+
+One step = one full pass of the hot path over the workload: the per-vesicle
+preprocessing kernel and the pair-sum kernel (FP32-compensated), on inputs
+already resident in HBM.  Workload: the dense suspension of 2,000 vesicles x
+128 points (256,000 targets) at 30% area fraction, seeded and synthetic.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_PAIR = 19          # sub x2, q: mul+fma, log, rcp, r.F: mul+fma, scale, 2 x (2 fma)
+PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32
+PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64
+METRIC = "Stokeslet pair-interactions/s (FP32-comp vs FP64) at ≤1e-5 rel err; % VALU peak"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sum would shard by targets with one all-gather of source records).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2606_25569_amd as V
+    from synth import suspension as S
+
+    t0 = time.time()
+    s = S.load_config(1)
+    P, M = s.n_points, s.n_vesicles
+    pairs = s.cross_pairs()
+    log(f"[bench] workload 2000x128: P={P} M={M} pairs={pairs:.4e} (generated in {time.time() - t0:.1f}s)")
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    X = torch.tensor(s.X, device=dev)
+    f = torch.tensor(s.f, device=dev)
+    w = torch.tensor(s.w, device=dev)
+    part = V.Partition(s.offsets, dev)
+    out = torch.empty((2, P), dtype=torch.float64, device=dev)
+    lib = V._lib.lib()
+    stream = torch.cuda.current_stream()
+    sp = V.farfield._ptr
+
+    cfg = None if args.no_tune else V.load_tuned(P, M, "fp32c")
+    if cfg is None and not args.no_tune:
+        t1 = time.time()
+        cfg, tms = V.autotune(X, X, f, w, part, s.mu, "fp32c", repeats=2)
+        log(f"[bench] autotuned {cfg.as_dict()} ({tms:.3f} ms) in {time.time() - t1:.1f}s")
+    if cfg is None:
+        cfg = V.default_config(P, M, "fp32c")
+    import ctypes
+    cfg_ref = ctypes.byref(cfg)
+    prec = V.FP32_COMPENSATED
+    ws_n = lib.vesnet_farfield_workspace_bytes(P, M, prec, cfg_ref)
+    ws = torch.empty(ws_n, dtype=torch.uint8, device=dev)
+    sh = ctypes.c_void_p(stream.cuda_stream)
+
+    def prepare(prec_code, c_ref, wsp):
+        V._lib.check(lib.vesnet_farfield_prepare(sp(X), sp(f), sp(w), sp(part.device), M, P, prec_code, sp(wsp),
+                                                 wsp.numel(), sh))
+
+    def evaluate(prec_code, c_ref, wsp):
+        V._lib.check(lib.vesnet_farfield_evaluate(sp(X), sp(part.device), M, P, float(s.mu), sp(out), prec_code,
+                                                  c_ref, sp(wsp), wsp.numel(), sh))
+
+    for _ in range(args.warmup):
+        prepare(prec, cfg_ref, ws)
+        evaluate(prec, cfg_ref, ws)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done; timing {args.steps} steps")
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        prepare(prec, cfg_ref, ws)
+        ev[k][1].record(stream)
+        evaluate(prec, cfg_ref, ws)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    prep_ms = np.array([a.elapsed_time(b) for a, b, _ in ev])
+    eval_ms = np.array([b.elapsed_time(c) for _, b, c in ev])
+    ms_step = wall * 1e3 / args.steps
+    value = pairs / (wall / args.steps)
+    u32 = out.cpu().numpy()
+    log(f"[bench] fp32c: {ms_step:.3f} ms/step, pair kernel {eval_ms.mean():.3f} ms (min {eval_ms.min():.3f}), "
+        f"prepare {prep_ms.mean() * 1e3:.1f} us -> {value:.4e} pairs/s")
+
+    # FP64 GPU kernel on the same inputs
+    prec64 = V.FP64
+    cfg64 = V.default_config(P, M, "fp64")
+    ws64 = torch.empty(lib.vesnet_farfield_workspace_bytes(P, M, prec64, ctypes.byref(cfg64)), dtype=torch.uint8,
+                       device=dev)
+    prepare(prec64, ctypes.byref(cfg64), ws64)
+    evaluate(prec64, ctypes.byref(cfg64), ws64)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.fp64_steps):
+        prepare(prec64, ctypes.byref(cfg64), ws64)
+        evaluate(prec64, ctypes.byref(cfg64), ws64)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms64 = e0.elapsed_time(e1) / args.fp64_steps
+    u64 = out.cpu().numpy()
+    log(f"[bench] fp64: {ms64:.3f} ms/step -> {pairs / (ms64 * 1e-3):.4e} pairs/s")
+
+    # accuracy on the seeded 1% target sample, and the CPU baseline on the same sample
+    sel = S.sample_targets(P, 0.01, 101)
+    errs = {}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        log(f"[bench] oracle on {sel.size} targets x {P} sources ({O.num_threads()} threads)")
+        tc = time.perf_counter()
+        ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu, select=sel)
+        tcpu = time.perf_counter() - tc
+        sample_pairs = int(sum(P - (s.offsets[v + 1] - s.offsets[v]) for v in O.vesicle_ids(s.offsets)[sel]))
+        scale = np.abs(ref).max()
+        for name, u in (("fp32c", u32), ("fp64", u64)):
+            d = u[:, sel] - ref
+            errs[name] = {"max_rel": float(np.abs(d).max() / scale),
+                          "rms_rel": float(np.sqrt(np.mean(d * d)) / np.sqrt(np.mean(ref * ref)))}
+        cpu = {"value": sample_pairs / tcpu, "unit": "pairs/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"seeded 1% target sample: {sel.size} targets x all {P} sources of the same workload "
+                         f"({sample_pairs:.3e} pairs, {tcpu:.2f} s wall)"}
+        log(f"[bench] errors {errs}; oracle {cpu['value']:.3e} pairs/s on {cpu['cores']} threads")
+
+    t_kernel = float(eval_ms.mean()) * 1e-3
+    achieved = FLOPS_PER_PAIR * pairs / t_kernel / 1e12
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "dense suspension: 2000 vesicles x 128 points (256000 targets), 30% area fraction "
+                               "by RSA, gap 0.1, ellipses of perimeter 2pi and reduced area 0.65, force-free "
+                               "Fourier forces k<=4, mu=1",
+                   "n_points": P, "n_vesicles": M, "cross_vesicle_pairs": pairs,
+                   "precision": "fp32-compensated (float32 pairs, float64 per-vesicle flush)",
+                   "tile": cfg.as_dict()},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "k_forward (pair sum)", "kernel_ms": float(eval_ms.mean()),
+                     "flops_per_pair": FLOPS_PER_PAIR},
+        "cpu_baseline": cpu,
+        "fp64": {"pairs_per_s": pairs / (ms64 * 1e-3), "ms_per_step": ms64,
+                 "tflops": FLOPS_PER_PAIR * pairs / (ms64 * 1e-3) / 1e12,
+                 "frac_fp64_peak": FLOPS_PER_PAIR * pairs / (ms64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                 "speedup_fp32c_over_fp64": ms64 / ms_step},
+        "max_rel_err": errs or None,
+        "prepare_us": float(prep_ms.mean() * 1e3),
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * vesnet.h - far-field Stokeslet single-layer sum on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Section 2.2, eq. (single_layer) with the 2D Stokeslet of
+ * eq. (Stokeslet); trapezoid rule for far-field targets, Section 2.2.1; the
+ * far-field velocity U_far of eq. (membrane_velocity), which is what
+ * DirectSingleLayerIntegral returns in Algorithm 4):
+ *
+ *   out_i = 1/(4 pi mu) * sum_{j : ves(j) != ves(i)} w_j [ -ln|r| f_j + ((r . f_j)/|r|^2) r ],
+ *   r = targets_i - sources_j.
+ *
+ * The Stokeslet is printed in the paper with "+log|r|" and no identity
+ * matrix; this library computes -ln|r| I + r r^T/|r|^2, the divergence-free
+ * fundamental solution.  w_j is the trapezoid weight |X'(alpha_j)| 2 pi/N of
+ * point j (the arclength element ds of eq. (single_layer)).  Each target
+ * skips every source of its own vesicle (self-interaction is handled
+ * separately in the paper).  The result overwrites out; near-field and
+ * background velocities are the caller's to add.
+ *
+ * Conventions shared by every entry point
+ *  - Arrays of 2D vectors are planar structure-of-arrays [2][P] float64:
+ *    x components at [0, P), y components at [P, 2P).
+ *  - targets and sources share one vesicle partition: int32
+ *    vesicle_offsets[M+1] with offsets[0] = 0, offsets[M] = P, non-decreasing;
+ *    vesicle v owns points offsets[v] .. offsets[v+1]-1 of both arrays.
+ *  - Every pointer argument marked "device" is device memory owned by the
+ *    caller; the library never allocates, frees or retains it.  Device
+ *    offsets cannot be read by the host without a synchronisation, so the
+ *    kernels clamp them into [0, P]: malformed offsets give wrong numbers
+ *    but never out-of-bounds accesses.  vesnet_check_offsets validates a
+ *    host copy.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *    are asynchronous and enqueue kernels only; no call synchronises except
+ *    vesnet_autotune and vesnet_graph_create_batched.
+ *  - Every call returns a vesnet_status.  Argument errors are detected on the
+ *    host before anything is enqueued; vesnet_last_error() then describes
+ *    the failure (thread-local, valid until the next call on the thread).
+ *  - Coincident points of different vesicles make the sum undefined (log of
+ *    zero); the output is then unspecified (inf/NaN) and no error is raised.
+ *  - Calls on different streams with separate workspaces may run concurrently.
+ */
+#ifndef VESNET_H
+#define VESNET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define VESNET_API __attribute__((visibility("default")))
+#else
+#define VESNET_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VESNET_OK = 0,
+  VESNET_ERR_INVALID_ARGUMENT = -1, /* bad pointer, size, mu, precision, aliasing, offsets */
+  VESNET_ERR_UNSUPPORTED = -2,      /* valid request this build does not implement        */
+  VESNET_ERR_WORKSPACE = -3,        /* workspace missing or smaller than required          */
+  VESNET_ERR_HIP = -4               /* a HIP runtime call or kernel launch failed          */
+} vesnet_status;
+
+typedef enum {
+  VESNET_FP64 = 0,              /* every operation in float64                                   */
+  VESNET_FP32_COMPENSATED = 1,  /* pairs in float32 on per-vesicle local, rescaled coordinates;
+                                   per-source-vesicle partials flushed into float64 together
+                                   with the exact float64 log-term correction                     */
+  VESNET_FP32_NAIVE = 2         /* everything in float32 on global coordinates (control only)   */
+} vesnet_precision;
+
+/* Launch shape of the pair kernels.  A zero field selects the built-in default. */
+typedef struct {
+  int32_t targets_per_thread; /* 1, 2 or 4                                                    */
+  int32_t block_threads;      /* 64, 128 or 256                                               */
+  int32_t source_splits;      /* >= 1: source vesicles split into this many chunks, reduced in
+                                 a fixed order by a second kernel (bitwise deterministic)      */
+  int32_t blocks_per_cu;      /* batched persistent grid: workgroups per compute unit (1..16) */
+} vesnet_tile_config;
+
+/* Library version string and the thread-local description of the last error. */
+VESNET_API const char* vesnet_version(void);
+VESNET_API const char* vesnet_last_error(void);
+
+/* Host check of a host copy of the partition: offsets[0] = 0, offsets[M] = P,
+   non-decreasing, M >= 0 (M = 0 requires P = 0).  Returns VESNET_OK or
+   VESNET_ERR_INVALID_ARGUMENT. */
+VESNET_API int vesnet_check_offsets(const int32_t* offsets_host, int32_t n_vesicles, int32_t n_points);
+
+/* The launch shape used when cfg is NULL or has zero fields. */
+VESNET_API int vesnet_default_tile_config(int32_t n_points, int32_t n_vesicles, int precision, vesnet_tile_config* cfg);
+
+/* ------------------------------------------------------------------ forward */
+
+/* Bytes of device workspace the forward calls need (256-byte aligned base). */
+VESNET_API size_t vesnet_farfield_workspace_bytes(int32_t n_points, int32_t n_vesicles, int precision,
+                                       const vesnet_tile_config* cfg);
+
+/* Step 1 of the forward: per-vesicle preprocessing into the workspace.
+   For each vesicle: reference point c_v (mean of its source points, float64)
+   and net weighted force F_v = sum_j w_j f_j (float64); for each source point
+   the record the pair kernel streams (local coordinates y_j - c_v and
+   w_j f_j in float32 for the compensated form, global float32 for the naive
+   form, global float64 for FP64), and the vesicle id of every point.
+     sources, force_density : device [2][P] float64
+     arc_weights            : device [P] float64
+     vesicle_offsets        : device [M+1] int32 */
+VESNET_API int vesnet_farfield_prepare(const double* sources, const double* force_density, const double* arc_weights,
+                            const int32_t* vesicle_offsets, int32_t n_vesicles, int32_t n_points,
+                            int precision, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Step 2 of the forward: the pair sum at every target from a prepared
+   workspace (same partition, precision and cfg as used for the workspace size).
+     targets : device [2][P] float64, read only
+     out     : device [2][P] float64, overwritten; must not overlap any input
+     mu      : viscosity, finite and > 0 */
+VESNET_API int vesnet_farfield_evaluate(const double* targets, const int32_t* vesicle_offsets, int32_t n_vesicles,
+                             int32_t n_points, double mu, double* out, int precision,
+                             const vesnet_tile_config* cfg, void* workspace, size_t workspace_bytes,
+                             void* stream);
+
+/* prepare + evaluate. */
+VESNET_API int vesnet_farfield_stokeslet(const double* targets, const double* sources, const double* force_density,
+                              const double* arc_weights, const int32_t* vesicle_offsets, int32_t n_vesicles,
+                              int32_t n_points, double mu, double* out, int precision,
+                              const vesnet_tile_config* cfg, void* workspace, size_t workspace_bytes,
+                              void* stream);
+
+/* ------------------------------------------------------------------ batched */
+
+/* S independent suspensions concatenated point-wise and vesicle-wise.
+   Suspension s owns vesicles suspension_offsets[s] .. suspension_offsets[s+1]-1
+   (device int32 [S+1], suspension_offsets[0] = 0, [S] = V) and has viscosity
+   mu[s] (device float64 [S], each > 0).  No interaction crosses suspensions.
+   One persistent launch: work items (suspension, block of targets) are ordered
+   largest suspension first on the device and handed out through a counter in
+   the workspace, so the call needs no host-side copy of the tables. */
+VESNET_API size_t vesnet_batched_workspace_bytes(int32_t n_points, int32_t n_vesicles, int32_t n_suspensions, int precision);
+
+VESNET_API int vesnet_farfield_stokeslet_batched(const double* targets, const double* sources, const double* force_density,
+                                      const double* arc_weights, const int32_t* vesicle_offsets,
+                                      int32_t n_vesicles, int32_t n_points, const int32_t* suspension_offsets,
+                                      int32_t n_suspensions, const double* mu, double* out, int precision,
+                                      const vesnet_tile_config* cfg, void* workspace, size_t workspace_bytes,
+                                      void* stream);
+
+/* The same batched call captured once into a HIP graph (the capture runs on
+   a private stream and synchronises it); replay with vesnet_graph_launch.
+   All pointers are baked into the graph and must stay valid until destroy. */
+typedef struct vesnet_graph vesnet_graph;
+VESNET_API int vesnet_graph_create_batched(const double* targets, const double* sources, const double* force_density,
+                                const double* arc_weights, const int32_t* vesicle_offsets, int32_t n_vesicles,
+                                int32_t n_points, const int32_t* suspension_offsets, int32_t n_suspensions,
+                                const double* mu, double* out, int precision, const vesnet_tile_config* cfg,
+                                void* workspace, size_t workspace_bytes, vesnet_graph** graph);
+VESNET_API int vesnet_graph_launch(vesnet_graph* graph, void* stream);
+VESNET_API int vesnet_graph_destroy(vesnet_graph* graph);
+
+/* ------------------------------------------------------------------ adjoint */
+
+/* Reverse mode of the forward sum (the paper has none; derived from it).
+   With c = 1/(4 pi mu), F_j = w_j f_j, g_i = grad_out_i = dL/dout_i and
+   phi(r; g, F) = g^T G(r) F:
+     grad_targets_i = sum_j grad_r phi(r_ij; g_i, F_j)
+     grad_sources_j = - sum_i grad_r phi(r_ij; g_i, F_j)
+     grad_force_j   = w_j v_j,  grad_weights_j = f_j . v_j,  v_j = sum_i G(r_ij) g_i
+   (sums over pairs in different vesicles).  When targets and sources are the
+   same array, dL/dX = grad_targets + grad_sources.
+     grad_out                     : device [2][P] float64
+     grad_targets, grad_sources,
+     grad_force                   : device [2][P] float64 or NULL (skipped)
+     grad_weights                 : device [P] float64 or NULL
+   Outputs are overwritten and must not overlap inputs or each other.
+   precision: VESNET_FP64 or VESNET_FP32_COMPENSATED. */
+VESNET_API size_t vesnet_backward_workspace_bytes(int32_t n_points, int32_t n_vesicles, int precision);
+
+VESNET_API int vesnet_farfield_stokeslet_backward(const double* targets, const double* sources, const double* force_density,
+                                       const double* arc_weights, const int32_t* vesicle_offsets,
+                                       int32_t n_vesicles, int32_t n_points, double mu, const double* grad_out,
+                                       double* grad_targets, double* grad_sources, double* grad_force,
+                                       double* grad_weights, int precision, void* workspace,
+                                       size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------ tuning */
+
+/* Times every supported launch shape on the given (prepared inside) problem
+   with HIP events and returns the fastest in *best and its time in *best_ms.
+   batched != 0 tunes the batched call (then suspension_offsets, n_suspensions
+   and mu_device are used; otherwise mu_host).  Host-synchronous; the
+   workspace must hold the largest shape tried (shapes that do not fit are
+   skipped). */
+VESNET_API int vesnet_autotune(const double* targets, const double* sources, const double* force_density,
+                    const double* arc_weights, const int32_t* vesicle_offsets, int32_t n_vesicles,
+                    int32_t n_points, int batched, const int32_t* suspension_offsets, int32_t n_suspensions,
+                    const double* mu_device, double mu_host, double* out, int precision, int repeats,
+                    void* workspace, size_t workspace_bytes, void* stream, vesnet_tile_config* best,
+                    float* best_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VESNET_H */

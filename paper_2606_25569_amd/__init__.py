@@ -1,0 +1,14 @@
+"""MI355X-native far-field Stokeslet sum (the far-field N-body hot path of the
+VesNet vesicle solver): C-ABI library libvesnet.so with gfx950 HIP kernels,
+and a thin PyTorch binding.  Importing fails loudly if the library is not built."""
+from . import _lib
+from ._lib import FP32_COMPENSATED, FP32_NAIVE, FP64, TileConfig, VesnetError
+
+_lib.lib()  # load now: no CPU fallback exists
+
+from .farfield import (BatchedProblem, Partition, autotune, default_config, farfield_backward,  # noqa: E402
+                       farfield_forward, farfield_stokeslet, load_tuned, workspace_bytes)
+
+__all__ = ["BatchedProblem", "Partition", "TileConfig", "VesnetError", "autotune", "default_config",
+           "farfield_backward", "farfield_forward", "farfield_stokeslet", "load_tuned", "workspace_bytes",
+           "FP64", "FP32_COMPENSATED", "FP32_NAIVE"]

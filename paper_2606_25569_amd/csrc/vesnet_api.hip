@@ -1,0 +1,530 @@
+// Host side of the C-ABI declared in include/vesnet.h: argument validation,
+// workspace layout, launch-shape selection, HIP graphs and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "vesnet.h"
+#include "vesnet_internal.h"
+
+using namespace vesnet;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int32_t kMaxPoints = 1 << 30;   // 2P indices stay inside int32
+constexpr int kMaxSplits = 64;
+constexpr double kPi = 3.14159265358979323846;
+
+thread_local char g_err[768] = "";
+
+int fail(int status, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+int ok() {
+  g_err[0] = '\0';
+  return VESNET_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(VESNET_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+size_t rec_bytes(int prec) { return prec == P64 ? sizeof(double4) : sizeof(float4); }
+
+size_t prepared_bytes(int32_t P, int32_t M, int prec) {
+  return align_up((size_t)M * sizeof(int2)) + align_up((size_t)P * sizeof(int32_t)) +
+         align_up((size_t)M * sizeof(double4)) + align_up((size_t)P * rec_bytes(prec));
+}
+
+// Carves the prepared region starting at *cursor (already aligned).
+PreparedView carve_prepared(char*& cursor, int32_t P, int32_t M, int prec) {
+  PreparedView pv;
+  pv.vrange = reinterpret_cast<int2*>(cursor);
+  cursor += align_up((size_t)M * sizeof(int2));
+  pv.vid = reinterpret_cast<int32_t*>(cursor);
+  cursor += align_up((size_t)P * sizeof(int32_t));
+  pv.vtab = reinterpret_cast<double4*>(cursor);
+  cursor += align_up((size_t)M * sizeof(double4));
+  pv.rec = cursor;
+  cursor += align_up((size_t)P * rec_bytes(prec));
+  return pv;
+}
+
+char* aligned_base(void* ws) {
+  uintptr_t p = reinterpret_cast<uintptr_t>(ws);
+  return reinterpret_cast<char*>((p + kAlign - 1) / kAlign * kAlign);
+}
+
+bool valid_precision(int prec) { return prec == VESNET_FP64 || prec == VESNET_FP32_COMPENSATED || prec == VESNET_FP32_NAIVE; }
+
+struct Shape {
+  int T, B, splits, bpc;
+};
+
+Shape default_shape(int32_t P, int32_t M, int prec) {
+  Shape s;
+  s.T = prec == P64 ? 1 : 2;
+  s.B = 256;
+  s.bpc = 2;
+  const int64_t waves = ((int64_t)P + 64 * s.T - 1) / (64 * s.T);
+  const int64_t want = 8192;  // about 8 waves per SIMD on 256 CUs x 4 SIMDs
+  int splits = 1;
+  while (waves * splits < want && splits < 16) splits *= 2;
+  s.splits = std::max(1, std::min<int>(splits, std::max(1, M)));
+  return s;
+}
+
+int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec, Shape* out) {
+  Shape s = default_shape(P, M, prec);
+  if (cfg) {
+    if (cfg->targets_per_thread) s.T = cfg->targets_per_thread;
+    if (cfg->block_threads) s.B = cfg->block_threads;
+    if (cfg->source_splits) s.splits = cfg->source_splits;
+    if (cfg->blocks_per_cu) s.bpc = cfg->blocks_per_cu;
+  }
+  if (s.T != 1 && s.T != 2 && s.T != 4)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread must be 1, 2 or 4 (got %d)", s.T);
+  if (s.B != 64 && s.B != 128 && s.B != 256)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "block_threads must be 64, 128 or 256 (got %d)", s.B);
+  if (s.splits < 1 || s.splits > kMaxSplits)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "source_splits must be in [1, %d] (got %d)", kMaxSplits, s.splits);
+  if (s.bpc < 1 || s.bpc > 16)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "blocks_per_cu must be in [1, 16] (got %d)", s.bpc);
+  *out = s;
+  return VESNET_OK;
+}
+
+size_t forward_bytes(int32_t P, int32_t M, int prec, const Shape& s) {
+  size_t b = kAlign + prepared_bytes(P, M, prec);
+  if (s.splits > 1) b += align_up((size_t)2 * s.splits * P * sizeof(double));
+  return b;
+}
+
+bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+  if (!a || !b || an == 0 || bn == 0) return false;
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + bn && pb < pa + an;
+}
+
+int check_sizes(int32_t P, int32_t M) {
+  if (P < 0 || M < 0) return fail(VESNET_ERR_INVALID_ARGUMENT, "negative size (n_points=%d, n_vesicles=%d)", P, M);
+  if (P > kMaxPoints) return fail(VESNET_ERR_INVALID_ARGUMENT, "n_points=%d exceeds the limit %d", P, kMaxPoints);
+  if (P > 0 && M == 0) return fail(VESNET_ERR_INVALID_ARGUMENT, "n_points=%d but no vesicles", P);
+  return VESNET_OK;
+}
+
+int check_mu(double mu) {
+  if (!(std::isfinite(mu) && mu > 0.0)) return fail(VESNET_ERR_INVALID_ARGUMENT, "mu must be finite and > 0 (got %g)", mu);
+  return VESNET_OK;
+}
+
+int check_workspace(void* ws, size_t have, size_t need) {
+  if (need > 0 && !ws) return fail(VESNET_ERR_WORKSPACE, "workspace is NULL but %zu bytes are needed", need);
+  if (have < need) return fail(VESNET_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", have, need);
+  return VESNET_OK;
+}
+
+// Checks common to the forward entry points (targets/sources may be NULL when unused).
+int check_forward_args(const double* targets, const double* sources, const double* f, const double* w,
+                       const int32_t* off, int32_t M, int32_t P, double* out, int prec, void* ws, size_t ws_bytes,
+                       bool need_targets, bool need_sources) {
+  int rc = check_sizes(P, M);
+  if (rc) return rc;
+  if (!valid_precision(prec)) return fail(VESNET_ERR_INVALID_ARGUMENT, "unknown precision %d", prec);
+  if (P == 0) return VESNET_OK;
+  if (!off) return fail(VESNET_ERR_INVALID_ARGUMENT, "vesicle_offsets is NULL");
+  if (need_targets && !targets) return fail(VESNET_ERR_INVALID_ARGUMENT, "targets is NULL");
+  if (need_sources && (!sources || !f || !w))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "sources, force_density and arc_weights must be non-NULL");
+  if (out) {
+    const size_t vb = (size_t)2 * P * sizeof(double);
+    if (overlaps(out, vb, targets, vb) || overlaps(out, vb, sources, vb) || overlaps(out, vb, f, vb) ||
+        overlaps(out, vb, w, (size_t)P * sizeof(double)) || overlaps(out, vb, ws, ws_bytes) ||
+        overlaps(out, vb, off, (size_t)(M + 1) * sizeof(int32_t)))
+      return fail(VESNET_ERR_INVALID_ARGUMENT, "out overlaps an input or the workspace");
+  }
+  return VESNET_OK;
+}
+
+}  // namespace
+
+// ============================================================================ general
+
+extern "C" const char* vesnet_version(void) { return "vesnet 0.1.0 (gfx950)"; }
+
+extern "C" const char* vesnet_last_error(void) { return g_err; }
+
+extern "C" int vesnet_check_offsets(const int32_t* off, int32_t M, int32_t P) {
+  int rc = check_sizes(P, M);
+  if (rc) return rc;
+  if (!off) return fail(VESNET_ERR_INVALID_ARGUMENT, "offsets is NULL");
+  if (off[0] != 0) return fail(VESNET_ERR_INVALID_ARGUMENT, "offsets[0] = %d, expected 0", off[0]);
+  for (int32_t v = 0; v < M; ++v)
+    if (off[v + 1] < off[v])
+      return fail(VESNET_ERR_INVALID_ARGUMENT, "offsets decrease at vesicle %d (%d > %d)", v, off[v], off[v + 1]);
+  if (off[M] != P) return fail(VESNET_ERR_INVALID_ARGUMENT, "offsets[M] = %d, expected n_points = %d", off[M], P);
+  return ok();
+}
+
+extern "C" int vesnet_default_tile_config(int32_t P, int32_t M, int prec, vesnet_tile_config* cfg) {
+  int rc = check_sizes(P, M);
+  if (rc) return rc;
+  if (!valid_precision(prec)) return fail(VESNET_ERR_INVALID_ARGUMENT, "unknown precision %d", prec);
+  if (!cfg) return fail(VESNET_ERR_INVALID_ARGUMENT, "cfg is NULL");
+  Shape s = default_shape(P, M, prec);
+  cfg->targets_per_thread = s.T;
+  cfg->block_threads = s.B;
+  cfg->source_splits = s.splits;
+  cfg->blocks_per_cu = s.bpc;
+  return ok();
+}
+
+// ============================================================================ forward
+
+extern "C" size_t vesnet_farfield_workspace_bytes(int32_t P, int32_t M, int prec, const vesnet_tile_config* cfg) {
+  if (check_sizes(P, M) || !valid_precision(prec)) return 0;
+  Shape s;
+  if (resolve_shape(cfg, P, M, prec, &s)) return 0;
+  return forward_bytes(P, M, prec, s);
+}
+
+extern "C" int vesnet_farfield_prepare(const double* sources, const double* f, const double* w, const int32_t* off,
+                                       int32_t M, int32_t P, int prec, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_forward_args(nullptr, sources, f, w, off, M, P, nullptr, prec, ws, ws_bytes, false, true);
+  if (rc) return rc;
+  if (P == 0) return ok();
+  const size_t need = kAlign + prepared_bytes(P, M, prec);
+  if ((rc = check_workspace(ws, ws_bytes, need))) return rc;
+  char* cur = aligned_base(ws);
+  PreparedView pv = carve_prepared(cur, P, M, prec);
+  hipError_t e = launch_prepare(prec, sources, f, w, off, M, P, pv, stream);
+  if (e != hipSuccess) return hip_fail(e, "prepare launch");
+  return ok();
+}
+
+extern "C" int vesnet_farfield_evaluate(const double* targets, const int32_t* off, int32_t M, int32_t P, double mu,
+                                        double* out, int prec, const vesnet_tile_config* cfg, void* ws,
+                                        size_t ws_bytes, void* stream) {
+  int rc = check_forward_args(targets, nullptr, nullptr, nullptr, off, M, P, out, prec, ws, ws_bytes, true, false);
+  if (rc) return rc;
+  if ((rc = check_mu(mu))) return rc;
+  if (P == 0) return ok();
+  if (!out) return fail(VESNET_ERR_INVALID_ARGUMENT, "out is NULL");
+  Shape s;
+  if ((rc = resolve_shape(cfg, P, M, prec, &s))) return rc;
+  if ((rc = check_workspace(ws, ws_bytes, forward_bytes(P, M, prec, s)))) return rc;
+  char* cur = aligned_base(ws);
+  PreparedView pv = carve_prepared(cur, P, M, prec);
+  double* partial = s.splits > 1 ? reinterpret_cast<double*>(cur) : nullptr;
+  const double scale = 1.0 / (4.0 * kPi * mu);
+  hipError_t e = launch_forward(prec, s.T, s.B, s.splits, targets, P, M, pv, scale, out, partial, stream);
+  if (e != hipSuccess) return hip_fail(e, "forward launch");
+  return ok();
+}
+
+extern "C" int vesnet_farfield_stokeslet(const double* targets, const double* sources, const double* f,
+                                         const double* w, const int32_t* off, int32_t M, int32_t P, double mu,
+                                         double* out, int prec, const vesnet_tile_config* cfg, void* ws,
+                                         size_t ws_bytes, void* stream) {
+  int rc = check_forward_args(targets, sources, f, w, off, M, P, out, prec, ws, ws_bytes, true, true);
+  if (rc) return rc;
+  if ((rc = check_mu(mu))) return rc;
+  if (P == 0) return ok();
+  if (!out) return fail(VESNET_ERR_INVALID_ARGUMENT, "out is NULL");
+  Shape s;
+  if ((rc = resolve_shape(cfg, P, M, prec, &s))) return rc;
+  if ((rc = check_workspace(ws, ws_bytes, forward_bytes(P, M, prec, s)))) return rc;
+  if ((rc = vesnet_farfield_prepare(sources, f, w, off, M, P, prec, ws, ws_bytes, stream))) return rc;
+  return vesnet_farfield_evaluate(targets, off, M, P, mu, out, prec, cfg, ws, ws_bytes, stream);
+}
+
+// ============================================================================ batched
+
+namespace {
+
+size_t plan_bytes(int32_t S) { return align_up((size_t)(4 * (size_t)S + 2) * sizeof(int32_t)); }
+
+PlanView carve_plan(char*& cur, int32_t S) {
+  PlanView pl;
+  int32_t* p = reinterpret_cast<int32_t*>(cur);
+  pl.psz = p;
+  pl.nitems = p + S;
+  pl.order = p + 2 * S;
+  pl.item_start = p + 3 * S;
+  pl.counter = p + 4 * S + 1;
+  cur += plan_bytes(S);
+  return pl;
+}
+
+int num_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+  return n;
+}
+
+int check_batched_args(const double* targets, const double* sources, const double* f, const double* w,
+                       const int32_t* off, int32_t M, int32_t P, const int32_t* sus_off, int32_t S, const double* mu,
+                       double* out, int prec, void* ws, size_t ws_bytes) {
+  int rc = check_forward_args(targets, sources, f, w, off, M, P, out, prec, ws, ws_bytes, true, true);
+  if (rc) return rc;
+  if (S < 0) return fail(VESNET_ERR_INVALID_ARGUMENT, "n_suspensions = %d < 0", S);
+  if (P > 0 && S == 0) return fail(VESNET_ERR_INVALID_ARGUMENT, "points given but no suspensions");
+  if (P > 0 && (!sus_off || !mu)) return fail(VESNET_ERR_INVALID_ARGUMENT, "suspension_offsets and mu must be non-NULL");
+  if (P > 0 && !out) return fail(VESNET_ERR_INVALID_ARGUMENT, "out is NULL");
+  if (out && overlaps(out, (size_t)2 * P * sizeof(double), mu, (size_t)S * sizeof(double)))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "out overlaps mu");
+  return VESNET_OK;
+}
+
+int enqueue_batched(const double* targets, const double* sources, const double* f, const double* w,
+                    const int32_t* off, int32_t M, int32_t P, const int32_t* sus_off, int32_t S, const double* mu,
+                    double* out, int prec, const Shape& s, void* ws, void* stream) {
+  char* cur = aligned_base(ws);
+  PreparedView pv = carve_prepared(cur, P, M, prec);
+  PlanView pl = carve_plan(cur, S);
+  hipError_t e = launch_prepare(prec, sources, f, w, off, M, P, pv, stream);
+  if (e != hipSuccess) return hip_fail(e, "prepare launch");
+  e = launch_plan(sus_off, S, M, pv, s.T * s.B, pl, stream);
+  if (e != hipSuccess) return hip_fail(e, "plan launch");
+  const int grid = num_cus() * s.bpc;
+  e = launch_batched(prec, s.T, s.B, grid, targets, P, M, pv, sus_off, mu, S, pl, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "batched launch");
+  return VESNET_OK;
+}
+
+}  // namespace
+
+extern "C" size_t vesnet_batched_workspace_bytes(int32_t P, int32_t M, int32_t S, int prec) {
+  if (check_sizes(P, M) || !valid_precision(prec) || S < 0) return 0;
+  return kAlign + prepared_bytes(P, M, prec) + plan_bytes(S);
+}
+
+extern "C" int vesnet_farfield_stokeslet_batched(const double* targets, const double* sources, const double* f,
+                                                 const double* w, const int32_t* off, int32_t M, int32_t P,
+                                                 const int32_t* sus_off, int32_t S, const double* mu, double* out,
+                                                 int prec, const vesnet_tile_config* cfg, void* ws, size_t ws_bytes,
+                                                 void* stream) {
+  int rc = check_batched_args(targets, sources, f, w, off, M, P, sus_off, S, mu, out, prec, ws, ws_bytes);
+  if (rc) return rc;
+  if (P == 0) return ok();
+  Shape s;
+  if ((rc = resolve_shape(cfg, P, M, prec, &s))) return rc;
+  if ((rc = check_workspace(ws, ws_bytes, vesnet_batched_workspace_bytes(P, M, S, prec)))) return rc;
+  if ((rc = enqueue_batched(targets, sources, f, w, off, M, P, sus_off, S, mu, out, prec, s, ws, stream))) return rc;
+  return ok();
+}
+
+struct vesnet_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+extern "C" int vesnet_graph_create_batched(const double* targets, const double* sources, const double* f,
+                                           const double* w, const int32_t* off, int32_t M, int32_t P,
+                                           const int32_t* sus_off, int32_t S, const double* mu, double* out,
+                                           int prec, const vesnet_tile_config* cfg, void* ws, size_t ws_bytes,
+                                           vesnet_graph** graph) {
+  if (!graph) return fail(VESNET_ERR_INVALID_ARGUMENT, "graph is NULL");
+  *graph = nullptr;
+  int rc = check_batched_args(targets, sources, f, w, off, M, P, sus_off, S, mu, out, prec, ws, ws_bytes);
+  if (rc) return rc;
+  if (P == 0) return fail(VESNET_ERR_INVALID_ARGUMENT, "nothing to capture (n_points = 0)");
+  Shape s;
+  if ((rc = resolve_shape(cfg, P, M, prec, &s))) return rc;
+  if ((rc = check_workspace(ws, ws_bytes, vesnet_batched_workspace_bytes(P, M, S, prec)))) return rc;
+  hipStream_t st = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    hipStreamDestroy(st);
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  rc = enqueue_batched(targets, sources, f, w, off, M, P, sus_off, S, mu, out, prec, s, ws, st);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(st, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    hipStreamDestroy(st);
+    return rc;
+  }
+  if (e2 != hipSuccess) {
+    hipStreamDestroy(st);
+    return hip_fail(e2, "hipStreamEndCapture");
+  }
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    hipStreamDestroy(st);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  hipStreamDestroy(st);
+  vesnet_graph* h = new vesnet_graph{g, ex};
+  *graph = h;
+  return ok();
+}
+
+extern "C" int vesnet_graph_launch(vesnet_graph* graph, void* stream) {
+  if (!graph) return fail(VESNET_ERR_INVALID_ARGUMENT, "graph is NULL");
+  hipError_t e = hipGraphLaunch(graph->exec, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ok();
+}
+
+extern "C" int vesnet_graph_destroy(vesnet_graph* graph) {
+  if (!graph) return ok();
+  hipGraphExecDestroy(graph->exec);
+  hipGraphDestroy(graph->graph);
+  delete graph;
+  return ok();
+}
+
+// ============================================================================ adjoint
+
+extern "C" size_t vesnet_backward_workspace_bytes(int32_t P, int32_t M, int prec) {
+  if (check_sizes(P, M) || (prec != VESNET_FP64 && prec != VESNET_FP32_COMPENSATED)) return 0;
+  return kAlign + 2 * prepared_bytes(P, M, prec);
+}
+
+extern "C" int vesnet_farfield_stokeslet_backward(const double* targets, const double* sources, const double* f,
+                                                  const double* w, const int32_t* off, int32_t M, int32_t P,
+                                                  double mu, const double* gout, double* grad_t, double* grad_s,
+                                                  double* grad_f, double* grad_w, int prec, void* ws,
+                                                  size_t ws_bytes, void* stream) {
+  int rc = check_forward_args(targets, sources, f, w, off, M, P, nullptr, prec, ws, ws_bytes, true, true);
+  if (rc) return rc;
+  if (prec == VESNET_FP32_NAIVE)
+    return fail(VESNET_ERR_UNSUPPORTED, "the backward pass supports VESNET_FP64 and VESNET_FP32_COMPENSATED only");
+  if ((rc = check_mu(mu))) return rc;
+  if (P == 0) return ok();
+  if (!gout) return fail(VESNET_ERR_INVALID_ARGUMENT, "grad_out is NULL");
+  const size_t vb = (size_t)2 * P * sizeof(double), sb = (size_t)P * sizeof(double);
+  const void* ins[] = {targets, sources, f, gout, off, ws};
+  const size_t inb[] = {vb, vb, vb, vb, (size_t)(M + 1) * sizeof(int32_t), ws_bytes};
+  const void* outs[] = {grad_t, grad_s, grad_f, grad_w};
+  const size_t outb[] = {vb, vb, vb, sb};
+  for (int a = 0; a < 4; ++a) {
+    if (!outs[a]) continue;
+    for (int b = 0; b < 6; ++b)
+      if (overlaps(outs[a], outb[a], ins[b], inb[b]))
+        return fail(VESNET_ERR_INVALID_ARGUMENT, "gradient output %d overlaps an input or the workspace", a);
+    if (overlaps(outs[a], outb[a], w, sb))
+      return fail(VESNET_ERR_INVALID_ARGUMENT, "gradient output %d overlaps arc_weights", a);
+    for (int b = a + 1; b < 4; ++b)
+      if (overlaps(outs[a], outb[a], outs[b], outb[b]))
+        return fail(VESNET_ERR_INVALID_ARGUMENT, "gradient outputs %d and %d overlap", a, b);
+  }
+  if (!grad_t && !grad_s && !grad_f && !grad_w) return ok();
+  if ((rc = check_workspace(ws, ws_bytes, vesnet_backward_workspace_bytes(P, M, prec)))) return rc;
+  char* cur = aligned_base(ws);
+  PreparedView pvS = carve_prepared(cur, P, M, prec);
+  PreparedView pvT = carve_prepared(cur, P, M, prec);
+  hipError_t e = hipSuccess;
+  if (grad_t) e = launch_prepare(prec, sources, f, w, off, M, P, pvS, stream);
+  if (e == hipSuccess && (grad_s || grad_f || grad_w)) e = launch_prepare(prec, targets, gout, nullptr, off, M, P, pvT, stream);
+  if (e != hipSuccess) return hip_fail(e, "backward prepare launch");
+  const double scale = 1.0 / (4.0 * kPi * mu);
+  const int T = prec == P64 ? 1 : 2;
+  e = launch_backward(prec, T, targets, sources, f, w, gout, P, M, pvS, pvT, scale, grad_t, grad_s, grad_f, grad_w,
+                      stream);
+  if (e != hipSuccess) return hip_fail(e, "backward launch");
+  return ok();
+}
+
+// ============================================================================ tuning
+
+extern "C" int vesnet_autotune(const double* targets, const double* sources, const double* f, const double* w,
+                               const int32_t* off, int32_t M, int32_t P, int batched, const int32_t* sus_off,
+                               int32_t S, const double* mu_dev, double mu_host, double* out, int prec, int repeats,
+                               void* ws, size_t ws_bytes, void* stream, vesnet_tile_config* best, float* best_ms) {
+  if (!best) return fail(VESNET_ERR_INVALID_ARGUMENT, "best is NULL");
+  int rc;
+  if (batched) rc = check_batched_args(targets, sources, f, w, off, M, P, sus_off, S, mu_dev, out, prec, ws, ws_bytes);
+  else rc = check_forward_args(targets, sources, f, w, off, M, P, out, prec, ws, ws_bytes, true, true);
+  if (rc) return rc;
+  if (!batched && (rc = check_mu(mu_host))) return rc;
+  if (P == 0) return fail(VESNET_ERR_INVALID_ARGUMENT, "nothing to tune (n_points = 0)");
+  if (!out) return fail(VESNET_ERR_INVALID_ARGUMENT, "out is NULL");
+  if (repeats < 1) repeats = 1;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+
+  std::vector<vesnet_tile_config> cands;
+  for (int T : {1, 2, 4})
+    for (int B : {64, 128, 256}) {
+      if (batched) {
+        for (int bpc : {1, 2, 4, 8}) cands.push_back({T, B, 1, bpc});
+      } else {
+        for (int sp : {1, 2, 4, 8, 16}) {
+          if (sp > std::max(1, M)) continue;
+          const Shape sh{T, B, sp, 1};
+          if (forward_bytes(P, M, prec, sh) > ws_bytes) continue;
+          cands.push_back({T, B, sp, 1});
+        }
+      }
+    }
+  if (batched && (rc = check_workspace(ws, ws_bytes, vesnet_batched_workspace_bytes(P, M, S, prec)))) return rc;
+  if (cands.empty()) return fail(VESNET_ERR_WORKSPACE, "workspace too small for any launch shape");
+
+  if (!batched) {
+    if ((rc = vesnet_farfield_prepare(sources, f, w, off, M, P, prec, ws, ws_bytes, stream))) return rc;
+  }
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  float best_t = 1e30f;
+  vesnet_tile_config best_c = cands[0];
+  rc = VESNET_OK;
+  for (const auto& c : cands) {
+    auto run = [&]() -> int {
+      if (batched)
+        return vesnet_farfield_stokeslet_batched(targets, sources, f, w, off, M, P, sus_off, S, mu_dev, out, prec, &c,
+                                                 ws, ws_bytes, stream);
+      return vesnet_farfield_evaluate(targets, off, M, P, mu_host, out, prec, &c, ws, ws_bytes, stream);
+    };
+    if ((rc = run())) break;  // warm-up
+    float tmin = 1e30f;
+    for (int r = 0; r < repeats && rc == VESNET_OK; ++r) {
+      hipEventRecord(e0, st);
+      rc = run();
+      hipEventRecord(e1, st);
+      if (rc) break;
+      e = hipEventSynchronize(e1);
+      if (e != hipSuccess) { rc = hip_fail(e, "hipEventSynchronize"); break; }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      tmin = std::min(tmin, ms);
+    }
+    if (rc) break;
+    if (tmin < best_t) {
+      best_t = tmin;
+      best_c = c;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  *best = best_c;
+  if (best_ms) *best_ms = best_t;
+  return ok();
+}

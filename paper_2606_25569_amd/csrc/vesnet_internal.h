@@ -1,0 +1,44 @@
+// Internal interfaces between the host API (vesnet_api.hip) and the kernels
+// (vesnet_kernels.hip).  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace vesnet {
+
+enum Prec { P64 = 0, P32C = 1, P32N = 2 };
+
+// Device views of a prepared workspace region.
+struct PreparedView {
+  int2* vrange;    // [M]   clamped point range (j0, j1) of each vesicle
+  int32_t* vid;    // [P]   vesicle id of each point
+  double4* vtab;   // [M]   (c_x, c_y, B_x, B_y): reference point and net weighted vector
+  void* rec;       // [P]   streamed records: float4 (P32C, P32N) or double4 (P64)
+};
+
+// Device views of the batched work plan.
+struct PlanView {
+  int32_t* psz;         // [S]   points per suspension
+  int32_t* nitems;      // [S]   work items per suspension
+  int32_t* order;       // [S]   suspensions, largest first
+  int32_t* item_start;  // [S+1] first item of each suspension in that order
+  int32_t* counter;     // [1]   next item to hand out
+};
+
+hipError_t launch_prepare(int prec, const double* pts, const double* vec, const double* wts, const int32_t* off,
+                          int M, int P, const PreparedView& pv, void* stream);
+hipError_t launch_forward(int prec, int T, int B, int splits, const double* tg, int P, int M, const PreparedView& pv,
+                          double scale, double* out, double* partial, void* stream);
+hipError_t launch_plan(const int32_t* sus_off, int S, int M, const PreparedView& pv, int tile, const PlanView& pl,
+                       void* stream);
+hipError_t launch_batched(int prec, int T, int B, int grid, const double* tg, int P, int M, const PreparedView& pv,
+                          const int32_t* sus_off, const double* mu, int S, const PlanView& pl, double* out,
+                          void* stream);
+hipError_t launch_backward(int prec, int T, const double* tg, const double* src, const double* f, const double* w,
+                           const double* gout, int P, int M, const PreparedView& pvS, const PreparedView& pvT,
+                           double scale, double* grad_t, double* grad_s, double* grad_f, double* grad_w,
+                           void* stream);
+
+}  // namespace vesnet

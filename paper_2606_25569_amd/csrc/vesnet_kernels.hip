@@ -1,0 +1,641 @@
+// Far-field Stokeslet kernels for gfx950 (wave64, vector ALUs).
+//
+// Operation: eq. (single_layer) with the 2D Stokeslet of eq. (Stokeslet), read as
+// -ln|r| I + r r^T/|r|^2, discretised by the trapezoid rule (Section 2.2.1), summed
+// over the vesicles other than the target's own (U_far of eq. (membrane_velocity),
+// DirectSingleLayerIntegral of Algorithm 4), plus its reverse-mode derivative.
+//
+// Design (one gather kernel template serves the forward and both adjoint passes):
+//  * one thread owns T "thread points" (targets in the forward); a wavefront owns 64*T
+//    consecutive points, so a wave usually sits inside one vesicle;
+//  * the loop runs over source vesicles, then over that vesicle's points; every lane reads
+//    the same streamed record, so the compiler turns those reads into scalar loads that
+//    land in SGPRs and feed the VALU directly (no LDS staging, no barriers);
+//  * per (thread point, source vesicle) the pair sums run in float32 on rescaled local
+//    coordinates r' = (x_i - c_v)/|x_i - c_v| - (y_j - c_v)/|x_i - c_v|, so log|r'| is
+//    small for distant vesicles; the rr-term is scale free and the log term differs by
+//    the exact constant ln(sigma) * sum_j F_j, added in float64 at the vesicle boundary
+//    together with the float32 partial (compensated form);
+//  * the own vesicle is dropped at the flush with a select, never inside the pair loop.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vesnet_internal.h"
+
+namespace vesnet {
+
+namespace {
+
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr float kHalfLn2 = -0.34657359027997265471f;  // -(1/2) ln 2 : converts log2(q) to -ln|r|
+
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+
+// Per-vesicle reference point, net vector and streamed records.
+//   pts  [2][P] : positions of the streamed set,  vec [2][P] : vector carried by each point,
+//   wts  [P] or null : weight multiplying vec (w for force densities, none for dL/du).
+// Output per vesicle: range (j0, j1) clamped into [0, P], vtab = (c_x, c_y, B_x, B_y) with
+// c = mean of the points and B = sum of weighted vectors (float64, fixed-order wave tree);
+// per point: vid and the record: P32C (y - c, w vec) float32, P32N (y, w vec) float32,
+// P64 (y, w vec) float64.
+template <int PREC>
+__global__ __launch_bounds__(64) void k_prepare(const double* __restrict__ pts, const double* __restrict__ vec,
+                                                const double* __restrict__ wts, const int32_t* __restrict__ off_in,
+                                                int M, int P, int2* __restrict__ vrange, int32_t* __restrict__ vid,
+                                                double4* __restrict__ vtab, void* __restrict__ rec) {
+  const int lane = threadIdx.x;
+  for (int v = blockIdx.x; v < M; v += gridDim.x) {
+    const int j0 = clampi(off_in[v], 0, P);
+    const int j1 = max(j0, clampi(off_in[v + 1], 0, P));
+    double sx = 0.0, sy = 0.0, bx = 0.0, by = 0.0;
+    for (int j = j0 + lane; j < j1; j += 64) {
+      const double wj = wts ? wts[j] : 1.0;
+      sx += pts[j];
+      sy += pts[P + j];
+      bx += wj * vec[j];
+      by += wj * vec[P + j];
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    bx = wave_sum(bx);
+    by = wave_sum(by);
+    const int n = j1 - j0;
+    const double cx = n > 0 ? sx / n : 0.0;
+    const double cy = n > 0 ? sy / n : 0.0;
+    if (lane == 0) {
+      vrange[v] = make_int2(j0, j1);
+      vtab[v] = make_double4(cx, cy, bx, by);
+    }
+    for (int j = j0 + lane; j < j1; j += 64) {
+      const double wj = wts ? wts[j] : 1.0;
+      const double x = pts[j], y = pts[P + j];
+      const double ex = wj * vec[j], ey = wj * vec[P + j];
+      vid[j] = v;
+      if constexpr (PREC == P32C) {
+        static_cast<float4*>(rec)[j] = make_float4((float)(x - cx), (float)(y - cy), (float)ex, (float)ey);
+      } else if constexpr (PREC == P32N) {
+        static_cast<float4*>(rec)[j] = make_float4((float)x, (float)y, (float)ex, (float)ey);
+      } else {
+        static_cast<double4*>(rec)[j] = make_double4(x, y, ex, ey);
+      }
+    }
+  }
+}
+
+template <int PREC> struct Real;
+template <> struct Real<P64> { using T = double; using R = double4; };
+template <> struct Real<P32C> { using T = float; using R = float4; };
+template <> struct Real<P32N> { using T = float; using R = float4; };
+
+// Accumulated results of one thread point.
+template <int PREC>
+struct Acc {
+  double vx, vy;   // sum of G(r) b      (float64 except for the naive form)
+  double gx, gy;   // sum of grad phi    (float64)
+  float nvx, nvy;  // naive form: float32 totals
+};
+
+// The gather over source vesicles [v_begin, v_end) for the thread points
+// [i_begin, i_end) of this workgroup.  Streamed records carry (position, b);
+// the thread points carry position and (NEED_GRAD) a vector a.
+//   NEED_V    : acc.v += sum_j G(r) b_j               (r = p_i - q_j)
+//   NEED_GRAD : acc.g += sum_j grad_r [a_i^T G(r) b_j]
+// Both without the 1/(4 pi mu) factor.
+template <int PREC, int T, int B, bool NEED_V, bool NEED_GRAD>
+__device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int v_end, const double* __restrict__ pts,
+                                       const double* __restrict__ avec, const double* __restrict__ awts, int P,
+                                       const int32_t* __restrict__ vid, const int2* __restrict__ vrange,
+                                       const double4* __restrict__ vtab,
+                                       const typename Real<PREC>::R* __restrict__ rec, Acc<PREC> (&acc)[T],
+                                       int (&idx)[T], bool (&valid)[T]) {
+  using real = typename Real<PREC>::T;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wbase = i_begin + wave * 64 * T;
+
+  double px[T], py[T];
+  real ax[T], ay[T];
+  int myv[T];
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    idx[k] = wbase + k * 64 + lane;
+    valid[k] = idx[k] < i_end;
+    const int ii = valid[k] ? idx[k] : i_begin;
+    px[k] = pts[ii];
+    py[k] = pts[P + ii];
+    myv[k] = valid[k] ? vid[ii] : -1;
+    if constexpr (NEED_GRAD) {
+      const double wa = awts ? awts[ii] : 1.0;
+      ax[k] = (real)(wa * avec[ii]);
+      ay[k] = (real)(wa * avec[P + ii]);
+    } else {
+      ax[k] = ay[k] = (real)0;
+    }
+    acc[k].vx = acc[k].vy = acc[k].gx = acc[k].gy = 0.0;
+    acc[k].nvx = acc[k].nvy = 0.0f;
+  }
+  float pxf[T], pyf[T];
+  if constexpr (PREC == P32N) {
+#pragma unroll
+    for (int k = 0; k < T; ++k) { pxf[k] = (float)px[k]; pyf[k] = (float)py[k]; }
+  }
+
+  for (int v = v_begin; v < v_end; ++v) {
+    // Skip a vesicle that is the own vesicle of every live point of this wave.
+    bool all_own = true;
+#pragma unroll
+    for (int k = 0; k < T; ++k) all_own = all_own && (!valid[k] || myv[k] == v);
+    if (__all(all_own)) continue;
+
+    const int2 jr = vrange[v];
+    const double4 vt = vtab[v];
+
+    // Per (thread point, vesicle) set-up.
+    real dx[T], dy[T], ns[T];
+    float sig[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      if constexpr (PREC == P32C) {
+        const double ddx = px[k] - vt.x, ddy = py[k] - vt.y;
+        const double D = ddx * ddx + ddy * ddy;
+        const float Df = (float)D;
+        const float s = (Df > 1e-30f && Df < 1e30f) ? __builtin_amdgcn_rsqf(Df) : 1.0f;
+        sig[k] = s;
+        dx[k] = (float)(ddx * (double)s);
+        dy[k] = (float)(ddy * (double)s);
+        ns[k] = -s;
+      } else if constexpr (PREC == P32N) {
+        dx[k] = pxf[k];
+        dy[k] = pyf[k];
+        ns[k] = -1.0f;
+        sig[k] = 1.0f;
+      } else {
+        dx[k] = px[k];
+        dy[k] = py[k];
+        ns[k] = -1.0;
+        sig[k] = 1.0f;
+      }
+    }
+
+    real lx[T], ly[T], rvx[T], rvy[T], s1[T], gx[T], gy[T], hx[T], hy[T];
+#pragma unroll
+    for (int k = 0; k < T; ++k) lx[k] = ly[k] = rvx[k] = rvy[k] = s1[k] = gx[k] = gy[k] = hx[k] = hy[k] = (real)0;
+
+    auto pair = [&](const typename Real<PREC>::R& s) __attribute__((always_inline)) {
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        real rx, ry;
+        if constexpr (PREC == P64) {
+          rx = dx[k] - s.x;
+          ry = dy[k] - s.y;
+        } else if constexpr (PREC == P32N) {
+          rx = dx[k] - s.x;
+          ry = dy[k] - s.y;
+        } else {
+          rx = fmaf(s.x, ns[k], dx[k]);
+          ry = fmaf(s.y, ns[k], dy[k]);
+        }
+        const real q = ry * ry + rx * rx;
+        real rho;
+        if constexpr (PREC == P64) rho = 1.0 / q;
+        else rho = __builtin_amdgcn_rcpf(q);
+        const real beta = ry * s.w + rx * s.z;  // r . b
+        if constexpr (NEED_V) {
+          real L;
+          if constexpr (PREC == P64) L = log(q);
+          else L = __builtin_amdgcn_logf(q);
+          lx[k] += L * s.z;
+          ly[k] += L * s.w;
+          const real t = beta * rho;
+          rvx[k] += t * rx;
+          rvy[k] += t * ry;
+        }
+        if constexpr (NEED_GRAD) {
+          const real alpha = ry * ay[k] + rx * ax[k];  // a . r
+          const real gam = ay[k] * s.w + ax[k] * s.z;  // a . b
+          const real abr = (alpha * beta) * rho;
+          const real kap = (real)-2 * abr - gam;
+          const real kr = kap * rho, ar = alpha * rho, br = beta * rho;
+          s1[k] += br;
+          gx[k] += s.z * ar;
+          gy[k] += s.w * ar;
+          hx[k] += rx * kr;
+          hy[k] += ry * kr;
+        }
+      }
+    };
+
+    int j = jr.x;
+    for (; j + 4 <= jr.y; j += 4) {
+      const typename Real<PREC>::R s0 = rec[j], sA = rec[j + 1], sB = rec[j + 2], sC = rec[j + 3];
+      pair(s0);
+      pair(sA);
+      pair(sB);
+      pair(sC);
+    }
+    for (; j < jr.y; ++j) pair(rec[j]);
+
+    // Flush the per-vesicle partials (own vesicle dropped by a select).
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const bool keep = myv[k] != v;
+      if constexpr (NEED_V) {
+        if constexpr (PREC == P32C) {
+          const float pvx = fmaf(kHalfLn2, lx[k], rvx[k]);
+          const float pvy = fmaf(kHalfLn2, ly[k], rvy[k]);
+          int e;
+          const float m = frexpf(sig[k], &e);
+          const double lnsig = ((double)e + (double)__builtin_amdgcn_logf(m)) * kLn2;
+          const double cvx = fma(lnsig, vt.z, (double)pvx);
+          const double cvy = fma(lnsig, vt.w, (double)pvy);
+          acc[k].vx += keep ? cvx : 0.0;
+          acc[k].vy += keep ? cvy : 0.0;
+        } else if constexpr (PREC == P32N) {
+          const float pvx = fmaf(kHalfLn2, lx[k], rvx[k]);
+          const float pvy = fmaf(kHalfLn2, ly[k], rvy[k]);
+          acc[k].nvx += keep ? pvx : 0.0f;
+          acc[k].nvy += keep ? pvy : 0.0f;
+        } else {
+          const double pvx = fma(-0.5, lx[k], rvx[k]);
+          const double pvy = fma(-0.5, ly[k], rvy[k]);
+          acc[k].vx += keep ? pvx : 0.0;
+          acc[k].vy += keep ? pvy : 0.0;
+        }
+      }
+      if constexpr (NEED_GRAD) {
+        const real pgx = ax[k] * s1[k] + gx[k] + hx[k];
+        const real pgy = ay[k] * s1[k] + gy[k] + hy[k];
+        if constexpr (PREC == P32C) {
+          const double sg = (double)sig[k];
+          acc[k].gx += keep ? sg * (double)pgx : 0.0;
+          acc[k].gy += keep ? sg * (double)pgy : 0.0;
+        } else {
+          acc[k].gx += keep ? (double)pgx : 0.0;
+          acc[k].gy += keep ? (double)pgy : 0.0;
+        }
+      }
+    }
+  }
+  if constexpr (PREC == P32N) {
+#pragma unroll
+    for (int k = 0; k < T; ++k) { acc[k].vx = acc[k].nvx; acc[k].vy = acc[k].nvy; }
+  }
+}
+
+// ----------------------------------------------------------------------------- forward
+
+template <int PREC, int T, int B>
+__global__ __launch_bounds__(B) void k_forward(const double* __restrict__ tg, int P, int M,
+                                               const int32_t* __restrict__ vid, const int2* __restrict__ vrange,
+                                               const double4* __restrict__ vtab,
+                                               const typename Real<PREC>::R* __restrict__ rec, double scale,
+                                               int splits, double* __restrict__ out, double* __restrict__ partial) {
+  const int tile = B * T;
+  const int i_begin = blockIdx.x * tile;
+  if (i_begin >= P) return;
+  const int i_end = min(P, i_begin + tile);
+  const int split = blockIdx.y;
+  const int v_begin = (int)(((int64_t)M * split) / splits);
+  const int v_end = (int)(((int64_t)M * (split + 1)) / splits);
+  Acc<PREC> acc[T];
+  int idx[T];
+  bool valid[T];
+  gather<PREC, T, B, true, false>(i_begin, i_end, v_begin, v_end, tg, nullptr, nullptr, P, vid, vrange, vtab, rec,
+                                  acc, idx, valid);
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    if (!valid[k]) continue;
+    if (splits == 1) {
+      out[idx[k]] = scale * acc[k].vx;
+      out[P + idx[k]] = scale * acc[k].vy;
+    } else {
+      partial[(size_t)(2 * split) * P + idx[k]] = acc[k].vx;
+      partial[(size_t)(2 * split + 1) * P + idx[k]] = acc[k].vy;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_splits(const double* __restrict__ partial, int P, int splits,
+                                                       double scale, double* __restrict__ out) {
+  const int64_t n = 2 * (int64_t)P;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / P);
+    const int64_t i = e - (int64_t)c * P;
+    double s = 0.0;
+    for (int k = 0; k < splits; ++k) s += partial[(size_t)(2 * k + c) * P + i];
+    out[e] = scale * s;
+  }
+}
+
+// ----------------------------------------------------------------------------- batched
+
+// Plan, step 1: size of each suspension (points), work items per suspension.
+__global__ void k_plan_sizes(const int32_t* __restrict__ sus_off, int S, int M, const int2* __restrict__ vrange,
+                             int tile, int32_t* __restrict__ psz, int32_t* __restrict__ nitems) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
+    const int vb = clampi(sus_off[s], 0, M);
+    const int ve = max(vb, clampi(sus_off[s + 1], 0, M));
+    int p = 0;
+    if (ve > vb) p = max(0, vrange[ve - 1].y - vrange[vb].x);
+    psz[s] = p;
+    nitems[s] = (p + tile - 1) / tile;
+  }
+}
+
+// Plan, step 2: order suspensions by size, largest first (ties by index).
+__global__ void k_plan_rank(const int32_t* __restrict__ psz, int S, int32_t* __restrict__ order) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
+    const int ps = psz[s];
+    int r = 0;
+    for (int t = 0; t < S; ++t) {
+      const int pt = psz[t];
+      r += (pt > ps) || (pt == ps && t < s);
+    }
+    order[r] = s;
+  }
+}
+
+// Plan, step 3: item offsets in that order, and reset of the work counter.
+__global__ __launch_bounds__(256) void k_plan_scan(const int32_t* __restrict__ order, const int32_t* __restrict__ nitems,
+                                                   int S, int32_t* __restrict__ item_start, int32_t* __restrict__ counter) {
+  __shared__ int32_t part[256];
+  const int t = threadIdx.x;
+  const int per = (S + 255) / 256;
+  const int b = min(S, t * per), e = min(S, b + per);
+  int32_t loc = 0;
+  for (int r = b; r < e; ++r) loc += nitems[order[r]];
+  part[t] = loc;
+  __syncthreads();
+  if (t == 0) {
+    int32_t run = 0;
+    for (int k = 0; k < 256; ++k) { const int32_t x = part[k]; part[k] = run; run += x; }
+  }
+  __syncthreads();
+  int32_t run = part[t];
+  for (int r = b; r < e; ++r) { item_start[r] = run; run += nitems[order[r]]; }
+  if (t == 255) item_start[S] = run;
+  if (t == 0) counter[0] = 0;
+}
+
+template <int PREC, int T, int B>
+__global__ __launch_bounds__(B) void k_forward_batched(const double* __restrict__ tg, int P, int M,
+                                                       const int32_t* __restrict__ vid,
+                                                       const int2* __restrict__ vrange,
+                                                       const double4* __restrict__ vtab,
+                                                       const typename Real<PREC>::R* __restrict__ rec,
+                                                       const int32_t* __restrict__ sus_off,
+                                                       const double* __restrict__ mu, int S,
+                                                       const int32_t* __restrict__ order,
+                                                       const int32_t* __restrict__ item_start,
+                                                       int32_t* __restrict__ counter, double* __restrict__ out) {
+  __shared__ int32_t s_item;
+  const int tile = B * T;
+  const int total = item_start[S];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int k = s_item;
+    __syncthreads();
+    if (k >= total) break;
+    int lo = 0, hi = S;  // item_start[lo] <= k < item_start[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (item_start[mid] <= k) lo = mid; else hi = mid;
+    }
+    const int s = order[lo];
+    const int blk = k - item_start[lo];
+    const int vb = clampi(sus_off[s], 0, M);
+    const int ve = max(vb, clampi(sus_off[s + 1], 0, M));
+    if (ve <= vb) continue;
+    const int pb = vrange[vb].x;
+    const int pe = max(pb, vrange[ve - 1].y);
+    const int i_begin = pb + blk * tile;
+    if (i_begin >= pe) continue;
+    const int i_end = min(pe, i_begin + tile);
+    const double scale = 1.0 / (4.0 * 3.14159265358979323846 * mu[s]);
+    Acc<PREC> acc[T];
+    int idx[T];
+    bool valid[T];
+    gather<PREC, T, B, true, false>(i_begin, i_end, vb, ve, tg, nullptr, nullptr, P, vid, vrange, vtab, rec, acc,
+                                    idx, valid);
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      if (!valid[q]) continue;
+      out[idx[q]] = scale * acc[q].vx;
+      out[P + idx[q]] = scale * acc[q].vy;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------- adjoint
+
+// Pass over targets: grad_targets_i = c * sum_j grad_r phi(x_i - y_j; g_i, F_j).
+template <int PREC, int T, int B>
+__global__ __launch_bounds__(B) void k_bwd_targets(const double* __restrict__ tg, const double* __restrict__ gout,
+                                                   int P, int M, const int32_t* __restrict__ vid,
+                                                   const int2* __restrict__ vrange, const double4* __restrict__ vtab,
+                                                   const typename Real<PREC>::R* __restrict__ rec, double scale,
+                                                   double* __restrict__ grad_t) {
+  const int tile = B * T;
+  const int i_begin = blockIdx.x * tile;
+  if (i_begin >= P) return;
+  const int i_end = min(P, i_begin + tile);
+  Acc<PREC> acc[T];
+  int idx[T];
+  bool valid[T];
+  gather<PREC, T, B, false, true>(i_begin, i_end, 0, M, tg, gout, nullptr, P, vid, vrange, vtab, rec, acc, idx,
+                                  valid);
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    if (!valid[k]) continue;
+    grad_t[idx[k]] = scale * acc[k].gx;
+    grad_t[P + idx[k]] = scale * acc[k].gy;
+  }
+}
+
+// Pass over sources: with r~ = y_j - x_i (G even, grad phi odd and symmetric in its vectors)
+//   grad_sources_j = c * sum_i grad phi(r~; F_j, g_i),  v_j = c * sum_i G(r~) g_i,
+//   grad_f_j = w_j v_j,  grad_w_j = f_j . v_j.
+template <int PREC, int T, int B>
+__global__ __launch_bounds__(B) void k_bwd_sources(const double* __restrict__ src, const double* __restrict__ f,
+                                                   const double* __restrict__ w, int P, int M,
+                                                   const int32_t* __restrict__ vid, const int2* __restrict__ vrange,
+                                                   const double4* __restrict__ vtab,
+                                                   const typename Real<PREC>::R* __restrict__ rec, double scale,
+                                                   double* __restrict__ grad_s, double* __restrict__ grad_f,
+                                                   double* __restrict__ grad_w) {
+  const int tile = B * T;
+  const int i_begin = blockIdx.x * tile;
+  if (i_begin >= P) return;
+  const int i_end = min(P, i_begin + tile);
+  Acc<PREC> acc[T];
+  int idx[T];
+  bool valid[T];
+  gather<PREC, T, B, true, true>(i_begin, i_end, 0, M, src, f, w, P, vid, vrange, vtab, rec, acc, idx, valid);
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    if (!valid[k]) continue;
+    const int j = idx[k];
+    if (grad_s) {
+      grad_s[j] = scale * acc[k].gx;
+      grad_s[P + j] = scale * acc[k].gy;
+    }
+    const double vx = scale * acc[k].vx, vy = scale * acc[k].vy;
+    if (grad_f) {
+      grad_f[j] = w[j] * vx;
+      grad_f[P + j] = w[j] * vy;
+    }
+    if (grad_w) grad_w[j] = f[j] * vx + f[P + j] * vy;
+  }
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------- launchers
+
+static inline hipStream_t S_(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+hipError_t launch_prepare(int prec, const double* pts, const double* vec, const double* wts, const int32_t* off,
+                          int M, int P, const PreparedView& pv, void* stream) {
+  if (M == 0) return hipSuccess;
+  const int grid = M < 65535 ? M : 65535;
+  switch (prec) {
+    case P64: hipLaunchKernelGGL(k_prepare<P64>, dim3(grid), dim3(64), 0, S_(stream), pts, vec, wts, off, M, P,
+                                 pv.vrange, pv.vid, pv.vtab, pv.rec); break;
+    case P32C: hipLaunchKernelGGL(k_prepare<P32C>, dim3(grid), dim3(64), 0, S_(stream), pts, vec, wts, off, M, P,
+                                  pv.vrange, pv.vid, pv.vtab, pv.rec); break;
+    case P32N: hipLaunchKernelGGL(k_prepare<P32N>, dim3(grid), dim3(64), 0, S_(stream), pts, vec, wts, off, M, P,
+                                  pv.vrange, pv.vid, pv.vtab, pv.rec); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int PREC, int T, int B>
+static void fwd_one(const double* tg, int P, int M, const PreparedView& pv, double scale, int splits, double* out,
+                    double* partial, hipStream_t st) {
+  const int tile = B * T;
+  dim3 grid((P + tile - 1) / tile, splits);
+  hipLaunchKernelGGL((k_forward<PREC, T, B>), grid, dim3(B), 0, st, tg, P, M, pv.vid, pv.vrange, pv.vtab,
+                     static_cast<const typename Real<PREC>::R*>(pv.rec), scale, splits, out, partial);
+}
+
+template <int PREC>
+static bool fwd_dispatch(int T, int B, const double* tg, int P, int M, const PreparedView& pv, double scale,
+                         int splits, double* out, double* partial, hipStream_t st) {
+#define VESNET_FWD_CASE(TT, BB) \
+  if (T == TT && B == BB) { fwd_one<PREC, TT, BB>(tg, P, M, pv, scale, splits, out, partial, st); return true; }
+  VESNET_FWD_CASE(1, 64) VESNET_FWD_CASE(1, 128) VESNET_FWD_CASE(1, 256)
+  VESNET_FWD_CASE(2, 64) VESNET_FWD_CASE(2, 128) VESNET_FWD_CASE(2, 256)
+  VESNET_FWD_CASE(4, 64) VESNET_FWD_CASE(4, 128) VESNET_FWD_CASE(4, 256)
+#undef VESNET_FWD_CASE
+  return false;
+}
+
+hipError_t launch_forward(int prec, int T, int B, int splits, const double* tg, int P, int M, const PreparedView& pv,
+                          double scale, double* out, double* partial, void* stream) {
+  if (P == 0) return hipSuccess;
+  hipStream_t st = S_(stream);
+  bool ok = false;
+  switch (prec) {
+    case P64: ok = fwd_dispatch<P64>(T, B, tg, P, M, pv, scale, splits, out, partial, st); break;
+    case P32C: ok = fwd_dispatch<P32C>(T, B, tg, P, M, pv, scale, splits, out, partial, st); break;
+    case P32N: ok = fwd_dispatch<P32N>(T, B, tg, P, M, pv, scale, splits, out, partial, st); break;
+    default: break;
+  }
+  if (!ok) return hipErrorInvalidValue;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || splits == 1) return e;
+  const int64_t n = 2 * (int64_t)P;
+  const int grid = (int)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
+  hipLaunchKernelGGL(k_reduce_splits, dim3(grid), dim3(256), 0, st, partial, P, splits, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan(const int32_t* sus_off, int S, int M, const PreparedView& pv, int tile, const PlanView& pl,
+                       void* stream) {
+  hipStream_t st = S_(stream);
+  const int g = (S + 255) / 256;
+  hipLaunchKernelGGL(k_plan_sizes, dim3(g > 0 ? g : 1), dim3(256), 0, st, sus_off, S, M, pv.vrange, tile, pl.psz,
+                     pl.nitems);
+  hipLaunchKernelGGL(k_plan_rank, dim3(g > 0 ? g : 1), dim3(256), 0, st, pl.psz, S, pl.order);
+  hipLaunchKernelGGL(k_plan_scan, dim3(1), dim3(256), 0, st, pl.order, pl.nitems, S, pl.item_start, pl.counter);
+  return hipGetLastError();
+}
+
+template <int PREC, int T, int B>
+static void bat_one(int grid, const double* tg, int P, int M, const PreparedView& pv, const int32_t* sus_off,
+                    const double* mu, int S, const PlanView& pl, double* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_forward_batched<PREC, T, B>), dim3(grid), dim3(B), 0, st, tg, P, M, pv.vid, pv.vrange,
+                     pv.vtab, static_cast<const typename Real<PREC>::R*>(pv.rec), sus_off, mu, S, pl.order,
+                     pl.item_start, pl.counter, out);
+}
+
+template <int PREC>
+static bool bat_dispatch(int T, int B, int grid, const double* tg, int P, int M, const PreparedView& pv,
+                         const int32_t* sus_off, const double* mu, int S, const PlanView& pl, double* out,
+                         hipStream_t st) {
+#define VESNET_BAT_CASE(TT, BB) \
+  if (T == TT && B == BB) { bat_one<PREC, TT, BB>(grid, tg, P, M, pv, sus_off, mu, S, pl, out, st); return true; }
+  VESNET_BAT_CASE(1, 64) VESNET_BAT_CASE(1, 128) VESNET_BAT_CASE(1, 256)
+  VESNET_BAT_CASE(2, 64) VESNET_BAT_CASE(2, 128) VESNET_BAT_CASE(2, 256)
+  VESNET_BAT_CASE(4, 64) VESNET_BAT_CASE(4, 128) VESNET_BAT_CASE(4, 256)
+#undef VESNET_BAT_CASE
+  return false;
+}
+
+hipError_t launch_batched(int prec, int T, int B, int grid, const double* tg, int P, int M, const PreparedView& pv,
+                          const int32_t* sus_off, const double* mu, int S, const PlanView& pl, double* out,
+                          void* stream) {
+  hipStream_t st = S_(stream);
+  bool ok = false;
+  switch (prec) {
+    case P64: ok = bat_dispatch<P64>(T, B, grid, tg, P, M, pv, sus_off, mu, S, pl, out, st); break;
+    case P32C: ok = bat_dispatch<P32C>(T, B, grid, tg, P, M, pv, sus_off, mu, S, pl, out, st); break;
+    case P32N: ok = bat_dispatch<P32N>(T, B, grid, tg, P, M, pv, sus_off, mu, S, pl, out, st); break;
+    default: break;
+  }
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int PREC, int T, int B>
+static void bwd_one(const double* tg, const double* src, const double* f, const double* w, const double* gout, int P,
+                    int M, const PreparedView& pvS, const PreparedView& pvT, double scale, double* grad_t,
+                    double* grad_s, double* grad_f, double* grad_w, hipStream_t st) {
+  const int tile = B * T;
+  const int grid = (P + tile - 1) / tile;
+  if (grad_t)
+    hipLaunchKernelGGL((k_bwd_targets<PREC, T, B>), dim3(grid), dim3(B), 0, st, tg, gout, P, M, pvS.vid, pvS.vrange,
+                       pvS.vtab, static_cast<const typename Real<PREC>::R*>(pvS.rec), scale, grad_t);
+  if (grad_s || grad_f || grad_w)
+    hipLaunchKernelGGL((k_bwd_sources<PREC, T, B>), dim3(grid), dim3(B), 0, st, src, f, w, P, M, pvT.vid,
+                       pvT.vrange, pvT.vtab, static_cast<const typename Real<PREC>::R*>(pvT.rec), scale, grad_s,
+                       grad_f, grad_w);
+}
+
+hipError_t launch_backward(int prec, int T, const double* tg, const double* src, const double* f, const double* w,
+                           const double* gout, int P, int M, const PreparedView& pvS, const PreparedView& pvT,
+                           double scale, double* grad_t, double* grad_s, double* grad_f, double* grad_w,
+                           void* stream) {
+  if (P == 0) return hipSuccess;
+  hipStream_t st = S_(stream);
+  if (prec == P64) {
+    if (T == 1) bwd_one<P64, 1, 256>(tg, src, f, w, gout, P, M, pvS, pvT, scale, grad_t, grad_s, grad_f, grad_w, st);
+    else bwd_one<P64, 2, 256>(tg, src, f, w, gout, P, M, pvS, pvT, scale, grad_t, grad_s, grad_f, grad_w, st);
+  } else if (prec == P32C) {
+    if (T == 1) bwd_one<P32C, 1, 256>(tg, src, f, w, gout, P, M, pvS, pvT, scale, grad_t, grad_s, grad_f, grad_w, st);
+    else bwd_one<P32C, 2, 256>(tg, src, f, w, gout, P, M, pvS, pvT, scale, grad_t, grad_s, grad_f, grad_w, st);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vesnet

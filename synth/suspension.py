@@ -110,6 +110,8 @@ def ellipse_axes(nu: float, perimeter: float = PERIMETER) -> tuple[float, float]
 
 def ellipse_curve(center, a, b, phi, n):
     """Points and arclength weights of a rotated ellipse at alpha_k = 2*pi*k/n."""
+    if n == 0:
+        return np.zeros((2, 0)), np.zeros(0), np.zeros(0)
     th = 2.0 * np.pi * np.arange(n) / n
     c, s = np.cos(phi), np.sin(phi)
     ex, ey = a * np.cos(th), b * np.sin(th)
@@ -246,6 +248,8 @@ def _assemble(rng, centers, axes, angles, n_per, force_kind, net_force_std, mu, 
             fv = fourier_force(rng, n, th, 1, 16, lambda k: 1.0 / k)
         else:
             raise ValueError(force_kind)
+        if n == 0:
+            continue
         fv = make_force_free(fv, wv)
         if net_force_std > 0.0:
             Fnet = rng.normal(0.0, net_force_std, size=2)

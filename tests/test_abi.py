@@ -1,0 +1,164 @@
+"""CPU tests of the C-ABI library: it loads, exports every symbol the header
+declares, and rejects bad arguments on the host before touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2606_25569_amd import _lib
+    return _lib
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "vesnet.h")).read()
+    return sorted(set(re.findall(r"VESNET_API\s+[\w\s\*]+?\b(vesnet_\w+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    lib = L.lib()
+    names = _declared()
+    assert len(names) == 16, names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_only_c_symbols_exported(L):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    funcs = [ln.split()[-1] for ln in out.splitlines() if " T " in ln]
+    assert funcs and all(f.startswith("vesnet_") for f in funcs), funcs
+
+
+def test_version(L):
+    assert b"gfx950" in L.lib().vesnet_version()
+
+
+def _offs(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def test_check_offsets(L):
+    lib = L.lib()
+    a, p = _offs([0, 3, 3, 7])
+    assert lib.vesnet_check_offsets(p, 3, 7) == 0
+    for bad, M, P in (([1, 3, 7], 2, 7), ([0, 5, 3], 2, 3), ([0, 3, 6], 2, 7)):
+        a, p = _offs(bad)
+        assert lib.vesnet_check_offsets(p, M, P) == L.ERR_INVALID_ARGUMENT
+        assert lib.vesnet_last_error()
+    assert lib.vesnet_check_offsets(None, 1, 1) == L.ERR_INVALID_ARGUMENT
+    assert lib.vesnet_check_offsets(p, -1, 3) == L.ERR_INVALID_ARGUMENT
+    a, p = _offs([0])
+    assert lib.vesnet_check_offsets(p, 0, 0) == 0
+    assert lib.vesnet_check_offsets(p, 0, 5) == L.ERR_INVALID_ARGUMENT
+
+
+def test_default_config_and_workspace_sizes(L):
+    lib = L.lib()
+    cfg = L.TileConfig()
+    assert lib.vesnet_default_tile_config(256000, 2000, 1, ctypes.byref(cfg)) == 0
+    d = cfg.as_dict()
+    assert d["targets_per_thread"] in (1, 2, 4) and d["block_threads"] in (64, 128, 256) and d["source_splits"] >= 1
+    n1 = lib.vesnet_farfield_workspace_bytes(256000, 2000, 1, ctypes.byref(L.TileConfig(2, 256, 1, 1)))
+    n4 = lib.vesnet_farfield_workspace_bytes(256000, 2000, 1, ctypes.byref(L.TileConfig(2, 256, 4, 1)))
+    n64 = lib.vesnet_farfield_workspace_bytes(256000, 2000, 0, ctypes.byref(L.TileConfig(2, 256, 1, 1)))
+    assert n1 >= 256000 * (16 + 4) + 2000 * 40
+    assert n4 - n1 >= 2 * 4 * 256000 * 8
+    assert n64 - n1 >= 256000 * 16
+    assert lib.vesnet_farfield_workspace_bytes(10, 2, 7, None) == 0          # bad precision
+    assert lib.vesnet_farfield_workspace_bytes(10, 2, 1, ctypes.byref(L.TileConfig(3, 256, 1, 1))) == 0
+    assert lib.vesnet_backward_workspace_bytes(10, 2, 2) == 0                # naive has no backward
+    assert lib.vesnet_batched_workspace_bytes(100, 10, 3, 1) > 0
+
+
+FAKE = 0x10000  # never dereferenced: every call below fails validation first
+
+
+def _p(x):
+    return ctypes.c_void_p(x)
+
+
+def _fwd(L, **kw):
+    a = dict(targets=FAKE, sources=FAKE + 0x100000, f=FAKE + 0x200000, w=FAKE + 0x300000, off=FAKE + 0x400000,
+             M=2, P=10, mu=1.0, out=FAKE + 0x500000, prec=1, cfg=None, ws=FAKE + 0x600000, wsb=1 << 30)
+    a.update(kw)
+    return L.lib().vesnet_farfield_stokeslet(_p(a["targets"]), _p(a["sources"]), _p(a["f"]), _p(a["w"]), _p(a["off"]),
+                                             a["M"], a["P"], a["mu"], _p(a["out"]), a["prec"], a["cfg"], _p(a["ws"]),
+                                             a["wsb"], None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    ({"targets": 0}, -1), ({"sources": 0}, -1), ({"f": 0}, -1), ({"w": 0}, -1), ({"off": 0}, -1), ({"out": 0}, -1),
+    ({"mu": 0.0}, -1), ({"mu": -1.0}, -1), ({"mu": float("nan")}, -1), ({"mu": float("inf")}, -1),
+    ({"prec": 9}, -1), ({"P": -1}, -1), ({"M": -2}, -1), ({"M": 0}, -1), ({"P": (1 << 30) + 1}, -1),
+    ({"ws": 0}, -3), ({"wsb": 16}, -3),
+    ({"out": FAKE}, -1), ({"out": FAKE + 0x100000 + 8}, -1), ({"out": FAKE + 0x600000 + 64}, -1),
+])
+def test_forward_rejects_bad_arguments(L, kw, code):
+    assert _fwd(L, **kw) == code
+    assert len(L.lib().vesnet_last_error()) > 0
+
+
+def test_bad_tile_configs_rejected(L):
+    for cfg in (L.TileConfig(3, 256, 1, 1), L.TileConfig(1, 96, 1, 1), L.TileConfig(1, 64, 65, 1),
+                L.TileConfig(1, 64, -1, 1), L.TileConfig(1, 64, 1, 17)):
+        assert _fwd(L, cfg=ctypes.byref(cfg)) == -1
+
+
+def test_empty_problem_is_a_no_op(L):
+    assert _fwd(L, P=0, M=0, targets=0, sources=0, f=0, w=0, off=0, out=0, ws=0, wsb=0) == 0
+
+
+def test_backward_rejects(L):
+    lib = L.lib()
+    args = [_p(FAKE), _p(FAKE + 0x100000), _p(FAKE + 0x200000), _p(FAKE + 0x300000), _p(FAKE + 0x400000), 2, 10, 1.0,
+            _p(FAKE + 0x500000)]
+    ws = [_p(FAKE + 0x600000), 1 << 30, None]
+    # naive precision unsupported
+    assert lib.vesnet_farfield_stokeslet_backward(*args, _p(FAKE + 0x700000), None, None, None, 2, *ws) == -2
+    # outputs overlapping each other
+    assert lib.vesnet_farfield_stokeslet_backward(*args, _p(FAKE + 0x700000), _p(FAKE + 0x700000 + 8), None, None, 1,
+                                                  *ws) == -1
+    # output overlapping grad_out
+    assert lib.vesnet_farfield_stokeslet_backward(*args, _p(FAKE + 0x500000), None, None, None, 1, *ws) == -1
+    # missing grad_out
+    a2 = list(args)
+    a2[8] = None
+    assert lib.vesnet_farfield_stokeslet_backward(*a2, _p(FAKE + 0x700000), None, None, None, 1, *ws) == -1
+    # workspace too small
+    assert lib.vesnet_farfield_stokeslet_backward(*args, _p(FAKE + 0x700000), None, None, None, 1, _p(FAKE + 0x600000),
+                                                  8, None) == -3
+
+
+def test_batched_rejects(L):
+    lib = L.lib()
+    base = [_p(FAKE), _p(FAKE + 0x100000), _p(FAKE + 0x200000), _p(FAKE + 0x300000), _p(FAKE + 0x400000), 2, 10]
+    tail = [_p(FAKE + 0x500000), 1, None, _p(FAKE + 0x600000), 1 << 30, None]
+    assert lib.vesnet_farfield_stokeslet_batched(*base, None, 1, _p(FAKE + 0x800000), *tail) == -1   # no sus offsets
+    assert lib.vesnet_farfield_stokeslet_batched(*base, _p(FAKE + 0x900000), 0, _p(FAKE + 0x800000), *tail) == -1
+    assert lib.vesnet_farfield_stokeslet_batched(*base, _p(FAKE + 0x900000), 1, None, *tail) == -1   # no mu
+    g = ctypes.c_void_p()
+    assert lib.vesnet_graph_create_batched(*base, None, 1, _p(FAKE + 0x800000), *tail[:5], ctypes.byref(g)) == -1
+    assert lib.vesnet_graph_launch(None, None) == -1
+    assert lib.vesnet_graph_destroy(None) == 0
+
+
+def test_product_package_has_no_cpu_fallback():
+    """The package imports the library eagerly and never imports the oracle."""
+    import ast
+    pkg = os.path.join(ROOT, "paper_2606_25569_amd")
+    for fn in os.listdir(pkg):
+        if fn.endswith(".py"):
+            tree = ast.parse(open(os.path.join(pkg, fn)).read())
+            for node in ast.walk(tree):
+                if isinstance(node, (ast.Import, ast.ImportFrom)):
+                    mods = [a.name for a in node.names] if isinstance(node, ast.Import) else [node.module or ""]
+                    assert not any(m.split(".")[0] == "oracle" for m in mods), (fn, mods)

@@ -1,0 +1,98 @@
+"""GPU tests of the hand-written adjoint (dL/dX, dL/df, dL/dw) through the C-ABI.
+
+Loss L = 1/2 sum_i |u_i - u*_i|^2 with u* a seeded N(0, 1) field.  The oracle's
+gradient receives dL/du = u_oracle - u* from the oracle's own forward.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import suspension as S
+from tests.gpu_util import rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    import paper_2606_25569_amd as V
+    return V
+
+
+def _grads(V, s, ustar, prec):
+    import torch
+    X = torch.tensor(s.X, device="cuda", requires_grad=True)
+    f = torch.tensor(s.f, device="cuda", requires_grad=True)
+    w = torch.tensor(s.w, device="cuda", requires_grad=True)
+    u = V.farfield_stokeslet(X, X, f, w, s.offsets, s.mu, precision=prec)
+    loss = 0.5 * ((u - torch.tensor(ustar, device="cuda")) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    return X.grad.cpu().numpy(), f.grad.cpu().numpy(), w.grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-11), ("fp32c", 1e-5)])
+def test_small_suspension_full_gradient(V, prec, bar):
+    s = S.make_config(0)
+    ustar = S.target_field(0, s.n_points)
+    u = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    ref = O.grad_suspension(s.X, s.f, s.w, s.offsets, s.mu, u - ustar)
+    gX, gf, gw = _grads(V, s, ustar, prec)
+    for name, a, r in (("X", gX, ref["grad_X"]), ("f", gf, ref["grad_f"]), ("w", gw, ref["grad_w"])):
+        err, _ = rel_err(a, r)
+        say(f"cfg0 grad {name} {prec}: {err:.3e}")
+        assert err <= bar, (name, err)
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-11), ("fp32c", 1e-5)])
+def test_config4_gradient_vs_oracle(V, prec, bar):
+    """512 x 64 at 30%: gradients on 400 sampled points against the oracle's."""
+    s = S.load_config(4)
+    ustar = S.target_field(4, s.n_points)
+    say("cfg4: oracle forward (all 32768 points)")
+    u = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    sel = S.sample_targets(s.n_points, 400 / s.n_points, 4040)
+    ref = O.grad_suspension(s.X, s.f, s.w, s.offsets, s.mu, u - ustar, select=sel)
+    gX, gf, gw = _grads(V, s, ustar, prec)
+    for name, a, r in (("X", gX[:, sel], ref["grad_X"]), ("f", gf[:, sel], ref["grad_f"]), ("w", gw[sel], ref["grad_w"])):
+        err, rms = rel_err(a, r)
+        say(f"cfg4 grad {name} {prec}: max rel err {err:.3e} rms {rms:.3e}")
+        assert err <= bar, (name, err)
+
+
+def test_config4_gradient_vs_central_differences(V):
+    """Central differences (h = 1e-6) of the FP64 GPU loss on 50 seeded position
+    coordinates and 50 force coordinates against the FP64 adjoint.  This checks
+    the adjoint kernels against the forward kernel (the forward itself is held
+    to the oracle by the forward parity tests)."""
+    import torch
+    s = S.load_config(4)
+    ustar_np = S.target_field(4, s.n_points)
+    gX, gf, _ = _grads(V, s, ustar_np, "fp64")
+    X0 = torch.tensor(s.X, device="cuda")
+    f0 = torch.tensor(s.f, device="cuda")
+    w0 = torch.tensor(s.w, device="cuda")
+    ustar = torch.tensor(ustar_np, device="cuda")
+    part = V.Partition(s.offsets)
+
+    def loss(X, f):
+        u = V.farfield_forward(X, X, f, w0, part, s.mu, precision="fp64")
+        return 0.5 * float(((u - ustar) ** 2).sum())
+
+    rng = np.random.default_rng(50)
+    h = 1e-6
+    worst = 0.0
+    for kind in ("X", "f"):
+        for _ in range(50):
+            c, k = int(rng.integers(2)), int(rng.integers(s.n_points))
+            A = (X0 if kind == "X" else f0).clone()
+            A[c, k] += h
+            Lp = loss(A, f0) if kind == "X" else loss(X0, A)
+            A[c, k] -= 2 * h
+            Lm = loss(A, f0) if kind == "X" else loss(X0, A)
+            fd = (Lp - Lm) / (2 * h)
+            an = (gX if kind == "X" else gf)[c, k]
+            rel = abs(fd - an) / max(abs(an), 1e-3 * np.abs(gX if kind == "X" else gf).max())
+            worst = max(worst, rel)
+    say(f"cfg4 FD check worst rel mismatch {worst:.3e}")
+    assert worst <= 1e-5
