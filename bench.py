@@ -35,6 +35,12 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tile", default=None, help="T,B,splits: fixed launch shape instead of the tuned one")
+    ap.add_argument("--cpu-sample", type=float, default=0.03, help="fraction of targets the oracle evaluates")
+    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "adjoint"],
+                    help="dense: the benchmark line; batched / adjoint: the other forms, reported separately")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -43,6 +49,21 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.copy_calibration_mb} MiB three times")
+        return
+
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
 
     import paper_2606_25569_amd as V
     from synth import suspension as S
@@ -64,8 +85,13 @@ def main():
     stream = torch.cuda.current_stream()
     sp = V.farfield._ptr
 
-    cfg = None if args.no_tune else V.load_tuned(P, M, "fp32c")
-    if cfg is None and not args.no_tune:
+    cfg = None
+    if args.tile:
+        T_, B_, sp_ = (int(x) for x in args.tile.split(","))
+        cfg = V.TileConfig(T_, B_, sp_, 1)
+    elif not args.no_tune:
+        cfg = V.load_tuned(P, M, "fp32c")
+    if cfg is None and not args.no_tune and not args.tile:
         t1 = time.time()
         cfg, tms = V.autotune(X, X, f, w, part, s.mu, "fp32c", repeats=2)
         log(f"[bench] autotuned {cfg.as_dict()} ({tms:.3f} ms) in {time.time() - t1:.1f}s")
@@ -131,8 +157,8 @@ def main():
     u64 = out.cpu().numpy()
     log(f"[bench] fp64: {ms64:.3f} ms/step -> {pairs / (ms64 * 1e-3):.4e} pairs/s")
 
-    # accuracy on the seeded 1% target sample, and the CPU baseline on the same sample
-    sel = S.sample_targets(P, 0.01, 101)
+    # accuracy on a seeded target sample, and the CPU baseline on the same sample
+    sel = S.sample_targets(P, args.cpu_sample, 101)
     errs = {}
     cpu = None
     if not args.no_cpu_baseline:
@@ -148,7 +174,7 @@ def main():
             errs[name] = {"max_rel": float(np.abs(d).max() / scale),
                           "rms_rel": float(np.sqrt(np.mean(d * d)) / np.sqrt(np.mean(ref * ref)))}
         cpu = {"value": sample_pairs / tcpu, "unit": "pairs/s", "cores": O.num_threads(), "kind": "oracle",
-               "sample": f"seeded 1% target sample: {sel.size} targets x all {P} sources of the same workload "
+               "sample": f"seeded {100 * args.cpu_sample:g}% target sample: {sel.size} targets x all {P} sources of the same workload "
                          f"({sample_pairs:.3e} pairs, {tcpu:.2f} s wall)"}
         log(f"[bench] errors {errs}; oracle {cpu['value']:.3e} pairs/s on {cpu['cores']} threads")
 
@@ -185,6 +211,103 @@ def main():
         "max_rel_err": errs or None,
         "prepare_us": float(prep_ms.mean() * 1e3),
     }
+    print(json.dumps(rec), flush=True)
+
+
+def _time(fn, reps, stream):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def bench_batched(args):
+    """64 independent suspensions: one persistent launch (eager and as a HIP graph)
+    against one launch pair per suspension (eager and captured in a graph)."""
+    import numpy as np
+    import torch
+
+    import paper_2606_25569_amd as V
+    from synth import suspension as S
+
+    t0 = time.time()
+    b = S.load_config(3)
+    pairs = b.cross_pairs()
+    log(f"[bench] batched: S={b.n_suspensions} P={b.n_points} pairs={pairs:.4e} ({time.time() - t0:.1f}s)")
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    X = torch.tensor(b.X, device=dev)
+    f = torch.tensor(b.f, device=dev)
+    w = torch.tensor(b.w, device=dev)
+    bp = V.BatchedProblem(X, X, f, w, b.vesicle_offsets, b.suspension_offsets, b.mu, precision="fp32c")
+    best, tms = V.autotune(None, None, None, None, None, batched=bp, repeats=2)
+    log(f"[bench] batched autotune: {best.as_dict()} {tms:.3f} ms")
+    bp.config = best
+    t_eager = _time(bp.run, args.steps, stream)
+    bp.capture()
+    t_graph = _time(bp.replay, args.steps, stream)
+    # one prepare+evaluate per suspension, each with its own tuned-by-default shape
+    parts, slices, wss, outs = [], [], [], []
+    base = 0
+    for k, m in enumerate(b.members):
+        sl = slice(base, base + m.n_points)
+        base += m.n_points
+        parts.append(V.Partition(m.offsets, dev))
+        slices.append((X[:, sl].contiguous(), f[:, sl].contiguous(), w[sl].contiguous()))
+        wss.append(torch.empty(V.workspace_bytes(m.n_points, m.n_vesicles, "fp32c"), dtype=torch.uint8, device=dev))
+        outs.append(torch.empty((2, m.n_points), dtype=torch.float64, device=dev))
+
+    def loop():
+        for k in range(len(b.members)):
+            Xs, fs, ws_ = slices[k]
+            V.farfield_forward(Xs, Xs, fs, ws_, parts[k], float(b.mu[k]), "fp32c", out=outs[k], workspace=wss[k])
+
+    t_loop = _time(loop, args.steps, stream)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        loop()
+    t_loop_graph = _time(g.replay, args.steps, stream)
+    rec = {"workload": "batched: 64 independent suspensions, M log-uniform in [10,1500], N in {32,64,128}, "
+                       "area fraction U[0.20,0.35], FP32-compensated",
+           "n_points": b.n_points, "cross_vesicle_pairs": pairs, "tile": best.as_dict(),
+           "ms": {"persistent_eager": t_eager, "persistent_graph": t_graph, "loop_eager": t_loop,
+                  "loop_graph": t_loop_graph},
+           "pairs_per_s": {"persistent_graph": pairs / (t_graph * 1e-3), "loop_graph": pairs / (t_loop_graph * 1e-3)},
+           "tflops_persistent_graph": FLOPS_PER_PAIR * pairs / (t_graph * 1e-3) / 1e12}
+    print(json.dumps(rec), flush=True)
+
+
+def bench_adjoint(args):
+    """512 x 64 suspension: forward and the hand-written backward, FP32-compensated and FP64."""
+    import numpy as np
+    import torch
+
+    import paper_2606_25569_amd as V
+    from synth import suspension as S
+
+    s = S.load_config(4)
+    pairs = s.cross_pairs()
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    X = torch.tensor(s.X, device=dev)
+    f = torch.tensor(s.f, device=dev)
+    w = torch.tensor(s.w, device=dev)
+    g = torch.tensor(S.target_field(4, s.n_points), device=dev)
+    part = V.Partition(s.offsets, dev)
+    rec = {"workload": "adjoint: 512 vesicles x 64 points at 30% area fraction, dL/du = u - u*",
+           "n_points": s.n_points, "cross_vesicle_pairs": pairs}
+    for prec in ("fp32c", "fp64"):
+        tf = _time(lambda: V.farfield_forward(X, X, f, w, part, s.mu, prec), args.steps, stream)
+        tb = _time(lambda: V.farfield_backward(X, X, f, w, part, s.mu, g, prec), args.steps, stream)
+        rec[prec] = {"forward_ms": tf, "backward_ms": tb, "forward_pairs_per_s": pairs / (tf * 1e-3),
+                     "backward_pairs_per_s": pairs / (tb * 1e-3)}
+        log(f"[bench] adjoint {prec}: forward {tf:.3f} ms, backward {tb:.3f} ms")
     print(json.dumps(rec), flush=True)
 
 

@@ -397,9 +397,29 @@ extern "C" int vesnet_graph_destroy(vesnet_graph* graph) {
 
 // ============================================================================ adjoint
 
+namespace {
+
+// Backward launch shape: two targets per thread in float32, one in float64, and
+// enough source chunks to give every SIMD several waves.
+Shape backward_shape(int32_t P, int32_t M, int prec) {
+  Shape s = default_shape(P, M, prec);
+  s.T = prec == P64 ? 1 : 2;
+  s.B = 256;
+  return s;
+}
+
+size_t backward_bytes(int32_t P, int32_t M, int prec) {
+  const Shape s = backward_shape(P, M, prec);
+  size_t b = kAlign + 2 * prepared_bytes(P, M, prec);
+  if (s.splits > 1) b += align_up((size_t)6 * s.splits * P * sizeof(double));
+  return b;
+}
+
+}  // namespace
+
 extern "C" size_t vesnet_backward_workspace_bytes(int32_t P, int32_t M, int prec) {
   if (check_sizes(P, M) || (prec != VESNET_FP64 && prec != VESNET_FP32_COMPENSATED)) return 0;
-  return kAlign + 2 * prepared_bytes(P, M, prec);
+  return backward_bytes(P, M, prec);
 }
 
 extern "C" int vesnet_farfield_stokeslet_backward(const double* targets, const double* sources, const double* f,
@@ -435,14 +455,20 @@ extern "C" int vesnet_farfield_stokeslet_backward(const double* targets, const d
   char* cur = aligned_base(ws);
   PreparedView pvS = carve_prepared(cur, P, M, prec);
   PreparedView pvT = carve_prepared(cur, P, M, prec);
+  const Shape sh = backward_shape(P, M, prec);
+  double* part_t = nullptr;
+  double* part_s = nullptr;
+  if (sh.splits > 1) {
+    part_t = reinterpret_cast<double*>(cur);
+    part_s = part_t + (size_t)2 * sh.splits * P;
+  }
   hipError_t e = hipSuccess;
   if (grad_t) e = launch_prepare(prec, sources, f, w, off, M, P, pvS, stream);
   if (e == hipSuccess && (grad_s || grad_f || grad_w)) e = launch_prepare(prec, targets, gout, nullptr, off, M, P, pvT, stream);
   if (e != hipSuccess) return hip_fail(e, "backward prepare launch");
   const double scale = 1.0 / (4.0 * kPi * mu);
-  const int T = prec == P64 ? 1 : 2;
-  e = launch_backward(prec, T, targets, sources, f, w, gout, P, M, pvS, pvT, scale, grad_t, grad_s, grad_f, grad_w,
-                      stream);
+  e = launch_backward(prec, sh.T, sh.splits, targets, sources, f, w, gout, P, M, pvS, pvT, scale, grad_t, grad_s,
+                      grad_f, grad_w, part_t, part_s, stream);
   if (e != hipSuccess) return hip_fail(e, "backward launch");
   return ok();
 }

@@ -36,9 +36,9 @@ hipError_t launch_plan(const int32_t* sus_off, int S, int M, const PreparedView&
 hipError_t launch_batched(int prec, int T, int B, int grid, const double* tg, int P, int M, const PreparedView& pv,
                           const int32_t* sus_off, const double* mu, int S, const PlanView& pl, double* out,
                           void* stream);
-hipError_t launch_backward(int prec, int T, const double* tg, const double* src, const double* f, const double* w,
-                           const double* gout, int P, int M, const PreparedView& pvS, const PreparedView& pvT,
-                           double scale, double* grad_t, double* grad_s, double* grad_f, double* grad_w,
-                           void* stream);
+hipError_t launch_backward(int prec, int T, int splits, const double* tg, const double* src, const double* f,
+                           const double* w, const double* gout, int P, int M, const PreparedView& pvS,
+                           const PreparedView& pvT, double scale, double* grad_t, double* grad_s, double* grad_f,
+                           double* grad_w, double* part_t, double* part_s, void* stream);
 
 }  // namespace vesnet

@@ -436,62 +436,107 @@ __global__ __launch_bounds__(B) void k_forward_batched(const double* __restrict_
 // ----------------------------------------------------------------------------- adjoint
 
 // Pass over targets: grad_targets_i = c * sum_j grad_r phi(x_i - y_j; g_i, F_j).
+// blockIdx.y selects a chunk of source vesicles; with several chunks the unscaled
+// partial sums go to partial[(2*chunk + comp)*P + i] and a second kernel adds them.
 template <int PREC, int T, int B>
 __global__ __launch_bounds__(B) void k_bwd_targets(const double* __restrict__ tg, const double* __restrict__ gout,
                                                    int P, int M, const int32_t* __restrict__ vid,
                                                    const int2* __restrict__ vrange, const double4* __restrict__ vtab,
                                                    const typename Real<PREC>::R* __restrict__ rec, double scale,
-                                                   double* __restrict__ grad_t) {
+                                                   int splits, double* __restrict__ grad_t,
+                                                   double* __restrict__ partial) {
   const int tile = B * T;
   const int i_begin = blockIdx.x * tile;
   if (i_begin >= P) return;
   const int i_end = min(P, i_begin + tile);
+  const int split = blockIdx.y;
+  const int v_begin = (int)(((int64_t)M * split) / splits);
+  const int v_end = (int)(((int64_t)M * (split + 1)) / splits);
   Acc<PREC> acc[T];
   int idx[T];
   bool valid[T];
-  gather<PREC, T, B, false, true>(i_begin, i_end, 0, M, tg, gout, nullptr, P, vid, vrange, vtab, rec, acc, idx,
-                                  valid);
+  gather<PREC, T, B, false, true>(i_begin, i_end, v_begin, v_end, tg, gout, nullptr, P, vid, vrange, vtab, rec, acc,
+                                  idx, valid);
 #pragma unroll
   for (int k = 0; k < T; ++k) {
     if (!valid[k]) continue;
-    grad_t[idx[k]] = scale * acc[k].gx;
-    grad_t[P + idx[k]] = scale * acc[k].gy;
+    if (splits == 1) {
+      grad_t[idx[k]] = scale * acc[k].gx;
+      grad_t[P + idx[k]] = scale * acc[k].gy;
+    } else {
+      partial[(size_t)(2 * split) * P + idx[k]] = acc[k].gx;
+      partial[(size_t)(2 * split + 1) * P + idx[k]] = acc[k].gy;
+    }
   }
+}
+
+// Epilogue of the pass over sources from the (unscaled) sums g (grad phi) and v (G g).
+__device__ __forceinline__ void finish_source(int j, int P, double gx, double gy, double vx, double vy, double scale,
+                                              const double* __restrict__ f, const double* __restrict__ w,
+                                              double* __restrict__ grad_s, double* __restrict__ grad_f,
+                                              double* __restrict__ grad_w) {
+  if (grad_s) {
+    grad_s[j] = scale * gx;
+    grad_s[P + j] = scale * gy;
+  }
+  const double sx = scale * vx, sy = scale * vy;
+  if (grad_f) {
+    grad_f[j] = w[j] * sx;
+    grad_f[P + j] = w[j] * sy;
+  }
+  if (grad_w) grad_w[j] = f[j] * sx + f[P + j] * sy;
 }
 
 // Pass over sources: with r~ = y_j - x_i (G even, grad phi odd and symmetric in its vectors)
 //   grad_sources_j = c * sum_i grad phi(r~; F_j, g_i),  v_j = c * sum_i G(r~) g_i,
 //   grad_f_j = w_j v_j,  grad_w_j = f_j . v_j.
+// Chunked like the pass over targets, with four partial components (g_x, g_y, v_x, v_y).
 template <int PREC, int T, int B>
 __global__ __launch_bounds__(B) void k_bwd_sources(const double* __restrict__ src, const double* __restrict__ f,
                                                    const double* __restrict__ w, int P, int M,
                                                    const int32_t* __restrict__ vid, const int2* __restrict__ vrange,
                                                    const double4* __restrict__ vtab,
                                                    const typename Real<PREC>::R* __restrict__ rec, double scale,
-                                                   double* __restrict__ grad_s, double* __restrict__ grad_f,
-                                                   double* __restrict__ grad_w) {
+                                                   int splits, double* __restrict__ grad_s,
+                                                   double* __restrict__ grad_f, double* __restrict__ grad_w,
+                                                   double* __restrict__ partial) {
   const int tile = B * T;
   const int i_begin = blockIdx.x * tile;
   if (i_begin >= P) return;
   const int i_end = min(P, i_begin + tile);
+  const int split = blockIdx.y;
+  const int v_begin = (int)(((int64_t)M * split) / splits);
+  const int v_end = (int)(((int64_t)M * (split + 1)) / splits);
   Acc<PREC> acc[T];
   int idx[T];
   bool valid[T];
-  gather<PREC, T, B, true, true>(i_begin, i_end, 0, M, src, f, w, P, vid, vrange, vtab, rec, acc, idx, valid);
+  gather<PREC, T, B, true, true>(i_begin, i_end, v_begin, v_end, src, f, w, P, vid, vrange, vtab, rec, acc, idx,
+                                 valid);
 #pragma unroll
   for (int k = 0; k < T; ++k) {
     if (!valid[k]) continue;
     const int j = idx[k];
-    if (grad_s) {
-      grad_s[j] = scale * acc[k].gx;
-      grad_s[P + j] = scale * acc[k].gy;
+    if (splits == 1) {
+      finish_source(j, P, acc[k].gx, acc[k].gy, acc[k].vx, acc[k].vy, scale, f, w, grad_s, grad_f, grad_w);
+    } else {
+      partial[(size_t)(4 * split) * P + j] = acc[k].gx;
+      partial[(size_t)(4 * split + 1) * P + j] = acc[k].gy;
+      partial[(size_t)(4 * split + 2) * P + j] = acc[k].vx;
+      partial[(size_t)(4 * split + 3) * P + j] = acc[k].vy;
     }
-    const double vx = scale * acc[k].vx, vy = scale * acc[k].vy;
-    if (grad_f) {
-      grad_f[j] = w[j] * vx;
-      grad_f[P + j] = w[j] * vy;
-    }
-    if (grad_w) grad_w[j] = f[j] * vx + f[P + j] * vy;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_sources(const double* __restrict__ partial, int P, int splits,
+                                                        double scale, const double* __restrict__ f,
+                                                        const double* __restrict__ w, double* __restrict__ grad_s,
+                                                        double* __restrict__ grad_f, double* __restrict__ grad_w) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P; j += gridDim.x * blockDim.x) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < splits; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a[c] += partial[(size_t)(4 * k + c) * P + j];
+    finish_source(j, P, a[0], a[1], a[2], a[3], scale, f, w, grad_s, grad_f, grad_w);
   }
 }
 
@@ -607,34 +652,46 @@ hipError_t launch_batched(int prec, int T, int B, int grid, const double* tg, in
 
 template <int PREC, int T, int B>
 static void bwd_one(const double* tg, const double* src, const double* f, const double* w, const double* gout, int P,
-                    int M, const PreparedView& pvS, const PreparedView& pvT, double scale, double* grad_t,
-                    double* grad_s, double* grad_f, double* grad_w, hipStream_t st) {
+                    int M, int splits, const PreparedView& pvS, const PreparedView& pvT, double scale,
+                    double* grad_t, double* grad_s, double* grad_f, double* grad_w, double* part_t, double* part_s,
+                    hipStream_t st) {
   const int tile = B * T;
-  const int grid = (P + tile - 1) / tile;
-  if (grad_t)
-    hipLaunchKernelGGL((k_bwd_targets<PREC, T, B>), dim3(grid), dim3(B), 0, st, tg, gout, P, M, pvS.vid, pvS.vrange,
-                       pvS.vtab, static_cast<const typename Real<PREC>::R*>(pvS.rec), scale, grad_t);
-  if (grad_s || grad_f || grad_w)
-    hipLaunchKernelGGL((k_bwd_sources<PREC, T, B>), dim3(grid), dim3(B), 0, st, src, f, w, P, M, pvT.vid,
-                       pvT.vrange, pvT.vtab, static_cast<const typename Real<PREC>::R*>(pvT.rec), scale, grad_s,
-                       grad_f, grad_w);
+  const dim3 grid((P + tile - 1) / tile, splits);
+  const int rgrid = (P + 255) / 256 < 16384 ? (P + 255) / 256 : 16384;
+  if (grad_t) {
+    hipLaunchKernelGGL((k_bwd_targets<PREC, T, B>), grid, dim3(B), 0, st, tg, gout, P, M, pvS.vid, pvS.vrange,
+                       pvS.vtab, static_cast<const typename Real<PREC>::R*>(pvS.rec), scale, splits, grad_t, part_t);
+    if (splits > 1) {
+      const int g2 = (2 * P + 255) / 256 < 16384 ? (2 * P + 255) / 256 : 16384;
+      hipLaunchKernelGGL(k_reduce_splits, dim3(g2), dim3(256), 0, st, part_t, P, splits, scale, grad_t);
+    }
+  }
+  if (grad_s || grad_f || grad_w) {
+    hipLaunchKernelGGL((k_bwd_sources<PREC, T, B>), grid, dim3(B), 0, st, src, f, w, P, M, pvT.vid, pvT.vrange,
+                       pvT.vtab, static_cast<const typename Real<PREC>::R*>(pvT.rec), scale, splits, grad_s, grad_f,
+                       grad_w, part_s);
+    if (splits > 1)
+      hipLaunchKernelGGL(k_reduce_sources, dim3(rgrid), dim3(256), 0, st, part_s, P, splits, scale, f, w, grad_s,
+                         grad_f, grad_w);
+  }
 }
 
-hipError_t launch_backward(int prec, int T, const double* tg, const double* src, const double* f, const double* w,
-                           const double* gout, int P, int M, const PreparedView& pvS, const PreparedView& pvT,
-                           double scale, double* grad_t, double* grad_s, double* grad_f, double* grad_w,
-                           void* stream) {
+hipError_t launch_backward(int prec, int T, int splits, const double* tg, const double* src, const double* f,
+                           const double* w, const double* gout, int P, int M, const PreparedView& pvS,
+                           const PreparedView& pvT, double scale, double* grad_t, double* grad_s, double* grad_f,
+                           double* grad_w, double* part_t, double* part_s, void* stream) {
   if (P == 0) return hipSuccess;
   hipStream_t st = S_(stream);
+#define VESNET_BWD(PR, TT) \
+  bwd_one<PR, TT, 256>(tg, src, f, w, gout, P, M, splits, pvS, pvT, scale, grad_t, grad_s, grad_f, grad_w, part_t, part_s, st)
   if (prec == P64) {
-    if (T == 1) bwd_one<P64, 1, 256>(tg, src, f, w, gout, P, M, pvS, pvT, scale, grad_t, grad_s, grad_f, grad_w, st);
-    else bwd_one<P64, 2, 256>(tg, src, f, w, gout, P, M, pvS, pvT, scale, grad_t, grad_s, grad_f, grad_w, st);
+    if (T == 1) VESNET_BWD(P64, 1); else VESNET_BWD(P64, 2);
   } else if (prec == P32C) {
-    if (T == 1) bwd_one<P32C, 1, 256>(tg, src, f, w, gout, P, M, pvS, pvT, scale, grad_t, grad_s, grad_f, grad_w, st);
-    else bwd_one<P32C, 2, 256>(tg, src, f, w, gout, P, M, pvS, pvT, scale, grad_t, grad_s, grad_f, grad_w, st);
+    if (T == 1) VESNET_BWD(P32C, 1); else VESNET_BWD(P32C, 2);
   } else {
     return hipErrorInvalidValue;
   }
+#undef VESNET_BWD
   return hipGetLastError();
 }
 
