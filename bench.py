@@ -35,7 +35,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--tile", default=None, help="T,B,splits: fixed launch shape instead of the tuned one")
+    ap.add_argument("--tile", default=None,
+                    help="T,B,splits[,staging]: fixed launch shape instead of the tuned one (staging 1 = SGPR, 2 = LDS)")
     ap.add_argument("--cpu-sample", type=float, default=0.03, help="fraction of targets the oracle evaluates")
     ap.add_argument("--workload", default="dense", choices=["dense", "batched", "adjoint"],
                     help="dense: the benchmark line; batched / adjoint: the other forms, reported separately")
@@ -87,8 +88,8 @@ def main():
 
     cfg = None
     if args.tile:
-        T_, B_, sp_ = (int(x) for x in args.tile.split(","))
-        cfg = V.TileConfig(T_, B_, sp_, 1)
+        vals = [int(x) for x in args.tile.split(",")]
+        cfg = V.TileConfig(vals[0], vals[1], vals[2], 1, vals[3] if len(vals) > 3 else 0)
     elif not args.no_tune:
         cfg = V.load_tuned(P, M, "fp32c")
     if cfg is None and not args.no_tune and not args.tile:

@@ -78,6 +78,9 @@ typedef struct {
   int32_t source_splits;      /* >= 1: source vesicles split into this many chunks, reduced in
                                  a fixed order by a second kernel (bitwise deterministic)      */
   int32_t blocks_per_cu;      /* batched persistent grid: workgroups per compute unit (1..16) */
+  int32_t source_staging;     /* 1: source records read at wave-uniform addresses into SGPRs;
+                                 2: records staged through LDS tiles of 1024 and read back with
+                                    broadcast LDS loads into VGPRs                               */
 } vesnet_tile_config;
 
 /* Library version string and the thread-local description of the last error. */
@@ -127,6 +130,32 @@ VESNET_API int vesnet_farfield_stokeslet(const double* targets, const double* so
                               int32_t n_points, double mu, double* out, int precision,
                               const vesnet_tile_config* cfg, void* workspace, size_t workspace_bytes,
                               void* stream);
+
+/* ------------------------------------------------------------------ near field */
+
+/* The far field as the paper's direct evaluation masks it (Section 4.1) and the
+   near-field detection FindNearFieldPoints of Algorithm 4: vesicle v is in the
+   near field of target i when the distance from the target to v's points,
+   min_j |targets_i - sources_j|, is at most the arclength spacing of v (the
+   near-field rule of Section 2.2), taken as h_v = sum_j w_j / N_v.  Near
+   vesicles are dropped from out like the own vesicle, and every near pair
+   (target index, vesicle index) is stored into near_pairs[2k], near_pairs[2k+1]
+   in unspecified order.  *near_count (device int32) is overwritten with the
+   number of near pairs found; when it exceeds near_capacity only the first
+   near_capacity pairs were stored and the call should be repeated with a larger
+   list.  The distance test runs in the precision of the pair loop (float32 on
+   the rescaled coordinates for the compensated form), so a pair whose distance
+   lies within about 1e-7 relative of h_v may be classified either way.
+     near_pairs : device int32 [near_capacity][2] (may be NULL if capacity is 0)
+     near_count : device int32 [1]
+   Other arguments as vesnet_farfield_stokeslet; targets_per_thread is capped at 2. */
+VESNET_API int vesnet_farfield_stokeslet_nearmasked(const double* targets, const double* sources,
+                                                    const double* force_density, const double* arc_weights,
+                                                    const int32_t* vesicle_offsets, int32_t n_vesicles,
+                                                    int32_t n_points, double mu, double* out, int32_t* near_pairs,
+                                                    int32_t near_capacity, int32_t* near_count, int precision,
+                                                    const vesnet_tile_config* cfg, void* workspace,
+                                                    size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------ batched */
 

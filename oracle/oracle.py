@@ -47,6 +47,8 @@ def _load():
         lib.vo_grad_targets_at.restype = ctypes.c_int
         lib.vo_grad_sources_at.argtypes = [I, P, I, P, P, P, P, P, P, P, P, P, D, P, P, P, P, P, P, P, P, P]
         lib.vo_grad_sources_at.restype = ctypes.c_int
+        lib.vo_farfield_nearmasked_at.argtypes = [I, P, P, P, P, I, P, P, P, ctypes.c_int32, P, P, P, D, P, P, P, I]
+        lib.vo_farfield_nearmasked_at.restype = ctypes.c_long
         _lib = lib
     return _lib
 
@@ -98,6 +100,39 @@ def farfield_suspension(X, f, w, offsets, mu, select=None, targets=None):
     vid = vesicle_ids(offsets)
     T = X if targets is None else targets
     return farfield(T, X, f, w, mu, vid, vid, select)
+
+
+def farfield_nearmasked(targets, sources, f, w, mu, target_excl, source_ves, n_ves, select=None):
+    """Near-field masked far field at targets[:, select] and the near pairs.
+
+    Returns (u (2, n_sel), pairs (n_pairs, 2) int64 of (selected position, vesicle id))."""
+    lib = _load()
+    tx, ty = _c(targets[0], np.float64), _c(targets[1], np.float64)
+    sx, sy = _c(sources[0], np.float64), _c(sources[1], np.float64)
+    fx, fy = _c(f[0], np.float64), _c(f[1], np.float64)
+    w = _c(w, np.float64)
+    te, sv = _c(target_excl, np.int32), _c(source_ves, np.int32)
+    sel = _c(np.arange(tx.shape[0]) if select is None else select, np.int64)
+    ux, uy = np.empty(sel.shape[0]), np.empty(sel.shape[0])
+    cap = 16 * sel.shape[0] + 16
+    while True:
+        pairs = np.empty((cap, 2), dtype=np.int64)
+        n = lib.vo_farfield_nearmasked_at(sel.shape[0], _ptr(sel), _ptr(tx), _ptr(ty), _ptr(te), sx.shape[0], _ptr(sx),
+                                          _ptr(sy), _ptr(sv), int(n_ves), _ptr(fx), _ptr(fy), _ptr(w), float(mu),
+                                          _ptr(ux), _ptr(uy), _ptr(pairs), cap)
+        if n == -2:
+            raise ValueError("oracle: coincident points in different vesicles (r = 0)")
+        if n < 0:
+            raise ValueError(f"oracle: near-masked sum failed ({n})")
+        if n <= cap:
+            return np.stack([ux, uy]), pairs[:n].copy()
+        cap = int(n)
+
+
+def nearmasked_suspension(X, f, w, offsets, mu, select=None, targets=None):
+    vid = vesicle_ids(offsets)
+    T = X if targets is None else targets
+    return farfield_nearmasked(T, X, f, w, mu, vid, vid, len(offsets) - 1, select)
 
 
 def grad_targets(targets, sources, f, w, mu, target_excl, source_ves, g, select=None):

@@ -159,3 +159,81 @@ int vo_grad_sources_at(int64_t n_sel, const int64_t* sel,
     }
     return bad ? -2 : 0;
 }
+
+/*
+ * Near-field masked far field (the masks of Section 4.1; FindNearFieldPoints of
+ * Algorithm 4; near-field rule of Section 2.2).  Vesicle v is in the near field
+ * of target i when min_{j in v} |x_i - y_j| <= h_v, with h_v = sum_{j in v} w_j / N_v
+ * the mean arclength spacing of v.  Such vesicles are dropped like the own one.
+ * Source vesicle ids must lie in [0, n_ves).  Near pairs (selected-target position
+ * k, vesicle v) are written to pairs[2*c], pairs[2*c+1] for c < capacity in target
+ * order, then vesicle order; the return value is the number of near pairs, or -2
+ * for a coincident included pair, -3 for a bad vesicle id, -4 if memory ran out.
+ */
+#include <stdlib.h>
+
+long vo_farfield_nearmasked_at(int64_t n_sel, const int64_t* sel,
+                               const double* tx, const double* ty, const int32_t* t_excl,
+                               int64_t n_src, const double* sx, const double* sy, const int32_t* s_ves,
+                               int32_t n_ves, const double* fx, const double* fy, const double* w, double mu,
+                               double* ux, double* uy, int64_t* pairs, int64_t capacity)
+{
+    const double c = 1.0 / (4.0 * VO_PI * mu);
+    for (int64_t j = 0; j < n_src; ++j)
+        if (s_ves[j] < 0 || s_ves[j] >= n_ves) return -3;
+    double* h = (double*)calloc((size_t)n_ves + 1, sizeof(double));
+    int64_t* cnt = (int64_t*)calloc((size_t)n_ves + 1, sizeof(int64_t));
+    char* near = (char*)calloc((size_t)n_sel * (size_t)n_ves + 1, 1);
+    if (!h || !cnt || !near) { free(h); free(cnt); free(near); return -4; }
+    for (int64_t j = 0; j < n_src; ++j) { h[s_ves[j]] += w[j]; cnt[s_ves[j]] += 1; }
+    for (int32_t v = 0; v < n_ves; ++v) h[v] = cnt[v] > 0 ? h[v] / (double)cnt[v] : 0.0;
+    int bad = 0, oom = 0;
+#pragma omp parallel reduction(|:bad) reduction(|:oom)
+    {
+        long double* ax = (long double*)malloc(((size_t)n_ves + 1) * sizeof(long double));
+        long double* ay = (long double*)malloc(((size_t)n_ves + 1) * sizeof(long double));
+        double* dmin = (double*)malloc(((size_t)n_ves + 1) * sizeof(double));
+        if (!ax || !ay || !dmin) {
+            oom = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4)
+            for (int64_t k = 0; k < n_sel; ++k) {
+                const int64_t i = sel[k];
+                for (int32_t v = 0; v < n_ves; ++v) { ax[v] = 0.0L; ay[v] = 0.0L; dmin[v] = INFINITY; }
+                for (int64_t j = 0; j < n_src; ++j) {
+                    const int32_t v = s_ves[j];
+                    if (v == t_excl[i]) continue;
+                    const double rx = tx[i] - sx[j];
+                    const double ry = ty[i] - sy[j];
+                    const double r2 = rx * rx + ry * ry;
+                    if (r2 < dmin[v]) dmin[v] = r2;
+                    if (r2 == 0.0) { bad = 1; continue; }
+                    const double lnr = 0.5 * log(r2);
+                    const double rdotf = rx * fx[j] + ry * fy[j];
+                    ax[v] += (long double)(w[j] * (-lnr * fx[j] + rdotf * rx / r2));
+                    ay[v] += (long double)(w[j] * (-lnr * fy[j] + rdotf * ry / r2));
+                }
+                long double sxv = 0.0L, syv = 0.0L;
+                for (int32_t v = 0; v < n_ves; ++v) {
+                    if (v == t_excl[i] || cnt[v] == 0) continue;
+                    if (dmin[v] <= h[v] * h[v]) { near[k * (int64_t)n_ves + v] = 1; continue; }
+                    sxv += ax[v];
+                    syv += ay[v];
+                }
+                ux[k] = (double)(c * sxv);
+                uy[k] = (double)(c * syv);
+            }
+        }
+        free(ax); free(ay); free(dmin);
+    }
+    long found = 0;
+    for (int64_t k = 0; k < n_sel; ++k)
+        for (int32_t v = 0; v < n_ves; ++v)
+            if (near[k * (int64_t)n_ves + v]) {
+                if (found < capacity) { pairs[2 * found] = k; pairs[2 * found + 1] = v; }
+                ++found;
+            }
+    free(h); free(cnt); free(near);
+    if (oom) return -4;
+    return bad ? -2 : found;
+}

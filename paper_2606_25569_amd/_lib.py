@@ -24,6 +24,7 @@ EXPORTED = (
     "vesnet_farfield_stokeslet", "vesnet_batched_workspace_bytes", "vesnet_farfield_stokeslet_batched",
     "vesnet_graph_create_batched", "vesnet_graph_launch", "vesnet_graph_destroy",
     "vesnet_backward_workspace_bytes", "vesnet_farfield_stokeslet_backward", "vesnet_autotune",
+    "vesnet_farfield_stokeslet_nearmasked",
 )
 
 
@@ -35,7 +36,8 @@ class VesnetError(RuntimeError):
 
 class TileConfig(ctypes.Structure):
     _fields_ = [("targets_per_thread", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("source_splits", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
+                ("source_splits", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("source_staging", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -43,7 +45,7 @@ class TileConfig(ctypes.Structure):
     @classmethod
     def from_dict(cls, d):
         return cls(int(d.get("targets_per_thread", 0)), int(d.get("block_threads", 0)),
-                   int(d.get("source_splits", 0)), int(d.get("blocks_per_cu", 0)))
+                   int(d.get("source_splits", 0)), int(d.get("blocks_per_cu", 0)), int(d.get("source_staging", 0)))
 
 
 _lib = None
@@ -76,6 +78,7 @@ def lib():
         "vesnet_graph_destroy": ([P], INT),
         "vesnet_backward_workspace_bytes": ([I32, I32, INT], SZ),
         "vesnet_farfield_stokeslet_backward": ([P, P, P, P, P, I32, I32, D, P, P, P, P, P, INT, P, SZ, P], INT),
+        "vesnet_farfield_stokeslet_nearmasked": ([P, P, P, P, P, I32, I32, D, P, P, I32, P, INT, CFG, P, SZ, P], INT),
         "vesnet_autotune": ([P, P, P, P, P, I32, I32, INT, P, I32, P, D, P, INT, INT, P, SZ, P, CFG,
                              ctypes.POINTER(ctypes.c_float)], INT),
     }

@@ -46,7 +46,8 @@ size_t rec_bytes(int prec) { return prec == P64 ? sizeof(double4) : sizeof(float
 
 size_t prepared_bytes(int32_t P, int32_t M, int prec) {
   return align_up((size_t)M * sizeof(int2)) + align_up((size_t)P * sizeof(int32_t)) +
-         align_up((size_t)M * sizeof(double4)) + align_up((size_t)P * rec_bytes(prec));
+         align_up((size_t)M * sizeof(double4)) + align_up((size_t)M * sizeof(double)) +
+         align_up((size_t)P * rec_bytes(prec));
 }
 
 // Carves the prepared region starting at *cursor (already aligned).
@@ -58,6 +59,8 @@ PreparedView carve_prepared(char*& cursor, int32_t P, int32_t M, int prec) {
   cursor += align_up((size_t)P * sizeof(int32_t));
   pv.vtab = reinterpret_cast<double4*>(cursor);
   cursor += align_up((size_t)M * sizeof(double4));
+  pv.hlen = reinterpret_cast<double*>(cursor);
+  cursor += align_up((size_t)M * sizeof(double));
   pv.rec = cursor;
   cursor += align_up((size_t)P * rec_bytes(prec));
   return pv;
@@ -71,7 +74,7 @@ char* aligned_base(void* ws) {
 bool valid_precision(int prec) { return prec == VESNET_FP64 || prec == VESNET_FP32_COMPENSATED || prec == VESNET_FP32_NAIVE; }
 
 struct Shape {
-  int T, B, splits, bpc;
+  int T, B, splits, bpc, staging;
 };
 
 Shape default_shape(int32_t P, int32_t M, int prec) {
@@ -79,6 +82,7 @@ Shape default_shape(int32_t P, int32_t M, int prec) {
   s.T = prec == P64 ? 1 : 2;
   s.B = 256;
   s.bpc = 2;
+  s.staging = 2;
   const int64_t waves = ((int64_t)P + 64 * s.T - 1) / (64 * s.T);
   const int64_t want = 8192;  // about 8 waves per SIMD on 256 CUs x 4 SIMDs
   int splits = 1;
@@ -94,6 +98,7 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     if (cfg->block_threads) s.B = cfg->block_threads;
     if (cfg->source_splits) s.splits = cfg->source_splits;
     if (cfg->blocks_per_cu) s.bpc = cfg->blocks_per_cu;
+    if (cfg->source_staging) s.staging = cfg->source_staging;
   }
   if (s.T != 1 && s.T != 2 && s.T != 4)
     return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread must be 1, 2 or 4 (got %d)", s.T);
@@ -103,6 +108,8 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     return fail(VESNET_ERR_INVALID_ARGUMENT, "source_splits must be in [1, %d] (got %d)", kMaxSplits, s.splits);
   if (s.bpc < 1 || s.bpc > 16)
     return fail(VESNET_ERR_INVALID_ARGUMENT, "blocks_per_cu must be in [1, 16] (got %d)", s.bpc);
+  if (s.staging != 1 && s.staging != 2)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "source_staging must be 1 or 2 (got %d)", s.staging);
   *out = s;
   return VESNET_OK;
 }
@@ -190,6 +197,7 @@ extern "C" int vesnet_default_tile_config(int32_t P, int32_t M, int prec, vesnet
   cfg->block_threads = s.B;
   cfg->source_splits = s.splits;
   cfg->blocks_per_cu = s.bpc;
+  cfg->source_staging = s.staging;
   return ok();
 }
 
@@ -231,7 +239,8 @@ extern "C" int vesnet_farfield_evaluate(const double* targets, const int32_t* of
   PreparedView pv = carve_prepared(cur, P, M, prec);
   double* partial = s.splits > 1 ? reinterpret_cast<double*>(cur) : nullptr;
   const double scale = 1.0 / (4.0 * kPi * mu);
-  hipError_t e = launch_forward(prec, s.T, s.B, s.splits, targets, P, M, pv, scale, out, partial, stream);
+  hipError_t e = launch_forward(prec, s.T, s.B, s.staging == 2, s.splits, targets, P, M, pv, scale, out, partial,
+                                stream);
   if (e != hipSuccess) return hip_fail(e, "forward launch");
   return ok();
 }
@@ -250,6 +259,48 @@ extern "C" int vesnet_farfield_stokeslet(const double* targets, const double* so
   if ((rc = check_workspace(ws, ws_bytes, forward_bytes(P, M, prec, s)))) return rc;
   if ((rc = vesnet_farfield_prepare(sources, f, w, off, M, P, prec, ws, ws_bytes, stream))) return rc;
   return vesnet_farfield_evaluate(targets, off, M, P, mu, out, prec, cfg, ws, ws_bytes, stream);
+}
+
+// ============================================================================ near-field masked
+
+extern "C" int vesnet_farfield_stokeslet_nearmasked(const double* targets, const double* sources, const double* f,
+                                                    const double* w, const int32_t* off, int32_t M, int32_t P,
+                                                    double mu, double* out, int32_t* near_pairs,
+                                                    int32_t near_capacity, int32_t* near_count, int prec,
+                                                    const vesnet_tile_config* cfg, void* ws, size_t ws_bytes,
+                                                    void* stream) {
+  int rc = check_forward_args(targets, sources, f, w, off, M, P, out, prec, ws, ws_bytes, true, true);
+  if (rc) return rc;
+  if ((rc = check_mu(mu))) return rc;
+  if (!near_count) return fail(VESNET_ERR_INVALID_ARGUMENT, "near_count is NULL");
+  if (near_capacity < 0) return fail(VESNET_ERR_INVALID_ARGUMENT, "near_capacity = %d < 0", near_capacity);
+  if (near_capacity > 0 && !near_pairs)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "near_pairs is NULL but near_capacity = %d", near_capacity);
+  if (P > 0 && !out) return fail(VESNET_ERR_INVALID_ARGUMENT, "out is NULL");
+  const size_t vb = (size_t)2 * P * sizeof(double);
+  const size_t pb = (size_t)2 * near_capacity * sizeof(int32_t);
+  if (overlaps(near_pairs, pb, out, vb) || overlaps(near_pairs, pb, ws, ws_bytes) ||
+      overlaps(near_count, sizeof(int32_t), out, vb) || overlaps(near_count, sizeof(int32_t), ws, ws_bytes) ||
+      overlaps(near_count, sizeof(int32_t), near_pairs, pb) || overlaps(near_pairs, pb, targets, vb) ||
+      overlaps(near_pairs, pb, sources, vb) || overlaps(near_pairs, pb, f, vb))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "near-field outputs overlap other arrays");
+  Shape s;
+  if ((rc = resolve_shape(cfg, P, M, prec, &s))) return rc;
+  if (s.T > 2) s.T = 2;
+  if (P > 0 && (rc = check_workspace(ws, ws_bytes, forward_bytes(P, M, prec, s)))) return rc;
+  PreparedView pv{};
+  double* partial = nullptr;
+  if (P > 0) {
+    if ((rc = vesnet_farfield_prepare(sources, f, w, off, M, P, prec, ws, ws_bytes, stream))) return rc;
+    char* cur = aligned_base(ws);
+    pv = carve_prepared(cur, P, M, prec);
+    partial = s.splits > 1 ? reinterpret_cast<double*>(cur) : nullptr;
+  }
+  const double scale = 1.0 / (4.0 * kPi * mu);
+  hipError_t e = launch_forward_near(prec, s.T, s.staging == 2, s.splits, targets, P, M, pv, scale, out, partial,
+                                     near_count, near_pairs, near_capacity, stream);
+  if (e != hipSuccess) return hip_fail(e, "near-masked forward launch");
+  return ok();
 }
 
 // ============================================================================ batched
@@ -302,7 +353,7 @@ int enqueue_batched(const double* targets, const double* sources, const double* 
   e = launch_plan(sus_off, S, M, pv, s.T * s.B, pl, stream);
   if (e != hipSuccess) return hip_fail(e, "plan launch");
   const int grid = num_cus() * s.bpc;
-  e = launch_batched(prec, s.T, s.B, grid, targets, P, M, pv, sus_off, mu, S, pl, out, stream);
+  e = launch_batched(prec, s.T, s.B, s.staging == 2, grid, targets, P, M, pv, sus_off, mu, S, pl, out, stream);
   if (e != hipSuccess) return hip_fail(e, "batched launch");
   return VESNET_OK;
 }
@@ -491,19 +542,20 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
 
   std::vector<vesnet_tile_config> cands;
-  for (int T : {1, 2, 4})
-    for (int B : {64, 128, 256}) {
-      if (batched) {
-        for (int bpc : {1, 2, 4, 8}) cands.push_back({T, B, 1, bpc});
-      } else {
-        for (int sp : {1, 2, 4, 8, 16}) {
-          if (sp > std::max(1, M)) continue;
-          const Shape sh{T, B, sp, 1};
-          if (forward_bytes(P, M, prec, sh) > ws_bytes) continue;
-          cands.push_back({T, B, sp, 1});
+  for (int stg : {1, 2})
+    for (int T : {1, 2, 4})
+      for (int B : {64, 128, 256}) {
+        if (batched) {
+          for (int bpc : {1, 2, 4, 8}) cands.push_back({T, B, 1, bpc, stg});
+        } else {
+          for (int sp : {1, 2, 4, 8, 16}) {
+            if (sp > std::max(1, M)) continue;
+            const Shape sh{T, B, sp, 1, stg};
+            if (forward_bytes(P, M, prec, sh) > ws_bytes) continue;
+            cands.push_back({T, B, sp, 1, stg});
+          }
         }
       }
-    }
   if (batched && (rc = check_workspace(ws, ws_bytes, vesnet_batched_workspace_bytes(P, M, S, prec)))) return rc;
   if (cands.empty()) return fail(VESNET_ERR_WORKSPACE, "workspace too small for any launch shape");
 

@@ -15,6 +15,7 @@ struct PreparedView {
   int2* vrange;    // [M]   clamped point range (j0, j1) of each vesicle
   int32_t* vid;    // [P]   vesicle id of each point
   double4* vtab;   // [M]   (c_x, c_y, B_x, B_y): reference point and net weighted vector
+  double* hlen;    // [M]   mean arclength spacing sum_j w_j / N_v
   void* rec;       // [P]   streamed records: float4 (P32C, P32N) or double4 (P64)
 };
 
@@ -29,13 +30,16 @@ struct PlanView {
 
 hipError_t launch_prepare(int prec, const double* pts, const double* vec, const double* wts, const int32_t* off,
                           int M, int P, const PreparedView& pv, void* stream);
-hipError_t launch_forward(int prec, int T, int B, int splits, const double* tg, int P, int M, const PreparedView& pv,
-                          double scale, double* out, double* partial, void* stream);
+hipError_t launch_forward(int prec, int T, int B, bool lds, int splits, const double* tg, int P, int M,
+                          const PreparedView& pv, double scale, double* out, double* partial, void* stream);
+hipError_t launch_forward_near(int prec, int T, bool lds, int splits, const double* tg, int P, int M,
+                               const PreparedView& pv, double scale, double* out, double* partial, int32_t* count,
+                               int32_t* pairs, int32_t capacity, void* stream);
 hipError_t launch_plan(const int32_t* sus_off, int S, int M, const PreparedView& pv, int tile, const PlanView& pl,
                        void* stream);
-hipError_t launch_batched(int prec, int T, int B, int grid, const double* tg, int P, int M, const PreparedView& pv,
-                          const int32_t* sus_off, const double* mu, int S, const PlanView& pl, double* out,
-                          void* stream);
+hipError_t launch_batched(int prec, int T, int B, bool lds, int grid, const double* tg, int P, int M,
+                          const PreparedView& pv, const int32_t* sus_off, const double* mu, int S, const PlanView& pl,
+                          double* out, void* stream);
 hipError_t launch_backward(int prec, int T, int splits, const double* tg, const double* src, const double* f,
                            const double* w, const double* gout, int P, int M, const PreparedView& pvS,
                            const PreparedView& pvT, double scale, double* grad_t, double* grad_s, double* grad_f,

@@ -28,6 +28,7 @@ namespace {
 
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr float kHalfLn2 = -0.34657359027997265471f;  // -(1/2) ln 2 : converts log2(q) to -ln|r|
+constexpr int kTile = 1024;                             // records per LDS tile
 
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
@@ -48,29 +49,33 @@ template <int PREC>
 __global__ __launch_bounds__(64) void k_prepare(const double* __restrict__ pts, const double* __restrict__ vec,
                                                 const double* __restrict__ wts, const int32_t* __restrict__ off_in,
                                                 int M, int P, int2* __restrict__ vrange, int32_t* __restrict__ vid,
-                                                double4* __restrict__ vtab, void* __restrict__ rec) {
+                                                double4* __restrict__ vtab, double* __restrict__ hlen,
+                                                void* __restrict__ rec) {
   const int lane = threadIdx.x;
   for (int v = blockIdx.x; v < M; v += gridDim.x) {
     const int j0 = clampi(off_in[v], 0, P);
     const int j1 = max(j0, clampi(off_in[v + 1], 0, P));
-    double sx = 0.0, sy = 0.0, bx = 0.0, by = 0.0;
+    double sx = 0.0, sy = 0.0, bx = 0.0, by = 0.0, sw = 0.0;
     for (int j = j0 + lane; j < j1; j += 64) {
       const double wj = wts ? wts[j] : 1.0;
       sx += pts[j];
       sy += pts[P + j];
       bx += wj * vec[j];
       by += wj * vec[P + j];
+      sw += wj;
     }
     sx = wave_sum(sx);
     sy = wave_sum(sy);
     bx = wave_sum(bx);
     by = wave_sum(by);
+    sw = wave_sum(sw);
     const int n = j1 - j0;
     const double cx = n > 0 ? sx / n : 0.0;
     const double cy = n > 0 ? sy / n : 0.0;
     if (lane == 0) {
       vrange[v] = make_int2(j0, j1);
       vtab[v] = make_double4(cx, cy, bx, by);
+      hlen[v] = n > 0 ? sw / n : 0.0;
     }
     for (int j = j0 + lane; j < j1; j += 64) {
       const double wj = wts ? wts[j] : 1.0;
@@ -93,6 +98,18 @@ template <> struct Real<P64> { using T = double; using R = double4; };
 template <> struct Real<P32C> { using T = float; using R = float4; };
 template <> struct Real<P32N> { using T = float; using R = float4; };
 
+// Near-field masking (FindNearFieldPoints of Algorithm 4; near-field rule of Section 2.2):
+// vesicle v is near target i when min_j |x_i - y_j| <= h_v, the mean arclength spacing
+// sum_j w_j / N_v of v.  Near vesicles are dropped from the sum and the pair (i, v) is
+// appended to a list through an atomic counter (order unspecified; entries past the
+// capacity are counted but not stored).
+struct NearOut {
+  const double* hlen;    // [M] h_v
+  int32_t* count;        // [1] pairs found (zeroed before the launch)
+  int32_t* pairs;        // [capacity][2] (target, vesicle)
+  int32_t capacity;
+};
+
 // Accumulated results of one thread point.
 template <int PREC>
 struct Acc {
@@ -107,13 +124,18 @@ struct Acc {
 //   NEED_V    : acc.v += sum_j G(r) b_j               (r = p_i - q_j)
 //   NEED_GRAD : acc.g += sum_j grad_r [a_i^T G(r) b_j]
 // Both without the 1/(4 pi mu) factor.
-template <int PREC, int T, int B, bool NEED_V, bool NEED_GRAD>
+// LDS = false: records are read at wave-uniform addresses (scalar loads into SGPRs).
+// LDS = true : the workgroup stages up to kTile consecutive records in LDS and every lane
+//              reads them back with broadcast LDS loads into VGPRs.  The tile window only
+//              moves forward through uniform control flow, so its barriers are block-wide.
+// NEAR = true: also track min_j |r|^2 per (thread point, vesicle) and apply NearOut.
+template <int PREC, int T, int B, bool NEED_V, bool NEED_GRAD, bool LDS, bool NEAR = false>
 __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int v_end, const double* __restrict__ pts,
                                        const double* __restrict__ avec, const double* __restrict__ awts, int P,
                                        const int32_t* __restrict__ vid, const int2* __restrict__ vrange,
                                        const double4* __restrict__ vtab,
                                        const typename Real<PREC>::R* __restrict__ rec, Acc<PREC> (&acc)[T],
-                                       int (&idx)[T], bool (&valid)[T]) {
+                                       int (&idx)[T], bool (&valid)[T], NearOut near = NearOut{}) {
   using real = typename Real<PREC>::T;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -146,12 +168,18 @@ __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int 
     for (int k = 0; k < T; ++k) { pxf[k] = (float)px[k]; pyf[k] = (float)py[k]; }
   }
 
+  using Rec = typename Real<PREC>::R;
+  __shared__ Rec tile[LDS ? kTile : 1];
+  int tile_lo = 0, tile_hi = 0;
+
   for (int v = v_begin; v < v_end; ++v) {
-    // Skip a vesicle that is the own vesicle of every live point of this wave.
-    bool all_own = true;
+    if constexpr (!LDS) {
+      // Skip a vesicle that is the own vesicle of every live point of this wave.
+      bool all_own = true;
 #pragma unroll
-    for (int k = 0; k < T; ++k) all_own = all_own && (!valid[k] || myv[k] == v);
-    if (__all(all_own)) continue;
+      for (int k = 0; k < T; ++k) all_own = all_own && (!valid[k] || myv[k] == v);
+      if (__all(all_own)) continue;
+    }
 
     const int2 jr = vrange[v];
     const double4 vt = vtab[v];
@@ -183,9 +211,12 @@ __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int 
       }
     }
 
-    real lx[T], ly[T], rvx[T], rvy[T], s1[T], gx[T], gy[T], hx[T], hy[T];
+    real lx[T], ly[T], rvx[T], rvy[T], s1[T], gx[T], gy[T], hx[T], hy[T], qmin[T];
 #pragma unroll
-    for (int k = 0; k < T; ++k) lx[k] = ly[k] = rvx[k] = rvy[k] = s1[k] = gx[k] = gy[k] = hx[k] = hy[k] = (real)0;
+    for (int k = 0; k < T; ++k) {
+      lx[k] = ly[k] = rvx[k] = rvy[k] = s1[k] = gx[k] = gy[k] = hx[k] = hy[k] = (real)0;
+      qmin[k] = (real)3.0e38f;
+    }
 
     auto pair = [&](const typename Real<PREC>::R& s) __attribute__((always_inline)) {
 #pragma unroll
@@ -202,6 +233,7 @@ __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int 
           ry = fmaf(s.y, ns[k], dy[k]);
         }
         const real q = ry * ry + rx * rx;
+        if constexpr (NEAR) qmin[k] = q < qmin[k] ? q : qmin[k];
         real rho;
         if constexpr (PREC == P64) rho = 1.0 / q;
         else rho = __builtin_amdgcn_rcpf(q);
@@ -231,20 +263,67 @@ __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int 
       }
     };
 
-    int j = jr.x;
-    for (; j + 4 <= jr.y; j += 4) {
-      const typename Real<PREC>::R s0 = rec[j], sA = rec[j + 1], sB = rec[j + 2], sC = rec[j + 3];
-      pair(s0);
-      pair(sA);
-      pair(sB);
-      pair(sC);
+    if constexpr (LDS) {
+      int j = jr.x;
+      while (j < jr.y) {
+        if (j < tile_lo || j >= tile_hi) {
+          tile_lo = j;
+          tile_hi = min(j + kTile, P);
+          __syncthreads();
+          for (int e = threadIdx.x; e < tile_hi - tile_lo; e += B) tile[e] = rec[tile_lo + e];
+          __syncthreads();
+        }
+        const int je = min(jr.y, tile_hi) - tile_lo;
+        int jj = j - tile_lo;
+        for (; jj + 4 <= je; jj += 4) {
+          const Rec s0 = tile[jj], sA = tile[jj + 1], sB = tile[jj + 2], sC = tile[jj + 3];
+          pair(s0);
+          pair(sA);
+          pair(sB);
+          pair(sC);
+        }
+        for (; jj < je; ++jj) pair(tile[jj]);
+        j = je + tile_lo;
+      }
+    } else {
+      int j = jr.x;
+      for (; j + 4 <= jr.y; j += 4) {
+        const Rec s0 = rec[j], sA = rec[j + 1], sB = rec[j + 2], sC = rec[j + 3];
+        pair(s0);
+        pair(sA);
+        pair(sB);
+        pair(sC);
+      }
+      for (; j < jr.y; ++j) pair(rec[j]);
     }
-    for (; j < jr.y; ++j) pair(rec[j]);
 
     // Flush the per-vesicle partials (own vesicle dropped by a select).
 #pragma unroll
     for (int k = 0; k < T; ++k) {
-      const bool keep = myv[k] != v;
+      bool keep = myv[k] != v;
+      if constexpr (NEAR) {
+        // squared distance test in the precision of the pair loop: on the rescaled
+        // coordinates of the compensated form the threshold scales by sigma^2
+        const double h = near.hlen[v];
+        bool is_near;
+        if constexpr (PREC == P32C) {
+          const float th = (float)(h * (double)sig[k]);
+          is_near = qmin[k] <= th * th;
+        } else if constexpr (PREC == P32N) {
+          const float th = (float)h;
+          is_near = qmin[k] <= th * th;
+        } else {
+          is_near = qmin[k] <= h * h;
+        }
+        if (keep && valid[k] && is_near) {
+          const int slot = atomicAdd(near.count, 1);
+          if (slot < near.capacity) {
+            near.pairs[2 * slot] = idx[k];
+            near.pairs[2 * slot + 1] = v;
+          }
+        }
+        keep = keep && !is_near;
+      }
       if constexpr (NEED_V) {
         if constexpr (PREC == P32C) {
           const float pvx = fmaf(kHalfLn2, lx[k], rvx[k]);
@@ -290,7 +369,7 @@ __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int 
 
 // ----------------------------------------------------------------------------- forward
 
-template <int PREC, int T, int B>
+template <int PREC, int T, int B, bool LDS>
 __global__ __launch_bounds__(B) void k_forward(const double* __restrict__ tg, int P, int M,
                                                const int32_t* __restrict__ vid, const int2* __restrict__ vrange,
                                                const double4* __restrict__ vtab,
@@ -306,8 +385,8 @@ __global__ __launch_bounds__(B) void k_forward(const double* __restrict__ tg, in
   Acc<PREC> acc[T];
   int idx[T];
   bool valid[T];
-  gather<PREC, T, B, true, false>(i_begin, i_end, v_begin, v_end, tg, nullptr, nullptr, P, vid, vrange, vtab, rec,
-                                  acc, idx, valid);
+  gather<PREC, T, B, true, false, LDS>(i_begin, i_end, v_begin, v_end, tg, nullptr, nullptr, P, vid, vrange, vtab,
+                                       rec, acc, idx, valid);
 #pragma unroll
   for (int k = 0; k < T; ++k) {
     if (!valid[k]) continue;
@@ -319,6 +398,43 @@ __global__ __launch_bounds__(B) void k_forward(const double* __restrict__ tg, in
       partial[(size_t)(2 * split + 1) * P + idx[k]] = acc[k].vy;
     }
   }
+}
+
+// Forward sum with near-field vesicles masked out (see NearOut).
+template <int PREC, int T, int B, bool LDS>
+__global__ __launch_bounds__(B) void k_forward_near(const double* __restrict__ tg, int P, int M,
+                                                    const int32_t* __restrict__ vid, const int2* __restrict__ vrange,
+                                                    const double4* __restrict__ vtab,
+                                                    const typename Real<PREC>::R* __restrict__ rec, double scale,
+                                                    int splits, double* __restrict__ out, double* __restrict__ partial,
+                                                    NearOut near) {
+  const int tile = B * T;
+  const int i_begin = blockIdx.x * tile;
+  if (i_begin >= P) return;
+  const int i_end = min(P, i_begin + tile);
+  const int split = blockIdx.y;
+  const int v_begin = (int)(((int64_t)M * split) / splits);
+  const int v_end = (int)(((int64_t)M * (split + 1)) / splits);
+  Acc<PREC> acc[T];
+  int idx[T];
+  bool valid[T];
+  gather<PREC, T, B, true, false, LDS, true>(i_begin, i_end, v_begin, v_end, tg, nullptr, nullptr, P, vid, vrange,
+                                             vtab, rec, acc, idx, valid, near);
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    if (!valid[k]) continue;
+    if (splits == 1) {
+      out[idx[k]] = scale * acc[k].vx;
+      out[P + idx[k]] = scale * acc[k].vy;
+    } else {
+      partial[(size_t)(2 * split) * P + idx[k]] = acc[k].vx;
+      partial[(size_t)(2 * split + 1) * P + idx[k]] = acc[k].vy;
+    }
+  }
+}
+
+__global__ void k_zero_i32(int32_t* __restrict__ p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_reduce_splits(const double* __restrict__ partial, int P, int splits,
@@ -383,7 +499,7 @@ __global__ __launch_bounds__(256) void k_plan_scan(const int32_t* __restrict__ o
   if (t == 0) counter[0] = 0;
 }
 
-template <int PREC, int T, int B>
+template <int PREC, int T, int B, bool LDS>
 __global__ __launch_bounds__(B) void k_forward_batched(const double* __restrict__ tg, int P, int M,
                                                        const int32_t* __restrict__ vid,
                                                        const int2* __restrict__ vrange,
@@ -422,8 +538,8 @@ __global__ __launch_bounds__(B) void k_forward_batched(const double* __restrict_
     Acc<PREC> acc[T];
     int idx[T];
     bool valid[T];
-    gather<PREC, T, B, true, false>(i_begin, i_end, vb, ve, tg, nullptr, nullptr, P, vid, vrange, vtab, rec, acc,
-                                    idx, valid);
+    gather<PREC, T, B, true, false, LDS>(i_begin, i_end, vb, ve, tg, nullptr, nullptr, P, vid, vrange, vtab, rec,
+                                         acc, idx, valid);
 #pragma unroll
     for (int q = 0; q < T; ++q) {
       if (!valid[q]) continue;
@@ -455,8 +571,8 @@ __global__ __launch_bounds__(B) void k_bwd_targets(const double* __restrict__ tg
   Acc<PREC> acc[T];
   int idx[T];
   bool valid[T];
-  gather<PREC, T, B, false, true>(i_begin, i_end, v_begin, v_end, tg, gout, nullptr, P, vid, vrange, vtab, rec, acc,
-                                  idx, valid);
+  gather<PREC, T, B, false, true, false>(i_begin, i_end, v_begin, v_end, tg, gout, nullptr, P, vid, vrange, vtab,
+                                         rec, acc, idx, valid);
 #pragma unroll
   for (int k = 0; k < T; ++k) {
     if (!valid[k]) continue;
@@ -510,8 +626,8 @@ __global__ __launch_bounds__(B) void k_bwd_sources(const double* __restrict__ sr
   Acc<PREC> acc[T];
   int idx[T];
   bool valid[T];
-  gather<PREC, T, B, true, true>(i_begin, i_end, v_begin, v_end, src, f, w, P, vid, vrange, vtab, rec, acc, idx,
-                                 valid);
+  gather<PREC, T, B, true, true, false>(i_begin, i_end, v_begin, v_end, src, f, w, P, vid, vrange, vtab, rec, acc,
+                                        idx, valid);
 #pragma unroll
   for (int k = 0; k < T; ++k) {
     if (!valid[k]) continue;
@@ -552,30 +668,34 @@ hipError_t launch_prepare(int prec, const double* pts, const double* vec, const 
   const int grid = M < 65535 ? M : 65535;
   switch (prec) {
     case P64: hipLaunchKernelGGL(k_prepare<P64>, dim3(grid), dim3(64), 0, S_(stream), pts, vec, wts, off, M, P,
-                                 pv.vrange, pv.vid, pv.vtab, pv.rec); break;
+                                 pv.vrange, pv.vid, pv.vtab, pv.hlen, pv.rec); break;
     case P32C: hipLaunchKernelGGL(k_prepare<P32C>, dim3(grid), dim3(64), 0, S_(stream), pts, vec, wts, off, M, P,
-                                  pv.vrange, pv.vid, pv.vtab, pv.rec); break;
+                                  pv.vrange, pv.vid, pv.vtab, pv.hlen, pv.rec); break;
     case P32N: hipLaunchKernelGGL(k_prepare<P32N>, dim3(grid), dim3(64), 0, S_(stream), pts, vec, wts, off, M, P,
-                                  pv.vrange, pv.vid, pv.vtab, pv.rec); break;
+                                  pv.vrange, pv.vid, pv.vtab, pv.hlen, pv.rec); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <int PREC, int T, int B>
+template <int PREC, int T, int B, bool LDS>
 static void fwd_one(const double* tg, int P, int M, const PreparedView& pv, double scale, int splits, double* out,
                     double* partial, hipStream_t st) {
   const int tile = B * T;
   dim3 grid((P + tile - 1) / tile, splits);
-  hipLaunchKernelGGL((k_forward<PREC, T, B>), grid, dim3(B), 0, st, tg, P, M, pv.vid, pv.vrange, pv.vtab,
+  hipLaunchKernelGGL((k_forward<PREC, T, B, LDS>), grid, dim3(B), 0, st, tg, P, M, pv.vid, pv.vrange, pv.vtab,
                      static_cast<const typename Real<PREC>::R*>(pv.rec), scale, splits, out, partial);
 }
 
 template <int PREC>
-static bool fwd_dispatch(int T, int B, const double* tg, int P, int M, const PreparedView& pv, double scale,
+static bool fwd_dispatch(int T, int B, bool lds, const double* tg, int P, int M, const PreparedView& pv, double scale,
                          int splits, double* out, double* partial, hipStream_t st) {
-#define VESNET_FWD_CASE(TT, BB) \
-  if (T == TT && B == BB) { fwd_one<PREC, TT, BB>(tg, P, M, pv, scale, splits, out, partial, st); return true; }
+#define VESNET_FWD_CASE(TT, BB)                                                               \
+  if (T == TT && B == BB) {                                                                   \
+    if (lds) fwd_one<PREC, TT, BB, true>(tg, P, M, pv, scale, splits, out, partial, st);      \
+    else fwd_one<PREC, TT, BB, false>(tg, P, M, pv, scale, splits, out, partial, st);         \
+    return true;                                                                              \
+  }
   VESNET_FWD_CASE(1, 64) VESNET_FWD_CASE(1, 128) VESNET_FWD_CASE(1, 256)
   VESNET_FWD_CASE(2, 64) VESNET_FWD_CASE(2, 128) VESNET_FWD_CASE(2, 256)
   VESNET_FWD_CASE(4, 64) VESNET_FWD_CASE(4, 128) VESNET_FWD_CASE(4, 256)
@@ -583,18 +703,55 @@ static bool fwd_dispatch(int T, int B, const double* tg, int P, int M, const Pre
   return false;
 }
 
-hipError_t launch_forward(int prec, int T, int B, int splits, const double* tg, int P, int M, const PreparedView& pv,
-                          double scale, double* out, double* partial, void* stream) {
+hipError_t launch_forward(int prec, int T, int B, bool lds, int splits, const double* tg, int P, int M,
+                          const PreparedView& pv, double scale, double* out, double* partial, void* stream) {
   if (P == 0) return hipSuccess;
   hipStream_t st = S_(stream);
   bool ok = false;
   switch (prec) {
-    case P64: ok = fwd_dispatch<P64>(T, B, tg, P, M, pv, scale, splits, out, partial, st); break;
-    case P32C: ok = fwd_dispatch<P32C>(T, B, tg, P, M, pv, scale, splits, out, partial, st); break;
-    case P32N: ok = fwd_dispatch<P32N>(T, B, tg, P, M, pv, scale, splits, out, partial, st); break;
+    case P64: ok = fwd_dispatch<P64>(T, B, lds, tg, P, M, pv, scale, splits, out, partial, st); break;
+    case P32C: ok = fwd_dispatch<P32C>(T, B, lds, tg, P, M, pv, scale, splits, out, partial, st); break;
+    case P32N: ok = fwd_dispatch<P32N>(T, B, lds, tg, P, M, pv, scale, splits, out, partial, st); break;
     default: break;
   }
   if (!ok) return hipErrorInvalidValue;
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || splits == 1) return e;
+  const int64_t n = 2 * (int64_t)P;
+  const int grid = (int)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
+  hipLaunchKernelGGL(k_reduce_splits, dim3(grid), dim3(256), 0, st, partial, P, splits, scale, out);
+  return hipGetLastError();
+}
+
+template <int PREC, int T, bool LDS>
+static void near_one(const double* tg, int P, int M, const PreparedView& pv, double scale, int splits, double* out,
+                     double* partial, const NearOut& nr, hipStream_t st) {
+  constexpr int B = 256;
+  const int tile = B * T;
+  dim3 grid((P + tile - 1) / tile, splits);
+  hipLaunchKernelGGL((k_forward_near<PREC, T, B, LDS>), grid, dim3(B), 0, st, tg, P, M, pv.vid, pv.vrange, pv.vtab,
+                     static_cast<const typename Real<PREC>::R*>(pv.rec), scale, splits, out, partial, nr);
+}
+
+hipError_t launch_forward_near(int prec, int T, bool lds, int splits, const double* tg, int P, int M,
+                               const PreparedView& pv, double scale, double* out, double* partial, int32_t* count,
+                               int32_t* pairs, int32_t capacity, void* stream) {
+  hipStream_t st = S_(stream);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, count);
+  if (P == 0) return hipGetLastError();
+  const NearOut nr{pv.hlen, count, pairs, capacity};
+#define VESNET_NEAR(PR)                                                                         \
+  if (T == 1) { if (lds) near_one<PR, 1, true>(tg, P, M, pv, scale, splits, out, partial, nr, st);    \
+                else near_one<PR, 1, false>(tg, P, M, pv, scale, splits, out, partial, nr, st); }   \
+  else { if (lds) near_one<PR, 2, true>(tg, P, M, pv, scale, splits, out, partial, nr, st);          \
+         else near_one<PR, 2, false>(tg, P, M, pv, scale, splits, out, partial, nr, st); }
+  switch (prec) {
+    case P64: VESNET_NEAR(P64) break;
+    case P32C: VESNET_NEAR(P32C) break;
+    case P32N: VESNET_NEAR(P32N) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef VESNET_NEAR
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splits == 1) return e;
   const int64_t n = 2 * (int64_t)P;
@@ -614,20 +771,24 @@ hipError_t launch_plan(const int32_t* sus_off, int S, int M, const PreparedView&
   return hipGetLastError();
 }
 
-template <int PREC, int T, int B>
+template <int PREC, int T, int B, bool LDS>
 static void bat_one(int grid, const double* tg, int P, int M, const PreparedView& pv, const int32_t* sus_off,
                     const double* mu, int S, const PlanView& pl, double* out, hipStream_t st) {
-  hipLaunchKernelGGL((k_forward_batched<PREC, T, B>), dim3(grid), dim3(B), 0, st, tg, P, M, pv.vid, pv.vrange,
+  hipLaunchKernelGGL((k_forward_batched<PREC, T, B, LDS>), dim3(grid), dim3(B), 0, st, tg, P, M, pv.vid, pv.vrange,
                      pv.vtab, static_cast<const typename Real<PREC>::R*>(pv.rec), sus_off, mu, S, pl.order,
                      pl.item_start, pl.counter, out);
 }
 
 template <int PREC>
-static bool bat_dispatch(int T, int B, int grid, const double* tg, int P, int M, const PreparedView& pv,
+static bool bat_dispatch(int T, int B, bool lds, int grid, const double* tg, int P, int M, const PreparedView& pv,
                          const int32_t* sus_off, const double* mu, int S, const PlanView& pl, double* out,
                          hipStream_t st) {
-#define VESNET_BAT_CASE(TT, BB) \
-  if (T == TT && B == BB) { bat_one<PREC, TT, BB>(grid, tg, P, M, pv, sus_off, mu, S, pl, out, st); return true; }
+#define VESNET_BAT_CASE(TT, BB)                                                                    \
+  if (T == TT && B == BB) {                                                                        \
+    if (lds) bat_one<PREC, TT, BB, true>(grid, tg, P, M, pv, sus_off, mu, S, pl, out, st);         \
+    else bat_one<PREC, TT, BB, false>(grid, tg, P, M, pv, sus_off, mu, S, pl, out, st);            \
+    return true;                                                                                   \
+  }
   VESNET_BAT_CASE(1, 64) VESNET_BAT_CASE(1, 128) VESNET_BAT_CASE(1, 256)
   VESNET_BAT_CASE(2, 64) VESNET_BAT_CASE(2, 128) VESNET_BAT_CASE(2, 256)
   VESNET_BAT_CASE(4, 64) VESNET_BAT_CASE(4, 128) VESNET_BAT_CASE(4, 256)
@@ -635,15 +796,15 @@ static bool bat_dispatch(int T, int B, int grid, const double* tg, int P, int M,
   return false;
 }
 
-hipError_t launch_batched(int prec, int T, int B, int grid, const double* tg, int P, int M, const PreparedView& pv,
-                          const int32_t* sus_off, const double* mu, int S, const PlanView& pl, double* out,
-                          void* stream) {
+hipError_t launch_batched(int prec, int T, int B, bool lds, int grid, const double* tg, int P, int M,
+                          const PreparedView& pv, const int32_t* sus_off, const double* mu, int S, const PlanView& pl,
+                          double* out, void* stream) {
   hipStream_t st = S_(stream);
   bool ok = false;
   switch (prec) {
-    case P64: ok = bat_dispatch<P64>(T, B, grid, tg, P, M, pv, sus_off, mu, S, pl, out, st); break;
-    case P32C: ok = bat_dispatch<P32C>(T, B, grid, tg, P, M, pv, sus_off, mu, S, pl, out, st); break;
-    case P32N: ok = bat_dispatch<P32N>(T, B, grid, tg, P, M, pv, sus_off, mu, S, pl, out, st); break;
+    case P64: ok = bat_dispatch<P64>(T, B, lds, grid, tg, P, M, pv, sus_off, mu, S, pl, out, st); break;
+    case P32C: ok = bat_dispatch<P32C>(T, B, lds, grid, tg, P, M, pv, sus_off, mu, S, pl, out, st); break;
+    case P32N: ok = bat_dispatch<P32N>(T, B, lds, grid, tg, P, M, pv, sus_off, mu, S, pl, out, st); break;
     default: break;
   }
   if (!ok) return hipErrorInvalidValue;

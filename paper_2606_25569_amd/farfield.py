@@ -119,6 +119,37 @@ def farfield_forward(targets, sources, force_density, arc_weights, partition, mu
     return out
 
 
+def farfield_nearmasked(targets, sources, force_density, arc_weights, partition, mu, precision="fp32c",
+                        config=None, capacity=None):
+    """Far field with near-field vesicles masked out, and the near pairs.
+
+    A vesicle v is near target i when min_j |x_i - y_j| <= sum_j w_j / N_v (its mean
+    arclength spacing).  Returns (out (2, P), pairs (n, 2) int32 device tensor of
+    (target, vesicle), unordered).  The list is re-run with a larger capacity when
+    the first pass overflows (one host synchronisation)."""
+    part = as_partition(partition)
+    P, M = part.n_points, part.n_vesicles
+    for n, t in (("targets", targets), ("sources", sources), ("force_density", force_density)):
+        _check_vec(n, t, P)
+    _check_w(arc_weights, P)
+    prec = L.precision_code(precision)
+    dev = targets.device
+    out = torch.empty((2, P), dtype=torch.float64, device=dev)
+    cap = int(capacity) if capacity is not None else max(1024, 4 * P)
+    ws = _workspace(workspace_bytes(P, M, prec, config), dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    while True:
+        pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        L.check(L.lib().vesnet_farfield_stokeslet_nearmasked(
+            _ptr(targets), _ptr(sources), _ptr(force_density), _ptr(arc_weights), _ptr(part.device), M, P,
+            float(mu), _ptr(out), _ptr(pairs), cap, _ptr(count), prec, _cfg_arg(config), _ptr(ws), ws.numel(),
+            _stream()))
+        n = int(count.item())
+        if n <= cap:
+            return out, pairs[:n]
+        cap = n
+
+
 def farfield_backward(targets, sources, force_density, arc_weights, partition, mu, grad_out, precision="fp32c",
                       need=(True, True, True, True)):
     """Reverse mode: returns (grad_targets, grad_sources, grad_force, grad_weights), None where not needed."""

@@ -24,7 +24,7 @@ def _declared():
 def test_every_declared_symbol_is_exported(L):
     lib = L.lib()
     names = _declared()
-    assert len(names) == 16, names
+    assert len(names) == 17, names
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(L.EXPORTED)
@@ -109,7 +109,7 @@ def test_forward_rejects_bad_arguments(L, kw, code):
 
 def test_bad_tile_configs_rejected(L):
     for cfg in (L.TileConfig(3, 256, 1, 1), L.TileConfig(1, 96, 1, 1), L.TileConfig(1, 64, 65, 1),
-                L.TileConfig(1, 64, -1, 1), L.TileConfig(1, 64, 1, 17)):
+                L.TileConfig(1, 64, -1, 1), L.TileConfig(1, 64, 1, 17), L.TileConfig(1, 64, 1, 1, 3)):
         assert _fwd(L, cfg=ctypes.byref(cfg)) == -1
 
 
@@ -149,6 +149,17 @@ def test_batched_rejects(L):
     assert lib.vesnet_graph_create_batched(*base, None, 1, _p(FAKE + 0x800000), *tail[:5], ctypes.byref(g)) == -1
     assert lib.vesnet_graph_launch(None, None) == -1
     assert lib.vesnet_graph_destroy(None) == 0
+
+
+def test_nearmasked_rejects(L):
+    lib = L.lib()
+    base = [_p(FAKE), _p(FAKE + 0x100000), _p(FAKE + 0x200000), _p(FAKE + 0x300000), _p(FAKE + 0x400000), 2, 10, 1.0,
+            _p(FAKE + 0x500000)]
+    ws = [1, None, _p(FAKE + 0x600000), 1 << 30, None]
+    assert lib.vesnet_farfield_stokeslet_nearmasked(*base, _p(FAKE + 0x700000), 4, None, *ws) == -1      # no count
+    assert lib.vesnet_farfield_stokeslet_nearmasked(*base, None, 4, _p(FAKE + 0x800000), *ws) == -1      # no list
+    assert lib.vesnet_farfield_stokeslet_nearmasked(*base, _p(FAKE + 0x700000), -1, _p(FAKE + 0x800000), *ws) == -1
+    assert lib.vesnet_farfield_stokeslet_nearmasked(*base, _p(FAKE + 0x500000), 4, _p(FAKE + 0x800000), *ws) == -1
 
 
 def test_product_package_has_no_cpu_fallback():

@@ -53,12 +53,14 @@ def _check_against(b, out, refs, bar):
 
 
 @pytest.mark.parametrize("prec,bar", [("fp64", 1e-12), ("fp32c", 1e-5)])
-def test_small_batch_matches_oracle_and_single_calls(V, prec, bar):
+@pytest.mark.parametrize("staging", [1, 2])
+def test_small_batch_matches_oracle_and_single_calls(V, prec, bar, staging):
     import torch
     b = _small_batch()
     X, f, w = _dev(b)
     bp = V.BatchedProblem(X, X, f, w, b.vesicle_offsets, b.suspension_offsets, b.mu, precision=prec,
-                          config={"targets_per_thread": 2, "block_threads": 128, "blocks_per_cu": 2})
+                          config={"targets_per_thread": 2, "block_threads": 128, "blocks_per_cu": 2,
+                                  "source_staging": staging})
     out = bp.run().cpu().numpy()
     worst = _check_against(b, out, _per_suspension_oracle(b), bar)
     say(f"small batch {prec}: worst rel err {worst:.3e}")
@@ -68,7 +70,8 @@ def test_small_batch_matches_oracle_and_single_calls(V, prec, bar):
         sl = slice(base, base + m.n_points)
         o1 = V.farfield_forward(X[:, sl].contiguous(), X[:, sl].contiguous(), f[:, sl].contiguous(),
                                 w[sl].contiguous(), m.offsets, b.mu[k], precision=prec,
-                                config={"targets_per_thread": 2, "block_threads": 128, "source_splits": 1})
+                                config={"targets_per_thread": 2, "block_threads": 128, "source_splits": 1,
+                                        "source_staging": staging})
         np.testing.assert_array_equal(o1.cpu().numpy(), out[:, sl])
         base += m.n_points
     torch.cuda.synchronize()

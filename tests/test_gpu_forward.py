@@ -56,14 +56,31 @@ def _ragged_suspension():
 @pytest.mark.parametrize("T", [1, 2, 4])
 @pytest.mark.parametrize("B", [64, 128, 256])
 @pytest.mark.parametrize("splits", [1, 3])
-def test_ragged_launch_shapes(V, T, B, splits):
+@pytest.mark.parametrize("staging", [1, 2])
+def test_ragged_launch_shapes(V, T, B, splits, staging):
     s = _ragged_suspension()
     ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
-    cfg = {"targets_per_thread": T, "block_threads": B, "source_splits": splits}
-    for prec in ("fp64", "fp32c"):
+    cfg = {"targets_per_thread": T, "block_threads": B, "source_splits": splits, "source_staging": staging}
+    for prec in ("fp64", "fp32c", "fp32"):
         err, _ = rel_err(_run(V, s, prec, cfg), ref)
-        say(f"ragged T={T} B={B} splits={splits} {prec}: {err:.3e}")
-        assert err <= BARS[prec], (prec, err)
+        say(f"ragged T={T} B={B} splits={splits} staging={staging} {prec}: {err:.3e}")
+        assert err <= BARS.get(prec, 1e-3), (prec, err)
+
+
+def test_vesicle_larger_than_lds_tile(V):
+    """One vesicle of 2500 points (more than an LDS tile of 1024 records) next to small ones."""
+    rng = np.random.default_rng(8)
+    sizes = np.array([2500, 7, 1030, 33])
+    centers = np.array([[0.0, 0.0], [30.0, 0.0], [0.0, 30.0], [30.0, 30.0]])
+    axes = np.array([[10.0, 4.0], [1.2, 0.5], [6.0, 3.0], [1.3, 0.4]])
+    s = S._assemble(rng, centers, axes, rng.uniform(0, 6.28, 4), sizes, "k4", 0.2, 1.0, 40.0)
+    ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    for staging in (1, 2):
+        for prec in ("fp64", "fp32c"):
+            cfg = {"targets_per_thread": 2, "block_threads": 128, "source_splits": 2, "source_staging": staging}
+            err, _ = rel_err(_run(V, s, prec, cfg), ref)
+            say(f"large vesicle staging={staging} {prec}: {err:.3e}")
+            assert err <= BARS[prec], (prec, err)
 
 
 def test_separate_targets_and_large_translation(V):

@@ -1,0 +1,68 @@
+"""GPU parity of the near-field masked far field and the near-pair list."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import suspension as S
+from tests.gpu_util import dev_inputs, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _margins(s, pairs_tol=1e-5):
+    """Smallest |d_iv - h_v| / h_v over all (target, other vesicle): decisions closer than
+    float32 rounding may legitimately differ, so the test inputs must stay clear of it."""
+    vid = O.vesicle_ids(s.offsets)
+    worst = np.inf
+    for v in range(s.n_vesicles):
+        a, b = s.offsets[v], s.offsets[v + 1]
+        if b == a:
+            continue
+        h = s.w[a:b].sum() / (b - a)
+        d = np.sqrt(((s.X[:, :, None] - s.X[:, None, a:b]) ** 2).sum(axis=0)).min(axis=1)
+        m = np.abs(d - h)[vid != v] / h
+        worst = min(worst, float(m.min()))
+    return worst
+
+
+@pytest.mark.parametrize("T,staging,splits", [(1, 1, 1), (2, 2, 1), (2, 1, 3), (1, 2, 4)])
+def test_nearmasked_parity(T, staging, splits):
+    import torch
+    import paper_2606_25569_amd as V
+    s = S.rsa_suspension(33, 120, 32, 0.40, gap=0.02)
+    assert _margins(s) > 1e-5
+    ref, pairs_ref = O.nearmasked_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    assert pairs_ref.shape[0] > 20
+    X, f, w = dev_inputs(s)
+    cfg = {"targets_per_thread": T, "block_threads": 256, "source_splits": splits, "source_staging": staging}
+    for prec, bar in (("fp64", 1e-12), ("fp32c", 1e-5)):
+        out, pairs = V.farfield_nearmasked(X, X, f, w, s.offsets, s.mu, prec, config=cfg)
+        torch.cuda.synchronize()
+        err, _ = rel_err(out.cpu().numpy(), ref)
+        got = {tuple(p) for p in pairs.cpu().numpy().tolist()}
+        say(f"nearmasked T={T} staging={staging} splits={splits} {prec}: err {err:.3e}, {len(got)} near pairs")
+        assert got == {tuple(p) for p in pairs_ref.tolist()}
+        assert err <= bar
+
+
+def test_nearmasked_overflow_retry():
+    import paper_2606_25569_amd as V
+    s = S.rsa_suspension(34, 60, 32, 0.40, gap=0.02)
+    ref, pairs_ref = O.nearmasked_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    X, f, w = dev_inputs(s)
+    out, pairs = V.farfield_nearmasked(X, X, f, w, s.offsets, s.mu, "fp64", capacity=3)
+    assert pairs.shape[0] == pairs_ref.shape[0] > 3
+    assert rel_err(out.cpu().numpy(), ref)[0] <= 1e-12
+
+
+def test_no_near_pairs_equals_plain_far_field():
+    """At 128 points per vesicle and gap 0.1 the spacing (0.049) is below every gap."""
+    import torch
+    import paper_2606_25569_amd as V
+    s = S.load_config(4)
+    X, f, w = dev_inputs(s)
+    plain = V.farfield_forward(X, X, f, w, s.offsets, s.mu, "fp32c")
+    out, pairs = V.farfield_nearmasked(X, X, f, w, s.offsets, s.mu, "fp32c")
+    torch.cuda.synchronize()
+    assert pairs.shape[0] == 0
+    assert torch.equal(out, plain) or rel_err(out.cpu().numpy(), plain.cpu().numpy())[0] < 1e-14
