@@ -81,6 +81,11 @@ typedef struct {
   int32_t source_staging;     /* 1: source records read at wave-uniform addresses into SGPRs;
                                  2: records staged through LDS tiles of 1024 and read back with
                                     broadcast LDS loads into VGPRs                               */
+  int32_t accumulate;         /* 1: per-pair sums accumulated with VALU FMAs;
+                                 2: (compensated forward only) the four accumulations of each pair
+                                    issued to the matrix cores as v_mfma_f32_4x4x1f32 products of
+                                    per-target values and per-source features, which then run
+                                    beside the VALU work                                          */
 } vesnet_tile_config;
 
 /* Library version string and the thread-local description of the last error. */

@@ -74,7 +74,7 @@ char* aligned_base(void* ws) {
 bool valid_precision(int prec) { return prec == VESNET_FP64 || prec == VESNET_FP32_COMPENSATED || prec == VESNET_FP32_NAIVE; }
 
 struct Shape {
-  int T, B, splits, bpc, staging;
+  int T, B, splits, bpc, staging, accumulate;
 };
 
 Shape default_shape(int32_t P, int32_t M, int prec) {
@@ -83,6 +83,7 @@ Shape default_shape(int32_t P, int32_t M, int prec) {
   s.B = 256;
   s.bpc = 2;
   s.staging = 2;
+  s.accumulate = 1;
   const int64_t waves = ((int64_t)P + 64 * s.T - 1) / (64 * s.T);
   const int64_t want = 8192;  // about 8 waves per SIMD on 256 CUs x 4 SIMDs
   int splits = 1;
@@ -99,6 +100,7 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     if (cfg->source_splits) s.splits = cfg->source_splits;
     if (cfg->blocks_per_cu) s.bpc = cfg->blocks_per_cu;
     if (cfg->source_staging) s.staging = cfg->source_staging;
+    if (cfg->accumulate) s.accumulate = cfg->accumulate;
   }
   if (s.T != 1 && s.T != 2 && s.T != 4)
     return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread must be 1, 2 or 4 (got %d)", s.T);
@@ -110,6 +112,10 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     return fail(VESNET_ERR_INVALID_ARGUMENT, "blocks_per_cu must be in [1, 16] (got %d)", s.bpc);
   if (s.staging != 1 && s.staging != 2)
     return fail(VESNET_ERR_INVALID_ARGUMENT, "source_staging must be 1 or 2 (got %d)", s.staging);
+  if (s.accumulate != 1 && s.accumulate != 2)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "accumulate must be 1 or 2 (got %d)", s.accumulate);
+  if (s.accumulate == 2 && prec != VESNET_FP32_COMPENSATED)
+    return fail(VESNET_ERR_UNSUPPORTED, "matrix-core accumulation exists for the compensated form only");
   *out = s;
   return VESNET_OK;
 }
@@ -198,6 +204,7 @@ extern "C" int vesnet_default_tile_config(int32_t P, int32_t M, int prec, vesnet
   cfg->source_splits = s.splits;
   cfg->blocks_per_cu = s.bpc;
   cfg->source_staging = s.staging;
+  cfg->accumulate = s.accumulate;
   return ok();
 }
 
@@ -239,8 +246,8 @@ extern "C" int vesnet_farfield_evaluate(const double* targets, const int32_t* of
   PreparedView pv = carve_prepared(cur, P, M, prec);
   double* partial = s.splits > 1 ? reinterpret_cast<double*>(cur) : nullptr;
   const double scale = 1.0 / (4.0 * kPi * mu);
-  hipError_t e = launch_forward(prec, s.T, s.B, s.staging == 2, s.splits, targets, P, M, pv, scale, out, partial,
-                                stream);
+  hipError_t e = launch_forward(prec, s.T, s.B, s.staging == 2, s.accumulate == 2, s.splits, targets, P, M, pv,
+                                scale, out, partial, stream);
   if (e != hipSuccess) return hip_fail(e, "forward launch");
   return ok();
 }
@@ -542,20 +549,23 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
 
   std::vector<vesnet_tile_config> cands;
-  for (int stg : {1, 2})
-    for (int T : {1, 2, 4})
-      for (int B : {64, 128, 256}) {
-        if (batched) {
-          for (int bpc : {1, 2, 4, 8}) cands.push_back({T, B, 1, bpc, stg});
-        } else {
-          for (int sp : {1, 2, 4, 8, 16}) {
-            if (sp > std::max(1, M)) continue;
-            const Shape sh{T, B, sp, 1, stg};
-            if (forward_bytes(P, M, prec, sh) > ws_bytes) continue;
-            cands.push_back({T, B, sp, 1, stg});
+  for (int acc : {1, 2}) {
+    if (acc == 2 && (batched || prec != VESNET_FP32_COMPENSATED)) continue;
+    for (int stg : {1, 2})
+      for (int T : {1, 2, 4})
+        for (int B : {64, 128, 256}) {
+          if (batched) {
+            for (int bpc : {1, 2, 4, 8}) cands.push_back({T, B, 1, bpc, stg, acc});
+          } else {
+            for (int sp : {1, 2, 4, 8, 16}) {
+              if (sp > std::max(1, M)) continue;
+              const Shape sh{T, B, sp, 1, stg, acc};
+              if (forward_bytes(P, M, prec, sh) > ws_bytes) continue;
+              cands.push_back({T, B, sp, 1, stg, acc});
+            }
           }
         }
-      }
+  }
   if (batched && (rc = check_workspace(ws, ws_bytes, vesnet_batched_workspace_bytes(P, M, S, prec)))) return rc;
   if (cands.empty()) return fail(VESNET_ERR_WORKSPACE, "workspace too small for any launch shape");
 

@@ -30,7 +30,7 @@ struct PlanView {
 
 hipError_t launch_prepare(int prec, const double* pts, const double* vec, const double* wts, const int32_t* off,
                           int M, int P, const PreparedView& pv, void* stream);
-hipError_t launch_forward(int prec, int T, int B, bool lds, int splits, const double* tg, int P, int M,
+hipError_t launch_forward(int prec, int T, int B, bool lds, bool mf, int splits, const double* tg, int P, int M,
                           const PreparedView& pv, double scale, double* out, double* partial, void* stream);
 hipError_t launch_forward_near(int prec, int T, bool lds, int splits, const double* tg, int P, int M,
                                const PreparedView& pv, double scale, double* out, double* partial, int32_t* count,

@@ -30,6 +30,8 @@ constexpr double kLn2 = 0.69314718055994530942;
 constexpr float kHalfLn2 = -0.34657359027997265471f;  // -(1/2) ln 2 : converts log2(q) to -ln|r|
 constexpr int kTile = 1024;                             // records per LDS tile
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -129,7 +131,13 @@ struct Acc {
 //              reads them back with broadcast LDS loads into VGPRs.  The tile window only
 //              moves forward through uniform control flow, so its barriers are block-wide.
 // NEAR = true: also track min_j |r|^2 per (thread point, vesicle) and apply NearOut.
-template <int PREC, int T, int B, bool NEED_V, bool NEED_GRAD, bool LDS, bool NEAR = false>
+// MF = true (compensated forward only): the four accumulations of a pair move to the
+//   matrix cores.  With r' = d' + n s_j (n = -sigma), sum_j t_j r'_j = d' sum_j t_j + n sum_j t_j s_j
+//   and sum_j L_j F_j are products of a per-target value (t_j or L_j) with per-source
+//   features (1, s_x, s_y) and (F_x, F_y): one v_mfma_f32_4x4x1f32 each, with the features
+//   in the A operand (lane 4b+m of block b carries feature m) and the per-target value in
+//   the B operand, so lane l's accumulator row m is feature m's sum for its own target.
+template <int PREC, int T, int B, bool NEED_V, bool NEED_GRAD, bool LDS, bool NEAR = false, bool MF = false>
 __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int v_end, const double* __restrict__ pts,
                                        const double* __restrict__ avec, const double* __restrict__ awts, int P,
                                        const int32_t* __restrict__ vid, const int2* __restrict__ vrange,
@@ -212,13 +220,25 @@ __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int 
     }
 
     real lx[T], ly[T], rvx[T], rvy[T], s1[T], gx[T], gy[T], hx[T], hy[T], qmin[T];
+    floatx4 mt[T], ml[T];
 #pragma unroll
     for (int k = 0; k < T; ++k) {
       lx[k] = ly[k] = rvx[k] = rvy[k] = s1[k] = gx[k] = gy[k] = hx[k] = hy[k] = (real)0;
       qmin[k] = (real)3.0e38f;
+      mt[k] = floatx4{0.f, 0.f, 0.f, 0.f};
+      ml[k] = floatx4{0.f, 0.f, 0.f, 0.f};
     }
+    // Per-lane feature selectors of the A operand (lane 4b+m carries feature m), applied
+    // with FMAs so that the selection stays branch-free.
+    const int q4 = threadIdx.x & 3;
+    const float sel0 = q4 == 0 ? 1.0f : 0.0f, sel1 = q4 == 1 ? 1.0f : 0.0f, sel2 = q4 == 2 ? 1.0f : 0.0f;
 
     auto pair = [&](const typename Real<PREC>::R& s) __attribute__((always_inline)) {
+      float fa = 0.f, fb = 0.f;
+      if constexpr (MF) {
+        fa = fmaf(sel1, (float)s.x, fmaf(sel2, (float)s.y, sel0));  // (1, s_x, s_y, 0)
+        fb = fmaf(sel0, (float)s.z, sel1 * (float)s.w);             // (F_x, F_y, 0, 0)
+      }
 #pragma unroll
       for (int k = 0; k < T; ++k) {
         real rx, ry;
@@ -242,11 +262,16 @@ __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int 
           real L;
           if constexpr (PREC == P64) L = log(q);
           else L = __builtin_amdgcn_logf(q);
-          lx[k] += L * s.z;
-          ly[k] += L * s.w;
           const real t = beta * rho;
-          rvx[k] += t * rx;
-          rvy[k] += t * ry;
+          if constexpr (MF) {
+            mt[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(fa, (float)t, mt[k], 0, 0, 0);
+            ml[k] = __builtin_amdgcn_mfma_f32_4x4x1f32(fb, (float)L, ml[k], 0, 0, 0);
+          } else {
+            lx[k] += L * s.z;
+            ly[k] += L * s.w;
+            rvx[k] += t * rx;
+            rvy[k] += t * ry;
+          }
         }
         if constexpr (NEED_GRAD) {
           const real alpha = ry * ay[k] + rx * ax[k];  // a . r
@@ -324,6 +349,13 @@ __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int 
         }
         keep = keep && !is_near;
       }
+      if constexpr (MF) {
+        // sum t r' = d' sum t + n sum t s  (n = ns = -sigma)
+        lx[k] = ml[k][0];
+        ly[k] = ml[k][1];
+        rvx[k] = fmaf(ns[k], mt[k][1], dx[k] * mt[k][0]);
+        rvy[k] = fmaf(ns[k], mt[k][2], dy[k] * mt[k][0]);
+      }
       if constexpr (NEED_V) {
         if constexpr (PREC == P32C) {
           const float pvx = fmaf(kHalfLn2, lx[k], rvx[k]);
@@ -369,7 +401,7 @@ __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int 
 
 // ----------------------------------------------------------------------------- forward
 
-template <int PREC, int T, int B, bool LDS>
+template <int PREC, int T, int B, bool LDS, bool MF>
 __global__ __launch_bounds__(B) void k_forward(const double* __restrict__ tg, int P, int M,
                                                const int32_t* __restrict__ vid, const int2* __restrict__ vrange,
                                                const double4* __restrict__ vtab,
@@ -385,8 +417,8 @@ __global__ __launch_bounds__(B) void k_forward(const double* __restrict__ tg, in
   Acc<PREC> acc[T];
   int idx[T];
   bool valid[T];
-  gather<PREC, T, B, true, false, LDS>(i_begin, i_end, v_begin, v_end, tg, nullptr, nullptr, P, vid, vrange, vtab,
-                                       rec, acc, idx, valid);
+  gather<PREC, T, B, true, false, LDS, false, MF>(i_begin, i_end, v_begin, v_end, tg, nullptr, nullptr, P, vid,
+                                                  vrange, vtab, rec, acc, idx, valid);
 #pragma unroll
   for (int k = 0; k < T; ++k) {
     if (!valid[k]) continue;
@@ -678,23 +710,23 @@ hipError_t launch_prepare(int prec, const double* pts, const double* vec, const 
   return hipGetLastError();
 }
 
-template <int PREC, int T, int B, bool LDS>
+template <int PREC, int T, int B, bool LDS, bool MF>
 static void fwd_one(const double* tg, int P, int M, const PreparedView& pv, double scale, int splits, double* out,
                     double* partial, hipStream_t st) {
   const int tile = B * T;
   dim3 grid((P + tile - 1) / tile, splits);
-  hipLaunchKernelGGL((k_forward<PREC, T, B, LDS>), grid, dim3(B), 0, st, tg, P, M, pv.vid, pv.vrange, pv.vtab,
+  hipLaunchKernelGGL((k_forward<PREC, T, B, LDS, MF>), grid, dim3(B), 0, st, tg, P, M, pv.vid, pv.vrange, pv.vtab,
                      static_cast<const typename Real<PREC>::R*>(pv.rec), scale, splits, out, partial);
 }
 
-template <int PREC>
+template <int PREC, bool MF>
 static bool fwd_dispatch(int T, int B, bool lds, const double* tg, int P, int M, const PreparedView& pv, double scale,
                          int splits, double* out, double* partial, hipStream_t st) {
-#define VESNET_FWD_CASE(TT, BB)                                                               \
-  if (T == TT && B == BB) {                                                                   \
-    if (lds) fwd_one<PREC, TT, BB, true>(tg, P, M, pv, scale, splits, out, partial, st);      \
-    else fwd_one<PREC, TT, BB, false>(tg, P, M, pv, scale, splits, out, partial, st);         \
-    return true;                                                                              \
+#define VESNET_FWD_CASE(TT, BB)                                                                   \
+  if (T == TT && B == BB) {                                                                       \
+    if (lds) fwd_one<PREC, TT, BB, true, MF>(tg, P, M, pv, scale, splits, out, partial, st);      \
+    else fwd_one<PREC, TT, BB, false, MF>(tg, P, M, pv, scale, splits, out, partial, st);         \
+    return true;                                                                                  \
   }
   VESNET_FWD_CASE(1, 64) VESNET_FWD_CASE(1, 128) VESNET_FWD_CASE(1, 256)
   VESNET_FWD_CASE(2, 64) VESNET_FWD_CASE(2, 128) VESNET_FWD_CASE(2, 256)
@@ -703,15 +735,18 @@ static bool fwd_dispatch(int T, int B, bool lds, const double* tg, int P, int M,
   return false;
 }
 
-hipError_t launch_forward(int prec, int T, int B, bool lds, int splits, const double* tg, int P, int M,
+hipError_t launch_forward(int prec, int T, int B, bool lds, bool mf, int splits, const double* tg, int P, int M,
                           const PreparedView& pv, double scale, double* out, double* partial, void* stream) {
   if (P == 0) return hipSuccess;
   hipStream_t st = S_(stream);
   bool ok = false;
   switch (prec) {
-    case P64: ok = fwd_dispatch<P64>(T, B, lds, tg, P, M, pv, scale, splits, out, partial, st); break;
-    case P32C: ok = fwd_dispatch<P32C>(T, B, lds, tg, P, M, pv, scale, splits, out, partial, st); break;
-    case P32N: ok = fwd_dispatch<P32N>(T, B, lds, tg, P, M, pv, scale, splits, out, partial, st); break;
+    case P64: ok = !mf && fwd_dispatch<P64, false>(T, B, lds, tg, P, M, pv, scale, splits, out, partial, st); break;
+    case P32C:
+      ok = mf ? fwd_dispatch<P32C, true>(T, B, lds, tg, P, M, pv, scale, splits, out, partial, st)
+              : fwd_dispatch<P32C, false>(T, B, lds, tg, P, M, pv, scale, splits, out, partial, st);
+      break;
+    case P32N: ok = !mf && fwd_dispatch<P32N, false>(T, B, lds, tg, P, M, pv, scale, splits, out, partial, st); break;
     default: break;
   }
   if (!ok) return hipErrorInvalidValue;

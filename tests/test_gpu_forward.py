@@ -154,3 +154,24 @@ def test_config2_precision_study(V, variant):
     assert res["fp64"][0] <= 1e-12
     assert res["fp32c"][0] <= 1e-5
     assert res["fp32c"][0] < res["fp32"][0]
+
+
+@pytest.mark.parametrize("T", [1, 2, 4])
+@pytest.mark.parametrize("staging", [1, 2])
+@pytest.mark.parametrize("splits", [1, 3])
+def test_matrix_core_accumulation(V, T, staging, splits):
+    """The compensated forward with its accumulations on the matrix cores
+    (accumulate = 2) on the ragged partition and on the 16 x 32 grid."""
+    for s in (_ragged_suspension(), S.make_config(0)):
+        ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+        cfg = {"targets_per_thread": T, "block_threads": 128, "source_splits": splits, "source_staging": staging,
+               "accumulate": 2}
+        err, _ = rel_err(_run(V, s, "fp32c", cfg), ref)
+        say(f"mfma T={T} staging={staging} splits={splits}: {err:.3e}")
+        assert err <= BARS["fp32c"], err
+
+
+def test_matrix_core_accumulation_rejected_for_fp64(V):
+    s = S.make_config(0)
+    with pytest.raises(V.VesnetError):
+        _run(V, s, "fp64", {"accumulate": 2})
