@@ -27,9 +27,10 @@ import tempfile
 
 import numpy as np
 from scipy.optimize import brentq
+from scipy.spatial import cKDTree
 from scipy.special import ellipe
 
-GENERATOR_VERSION = 3
+GENERATOR_VERSION = 4
 BASE_SEED = 260625569
 PERIMETER = 2.0 * np.pi
 
@@ -145,13 +146,28 @@ def _extent(a, b, phi):
     return np.sqrt((a * c) ** 2 + (b * s) ** 2), np.sqrt((a * s) ** 2 + (b * c) ** 2)
 
 
+_UNIT = {}
+
+
+def _unit(n):
+    if n not in _UNIT:
+        th = 2.0 * np.pi * np.arange(n) / n
+        _UNIT[n] = (np.cos(th), np.sin(th))
+    return _UNIT[n]
+
+
 def _sample(center, a, b, phi, n):
-    return ellipse_curve(center, a, b, phi, n)[0].T  # (n, 2)
+    """(x, y) of n boundary points of a rotated ellipse (same points as ellipse_curve)."""
+    ct, st = _unit(n)
+    c, s = np.cos(phi), np.sin(phi)
+    ex, ey = a * ct, b * st
+    return center[0] + c * ex - s * ey, center[1] + s * ex + c * ey
 
 
 def _min_dist(p, q):
-    d = p[:, None, :] - q[None, :, :]
-    return float(np.sqrt(np.min(np.einsum("ijk,ijk->ij", d, d))))
+    dx = p[0][:, None] - q[0][None, :]
+    dy = p[1][:, None] - q[1][None, :]
+    return float(np.sqrt(np.min(dx * dx + dy * dy)))
 
 
 def rsa_pack(rng, axes, box, gap, max_tries=10_000_000):
@@ -192,34 +208,37 @@ def rsa_pack(rng, axes, box, gap, max_tries=10_000_000):
                 for dj in (-1, 0, 1):
                     nbrs.extend(grid.get((ci + di, cj + dj), ()))
             ok = True
-            cpts = None
-            fpts = None
+            close = []
             for u in nbrs:
-                dc = float(np.hypot(*(centers[u] - c)))
+                dc = float(np.hypot(centers[u, 0] - c[0], centers[u, 1] - c[1]))
                 if dc >= a + axes[u, 0] + gap:
                     continue
                 if dc < axes[u, 1] + b:  # inscribed circles overlap
                     ok = False
                     break
-                if cpts is None:
-                    cpts = _sample(c, a, b, phi, coarse_n)
-                if coarse_pts[u] is None:
-                    coarse_pts[u] = _sample(centers[u], axes[u, 0], axes[u, 1], angles[u], coarse_n)
-                dco = _min_dist(cpts, coarse_pts[u])
-                if dco < gap:
-                    ok = False
-                    break
-                margin_c = 0.5 * (a + axes[u, 0]) * 2.0 * np.pi / coarse_n
-                if dco - margin_c >= gap:
-                    continue
-                if fpts is None:
-                    fpts = _sample(c, a, b, phi, fine_n)
-                if fine_pts[u] is None:
-                    fine_pts[u] = _sample(centers[u], axes[u, 0], axes[u, 1], angles[u], fine_n)
-                margin_f = 0.5 * (a + axes[u, 0]) * 2.0 * np.pi / fine_n
-                if _min_dist(fpts, fine_pts[u]) - margin_f < gap:
-                    ok = False
-                    break
+                close.append(u)
+            if ok and close:
+                cpts = _sample(c, a, b, phi, coarse_n)
+                fpts = None
+                for u in close:
+                    if coarse_pts[u] is None:
+                        coarse_pts[u] = _sample(centers[u], axes[u, 0], axes[u, 1], angles[u], coarse_n)
+                    dco = _min_dist(cpts, coarse_pts[u])
+                    if dco < gap:
+                        ok = False
+                        break
+                    margin_c = 0.5 * (a + axes[u, 0]) * 2.0 * np.pi / coarse_n
+                    if dco - margin_c >= gap:
+                        continue
+                    if fpts is None:
+                        fpts = np.stack(_sample(c, a, b, phi, fine_n), axis=1)
+                    if fine_pts[u] is None:
+                        fine_pts[u] = cKDTree(np.stack(_sample(centers[u], axes[u, 0], axes[u, 1], angles[u],
+                                                               fine_n), axis=1))
+                    margin_f = 0.5 * (a + axes[u, 0]) * 2.0 * np.pi / fine_n
+                    if float(fine_pts[u].query(fpts, k=1)[0].min()) - margin_f < gap:
+                        ok = False
+                        break
             if ok:
                 centers[v] = c
                 angles[v] = phi
