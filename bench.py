@@ -27,6 +27,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(tile):
+    """HBM bytes per launch of the pair kernel from the committed rocprofv3 counter summary,
+    or None when the kernel source or the launch shape differs from the one measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_forward_fp32c_2000x128_counters.txt")
+    src = os.path.join(ROOT, "paper_2606_25569_amd", "csrc", "vesnet_kernels.hip")
+    try:
+        fields = {}
+        for line in open(path):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+        if fields.get("kernel_source_sha1") != sha or fields.get("tile") != tile:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -34,7 +54,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch shape instead of the library default")
     ap.add_argument("--tile", default=None,
                     help="T,B,splits[,staging]: fixed launch shape instead of the tuned one (staging 1 = SGPR, 2 = LDS)")
     ap.add_argument("--cpu-sample", type=float, default=0.03, help="fraction of targets the oracle evaluates")
@@ -89,15 +109,14 @@ def main():
     cfg = None
     if args.tile:
         vals = [int(x) for x in args.tile.split(",")]
-        cfg = V.TileConfig(vals[0], vals[1], vals[2], 1, vals[3] if len(vals) > 3 else 0)
-    elif not args.no_tune:
-        cfg = V.load_tuned(P, M, "fp32c")
-    if cfg is None and not args.no_tune and not args.tile:
+        cfg = V.TileConfig(vals[0], vals[1], vals[2], 1, vals[3] if len(vals) > 3 else 2, 1)
+    elif args.tune:
         t1 = time.time()
         cfg, tms = V.autotune(X, X, f, w, part, s.mu, "fp32c", repeats=2)
         log(f"[bench] autotuned {cfg.as_dict()} ({tms:.3f} ms) in {time.time() - t1:.1f}s")
     if cfg is None:
         cfg = V.default_config(P, M, "fp32c")
+    log(f"[bench] launch shape {cfg.as_dict()}")
     import ctypes
     cfg_ref = ctypes.byref(cfg)
     prec = V.FP32_COMPENSATED
@@ -181,6 +200,10 @@ def main():
 
     t_kernel = float(eval_ms.mean()) * 1e-3
     achieved = FLOPS_PER_PAIR * pairs / t_kernel / 1e12
+    d = cfg.as_dict()
+    tile_key = ",".join(str(d[k]) for k in ("targets_per_thread", "block_threads", "source_splits", "source_staging",
+                                            "accumulate"))
+    traffic = measured_traffic(tile_key)
     rec = {
         "metric": METRIC,
         "value": value,
@@ -201,7 +224,7 @@ def main():
                    "precision": "fp32-compensated (float32 pairs, float64 per-vesicle flush)",
                    "tile": cfg.as_dict()},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel": "k_forward (pair sum)", "kernel_ms": float(eval_ms.mean()),
                      "flops_per_pair": FLOPS_PER_PAIR},
         "cpu_baseline": cpu,

@@ -77,15 +77,19 @@ struct Shape {
   int T, B, splits, bpc, staging, accumulate;
 };
 
+// The default launch shape is the one the autotuner picks on the 2000 x 128 suspension
+// (T = 1, 256 threads, LDS staging, VALU accumulation) with enough source chunks for
+// about 64 waves per SIMD over the launch (at least 16 chunks would be needed at 256k
+// targets), which keeps the tail of the last wave round short.
 Shape default_shape(int32_t P, int32_t M, int prec) {
   Shape s;
-  s.T = prec == P64 ? 1 : 2;
+  s.T = 1;
   s.B = 256;
-  s.bpc = 2;
+  s.bpc = 4;
   s.staging = 2;
   s.accumulate = 1;
   const int64_t waves = ((int64_t)P + 64 * s.T - 1) / (64 * s.T);
-  const int64_t want = 8192;  // about 8 waves per SIMD on 256 CUs x 4 SIMDs
+  const int64_t want = 65536;
   int splits = 1;
   while (waves * splits < want && splits < 16) splits *= 2;
   s.splits = std::max(1, std::min<int>(splits, std::max(1, M)));
