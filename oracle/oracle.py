@@ -19,6 +19,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vesnet_oracle.c")
 _LIB = os.path.join(_HERE, "libvesnet_oracle.so")
+# A test may point this at a deliberately broken copy to check that the pins catch it.
+_LIB_OVERRIDE = os.environ.get("VESNET_ORACLE_LIB")
 _lib = None
 
 
@@ -35,8 +37,11 @@ def build(force: bool = False) -> str:
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            lib = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            build()
+            lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         I = ctypes.c_int64
         D = ctypes.c_double

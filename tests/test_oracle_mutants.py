@@ -1,0 +1,68 @@
+"""The pins have teeth: plausible mistakes planted in a copy of the oracle (on the
+CPU) must each make at least one pin of tests/test_oracle_pins.py fail."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "vesnet_oracle.c")
+
+# (name, original text, planted mistake) -- each original occurs in the forward sum
+MUTANTS = [
+    ("log sign", "ax += (long double)(w[j] * (-lnr * fx[j]", "ax += (long double)(w[j] * (+lnr * fx[j]"),
+    ("dropped rr-term", "ax += (long double)(w[j] * (-lnr * fx[j] + rdotf * rx / r2",
+     "ax += (long double)(w[j] * (-lnr * fx[j] + 0.0 * rdotf * rx / r2"),
+    ("rr-term component swap", "ay += (long double)(w[j] * (-lnr * fy[j] + rdotf * ry / r2",
+     "ay += (long double)(w[j] * (-lnr * fy[j] + rdotf * rx / r2"),
+    ("ln|r| taken as ln|r|^2", "const double lnr = 0.5 * log(r2);\n            const double rdotf = rx * fx[j]",
+     "const double lnr = log(r2);\n            const double rdotf = rx * fx[j]"),
+    ("prefactor 1/(8 pi mu)", "const double c = 1.0 / (4.0 * VO_PI * mu);\n    int bad = 0;\n#pragma omp parallel for schedule(dynamic, 4) reduction(|:bad)\n    for (int64_t k = 0; k < n_sel; ++k) {\n        const int64_t i = sel[k];\n        long double ax = 0.0L, ay = 0.0L;\n        for (int64_t j = 0; j < n_src; ++j) {\n            if (s_ves[j] == t_excl[i]) continue;\n            const double rx = tx[i] - sx[j];\n            const double ry = ty[i] - sy[j];\n            const double r2",
+     "const double c = 1.0 / (8.0 * VO_PI * mu);\n    int bad = 0;\n#pragma omp parallel for schedule(dynamic, 4) reduction(|:bad)\n    for (int64_t k = 0; k < n_sel; ++k) {\n        const int64_t i = sel[k];\n        long double ax = 0.0L, ay = 0.0L;\n        for (int64_t j = 0; j < n_src; ++j) {\n            if (s_ves[j] == t_excl[i]) continue;\n            const double rx = tx[i] - sx[j];\n            const double ry = ty[i] - sy[j];\n            const double r2"),
+    ("weights dropped", "ax += (long double)(w[j] * (-lnr", "ax += (long double)(1.0 * (-lnr"),
+    ("wrong vesicle excluded", "if (s_ves[j] == t_excl[i]) continue;\n            const double rx = tx[i] - sx[j];\n            const double ry = ty[i] - sy[j];\n            const double r2 = rx * rx + ry * ry;\n            if (r2 == 0.0) { bad = 1; continue; }\n            const double lnr = 0.5",
+     "if (s_ves[j] == t_excl[i] + 1) continue;\n            const double rx = tx[i] - sx[j];\n            const double ry = ty[i] - sy[j];\n            const double r2 = rx * rx + ry * ry;\n            if (r2 == 0.0) { bad = 1; continue; }\n            const double lnr = 0.5"),
+]
+
+
+# planted in the analytic gradient: caught by the central-difference and complex-step pins
+GRAD_MUTANTS = [
+    ("gradient: sign of the r r^T term", "- 2.0 * gr * rF * rx / (r2 * r2);", "+ 2.0 * gr * rF * rx / (r2 * r2);"),
+    ("gradient: dropped (g.F) term", "*ox = -gF * rx / r2 + (gx * rF", "*ox = 0.0 * gF * rx / r2 + (gx * rF"),
+    ("gradient: dL/dw without f", "grad_w[k] = fx[j] * v_x + fy[j] * v_y;", "grad_w[k] = v_x + v_y;"),
+]
+
+
+def _run_pins(tmp_path, orig, bad, select):
+    src = open(SRC).read()
+    assert src.count(orig) == 1, f"mutation anchor {orig!r} not unique"
+    mutant = tmp_path / "mutant.c"
+    mutant.write_text(src.replace(orig, bad))
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", str(lib), str(mutant), "-lm"])
+    env = dict(os.environ, VESNET_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    return subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                           os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", select],
+                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+@pytest.mark.parametrize("name,orig,bad", GRAD_MUTANTS, ids=[m[0] for m in GRAD_MUTANTS])
+def test_planted_gradient_mistake_is_caught(tmp_path, name, orig, bad):
+    r = _run_pins(tmp_path, orig, bad, "gradient or adjoint")
+    assert r.returncode != 0, f"no pin caught the planted mistake {name!r}:\n{r.stdout[-2000:]}"
+
+
+@pytest.mark.parametrize("name,orig,bad", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(tmp_path, name, orig, bad):
+    src = open(SRC).read()
+    assert src.count(orig) == 1, f"mutation anchor for {name!r} not unique"
+    mutant = tmp_path / "mutant.c"
+    mutant.write_text(src.replace(orig, bad))
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", str(lib), str(mutant), "-lm"])
+    env = dict(os.environ, VESNET_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", "not gradient and not adjoint"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"no pin caught the planted mistake {name!r}:\n{r.stdout[-2000:]}"
