@@ -136,6 +136,25 @@ VESNET_API int vesnet_farfield_stokeslet(const double* targets, const double* so
                               const vesnet_tile_config* cfg, void* workspace, size_t workspace_bytes,
                               void* stream);
 
+/* ------------------------------------------------------------------ membrane force */
+
+/* The step before the sum, on the device: the elastic force density of
+   eq. (elastic_force), f = -kappa_b X_ssss + (sigma X_s)_s, and the trapezoid
+   weights w = |X_alpha| 2 pi / N, with spectral arclength derivatives
+   d/ds = (1/|X_alpha|) d/dalpha (Section 2.2.1).  Each vesicle's N points are
+   read as the samples alpha_k = 2 pi k / N of a periodic curve; d/dalpha is exact
+   on their band-limited interpolant (the even-N Nyquist mode has zero
+   derivative).  Computed in float64.
+     X              : device [2][P] float64 membrane points
+     sigma          : device [P] float64 tension, or NULL for zero tension
+     force_density  : device [2][P] float64, overwritten (the sum's force_density)
+     arc_weights    : device [P] float64, overwritten (the sum's arc_weights)
+   Vesicles of more than 1024 points get NaN outputs; vesicles of fewer than 3
+   points have no tangent and give NaN as well. */
+VESNET_API int vesnet_elastic_force(const double* X, const double* sigma, double kappa_b,
+                                    const int32_t* vesicle_offsets, int32_t n_vesicles, int32_t n_points,
+                                    double* force_density, double* arc_weights, void* stream);
+
 /* ------------------------------------------------------------------ near field */
 
 /* The far field as the paper's direct evaluation masks it (Section 4.1) and the

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, "vesnet_kernels.hip"), os.path.join(CSRC, "vesnet_api.hip")]
+SOURCES = [os.path.join(CSRC, "vesnet_kernels.hip"), os.path.join(CSRC, "vesnet_spectral.hip"),
+           os.path.join(CSRC, "vesnet_api.hip")]
 LIB = os.path.join(HERE, "libvesnet.so")
 
 # Packed-FP32 VALU forms are disabled for every device compilation.

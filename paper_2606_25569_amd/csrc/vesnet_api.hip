@@ -272,6 +272,25 @@ extern "C" int vesnet_farfield_stokeslet(const double* targets, const double* so
   return vesnet_farfield_evaluate(targets, off, M, P, mu, out, prec, cfg, ws, ws_bytes, stream);
 }
 
+// ============================================================================ membrane force
+
+extern "C" int vesnet_elastic_force(const double* X, const double* sigma, double kappa_b, const int32_t* off,
+                                    int32_t M, int32_t P, double* f, double* w, void* stream) {
+  int rc = check_sizes(P, M);
+  if (rc) return rc;
+  if (!std::isfinite(kappa_b)) return fail(VESNET_ERR_INVALID_ARGUMENT, "kappa_b must be finite (got %g)", kappa_b);
+  if (P == 0) return ok();
+  if (!X || !off || !f || !w) return fail(VESNET_ERR_INVALID_ARGUMENT, "X, offsets, force and weights must be non-NULL");
+  const size_t vb = (size_t)2 * P * sizeof(double), sb = (size_t)P * sizeof(double);
+  if (overlaps(f, vb, X, vb) || overlaps(f, vb, sigma, sb) || overlaps(f, vb, w, sb) || overlaps(w, sb, X, vb) ||
+      overlaps(w, sb, sigma, sb) || overlaps(f, vb, off, (size_t)(M + 1) * sizeof(int32_t)) ||
+      overlaps(w, sb, off, (size_t)(M + 1) * sizeof(int32_t)))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "outputs overlap an input or each other");
+  hipError_t e = launch_elastic(X, sigma, kappa_b, off, M, P, f, w, stream);
+  if (e != hipSuccess) return hip_fail(e, "elastic force launch");
+  return ok();
+}
+
 // ============================================================================ near-field masked
 
 extern "C" int vesnet_farfield_stokeslet_nearmasked(const double* targets, const double* sources, const double* f,
@@ -414,29 +433,29 @@ extern "C" int vesnet_graph_create_batched(const double* targets, const double* 
   if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
   e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
-    hipStreamDestroy(st);
+    (void)hipStreamDestroy(st);
     return hip_fail(e, "hipStreamBeginCapture");
   }
   rc = enqueue_batched(targets, sources, f, w, off, M, P, sus_off, S, mu, out, prec, s, ws, st);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(st, &g);
   if (rc) {
-    if (g) hipGraphDestroy(g);
-    hipStreamDestroy(st);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(st);
     return rc;
   }
   if (e2 != hipSuccess) {
-    hipStreamDestroy(st);
+    (void)hipStreamDestroy(st);
     return hip_fail(e2, "hipStreamEndCapture");
   }
   hipGraphExec_t ex = nullptr;
   e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
-    hipGraphDestroy(g);
-    hipStreamDestroy(st);
+    (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(st);
     return hip_fail(e, "hipGraphInstantiate");
   }
-  hipStreamDestroy(st);
+  (void)hipStreamDestroy(st);
   vesnet_graph* h = new vesnet_graph{g, ex};
   *graph = h;
   return ok();
@@ -451,8 +470,8 @@ extern "C" int vesnet_graph_launch(vesnet_graph* graph, void* stream) {
 
 extern "C" int vesnet_graph_destroy(vesnet_graph* graph) {
   if (!graph) return ok();
-  hipGraphExecDestroy(graph->exec);
-  hipGraphDestroy(graph->graph);
+  (void)hipGraphExecDestroy(graph->exec);
+  (void)hipGraphDestroy(graph->graph);
   delete graph;
   return ok();
 }
@@ -581,7 +600,7 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
   if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
   e = hipEventCreate(&e1);
   if (e != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return hip_fail(e, "hipEventCreate");
   }
   float best_t = 1e30f;
@@ -597,14 +616,14 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
     if ((rc = run())) break;  // warm-up
     float tmin = 1e30f;
     for (int r = 0; r < repeats && rc == VESNET_OK; ++r) {
-      hipEventRecord(e0, st);
+      (void)hipEventRecord(e0, st);
       rc = run();
-      hipEventRecord(e1, st);
+      (void)hipEventRecord(e1, st);
       if (rc) break;
       e = hipEventSynchronize(e1);
       if (e != hipSuccess) { rc = hip_fail(e, "hipEventSynchronize"); break; }
       float ms = 0.f;
-      hipEventElapsedTime(&ms, e0, e1);
+      (void)hipEventElapsedTime(&ms, e0, e1);
       tmin = std::min(tmin, ms);
     }
     if (rc) break;
@@ -613,8 +632,8 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
       best_c = c;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (rc) return rc;
   *best = best_c;
   if (best_ms) *best_ms = best_t;

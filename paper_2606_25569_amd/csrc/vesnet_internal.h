@@ -35,6 +35,8 @@ hipError_t launch_forward(int prec, int T, int B, bool lds, bool mf, int splits,
 hipError_t launch_forward_near(int prec, int T, bool lds, int splits, const double* tg, int P, int M,
                                const PreparedView& pv, double scale, double* out, double* partial, int32_t* count,
                                int32_t* pairs, int32_t capacity, void* stream);
+hipError_t launch_elastic(const double* X, const double* sigma, double kappa_b, const int32_t* off, int M, int P,
+                          double* f, double* w, void* stream);
 hipError_t launch_plan(const int32_t* sus_off, int S, int M, const PreparedView& pv, int tile, const PlanView& pl,
                        void* stream);
 hipError_t launch_batched(int prec, int T, int B, bool lds, int grid, const double* tg, int P, int M,

@@ -1,0 +1,163 @@
+// Membrane force and trapezoid weights on gfx950: the step that produces the far-field
+// sum's inputs on the device.
+//
+//   f = -kappa_b X_ssss + (sigma X_s)_s            (eq. (elastic_force))
+//   w = |X_alpha| 2 pi / N                          (the ds of eq. (single_layer))
+//
+// Arclength derivatives are spectral (Section 2.2.1): d/ds = (1/|X_alpha|) d/dalpha with
+// d/dalpha exact on the band-limited interpolant of the N points alpha_k = 2 pi k / N.
+// On the grid that operator is the circulant matrix with first column
+//   d_0 = 0,  d_m = (1/2) (-1)^m cot(pi m / N)  (N even),  (1/2) (-1)^m csc(pi m / N)  (N odd),
+// which equals multiplying Fourier mode k by i k with the even-N Nyquist mode dropped.  For the
+// N <= 1024 points of one vesicle a workgroup applies it as a direct O(N^2) sum from LDS (a few
+// microseconds for a whole suspension, negligible beside the pair sum), in float64: the fourth
+// derivative amplifies rounding by up to (N/2)^4.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "vesnet_internal.h"
+
+namespace vesnet {
+
+namespace {
+
+constexpr int kMaxN = 1024;
+constexpr int kB = 256;
+constexpr int kPer = kMaxN / kB;
+
+__device__ __forceinline__ int clamp_i(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+// (D u)_i for the points this thread owns, u and d in LDS.
+__device__ __forceinline__ void apply_d(const double* __restrict__ d, const double* __restrict__ ux,
+                                        const double* __restrict__ uy, int n, double (&ox)[kPer],
+                                        double (&oy)[kPer]) {
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = threadIdx.x + k * kB;
+    double sx = 0.0, sy = 0.0;
+    if (i < n) {
+      int idx = i;  // (i - m) mod n, walking m = 0 .. n-1
+      for (int m = 0; m < n; ++m) {
+        const double c = d[m];
+        sx = fma(c, ux[idx], sx);
+        sy = fma(c, uy[idx], sy);
+        idx = idx == 0 ? n - 1 : idx - 1;
+      }
+    }
+    ox[k] = sx;
+    oy[k] = sy;
+  }
+}
+
+__global__ __launch_bounds__(kB) void k_elastic(const double* __restrict__ X, const double* __restrict__ sigma,
+                                                double kappa_b, const int32_t* __restrict__ off, int M, int P,
+                                                double* __restrict__ f, double* __restrict__ w) {
+  __shared__ double d[kMaxN];
+  __shared__ double ux[kMaxN];
+  __shared__ double uy[kMaxN];
+  const double two_pi = 6.28318530717958647693;
+  for (int v = blockIdx.x; v < M; v += gridDim.x) {
+    const int j0 = clamp_i(off[v], 0, P);
+    const int j1 = max(j0, clamp_i(off[v + 1], 0, P));
+    const int n = j1 - j0;
+    if (n == 0) continue;
+    if (n > kMaxN) {
+      for (int i = threadIdx.x; i < n; i += kB) {
+        f[j0 + i] = NAN;
+        f[P + j0 + i] = NAN;
+        w[j0 + i] = NAN;
+      }
+      continue;
+    }
+    __syncthreads();  // the previous vesicle is done with LDS
+    for (int m = threadIdx.x; m < n; m += kB) {
+      double c = 0.0;
+      if (m > 0) {
+        double s, co;
+        sincospi((double)m / (double)n, &s, &co);
+        const double sg = (m & 1) ? -0.5 : 0.5;
+        c = (n & 1) ? sg / s : sg * co / s;
+      }
+      d[m] = c;
+      ux[m] = X[j0 + m];
+      uy[m] = X[P + j0 + m];
+    }
+    __syncthreads();
+
+    double ax[kPer], ay[kPer], jinv[kPer], sx[kPer], sy[kPer], tx[kPer], ty[kPer], bx[kPer], by[kPer];
+    apply_d(d, ux, uy, n, ax, ay);  // X_alpha
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const double J = sqrt(ax[k] * ax[k] + ay[k] * ay[k]);
+      jinv[k] = 1.0 / J;
+      sx[k] = ax[k] * jinv[k];  // X_s
+      sy[k] = ay[k] * jinv[k];
+      const int i = threadIdx.x + k * kB;
+      if (i < n) w[j0 + i] = J * (two_pi / (double)n);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = threadIdx.x + k * kB;
+      if (i < n) { ux[i] = sx[k]; uy[i] = sy[k]; }
+    }
+    __syncthreads();
+    apply_d(d, ux, uy, n, bx, by);  // X_ss * J
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) { bx[k] *= jinv[k]; by[k] *= jinv[k]; }
+    // tension term (sigma X_s)_s
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) tx[k] = ty[k] = 0.0;
+    if (sigma) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int i = threadIdx.x + k * kB;
+        if (i < n) {
+          const double sg = sigma[j0 + i];
+          ux[i] = sg * sx[k];
+          uy[i] = sg * sy[k];
+        }
+      }
+      __syncthreads();
+      apply_d(d, ux, uy, n, tx, ty);
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) { tx[k] *= jinv[k]; ty[k] *= jinv[k]; }
+    }
+    // X_sss, then X_ssss
+    for (int pass = 0; pass < 2; ++pass) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        const int i = threadIdx.x + k * kB;
+        if (i < n) { ux[i] = bx[k]; uy[i] = by[k]; }
+      }
+      __syncthreads();
+      apply_d(d, ux, uy, n, bx, by);
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) { bx[k] *= jinv[k]; by[k] *= jinv[k]; }
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = threadIdx.x + k * kB;
+      if (i < n) {
+        f[j0 + i] = fma(-kappa_b, bx[k], tx[k]);
+        f[P + j0 + i] = fma(-kappa_b, by[k], ty[k]);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_elastic(const double* X, const double* sigma, double kappa_b, const int32_t* off, int M, int P,
+                          double* f, double* w, void* stream) {
+  if (M == 0 || P == 0) return hipSuccess;
+  const int grid = M < 65535 ? M : 65535;
+  hipLaunchKernelGGL(k_elastic, dim3(grid), dim3(kB), 0, reinterpret_cast<hipStream_t>(stream), X, sigma, kappa_b,
+                     off, M, P, f, w);
+  return hipGetLastError();
+}
+
+}  // namespace vesnet

@@ -150,6 +150,21 @@ def farfield_nearmasked(targets, sources, force_density, arc_weights, partition,
         cap = n
 
 
+def elastic_force(X, partition, kappa_b=1.0, sigma=None):
+    """Membrane force density f = -kappa_b X_ssss + (sigma X_s)_s and trapezoid weights
+    w = |X_alpha| 2 pi / N (spectral derivatives, float64): returns (f (2, P), w (P,))."""
+    part = as_partition(partition)
+    P, M = part.n_points, part.n_vesicles
+    _check_vec("X", X, P)
+    if sigma is not None:
+        _check_w(sigma, P)
+    f = torch.empty((2, P), dtype=torch.float64, device=X.device)
+    w = torch.empty((P,), dtype=torch.float64, device=X.device)
+    L.check(L.lib().vesnet_elastic_force(_ptr(X), _ptr(sigma), float(kappa_b), _ptr(part.device), M, P, _ptr(f),
+                                         _ptr(w), _stream()))
+    return f, w
+
+
 def farfield_backward(targets, sources, force_density, arc_weights, partition, mu, grad_out, precision="fp32c",
                       need=(True, True, True, True)):
     """Reverse mode: returns (grad_targets, grad_sources, grad_force, grad_weights), None where not needed."""

@@ -24,7 +24,7 @@ def _declared():
 def test_every_declared_symbol_is_exported(L):
     lib = L.lib()
     names = _declared()
-    assert len(names) == 17, names
+    assert len(names) == 18, names
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(L.EXPORTED)
@@ -160,6 +160,17 @@ def test_nearmasked_rejects(L):
     assert lib.vesnet_farfield_stokeslet_nearmasked(*base, None, 4, _p(FAKE + 0x800000), *ws) == -1      # no list
     assert lib.vesnet_farfield_stokeslet_nearmasked(*base, _p(FAKE + 0x700000), -1, _p(FAKE + 0x800000), *ws) == -1
     assert lib.vesnet_farfield_stokeslet_nearmasked(*base, _p(FAKE + 0x500000), 4, _p(FAKE + 0x800000), *ws) == -1
+
+
+def test_elastic_force_rejects(L):
+    lib = L.lib()
+    X, off, f, w = _p(FAKE), _p(FAKE + 0x100000), _p(FAKE + 0x200000), _p(FAKE + 0x300000)
+    assert lib.vesnet_elastic_force(X, None, float("nan"), off, 2, 10, f, w, None) == -1
+    assert lib.vesnet_elastic_force(None, None, 1.0, off, 2, 10, f, w, None) == -1
+    assert lib.vesnet_elastic_force(X, None, 1.0, off, 2, 10, None, w, None) == -1
+    assert lib.vesnet_elastic_force(X, None, 1.0, off, 2, 10, X, w, None) == -1          # f overlaps X
+    assert lib.vesnet_elastic_force(X, None, 1.0, off, 2, 10, f, _p(FAKE + 0x200000 + 8), None) == -1
+    assert lib.vesnet_elastic_force(None, None, 1.0, None, 0, 0, None, None, None) == 0
 
 
 def test_product_package_has_no_cpu_fallback():
