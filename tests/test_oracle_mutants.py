@@ -1,6 +1,7 @@
 """The pins have teeth: plausible mistakes planted in a copy of the oracle (on the
-CPU) must each make at least one pin of tests/test_oracle_pins.py fail."""
+CPU) must each make at least one of its pins fail."""
 import os
+import shutil
 import subprocess
 import sys
 
@@ -65,4 +66,47 @@ def test_planted_mistake_is_caught(tmp_path, name, orig, bad):
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", "not gradient and not adjoint"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"no pin caught the planted mistake {name!r}:\n{r.stdout[-2000:]}"
+
+
+# planted in the Python oracles: (name, module, original text, mistake, pin file)
+PY_MUTANTS = [
+    ("layers: inward normal", "nearfield_rbf.py", "normal = s * np.stack([t[1], -t[0]])",
+     "normal = -s * np.stack([t[1], -t[0]])", "test_oracle_rbf.py"),
+    ("layers: orientation ignored", "nearfield_rbf.py", "s = 1.0 if area >= 0.0 else -1.0", "s = 1.0",
+     "test_oracle_rbf.py"),
+    ("layers: h as the perimeter", "nearfield_rbf.py", "h = w.sum() / n", "h = w.sum()", "test_oracle_rbf.py"),
+    ("layers: reversed order", "nearfield_rbf.py", "LAYER_OFFSETS = (-1.0, -0.5, 0.0, 0.5, 1.0)",
+     "LAYER_OFFSETS = (1.0, 0.5, 0.0, -0.5, -1.0)", "test_oracle_rbf.py"),
+    ("rbf: width not squared", "nearfield_rbf.py", "np.exp(-r2 / (width * width))", "np.exp(-r2 / width)",
+     "test_oracle_rbf.py"),
+    ("rbf: back substitution with L", "nearfield_rbf.py", "solve_triangular(L.T, y, lower=False)",
+     "solve_triangular(L, y, lower=True)", "test_oracle_rbf.py"),
+    ("rbf: pairs not accumulated", "nearfield_rbf.py", "out[:, i] += vesicle_eval", "out[:, i] = vesicle_eval",
+     "test_oracle_rbf.py"),
+    ("spectral: derivative sign", "spectral.py", "1j * k * np.fft.fft(v", "-1j * k * np.fft.fft(v",
+     "test_oracle_spectral.py"),
+    ("spectral: tension without 1/J", "spectral.py", "tension = spectral_derivative(sigma * xs) / J",
+     "tension = spectral_derivative(sigma * xs)", "test_oracle_spectral.py"),
+    ("spectral: weights without 2 pi / N", "spectral.py", "J * (2.0 * np.pi / n)", "J",
+     "test_oracle_spectral.py"),
+]
+# Not listed: keeping the even-N Nyquist wavenumber in the spectral derivative.  For real
+# samples that mode's coefficient is real, so its derivative is purely imaginary and the real
+# part taken at the end drops it: the change leaves every output as it was.
+
+
+@pytest.mark.parametrize("name,module,orig,bad,pins", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_planted_python_oracle_mistake_is_caught(tmp_path, name, module, orig, bad, pins):
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    for f in ("__init__.py", "spectral.py", "nearfield_rbf.py"):
+        shutil.copy(os.path.join(ROOT, "oracle", f), pkg / f)
+    src = (pkg / module).read_text()
+    assert src.count(orig) == 1, f"mutation anchor for {name!r} not unique"
+    (pkg / module).write_text(src.replace(orig, bad))
+    env = dict(os.environ, VESNET_ORACLE_PY_ROOT=str(tmp_path))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", pins)], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
     assert r.returncode != 0, f"no pin caught the planted mistake {name!r}:\n{r.stdout[-2000:]}"
