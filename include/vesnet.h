@@ -181,6 +181,57 @@ VESNET_API int vesnet_farfield_stokeslet_nearmasked(const double* targets, const
                                                     const vesnet_tile_config* cfg, void* workspace,
                                                     size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------------------------------ near-field interpolation */
+
+/* CreateNearLayers of Algorithm 4 (Section 3.3): around each vesicle, five layers of target
+   points, its N_v membrane points moved along the outward unit normal by d_l = (l - 2) h_v / 2,
+   l = 0..4 (that is -h, -h/2, 0, h/2, h), with h_v = sum_j w_j / N_v the mean arclength spacing.
+   The tangent is X_alpha / |X_alpha| with the spectral derivative of vesnet_elastic_force; the
+   outward side follows from the sign of the enclosed signed area, so the points may run either
+   way round.  Computed in float64.
+     X          : device [2][P] float64 membrane points
+     arc_weights: device [P] float64 w
+     layers     : device [2][5P] float64, overwritten; node a = l N_v + k of vesicle v is stored
+                  at index 5 offsets[v] + a (x row, then y row at offset 5P)
+   Vesicles of more than 1024 or fewer than 3 points get NaN layers. */
+VESNET_API int vesnet_near_layers(const double* X, const double* arc_weights, const int32_t* vesicle_offsets,
+                                  int32_t n_vesicles, int32_t n_points, double* layers, void* stream);
+
+/* Workspace of vesnet_rbf_fit: one slot of packed 32 x 32 float64 tiles per concurrently
+   factored vesicle (at most 512 slots).  max_points bounds N_v (1 .. 256); returns 0 when
+   max_points or n_vesicles is out of range.  A smaller workspace of at least one slot also
+   works, with fewer vesicles factored at once. */
+VESNET_API size_t vesnet_rbf_workspace_bytes(int32_t max_points, int32_t n_vesicles);
+
+/* Gaussian radial basis interpolation of the layer velocities (Section 3.3): for each vesicle
+   the coefficients c of  s(x) = sum_a exp(-|x - x_a|^2 / (width h_v)^2) c_a  that reproduce the
+   velocities at its 5 N_v layer nodes, from K c = u with the symmetric positive definite Gaussian
+   matrix K, by Cholesky factorisation K = L L^T in float64 (the paper's batched Cholesky).  K is
+   ill-conditioned for wide Gaussians (condition about 2e8 at width 1 and N_v = 32): the values
+   of s are accurate to about that condition number times the float64 epsilon, the individual
+   coefficients may be much less so.  A vesicle whose K is not numerically positive definite, or
+   with N_v above max_points, gets NaN coefficients.
+     layers, layer_velocity : device [2][5P] float64 in the layout of vesnet_near_layers
+     width                  : Gaussian width in units of h_v (> 0; the paper gives no value)
+     coeffs                 : device [2][5P] float64, overwritten
+     workspace              : device, at least one slot (see vesnet_rbf_workspace_bytes) */
+VESNET_API int vesnet_rbf_fit(const double* layers, const double* layer_velocity, const double* arc_weights,
+                              const int32_t* vesicle_offsets, int32_t n_vesicles, int32_t n_points, int32_t max_points,
+                              double width, double* coeffs, void* workspace, size_t workspace_bytes, void* stream);
+
+/* interpolateInNearField of Algorithm 4: for each near pair k < min(*near_count, near_capacity),
+   (i, v) = (near_pairs[2k], near_pairs[2k+1]) as vesnet_farfield_stokeslet_nearmasked writes
+   them, adds vesicle v's interpolant at targets[:, i] into out[:, i].  Pairs whose indices fall
+   outside the problem are skipped.  The additions are atomic: a target near several vesicles
+   receives their contributions in an unspecified order (last-bit differences between runs).
+     targets : device [2][n_targets] float64
+     out     : device [2][n_targets] float64, accumulated into (u_far + u_near of Algorithm 4)
+   Other arguments as vesnet_rbf_fit. */
+VESNET_API int vesnet_rbf_eval_near(const double* layers, const double* coeffs, const double* arc_weights,
+                                    const int32_t* vesicle_offsets, int32_t n_vesicles, int32_t n_points, double width,
+                                    const double* targets, int32_t n_targets, const int32_t* near_pairs,
+                                    const int32_t* near_count, int32_t near_capacity, double* out, void* stream);
+
 /* ------------------------------------------------------------------ batched */
 
 /* S independent suspensions concatenated point-wise and vesicle-wise.

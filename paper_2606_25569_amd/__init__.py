@@ -8,8 +8,9 @@ _lib.lib()  # load now: no CPU fallback exists
 
 from .farfield import (BatchedProblem, Partition, autotune, default_config, elastic_force,  # noqa: E402
                        farfield_backward, farfield_forward, farfield_nearmasked, farfield_stokeslet, load_tuned,
-                       workspace_bytes)
+                       near_layers, rbf_eval_near, rbf_fit, workspace_bytes)
 
 __all__ = ["BatchedProblem", "Partition", "TileConfig", "VesnetError", "autotune", "default_config", "elastic_force",
-           "farfield_backward", "farfield_forward", "farfield_nearmasked", "farfield_stokeslet", "load_tuned", "workspace_bytes",
+           "farfield_backward", "farfield_forward", "farfield_nearmasked", "farfield_stokeslet", "load_tuned",
+           "near_layers", "rbf_eval_near", "rbf_fit", "workspace_bytes",
            "FP64", "FP32_COMPENSATED", "FP32_NAIVE"]

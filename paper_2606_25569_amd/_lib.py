@@ -24,7 +24,8 @@ EXPORTED = (
     "vesnet_farfield_stokeslet", "vesnet_batched_workspace_bytes", "vesnet_farfield_stokeslet_batched",
     "vesnet_graph_create_batched", "vesnet_graph_launch", "vesnet_graph_destroy",
     "vesnet_backward_workspace_bytes", "vesnet_farfield_stokeslet_backward", "vesnet_autotune",
-    "vesnet_farfield_stokeslet_nearmasked", "vesnet_elastic_force",
+    "vesnet_farfield_stokeslet_nearmasked", "vesnet_elastic_force", "vesnet_near_layers",
+    "vesnet_rbf_workspace_bytes", "vesnet_rbf_fit", "vesnet_rbf_eval_near",
 )
 
 
@@ -81,6 +82,10 @@ def lib():
         "vesnet_farfield_stokeslet_backward": ([P, P, P, P, P, I32, I32, D, P, P, P, P, P, INT, P, SZ, P], INT),
         "vesnet_farfield_stokeslet_nearmasked": ([P, P, P, P, P, I32, I32, D, P, P, I32, P, INT, CFG, P, SZ, P], INT),
         "vesnet_elastic_force": ([P, P, D, P, I32, I32, P, P, P], INT),
+        "vesnet_near_layers": ([P, P, P, I32, I32, P, P], INT),
+        "vesnet_rbf_workspace_bytes": ([I32, I32], SZ),
+        "vesnet_rbf_fit": ([P, P, P, P, I32, I32, I32, D, P, P, SZ, P], INT),
+        "vesnet_rbf_eval_near": ([P, P, P, P, I32, I32, D, P, I32, P, P, I32, P, P], INT),
         "vesnet_autotune": ([P, P, P, P, P, I32, I32, INT, P, I32, P, D, P, INT, INT, P, SZ, P, CFG,
                              ctypes.POINTER(ctypes.c_float)], INT),
     }

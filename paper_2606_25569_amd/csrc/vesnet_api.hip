@@ -291,6 +291,92 @@ extern "C" int vesnet_elastic_force(const double* X, const double* sigma, double
   return ok();
 }
 
+// ============================================================================ near-field interpolation
+
+namespace {
+
+constexpr int32_t kRbfMaxPoints = 256;  // 5 x 256 nodes per vesicle
+constexpr int kRbfMaxSlots = 512;       // two fit workgroups per compute unit
+
+int rbf_slots(int32_t M) { return M < kRbfMaxSlots ? (int)M : kRbfMaxSlots; }
+
+int check_width(double eps) {
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(VESNET_ERR_INVALID_ARGUMENT, "width must be > 0 and finite (got %g)", eps);
+  return VESNET_OK;
+}
+
+}  // namespace
+
+extern "C" int vesnet_near_layers(const double* X, const double* w, const int32_t* off, int32_t M, int32_t P,
+                                  double* layers, void* stream) {
+  int rc = check_sizes(P, M);
+  if (rc) return rc;
+  if (P == 0) return ok();
+  if (!X || !w || !off || !layers) return fail(VESNET_ERR_INVALID_ARGUMENT, "X, weights, offsets and layers must be non-NULL");
+  const size_t vb = (size_t)2 * P * sizeof(double), lb = (size_t)10 * P * sizeof(double);
+  if (overlaps(layers, lb, X, vb) || overlaps(layers, lb, w, (size_t)P * sizeof(double)) ||
+      overlaps(layers, lb, off, (size_t)(M + 1) * sizeof(int32_t)))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "layers overlap an input");
+  hipError_t e = launch_near_layers(X, w, off, M, P, layers, stream);
+  if (e != hipSuccess) return hip_fail(e, "near layers launch");
+  return ok();
+}
+
+extern "C" size_t vesnet_rbf_workspace_bytes(int32_t max_points, int32_t M) {
+  if (max_points < 1 || max_points > kRbfMaxPoints || M < 1) return 0;
+  return (size_t)rbf_slots(M) * rbf_slot_doubles(max_points) * sizeof(double);
+}
+
+extern "C" int vesnet_rbf_fit(const double* layers, const double* vel, const double* w, const int32_t* off, int32_t M,
+                              int32_t P, int32_t max_points, double width, double* coeffs, void* ws, size_t ws_bytes,
+                              void* stream) {
+  int rc = check_sizes(P, M);
+  if (rc) return rc;
+  if ((rc = check_width(width))) return rc;
+  if (P == 0) return ok();
+  if (max_points < 1 || max_points > kRbfMaxPoints)
+    return fail(VESNET_ERR_UNSUPPORTED, "max_points = %d outside 1..%d", max_points, kRbfMaxPoints);
+  if (!layers || !vel || !w || !off || !coeffs)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "layers, velocities, weights, offsets and coeffs must be non-NULL");
+  const size_t slot = rbf_slot_doubles(max_points) * sizeof(double);
+  if (!ws || ws_bytes < slot)
+    return fail(VESNET_ERR_WORKSPACE, "workspace of %zu bytes is below one slot (%zu bytes)", ws_bytes, slot);
+  const size_t lb = (size_t)10 * P * sizeof(double);
+  if (overlaps(coeffs, lb, layers, lb) || overlaps(coeffs, lb, vel, lb) ||
+      overlaps(coeffs, lb, w, (size_t)P * sizeof(double)) || overlaps(coeffs, lb, off, (size_t)(M + 1) * sizeof(int32_t)) ||
+      overlaps(coeffs, lb, ws, ws_bytes) || overlaps(ws, ws_bytes, layers, lb) || overlaps(ws, ws_bytes, vel, lb))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "coeffs or workspace overlap another array");
+  size_t slots = ws_bytes / slot;
+  if (slots > (size_t)rbf_slots(M)) slots = (size_t)rbf_slots(M);
+  hipError_t e = launch_rbf_fit(layers, vel, w, off, M, P, max_points, width, coeffs, static_cast<double*>(ws),
+                                (int)slots, stream);
+  if (e != hipSuccess) return hip_fail(e, "rbf fit launch");
+  return ok();
+}
+
+extern "C" int vesnet_rbf_eval_near(const double* layers, const double* coeffs, const double* w, const int32_t* off,
+                                    int32_t M, int32_t P, double width, const double* targets, int32_t n_targets,
+                                    const int32_t* near_pairs, const int32_t* near_count, int32_t near_capacity,
+                                    double* out, void* stream) {
+  int rc = check_sizes(P, M);
+  if (rc) return rc;
+  if ((rc = check_width(width))) return rc;
+  if (n_targets < 0 || n_targets > kMaxPoints) return fail(VESNET_ERR_INVALID_ARGUMENT, "n_targets = %d", n_targets);
+  if (near_capacity < 0) return fail(VESNET_ERR_INVALID_ARGUMENT, "near_capacity = %d < 0", near_capacity);
+  if (P == 0 || n_targets == 0 || near_capacity == 0) return ok();
+  if (!layers || !coeffs || !w || !off || !targets || !near_pairs || !near_count || !out)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "a required pointer is NULL");
+  const size_t ob = (size_t)2 * n_targets * sizeof(double), lb = (size_t)10 * P * sizeof(double);
+  if (overlaps(out, ob, layers, lb) || overlaps(out, ob, coeffs, lb) || overlaps(out, ob, targets, ob) ||
+      overlaps(out, ob, w, (size_t)P * sizeof(double)) || overlaps(out, ob, near_pairs, (size_t)2 * near_capacity * sizeof(int32_t)) ||
+      overlaps(out, ob, near_count, sizeof(int32_t)) || overlaps(out, ob, off, (size_t)(M + 1) * sizeof(int32_t)))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "out overlaps an input");
+  hipError_t e = launch_rbf_eval_near(layers, coeffs, w, off, M, P, width, targets, n_targets, near_pairs, near_count,
+                                      near_capacity, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "rbf evaluation launch");
+  return ok();
+}
+
 // ============================================================================ near-field masked
 
 extern "C" int vesnet_farfield_stokeslet_nearmasked(const double* targets, const double* sources, const double* f,
@@ -480,11 +566,11 @@ extern "C" int vesnet_graph_destroy(vesnet_graph* graph) {
 
 namespace {
 
-// Backward launch shape: two targets per thread in float32, one in float64, and
-// enough source chunks to give every SIMD several waves.
+// Backward launch shape: the forward default (one point per thread, 256 threads, LDS
+// staging, enough source chunks to give every SIMD many waves).
 Shape backward_shape(int32_t P, int32_t M, int prec) {
   Shape s = default_shape(P, M, prec);
-  s.T = prec == P64 ? 1 : 2;
+  s.T = 1;
   s.B = 256;
   return s;
 }

@@ -10,6 +10,18 @@ namespace vesnet {
 
 enum Prec { P64 = 0, P32C = 1, P32N = 2 };
 
+// Mean arclength spacing h_v = sum_j w_j / n of the n weights w[0..n-1], formed by one
+// whole wavefront (all 64 lanes call it with the same arguments) in a fixed order, so
+// that every kernel that needs h_v gets the same bits.
+__device__ inline double wave_mean_spacing(const double* __restrict__ w, int n) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += w[j];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+  return s / (double)n;
+}
+
 // Device views of a prepared workspace region.
 struct PreparedView {
   int2* vrange;    // [M]   clamped point range (j0, j1) of each vesicle
@@ -37,6 +49,16 @@ hipError_t launch_forward_near(int prec, int T, bool lds, int splits, const doub
                                int32_t* pairs, int32_t capacity, void* stream);
 hipError_t launch_elastic(const double* X, const double* sigma, double kappa_b, const int32_t* off, int M, int P,
                           double* f, double* w, void* stream);
+hipError_t launch_near_layers(const double* X, const double* w, const int32_t* off, int M, int P, double* layers,
+                              void* stream);
+// Gaussian RBF fit of every vesicle's five layers: the tile workspace holds `slots` regions of
+// rbf_slot_doubles(nmax) doubles, one per concurrently running workgroup.
+size_t rbf_slot_doubles(int nmax);
+hipError_t launch_rbf_fit(const double* layers, const double* vel, const double* w, const int32_t* off, int M, int P,
+                          int nmax, double eps, double* coeffs, double* tiles, int slots, void* stream);
+hipError_t launch_rbf_eval_near(const double* layers, const double* coeffs, const double* w, const int32_t* off,
+                                int M, int P, double eps, const double* targets, int n_targets,
+                                const int32_t* pairs, const int32_t* count, int capacity, double* out, void* stream);
 hipError_t launch_plan(const int32_t* sus_off, int S, int M, const PreparedView& pv, int tile, const PlanView& pl,
                        void* stream);
 hipError_t launch_batched(int prec, int T, int B, bool lds, int grid, const double* tg, int P, int M,

@@ -603,7 +603,7 @@ __global__ __launch_bounds__(B) void k_bwd_targets(const double* __restrict__ tg
   Acc<PREC> acc[T];
   int idx[T];
   bool valid[T];
-  gather<PREC, T, B, false, true, false>(i_begin, i_end, v_begin, v_end, tg, gout, nullptr, P, vid, vrange, vtab,
+  gather<PREC, T, B, false, true, true>(i_begin, i_end, v_begin, v_end, tg, gout, nullptr, P, vid, vrange, vtab,
                                          rec, acc, idx, valid);
 #pragma unroll
   for (int k = 0; k < T; ++k) {
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(B) void k_bwd_sources(const double* __restrict__ sr
   Acc<PREC> acc[T];
   int idx[T];
   bool valid[T];
-  gather<PREC, T, B, true, true, false>(i_begin, i_end, v_begin, v_end, src, f, w, P, vid, vrange, vtab, rec, acc,
+  gather<PREC, T, B, true, true, true>(i_begin, i_end, v_begin, v_end, src, f, w, P, vid, vrange, vtab, rec, acc,
                                         idx, valid);
 #pragma unroll
   for (int k = 0; k < T; ++k) {

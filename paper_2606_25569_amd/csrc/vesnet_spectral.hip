@@ -149,7 +149,97 @@ __global__ __launch_bounds__(kB) void k_elastic(const double* __restrict__ X, co
   }
 }
 
+// Sum of one value per thread over the workgroup in a fixed order (waves in index order).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  __syncthreads();  // red is free
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < kB / 64; ++k) s += red[k];
+  return s;
+}
+
+// CreateNearLayers (Algorithm 4, Section 3.3): node a = l * n + k of vesicle v is membrane point
+// k moved along the outward unit normal by d_l = (l - 2) h_v / 2, l = 0..4.  The tangent is the
+// spectral X_alpha / |X_alpha|; the outward side is fixed by the sign of the enclosed signed area
+// (trapezoid rule of (x y_alpha - y x_alpha) / 2), so either orientation of the points works.
+__global__ __launch_bounds__(kB) void k_near_layers(const double* __restrict__ X, const double* __restrict__ w,
+                                                    const int32_t* __restrict__ off, int M, int P,
+                                                    double* __restrict__ layers) {
+  __shared__ double d[kMaxN];
+  __shared__ double ux[kMaxN];
+  __shared__ double uy[kMaxN];
+  __shared__ double red[kB / 64];
+  const size_t P5 = (size_t)5 * P;
+  for (int v = blockIdx.x; v < M; v += gridDim.x) {
+    const int j0 = clamp_i(off[v], 0, P);
+    const int j1 = max(j0, clamp_i(off[v + 1], 0, P));
+    const int n = j1 - j0;
+    if (n == 0) continue;
+    double* lx = layers + (size_t)5 * j0;
+    double* ly = layers + P5 + (size_t)5 * j0;
+    if (n > kMaxN || n < 3) {
+      for (int a = threadIdx.x; a < 5 * n; a += kB) {
+        lx[a] = NAN;
+        ly[a] = NAN;
+      }
+      continue;
+    }
+    __syncthreads();  // the previous vesicle is done with LDS
+    for (int m = threadIdx.x; m < n; m += kB) {
+      double c = 0.0;
+      if (m > 0) {
+        double s, co;
+        sincospi((double)m / (double)n, &s, &co);
+        const double sg = (m & 1) ? -0.5 : 0.5;
+        c = (n & 1) ? sg / s : sg * co / s;
+      }
+      d[m] = c;
+      ux[m] = X[j0 + m];
+      uy[m] = X[P + j0 + m];
+    }
+    __syncthreads();
+    double ax[kPer], ay[kPer];
+    apply_d(d, ux, uy, n, ax, ay);  // X_alpha
+    double part = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = threadIdx.x + k * kB;
+      if (i < n) part += ux[i] * ay[k] - uy[i] * ax[k];
+    }
+    const double orient = block_sum(part, red) >= 0.0 ? 1.0 : -1.0;
+    const double h = wave_mean_spacing(w + j0, n);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = threadIdx.x + k * kB;
+      if (i < n) {
+        const double jinv = 1.0 / sqrt(ax[k] * ax[k] + ay[k] * ay[k]);
+        const double nx = orient * ay[k] * jinv;  // tangent turned clockwise: outward when counter-clockwise
+        const double ny = -orient * ax[k] * jinv;
+#pragma unroll
+        for (int l = 0; l < 5; ++l) {
+          const double dl = 0.5 * (double)(l - 2) * h;
+          lx[l * n + i] = fma(dl, nx, ux[i]);
+          ly[l * n + i] = fma(dl, ny, uy[i]);
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_near_layers(const double* X, const double* w, const int32_t* off, int M, int P, double* layers,
+                              void* stream) {
+  if (M == 0 || P == 0) return hipSuccess;
+  const int grid = M < 65535 ? M : 65535;
+  hipLaunchKernelGGL(k_near_layers, dim3(grid), dim3(kB), 0, reinterpret_cast<hipStream_t>(stream), X, w, off, M, P,
+                     layers);
+  return hipGetLastError();
+}
 
 hipError_t launch_elastic(const double* X, const double* sigma, double kappa_b, const int32_t* off, int M, int P,
                           double* f, double* w, void* stream) {

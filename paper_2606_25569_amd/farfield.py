@@ -165,6 +165,65 @@ def elastic_force(X, partition, kappa_b=1.0, sigma=None):
     return f, w
 
 
+def near_layers(X, arc_weights, partition):
+    """CreateNearLayers (Section 3.3): the five layers of every vesicle, membrane points moved along
+    the outward normal by (-h, -h/2, 0, h/2, h) h_v; returns (2, 5P) with vesicle v's 5 N_v nodes at
+    5 offsets[v] + l N_v + k."""
+    part = as_partition(partition)
+    P, M = part.n_points, part.n_vesicles
+    _check_vec("X", X, P)
+    _check_w(arc_weights, P)
+    layers = torch.empty((2, 5 * P), dtype=torch.float64, device=X.device)
+    L.check(L.lib().vesnet_near_layers(_ptr(X), _ptr(arc_weights), _ptr(part.device), M, P, _ptr(layers), _stream()))
+    return layers
+
+
+def _check_layers(name, t, P):
+    if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != (2, 5 * P):
+        raise ValueError(f"{name} must be a contiguous float64 tensor of shape (2, {5 * P})")
+
+
+def rbf_fit(layers, layer_velocity, arc_weights, partition, width=1.0, max_points=None):
+    """Gaussian RBF coefficients of every vesicle's layer velocities (batched Cholesky, float64).
+    The Gaussian of vesicle v is exp(-r^2 / (width h_v)^2); returns (2, 5P)."""
+    part = as_partition(partition)
+    P, M = part.n_points, part.n_vesicles
+    _check_layers("layers", layers, P)
+    _check_layers("layer_velocity", layer_velocity, P)
+    _check_w(arc_weights, P)
+    nmax = int(part.sizes().max()) if max_points is None and M > 0 else int(max_points or 1)
+    coeffs = torch.empty_like(layer_velocity)
+    if P == 0:
+        return coeffs
+    ws = _workspace(L.lib().vesnet_rbf_workspace_bytes(nmax, M), layers.device)
+    L.check(L.lib().vesnet_rbf_fit(_ptr(layers), _ptr(layer_velocity), _ptr(arc_weights), _ptr(part.device), M, P,
+                                   nmax, float(width), _ptr(coeffs), _ptr(ws), ws.numel(), _stream()))
+    return coeffs
+
+
+def rbf_eval_near(layers, coeffs, arc_weights, partition, targets, near_pairs, out, width=1.0, near_count=None):
+    """interpolateInNearField (Algorithm 4): out[:, i] += s_v(targets[:, i]) for every near pair
+    (i, v) in near_pairs (int32 (capacity, 2)).  near_count, a device int32 tensor of one element,
+    limits the pairs read; by default all rows of near_pairs are used."""
+    part = as_partition(partition)
+    P, M = part.n_points, part.n_vesicles
+    _check_layers("layers", layers, P)
+    _check_layers("coeffs", coeffs, P)
+    _check_w(arc_weights, P)
+    nt = targets.shape[1]
+    _check_vec("targets", targets, nt)
+    _check_vec("out", out, nt)
+    if near_pairs.dtype != torch.int32 or not near_pairs.is_contiguous():
+        raise ValueError("near_pairs must be a contiguous int32 tensor")
+    cap = near_pairs.numel() // 2
+    if near_count is None:
+        near_count = torch.full((1,), cap, dtype=torch.int32, device=out.device)
+    L.check(L.lib().vesnet_rbf_eval_near(_ptr(layers), _ptr(coeffs), _ptr(arc_weights), _ptr(part.device), M, P,
+                                         float(width), _ptr(targets), nt, _ptr(near_pairs), _ptr(near_count), cap,
+                                         _ptr(out), _stream()))
+    return out
+
+
 def farfield_backward(targets, sources, force_density, arc_weights, partition, mu, grad_out, precision="fp32c",
                       need=(True, True, True, True)):
     """Reverse mode: returns (grad_targets, grad_sources, grad_force, grad_weights), None where not needed."""

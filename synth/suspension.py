@@ -309,6 +309,20 @@ def rsa_suspension(seed, m, n, phi, nu=0.65, gap=0.1, force_kind="k4", net_force
     return _assemble(rng, centers, axes, angles, n, force_kind, net_force_std, mu, box)
 
 
+def smooth_field(seed, points, n_modes=8, length=4.0):
+    """A seeded smooth random vector field at points (2, Q): a sum of n_modes plane waves
+    a_m cos(k_m . x + p_m) with wavelengths between length and 2 length.  Stands in for the
+    layer velocities that the paper's near-field networks predict."""
+    rng = np.random.default_rng(seed)
+    ang = rng.uniform(0.0, 2.0 * np.pi, n_modes)
+    kmag = 2.0 * np.pi / (length * rng.uniform(1.0, 2.0, n_modes))
+    k = kmag[:, None] * np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    amp = rng.normal(size=(2, n_modes))
+    phase = rng.uniform(0.0, 2.0 * np.pi, n_modes)
+    pts = np.asarray(points, dtype=np.float64)
+    return amp @ np.cos(k @ pts + phase[:, None])
+
+
 def batch_of(members, mus=None) -> Batch:
     X = np.concatenate([s.X for s in members], axis=1)
     f = np.concatenate([s.f for s in members], axis=1)

@@ -24,3 +24,21 @@ def dev_inputs(s, device="cuda"):
 def say(*args):
     print(*args, flush=True)
     sys.stdout.flush()
+
+
+def near_margin(s):
+    """Smallest |d_iv - h_v| / h_v over all (target, other vesicle) of a suspension: near-field
+    decisions closer than float32 rounding may legitimately differ between the GPU and the
+    oracle, so test inputs must stay clear of it."""
+    from oracle import oracle as O
+    vid = O.vesicle_ids(s.offsets)
+    worst = np.inf
+    for v in range(s.n_vesicles):
+        a, b = s.offsets[v], s.offsets[v + 1]
+        if b == a:
+            continue
+        h = s.w[a:b].sum() / (b - a)
+        d = np.sqrt(((s.X[:, :, None] - s.X[:, None, a:b]) ** 2).sum(axis=0)).min(axis=1)
+        m = np.abs(d - h)[vid != v] / h
+        worst = min(worst, float(m.min()))
+    return worst

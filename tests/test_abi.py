@@ -24,7 +24,7 @@ def _declared():
 def test_every_declared_symbol_is_exported(L):
     lib = L.lib()
     names = _declared()
-    assert len(names) == 18, names
+    assert len(names) == 22, names
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(L.EXPORTED)
@@ -171,6 +171,44 @@ def test_elastic_force_rejects(L):
     assert lib.vesnet_elastic_force(X, None, 1.0, off, 2, 10, X, w, None) == -1          # f overlaps X
     assert lib.vesnet_elastic_force(X, None, 1.0, off, 2, 10, f, _p(FAKE + 0x200000 + 8), None) == -1
     assert lib.vesnet_elastic_force(None, None, 1.0, None, 0, 0, None, None, None) == 0
+
+
+def test_near_layers_and_rbf_reject(L):
+    lib = L.lib()
+    X, off, w, lay = _p(FAKE), _p(FAKE + 0x100000), _p(FAKE + 0x200000), _p(FAKE + 0x300000)
+    vel, co, ws, tg = _p(FAKE + 0x400000), _p(FAKE + 0x500000), _p(FAKE + 0x600000), _p(FAKE + 0x8000000)
+    pairs, cnt, out = _p(FAKE + 0x9000000), _p(FAKE + 0x9100000), _p(FAKE + 0x9200000)
+    # layers: NULLs, overlap with X (10P doubles from X's start)
+    assert lib.vesnet_near_layers(None, w, off, 2, 10, lay, None) == -1
+    assert lib.vesnet_near_layers(X, w, off, 2, 10, None, None) == -1
+    assert lib.vesnet_near_layers(X, w, off, 2, 10, _p(FAKE + 8), None) == -1
+    assert lib.vesnet_near_layers(None, None, None, 0, 0, None, None) == 0
+    # workspace query: out-of-range max_points or vesicle count gives 0
+    assert lib.vesnet_rbf_workspace_bytes(0, 4) == 0
+    assert lib.vesnet_rbf_workspace_bytes(257, 4) == 0
+    assert lib.vesnet_rbf_workspace_bytes(32, 0) == 0
+    slot = lib.vesnet_rbf_workspace_bytes(32, 1)
+    assert slot > 0 and lib.vesnet_rbf_workspace_bytes(32, 4) == 4 * slot
+    assert lib.vesnet_rbf_workspace_bytes(32, 100000) == 512 * slot
+    fit = lambda **k: lib.vesnet_rbf_fit(k.get("lay", lay), vel, w, off, 2, 10, k.get("nmax", 32),
+                                         k.get("width", 1.0), k.get("co", co), k.get("ws", ws),
+                                         k.get("wsb", slot), None)
+    assert fit(width=0.0) == -1
+    assert fit(width=float("inf")) == -1
+    assert fit(nmax=300) == -2
+    assert fit(lay=None) == -1
+    assert fit(wsb=slot - 1) == -3
+    assert fit(ws=None) == -3
+    assert fit(co=_p(FAKE + 0x400000 + 8)) == -1   # coeffs overlap the velocities
+    assert fit(ws=_p(FAKE + 0x500000 + 64)) == -1  # workspace overlaps coeffs
+    ev = lambda **k: lib.vesnet_rbf_eval_near(lay, co, w, off, 2, 10, k.get("width", 1.0), tg, k.get("nt", 10),
+                                              pairs, cnt, k.get("cap", 16), k.get("out", out), None)
+    assert ev(width=-1.0) == -1
+    assert ev(cap=-1) == -1
+    assert ev(nt=-3) == -1
+    assert ev(out=None) == -1
+    assert ev(out=_p(FAKE + 0x8000000 + 8)) == -1  # out overlaps the targets
+    assert ev(cap=0) == 0 and ev(nt=0) == 0
 
 
 def test_product_package_has_no_cpu_fallback():

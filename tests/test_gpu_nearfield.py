@@ -4,25 +4,9 @@ import pytest
 
 from oracle import oracle as O
 from synth import suspension as S
-from tests.gpu_util import dev_inputs, rel_err, say
+from tests.gpu_util import dev_inputs, near_margin, rel_err, say
 
 pytestmark = pytest.mark.gpu
-
-
-def _margins(s, pairs_tol=1e-5):
-    """Smallest |d_iv - h_v| / h_v over all (target, other vesicle): decisions closer than
-    float32 rounding may legitimately differ, so the test inputs must stay clear of it."""
-    vid = O.vesicle_ids(s.offsets)
-    worst = np.inf
-    for v in range(s.n_vesicles):
-        a, b = s.offsets[v], s.offsets[v + 1]
-        if b == a:
-            continue
-        h = s.w[a:b].sum() / (b - a)
-        d = np.sqrt(((s.X[:, :, None] - s.X[:, None, a:b]) ** 2).sum(axis=0)).min(axis=1)
-        m = np.abs(d - h)[vid != v] / h
-        worst = min(worst, float(m.min()))
-    return worst
 
 
 @pytest.mark.parametrize("T,staging,splits", [(1, 1, 1), (2, 2, 1), (2, 1, 3), (1, 2, 4)])
@@ -30,7 +14,7 @@ def test_nearmasked_parity(T, staging, splits):
     import torch
     import paper_2606_25569_amd as V
     s = S.rsa_suspension(33, 120, 32, 0.40, gap=0.02)
-    assert _margins(s) > 1e-5
+    assert near_margin(s) > 1e-5
     ref, pairs_ref = O.nearmasked_suspension(s.X, s.f, s.w, s.offsets, s.mu)
     assert pairs_ref.shape[0] > 20
     X, f, w = dev_inputs(s)
