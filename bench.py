@@ -58,8 +58,8 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="T,B,splits[,staging]: fixed launch shape instead of the tuned one (staging 1 = SGPR, 2 = LDS)")
     ap.add_argument("--cpu-sample", type=float, default=0.03, help="fraction of targets the oracle evaluates")
-    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "adjoint"],
-                    help="dense: the benchmark line; batched / adjoint: the other forms, reported separately")
+    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "adjoint", "nearfield"],
+                    help="dense: the benchmark line; batched / adjoint / nearfield: the other forms, reported separately")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -85,6 +85,8 @@ def main():
         return bench_batched(args)
     if args.workload == "adjoint":
         return bench_adjoint(args)
+    if args.workload == "nearfield":
+        return bench_nearfield(args)
 
     import paper_2606_25569_amd as V
     from synth import suspension as S
@@ -332,6 +334,97 @@ def bench_adjoint(args):
         rec[prec] = {"forward_ms": tf, "backward_ms": tb, "forward_pairs_per_s": pairs / (tf * 1e-3),
                      "backward_pairs_per_s": pairs / (tb * 1e-3)}
         log(f"[bench] adjoint {prec}: forward {tf:.3f} ms, backward {tb:.3f} ms")
+    print(json.dumps(rec), flush=True)
+
+
+def bench_nearfield(args):
+    """Algorithm 4 with the layer velocities given (the paper predicts them with networks):
+    masked far field with near-pair detection, five layers, Gaussian RBF fit by batched
+    Cholesky, interpolation at the near pairs; 2000 vesicles x 32 points at 30% area fraction."""
+    import numpy as np
+    import torch
+
+    import paper_2606_25569_amd as V
+    from paper_2606_25569_amd import _lib as L
+    from paper_2606_25569_amd.farfield import _ptr
+    from synth import suspension as S
+
+    t0 = time.time()
+    s = S.rsa_suspension(S.config_seed(5), 2000, 32, 0.30)
+    P, M, N = s.n_points, s.n_vesicles, 32
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    X = torch.tensor(s.X, device=dev)
+    f = torch.tensor(s.f, device=dev)
+    w = torch.tensor(s.w, device=dev)
+    part = V.Partition(s.offsets, dev)
+    lib = L.lib()
+    prec = L.precision_code("fp32c")
+    ws = torch.empty(V.workspace_bytes(P, M, "fp32c"), dtype=torch.uint8, device=dev)
+    out = torch.empty((2, P), dtype=torch.float64, device=dev)
+    cap = 8 * P
+    pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    layers = torch.empty((2, 5 * P), dtype=torch.float64, device=dev)
+    coeffs = torch.empty_like(layers)
+    rws = torch.empty(lib.vesnet_rbf_workspace_bytes(N, M), dtype=torch.uint8, device=dev)
+    width = 1.0
+
+    def far():
+        L.check(lib.vesnet_farfield_stokeslet_nearmasked(_ptr(X), _ptr(X), _ptr(f), _ptr(w), _ptr(part.device), M, P,
+                                                         s.mu, _ptr(out), _ptr(pairs), cap, _ptr(count), prec, None,
+                                                         _ptr(ws), ws.numel(), sp))
+
+    def lay():
+        L.check(lib.vesnet_near_layers(_ptr(X), _ptr(w), _ptr(part.device), M, P, _ptr(layers), sp))
+
+    far()
+    lay()
+    torch.cuda.synchronize()
+    n_near = int(count.item())
+    assert n_near <= cap
+    vel = torch.tensor(S.smooth_field(S.config_seed(5, 1), layers.cpu().numpy()), device=dev)
+
+    def fit():
+        L.check(lib.vesnet_rbf_fit(_ptr(layers), _ptr(vel), _ptr(w), _ptr(part.device), M, P, N, width, _ptr(coeffs),
+                                   _ptr(rws), rws.numel(), sp))
+
+    def ev():
+        L.check(lib.vesnet_rbf_eval_near(_ptr(layers), _ptr(coeffs), _ptr(w), _ptr(part.device), M, P, width, _ptr(X),
+                                         P, _ptr(pairs), _ptr(count), cap, _ptr(out), sp))
+
+    def step():
+        far()
+        lay()
+        fit()
+        ev()
+
+    log(f"[bench] nearfield 2000x32: P={P}, {n_near} near pairs ({time.time() - t0:.1f}s)")
+    times = {k: _time(fn, args.steps, stream) for k, fn in
+             (("far_masked", far), ("layers", lay), ("rbf_fit", fit), ("rbf_eval", ev), ("step", step))}
+    n = 5 * N
+    fit_flops = M * (n ** 3 / 3 + 4 * n * n)  # Cholesky and two triangular solves of two right-hand sides
+    pairs_far = s.cross_pairs()
+    # the oracle's fit (numpy Cholesky) of a sample of vesicles, for context
+    from oracle import nearfield_rbf as NR
+    lay_h = layers.cpu().numpy()
+    vel_h = vel.cpu().numpy()
+    sample = 100
+    tc = time.time()
+    for v in range(sample):
+        a, b = 5 * s.offsets[v], 5 * s.offsets[v + 1]
+        NR.vesicle_fit(lay_h[:, a:b], vel_h[:, a:b], width * s.w[s.offsets[v]:s.offsets[v + 1]].mean())
+    cpu_fit_vps = sample / (time.time() - tc)
+    rec = {"workload": "near field: 2000 vesicles x 32 points at 30% area fraction (gap >= 0.1 < h), "
+                       "FP32-compensated masked far field + FP64 layers, RBF fit (width h) and interpolation",
+           "n_points": P, "near_pairs": n_near, "ms": times,
+           "far_masked_pairs_per_s": pairs_far / (times["far_masked"] * 1e-3),
+           "rbf_fit": {"vesicles_per_s": M / (times["rbf_fit"] * 1e-3), "algorithmic_tflops_fp64": fit_flops / (times["rbf_fit"] * 1e-3) / 1e12,
+                       "frac_of_fp64_peak": fit_flops / (times["rbf_fit"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                       "oracle_numpy_vesicles_per_s": cpu_fit_vps},
+           "rbf_eval_pairs_per_s": n_near / (times["rbf_eval"] * 1e-3)}
+    log(f"[bench] nearfield: " + ", ".join(f"{k} {v:.3f} ms" for k, v in times.items()))
     print(json.dumps(rec), flush=True)
 
 

@@ -62,7 +62,7 @@ __device__ __forceinline__ double bordered_entry(const NodeView& nv, int row, in
   return exp(-(dx * dx + dy * dy) * nv.inv_w2);
 }
 
-__global__ __launch_bounds__(kFB) void k_rbf_fit(const double* __restrict__ layers, const double* __restrict__ vel,
+__global__ __launch_bounds__(kFB, 2) void k_rbf_fit(const double* __restrict__ layers, const double* __restrict__ vel,
                                                  const double* __restrict__ w, const int32_t* __restrict__ off,
                                                  int M, int P, int nmax, double eps, double* __restrict__ coeffs,
                                                  double* __restrict__ tiles, size_t slot_doubles) {
@@ -149,27 +149,26 @@ __global__ __launch_bounds__(kFB) void k_rbf_fit(const double* __restrict__ laye
         }
         __syncthreads();
         if (I0 == J) {
-          // unblocked Cholesky of the diagonal tile (chunk rows 0..31), in place
+          // unblocked Cholesky of the diagonal tile (chunk rows 0..31), in place.  Step c updates the
+          // trailing lower triangle with the unscaled column c and the pivot A_cc (one barrier per
+          // step); the columns are scaled by 1 / sqrt(pivot) once all steps are done.
           for (int c = 0; c < kT; ++c) {
-            const double dcc = sqrt(A[c * kLd + c]);
-            if (tid > c && tid < kT) A[tid * kLd + c] /= dcc;
-            __syncthreads();
-            if (tid == 0) {
-              A[c * kLd + c] = dcc;
-              dinv[c] = 1.0 / dcc;
-            }
-            // trailing update of rows/columns c+1..31 (lower part only)
+            const double rp = 1.0 / A[c * kLd + c];
             for (int e = tid; e < kT * kT; e += kFB) {
-              const int r = e >> 5, s = e & 31;
-              if (s > c && r >= s) A[r * kLd + s] = fma(-A[r * kLd + c], A[s * kLd + c], A[r * kLd + s]);
+              const int r = e >> 5, s2 = e & 31;
+              if (s2 > c && r >= s2) A[r * kLd + s2] = fma(-A[r * kLd + c] * rp, A[s2 * kLd + c], A[r * kLd + s2]);
             }
             __syncthreads();
           }
+          if (tid < kT) dinv[tid] = 1.0 / sqrt(A[tid * kLd + tid]);
+          __syncthreads();
           for (int e = tid; e < kT * kT; e += kFB) {
-            const int r = e >> 5, s = e & 31;
-            if (s > r) A[r * kLd + s] = 0.0;
-            Ljj[r * kLd + s] = s > r ? 0.0 : A[r * kLd + s];
+            const int r = e >> 5, s2 = e & 31;
+            const double l = s2 > r ? 0.0 : A[r * kLd + s2] * dinv[s2];
+            Ljj[r * kLd + s2] = l;
           }
+          __syncthreads();
+          for (int e = tid; e < kT * kT; e += kFB) A[(e >> 5) * kLd + (e & 31)] = Ljj[(e >> 5) * kLd + (e & 31)];
           __syncthreads();
         }
         // triangular solve of the chunk's other rows: x L_jj^T = t, one thread per row
@@ -179,12 +178,13 @@ __global__ __launch_bounds__(kFB) void k_rbf_fit(const double* __restrict__ laye
           double x[kT];
 #pragma unroll
           for (int c = 0; c < kT; ++c) x[c] = A[r * kLd + c];
+          // column by column: x_c is final once scaled, then removed from the later unknowns
+          // (independent updates rather than one dependent chain per unknown)
 #pragma unroll
           for (int c = 0; c < kT; ++c) {
-            double t = x[c];
+            x[c] *= dinv[c];
 #pragma unroll
-            for (int m = 0; m < c; ++m) t = fma(-x[m], Ljj[c * kLd + m], t);
-            x[c] = t * dinv[c];
+            for (int m = c + 1; m < kT; ++m) x[m] = fma(-x[c], Ljj[m * kLd + c], x[m]);
           }
 #pragma unroll
           for (int c = 0; c < kT; ++c) A[r * kLd + c] = x[c];
