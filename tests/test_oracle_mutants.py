@@ -84,6 +84,21 @@ PY_MUTANTS = [
      "solve_triangular(L, y, lower=True)", "test_oracle_rbf.py"),
     ("rbf: pairs not accumulated", "nearfield_rbf.py", "out[:, i] += vesicle_eval", "out[:, i] = vesicle_eval",
      "test_oracle_rbf.py"),
+    ("treecode: log term sign", "treecode.py", "logpart = -MF[..., 0] * np.log(np.abs(w))",
+     "logpart = MF[..., 0] * np.log(np.abs(w))", "test_oracle_treecode.py"),
+    ("treecode: series index off by one", "treecode.py", "np.sum(MF[..., 1:] / k * tk[..., 1:p + 1], axis=-1)",
+     "np.sum(MF[..., 1:] / (k + 1) * tk[..., 1:p + 1], axis=-1)", "test_oracle_treecode.py"),
+    ("treecode: Psi not conjugated", "treecode.py", "0.5 * (w * np.conj(Phi) - np.conj(Psi))",
+     "0.5 * (w * np.conj(Phi) - Psi)", "test_oracle_treecode.py"),
+    ("treecode: dropped constant term", "treecode.py", "series + 0.5 * MF[..., 0] + 0.5",
+     "series + 0.5", "test_oracle_treecode.py"),
+    ("treecode: conj(zeta) taken about the origin", "treecode.py",
+     "MPsi = box_moments(z, np.conj(zeta) * F,", "MPsi = box_moments(z, np.conj(z) * F,", "test_oracle_treecode.py"),
+    ("treecode: adjacent boxes in the interaction list", "treecode.py",
+     "((np.abs(sx - bx) > 1) | (np.abs(sy - by) > 1))\n            if not ok.any():",
+     "((np.abs(sx - bx) > 0) | (np.abs(sy - by) > 0))\n            if not ok.any():", "test_oracle_treecode.py"),
+    ("treecode: own vesicle not subtracted", "treecode.py", "u[a:b] -= direct_terms(", "u[a:b] += 0 * direct_terms(",
+     "test_oracle_treecode.py"),
     ("spectral: derivative sign", "spectral.py", "1j * k * np.fft.fft(v", "-1j * k * np.fft.fft(v",
      "test_oracle_spectral.py"),
     ("spectral: tension without 1/J", "spectral.py", "tension = spectral_derivative(sigma * xs) / J",
@@ -100,8 +115,10 @@ PY_MUTANTS = [
 def test_planted_python_oracle_mistake_is_caught(tmp_path, name, module, orig, bad, pins):
     pkg = tmp_path / "oracle"
     pkg.mkdir()
-    for f in ("__init__.py", "spectral.py", "nearfield_rbf.py"):
-        shutil.copy(os.path.join(ROOT, "oracle", f), pkg / f)
+    for f in ("__init__.py", "spectral.py", "nearfield_rbf.py", "treecode.py", "oracle.py", "vesnet_oracle.c",
+              "libvesnet_oracle.so"):
+        if os.path.exists(os.path.join(ROOT, "oracle", f)):
+            shutil.copy2(os.path.join(ROOT, "oracle", f), pkg / f)  # keeps mtimes: no rebuild of the C oracle
     src = (pkg / module).read_text()
     assert src.count(orig) == 1, f"mutation anchor for {name!r} not unique"
     (pkg / module).write_text(src.replace(orig, bad))
