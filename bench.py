@@ -58,8 +58,9 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="T,B,splits[,staging]: fixed launch shape instead of the tuned one (staging 1 = SGPR, 2 = LDS)")
     ap.add_argument("--cpu-sample", type=float, default=0.03, help="fraction of targets the oracle evaluates")
-    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "adjoint", "nearfield"],
-                    help="dense: the benchmark line; batched / adjoint / nearfield: the other forms, reported separately")
+    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "adjoint", "nearfield", "treecode"],
+                    help="dense: the benchmark line; batched / adjoint / nearfield / treecode: the other forms, "
+                         "reported separately")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -87,6 +88,8 @@ def main():
         return bench_adjoint(args)
     if args.workload == "nearfield":
         return bench_nearfield(args)
+    if args.workload == "treecode":
+        return bench_treecode(args)
 
     import paper_2606_25569_amd as V
     from synth import suspension as S
@@ -425,6 +428,88 @@ def bench_nearfield(args):
                        "oracle_numpy_vesicles_per_s": cpu_fit_vps},
            "rbf_eval_pairs_per_s": n_near / (times["rbf_eval"] * 1e-3)}
     log(f"[bench] nearfield: " + ", ".join(f"{k} {v:.3f} ms" for k, v in times.items()))
+    print(json.dumps(rec), flush=True)
+
+
+def _treecode_work(X, sizes, depth):
+    """Work of one treecode evaluation from its tree: (target, non-empty far box) evaluations and
+    direct pairs with other vesicles' points in the 3 x 3 leaves (own vesicle assumed inside them)."""
+    import numpy as np
+    x, y = X
+    side = max(x.max() - x.min(), y.max() - y.min())
+    x0 = 0.5 * (x.min() + x.max()) - 0.5 * side
+    y0 = 0.5 * (y.min() + y.max()) - 0.5 * side
+    n = 1 << depth
+    ix = np.clip(np.floor((x - x0) / (side / n)), 0, n - 1).astype(np.int64)
+    iy = np.clip(np.floor((y - y0) / (side / n)), 0, n - 1).astype(np.int64)
+    n_box = 0
+    for l in range(2, depth + 1):
+        nl = 1 << l
+        bx, by = ix >> (depth - l), iy >> (depth - l)
+        occ = np.bincount(bx * nl + by, minlength=nl * nl) > 0
+        for a in range(-2, 4):
+            for b in range(-2, 4):
+                sx, sy = 2 * (bx >> 1) + a, 2 * (by >> 1) + b
+                ok = (sx >= 0) & (sx < nl) & (sy >= 0) & (sy < nl) & ((np.abs(sx - bx) > 1) | (np.abs(sy - by) > 1))
+                n_box += int(occ[np.where(ok, sx * nl + sy, 0)][ok].sum())
+    cnt = np.bincount(ix * n + iy, minlength=n * n).reshape(n, n)
+    pad = np.pad(cnt, 1)
+    near = sum(pad[1 + a:1 + a + n, 1 + b:1 + b + n] for a in (-1, 0, 1) for b in (-1, 0, 1))
+    n_direct = int(near[ix, iy].sum() - np.repeat(sizes, sizes).sum())
+    return n_box, n_direct
+
+
+def bench_treecode(args):
+    """The 2000 x 128 workload by the FP64 treecode (default depth), at several orders, against the
+    exact sum on a seeded target sample; the direct FP32-compensated sum timed alongside."""
+    import numpy as np
+    import torch
+
+    import paper_2606_25569_amd as V
+    from paper_2606_25569_amd import _lib as L
+    from synth import suspension as S
+
+    s = S.load_config(1)
+    P, M = s.n_points, s.n_vesicles
+    pairs = s.cross_pairs()
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    X = torch.tensor(s.X, device=dev)
+    f = torch.tensor(s.f, device=dev)
+    w = torch.tensor(s.w, device=dev)
+    part = V.Partition(s.offsets, dev)
+    lib = L.lib()
+    depth = int(lib.vesnet_treecode_default_depth(P))
+    out = torch.empty((2, P), dtype=torch.float64, device=dev)
+    sel = np.sort(np.random.default_rng(S.config_seed(1, 7)).choice(P, 2000, replace=False))
+    from oracle import oracle as O
+    t0 = time.time()
+    exact = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu, select=sel)
+    t_oracle = time.time() - t0
+    scale = float(np.abs(exact).max())
+    n_box, n_direct = _treecode_work(s.X, s.sizes(), depth)
+    rec = {"workload": "treecode far field of the dense suspension: 2000 vesicles x 128 points (256000), "
+                       f"uniform quadtree depth {depth}, FP64",
+           "far_box_evaluations": n_box, "direct_pairs": n_direct,
+           "n_points": P, "cross_vesicle_pairs": pairs, "depth": depth, "orders": {}}
+    for order in (20, 30, 40):
+        ws = torch.empty(lib.vesnet_treecode_workspace_bytes(P, depth, order), dtype=torch.uint8, device=dev)
+        fn = lambda: V.farfield_treecode(X, f, w, part, s.mu, order, depth, out=out, workspace=ws)
+        ms = _time(fn, args.steps, stream)
+        fn()
+        torch.cuda.synchronize()
+        err = float(np.abs(out.cpu().numpy()[:, sel] - exact).max() / scale)
+        flops = (32 * order + 60) * n_box + FLOPS_PER_PAIR * n_direct
+        rec["orders"][order] = {"ms": ms, "max_rel_err_vs_exact": err,
+                                "equivalent_pairs_per_s": pairs / (ms * 1e-3),
+                                "algorithmic_tflops_fp64": flops / (ms * 1e-3) / 1e12,
+                                "frac_of_fp64_peak": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
+        log(f"[bench] treecode order {order}: {ms:.3f} ms, err {err:.2e} of max|u| on {sel.size} targets")
+    wsd = torch.empty(V.workspace_bytes(P, M, "fp32c"), dtype=torch.uint8, device=dev)
+    ms_direct = _time(lambda: V.farfield_forward(X, X, f, w, part, s.mu, "fp32c", out=out, workspace=wsd), 5, stream)
+    rec["direct_fp32c_ms"] = ms_direct
+    rec["oracle_sample"] = {"targets": int(sel.size), "seconds": t_oracle}
+    log(f"[bench] direct FP32-compensated sum: {ms_direct:.3f} ms")
     print(json.dumps(rec), flush=True)
 
 

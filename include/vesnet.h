@@ -232,6 +232,32 @@ VESNET_API int vesnet_rbf_eval_near(const double* layers, const double* coeffs, 
                                     const double* targets, int32_t n_targets, const int32_t* near_pairs,
                                     const int32_t* near_count, int32_t near_capacity, double* out, void* stream);
 
+/* ------------------------------------------------------------------ treecode far field */
+
+/* A fast, approximate evaluation of the far-field sum for targets = sources = points (the paper
+   evaluates the sum directly and leaves fast summation, e.g. the fast multipole method, out of
+   scope: Section 4.1).  A uniform quadtree of the given depth covers the bounding square of the
+   points; sources in boxes of a target's interaction lists (levels 2..depth) act through power-
+   moment expansions truncated after the given order, sources in the 3 x 3 leaves around the
+   target's leaf act directly, and the target's own vesicle is excluded (exactly, also where the
+   expansions included it).  Cost O(P log P); everything in float64.
+   Accuracy: for a box of radius rho seen from distance R, the dropped terms are below
+   sum_box |w f| x^(order+1) (1/((order+1)(1-x)) + (1+x)/(2(1-x))) / (4 pi mu), x = rho/R <= 0.55;
+   order 30 gives about 1e-8 relative to max|u| on dense suspensions, order 45 reaches rounding.
+   Results are deterministic unless a leaf holds more than 2048 points (then its summation order
+   follows an atomic scatter).
+     points, force_density : device [2][P] float64; arc_weights device [P] float64
+     order                 : 1 .. 48;  depth: 0 .. 10 (vesnet_treecode_default_depth: leaves of
+                             at most about 64 points)
+     out                   : device [2][P] float64, overwritten with u_far
+     workspace             : device, vesnet_treecode_workspace_bytes(P, depth, order) bytes */
+VESNET_API int32_t vesnet_treecode_default_depth(int32_t n_points);
+VESNET_API size_t vesnet_treecode_workspace_bytes(int32_t n_points, int32_t depth, int32_t order);
+VESNET_API int vesnet_farfield_treecode(const double* points, const double* force_density, const double* arc_weights,
+                                        const int32_t* vesicle_offsets, int32_t n_vesicles, int32_t n_points,
+                                        double mu, int32_t order, int32_t depth, double* out, void* workspace,
+                                        size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------ batched */
 
 /* S independent suspensions concatenated point-wise and vesicle-wise.

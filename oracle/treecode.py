@@ -107,8 +107,9 @@ def interaction_offsets():
     return [(a, b) for a in range(-2, 4) for b in range(-2, 4)]
 
 
-def treecode(X, f, w, offsets, mu, order, depth):
-    """Treecode far field (2, P) of all points, own vesicle excluded."""
+def treecode(X, f, w, offsets, mu, order, depth, sel=None):
+    """Treecode far field of all points on themselves, own vesicle excluded: (2, P), or
+    (2, len(sel)) at the targets sel only (the tree and moments still use every point)."""
     X = np.asarray(X, np.float64)
     P = X.shape[1]
     z = X[0] + 1j * X[1]
@@ -116,6 +117,8 @@ def treecode(X, f, w, offsets, mu, order, depth):
     ves = np.repeat(np.arange(len(offsets) - 1), np.diff(np.asarray(offsets, np.int64)))
     tree = build_tree(X, depth)
     p = order
+    target = np.zeros(P, bool)
+    target[np.arange(P) if sel is None else np.asarray(sel)] = True
     u = np.zeros(P, complex)
     for l in range(2, depth + 1):
         n = 1 << l
@@ -132,6 +135,7 @@ def treecode(X, f, w, offsets, mu, order, depth):
             sx = 2 * (bx >> 1) + a
             sy = 2 * (by >> 1) + b
             ok = (sx >= 0) & (sx < n) & (sy >= 0) & (sy < n) & ((np.abs(sx - bx) > 1) | (np.abs(sy - by) > 1))
+            ok &= target
             if not ok.any():
                 continue
             s = sx[ok] * n + sy[ok]
@@ -144,6 +148,7 @@ def treecode(X, f, w, offsets, mu, order, depth):
     for lx in range(n):
         for ly in range(n):
             tgt = order_[starts[lx * n + ly]:starts[lx * n + ly + 1]]
+            tgt = tgt[target[tgt]]
             if tgt.size == 0:
                 continue
             src = np.concatenate([order_[starts[jx * n + jy]:starts[jx * n + jy + 1]]
@@ -156,7 +161,7 @@ def treecode(X, f, w, offsets, mu, order, depth):
     # own-vesicle sources that the expansions included: subtract them exactly
     for v in range(len(offsets) - 1):
         a, b = int(offsets[v]), int(offsets[v + 1])
-        if b - a < 2:
+        if b - a < 2 or not target[a:b].any():
             continue
         far = (np.abs(tree.ix[a:b, None] - tree.ix[None, a:b]) > 1) | (np.abs(tree.iy[a:b, None] - tree.iy[None, a:b]) > 1)
         if not far.any():
@@ -165,6 +170,8 @@ def treecode(X, f, w, offsets, mu, order, depth):
         zs = np.where(far, z[None, a:b], z[a:b, None] + 1.0)
         u[a:b] -= direct_terms(z[a:b, None], zs, Fm)
     u /= 4.0 * np.pi * mu
+    if sel is not None:
+        u = u[np.asarray(sel)]
     return np.stack([u.real, u.imag])
 
 

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, "vesnet_kernels.hip"), os.path.join(CSRC, "vesnet_spectral.hip"),
-           os.path.join(CSRC, "vesnet_rbf.hip"),
+           os.path.join(CSRC, "vesnet_rbf.hip"), os.path.join(CSRC, "vesnet_tree.hip"),
            os.path.join(CSRC, "vesnet_api.hip")]
 LIB = os.path.join(HERE, "libvesnet.so")
 

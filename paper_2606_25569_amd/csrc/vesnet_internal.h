@@ -59,6 +59,10 @@ hipError_t launch_rbf_fit(const double* layers, const double* vel, const double*
 hipError_t launch_rbf_eval_near(const double* layers, const double* coeffs, const double* w, const int32_t* off,
                                 int M, int P, double eps, const double* targets, int n_targets,
                                 const int32_t* pairs, const int32_t* count, int capacity, double* out, void* stream);
+// Treecode far field (targets = sources): workspace size and the whole build + evaluation.
+size_t treecode_workspace_bytes(int P, int depth, int p);
+hipError_t launch_treecode(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
+                           double scale, int p, int depth, double* out, void* ws, void* stream);
 hipError_t launch_plan(const int32_t* sus_off, int S, int M, const PreparedView& pv, int tile, const PlanView& pl,
                        void* stream);
 hipError_t launch_batched(int prec, int T, int B, bool lds, int grid, const double* tg, int P, int M,

@@ -1,0 +1,567 @@
+// Treecode far field on gfx950: the far-field sum of eq. (single_layer) at O(P log P) cost.  The
+// paper evaluates the sum directly and leaves fast summation out of scope (Section 4.1); this is
+// a fast, approximate alternative with its own accuracy contract (order p of the expansions).
+//
+// With complex numbers z = x + i y, F_j = w_j (f_x + i f_y)_j, u = u_x + i u_y, each Stokeslet term is
+//   -F_j ln|z - z_j| + F_j / 2 + (z - z_j) conj(F_j / (z - z_j)) / 2,
+// so a box of sources with centre c, zeta_j = z_j - c, acts at w = z - c, t = 1/w, through the
+// power moments M_k[q] = sum_j q_j zeta_j^k of three charge sets (F, conj F, conj(zeta) F):
+//   -M_0[F] ln|w| + 1/2 sum_{k=1}^p (M_k[F] t^k + conj(M_k[conj F] t^k)) / k + M_0[F] / 2
+//   + (w conj(Phi) - conj(Psi)) / 2,   Phi = sum_{k=0}^p M_k[F] t^(k+1),  Psi = sum_k M_k[conj(zeta) F] t^(k+1).
+//
+// Tree: a uniform quadtree of depth L over the bounding square of the points.  Leaf moments come
+// from the points (k_tc_p2m), coarser ones by exact binomial translation (k_tc_m2m).  A target takes,
+// at each level l = 2..L, the interaction list of its level-l ancestor (children of the parent's
+// 3 x 3 neighbourhood not adjacent to the ancestor) through the expansions, and the 3 x 3 leaves
+// around its own directly, skipping its own vesicle; own-vesicle sources outside those leaves,
+// which the expansions included, are subtracted exactly.  Everything is FP64.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "vesnet_internal.h"
+
+namespace vesnet {
+
+namespace {
+
+constexpr int kTB = 256;       // threads of the point-parallel kernels
+constexpr int kBBoxBlocks = 256;
+constexpr int kSortMax = 2048;  // larger leaves keep the order of the atomic scatter
+
+struct Geom {
+  double x0, y0, side;  // lower-left corner and side of the root square
+};
+
+constexpr int kMaxDepth = 10;
+
+// Where each level's boxes start: in boxes (counts) and in complex moment entries.
+struct Levels {
+  unsigned long long box[kMaxDepth + 1];
+  unsigned long long mom[kMaxDepth + 1];
+};
+
+__device__ __forceinline__ int clamp_i(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// a * t + c
+__device__ __forceinline__ double2 cfma(double2 a, double2 t, double2 c) {
+  return make_double2(fma(a.x, t.x, fma(-a.y, t.y, c.x)), fma(a.x, t.y, fma(a.y, t.x, c.y)));
+}
+
+// Natural log of a finite q > 0, in about 20 FP64 operations: q = m 2^e with m in [1/sqrt 2, sqrt 2),
+// ln m = 2 atanh(s) = 2 sum_k s^(2k+1) / (2k+1), s = (m - 1) / (m + 1), |s| <= 0.1716; the terms
+// after s^21 are below 3e-17 of ln m.  ln 2 is split into a 32-bit high part (exact products with e)
+// and a low part.  Measured against 40-digit references: at most 2 ulp.
+__device__ __forceinline__ double log_pos(double q) {
+  constexpr double kLn2Hi = 6.93147180369123816490e-01;
+  constexpr double kLn2Lo = 1.90821492927058770002e-10;
+  int e;
+  double m = frexp(q, &e);
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    --e;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double s2 = s * s;
+  double pol = 1.0 / 21.0;
+  pol = fma(pol, s2, 1.0 / 19.0);
+  pol = fma(pol, s2, 1.0 / 17.0);
+  pol = fma(pol, s2, 1.0 / 15.0);
+  pol = fma(pol, s2, 1.0 / 13.0);
+  pol = fma(pol, s2, 1.0 / 11.0);
+  pol = fma(pol, s2, 1.0 / 9.0);
+  pol = fma(pol, s2, 1.0 / 7.0);
+  pol = fma(pol, s2, 1.0 / 5.0);
+  pol = fma(pol, s2, 1.0 / 3.0);
+  pol = fma(pol, s2, 1.0);
+  return fma((double)e, kLn2Hi, fma((double)e, kLn2Lo, 2.0 * s * pol));
+}
+
+// Box centre at a level with n boxes per side (contraction off: the same bits as the plain formula).
+__device__ __forceinline__ double2 box_center(const Geom& g, int n, int bx, int by) {
+#pragma clang fp contract(off)
+  const double wl = g.side / (double)n;
+  return make_double2(g.x0 + ((double)bx + 0.5) * wl, g.y0 + ((double)by + 0.5) * wl);
+}
+
+// ---------------------------------------------------------------- tree construction
+
+__global__ __launch_bounds__(kTB) void k_tc_bbox_partial(const double* __restrict__ X, int P,
+                                                         double* __restrict__ part) {
+  __shared__ double red[4][kTB];
+  double xl = INFINITY, xh = -INFINITY, yl = INFINITY, yh = -INFINITY;
+  for (int j = blockIdx.x * kTB + threadIdx.x; j < P; j += gridDim.x * kTB) {
+    const double x = X[j], y = X[P + j];
+    xl = fmin(xl, x);
+    xh = fmax(xh, x);
+    yl = fmin(yl, y);
+    yh = fmax(yh, y);
+  }
+  red[0][threadIdx.x] = xl;
+  red[1][threadIdx.x] = xh;
+  red[2][threadIdx.x] = yl;
+  red[3][threadIdx.x] = yh;
+  __syncthreads();
+  for (int s = kTB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+      red[2][threadIdx.x] = fmin(red[2][threadIdx.x], red[2][threadIdx.x + s]);
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_tc_bbox_final(const double* __restrict__ part, int nparts, Geom* __restrict__ geom) {
+  if (threadIdx.x != 0) return;
+  double xl = INFINITY, xh = -INFINITY, yl = INFINITY, yh = -INFINITY;
+  for (int b = 0; b < nparts; ++b) {
+    xl = fmin(xl, part[4 * b]);
+    xh = fmax(xh, part[4 * b + 1]);
+    yl = fmin(yl, part[4 * b + 2]);
+    yh = fmax(yh, part[4 * b + 3]);
+  }
+  {
+#pragma clang fp contract(off)
+    double side = fmax(xh - xl, yh - yl);
+    if (side == 0.0) side = 1.0;
+    Geom g;
+    g.x0 = 0.5 * (xl + xh) - 0.5 * side;
+    g.y0 = 0.5 * (yl + yh) - 0.5 * side;
+    g.side = side;
+    *geom = g;
+  }
+}
+
+__global__ __launch_bounds__(kTB) void k_tc_zero(int32_t* __restrict__ a, int n) {
+  for (int i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) a[i] = 0;
+}
+
+// Leaf of every point, leaf occupancy, vesicle id of every point.
+__global__ __launch_bounds__(kTB) void k_tc_leaf(const double* __restrict__ X, int P, const Geom* __restrict__ geom,
+                                                 int depth, const int32_t* __restrict__ off, int M,
+                                                 int32_t* __restrict__ leafid, int32_t* __restrict__ vid,
+                                                 int32_t* __restrict__ counts) {
+  const Geom g = *geom;
+  const int n = 1 << depth;
+  for (int j = blockIdx.x * kTB + threadIdx.x; j < P; j += gridDim.x * kTB) {
+    int ix, iy;
+    {
+#pragma clang fp contract(off)
+      const double wl = g.side / (double)n;
+      ix = clamp_i((int)floor((X[j] - g.x0) / wl), 0, n - 1);
+      iy = clamp_i((int)floor((X[P + j] - g.y0) / wl), 0, n - 1);
+    }
+    const int leaf = ix * n + iy;
+    leafid[j] = leaf;
+    atomicAdd(counts + leaf, 1);
+    // vesicle of j: the last v with off[v] <= j
+    int lo = 0, hi = M;  // off[lo] <= j < off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (off[mid] <= j) lo = mid; else hi = mid;
+    }
+    vid[j] = lo;
+  }
+}
+
+// Exclusive scans of the leaf occupancies (starts) and of their 64-point chunks (wave starts).
+__global__ __launch_bounds__(1024) void k_tc_scan(const int32_t* __restrict__ counts, int nleaf,
+                                                  int32_t* __restrict__ starts, int32_t* __restrict__ wstart) {
+  __shared__ int32_t sa[1024];
+  __shared__ int32_t sb[1024];
+  const int t = threadIdx.x;
+  const int seg = (nleaf + 1023) / 1024;
+  const int b0 = min(t * seg, nleaf), b1 = min(b0 + seg, nleaf);
+  int32_t a = 0, b = 0;
+  for (int i = b0; i < b1; ++i) {
+    a += counts[i];
+    b += (counts[i] + 63) >> 6;
+  }
+  sa[t] = a;
+  sb[t] = b;
+  __syncthreads();
+  if (t == 0) {
+    int32_t ra = 0, rb = 0;
+    for (int k = 0; k < 1024; ++k) {
+      const int32_t xa = sa[k], xb = sb[k];
+      sa[k] = ra;
+      sb[k] = rb;
+      ra += xa;
+      rb += xb;
+    }
+    starts[nleaf] = ra;
+    wstart[nleaf] = rb;
+  }
+  __syncthreads();
+  a = sa[t];
+  b = sb[t];
+  for (int i = b0; i < b1; ++i) {
+    starts[i] = a;
+    wstart[i] = b;
+    a += counts[i];
+    b += (counts[i] + 63) >> 6;
+  }
+}
+
+__global__ __launch_bounds__(kTB) void k_tc_scatter(const int32_t* __restrict__ leafid, int P,
+                                                    const int32_t* __restrict__ starts, int32_t* __restrict__ cursor,
+                                                    int32_t* __restrict__ perm) {
+  for (int j = blockIdx.x * kTB + threadIdx.x; j < P; j += gridDim.x * kTB) {
+    const int leaf = leafid[j];
+    perm[starts[leaf] + atomicAdd(cursor + leaf, 1)] = j;
+  }
+}
+
+// Points of each leaf in ascending index order (deterministic sums).  One wavefront per leaf: the
+// keys (distinct point indices) go to LDS and each is written at its rank, the number of smaller
+// keys in the leaf.
+__global__ __launch_bounds__(64) void k_tc_sort(const int32_t* __restrict__ starts, int32_t* __restrict__ perm) {
+  __shared__ int32_t key[kSortMax];
+  const int leaf = blockIdx.x;
+  const int s0 = starts[leaf], n = starts[leaf + 1] - s0;
+  if (n < 2 || n > kSortMax) return;
+  for (int a = threadIdx.x; a < n; a += 64) key[a] = perm[s0 + a];
+  __syncthreads();
+  for (int a = threadIdx.x; a < n; a += 64) {
+    const int32_t k = key[a];
+    int rank = 0;
+    for (int b = 0; b < n; ++b) rank += key[b] < k;
+    perm[s0 + rank] = k;
+  }
+}
+
+// ---------------------------------------------------------------- moments
+//
+// Moments of a box: 4 rows of (p + 1) complex numbers: row 0 M_k[F], row 1 M_k[conj F] (divided by k
+// for k >= 1 once all translations are done), row 2 M_k[conj(zeta) F], row 3 M_k[F] / k (filled last).
+
+__device__ __forceinline__ double2 cpow_int(double2 z, int k) {
+  double2 r = make_double2(1.0, 0.0);
+  double2 b = z;
+  while (k > 0) {
+    if (k & 1) r = cmul(r, b);
+    b = cmul(b, b);
+    k >>= 1;
+  }
+  return r;
+}
+
+// One wavefront per leaf, lane k = order.
+__global__ __launch_bounds__(64) void k_tc_p2m(const double* __restrict__ X, const double* __restrict__ f,
+                                               const double* __restrict__ w, int P, const int32_t* __restrict__ perm,
+                                               const int32_t* __restrict__ starts, const Geom* __restrict__ geom,
+                                               int depth, int p, double2* __restrict__ mom,
+                                               int32_t* __restrict__ bcount) {
+  const int leaf = blockIdx.x;
+  const int k = threadIdx.x;
+  const int n = 1 << depth;
+  const int s0 = starts[leaf], s1 = starts[leaf + 1];
+  if (k == 0) bcount[leaf] = s1 - s0;
+  if (k > p) return;
+  const double2 c = box_center(*geom, n, leaf / n, leaf % n);
+  double2 m0 = make_double2(0.0, 0.0), m1 = m0, m2 = m0;
+  for (int s = s0; s < s1; ++s) {
+    const int j = perm[s];
+    const double2 zeta = make_double2(X[j] - c.x, X[P + j] - c.y);
+    const double2 F = make_double2(w[j] * f[j], w[j] * f[P + j]);
+    const double2 zk = cpow_int(zeta, k);
+    const double2 Fz = cmul(F, zk);
+    m0.x += Fz.x;
+    m0.y += Fz.y;
+    const double2 Fcz = cmul(make_double2(F.x, -F.y), zk);
+    m1.x += Fcz.x;
+    m1.y += Fcz.y;
+    const double2 Pz = cmul(make_double2(zeta.x, -zeta.y), Fz);
+    m2.x += Pz.x;
+    m2.y += Pz.y;
+  }
+  double2* mb = mom + (size_t)leaf * 4 * (p + 1);
+  mb[k] = m0;
+  mb[(p + 1) + k] = m1;
+  mb[2 * (p + 1) + k] = m2;
+}
+
+// Parent moments at a level with n boxes per side from the children one level down:
+// M'_k = sum_children sum_{m <= k} C(k, m) d^(k-m) M_m, d = child centre - parent centre; the
+// conj(zeta) F row gains conj(d) times the translated F row.  One thread per (parent, k).
+__global__ __launch_bounds__(kTB) void k_tc_m2m(const Geom* __restrict__ geom, int n, int p,
+                                                const double2* __restrict__ child, const int32_t* __restrict__ ccount,
+                                                double2* __restrict__ parent, int32_t* __restrict__ pcount) {
+  const int nbox = n * n;
+  const int stride = 4 * (p + 1);
+  for (int e = blockIdx.x * kTB + threadIdx.x; e < nbox * (p + 1); e += gridDim.x * kTB) {
+    const int box = e / (p + 1), k = e - box * (p + 1);
+    const int bx = box / n, by = box % n;
+    const double wc = geom->side / (double)(2 * n);  // child width
+    double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0;
+    int cnt = 0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const int cb = (2 * bx + a) * (2 * n) + (2 * by + b);
+        const int cc = ccount[cb];
+        cnt += cc;
+        if (cc == 0) continue;
+        const double2 d = make_double2(((double)a - 0.5) * wc, ((double)b - 0.5) * wc);
+        const double2* cm = child + (size_t)cb * stride;
+        // sum_m C(k, m) d^(k - m) M_m by Horner in d: (((M_0) d + C(k,1)/C(k,0)...)) -- done directly
+        double2 t0 = make_double2(0.0, 0.0), t1 = t0, t2 = t0;
+        double binom = 1.0;      // C(k, m)
+        double2 dp = cpow_int(d, k);  // d^(k - m) for m = 0
+        const double2 dinv = make_double2(d.x / (d.x * d.x + d.y * d.y), -d.y / (d.x * d.x + d.y * d.y));
+        for (int m = 0; m <= k; ++m) {
+          const double2 coef = make_double2(binom * dp.x, binom * dp.y);
+          t0 = cfma(coef, cm[m], t0);
+          t1 = cfma(coef, cm[(p + 1) + m], t1);
+          t2 = cfma(coef, cm[2 * (p + 1) + m], t2);
+          binom = binom * (double)(k - m) / (double)(m + 1);
+          dp = cmul(dp, dinv);
+        }
+        s0.x += t0.x;
+        s0.y += t0.y;
+        s1.x += t1.x;
+        s1.y += t1.y;
+        const double2 extra = cmul(make_double2(d.x, -d.y), t0);
+        s2.x += t2.x + extra.x;
+        s2.y += t2.y + extra.y;
+      }
+    double2* pm = parent + (size_t)box * stride;
+    pm[k] = s0;
+    pm[(p + 1) + k] = s1;
+    pm[2 * (p + 1) + k] = s2;
+    if (k == 0) pcount[box] = cnt;
+  }
+}
+
+// Row 3 = M_k[F] / k and row 1 divided by k (k >= 1), for the log series.
+__global__ __launch_bounds__(kTB) void k_tc_finalize(double2* __restrict__ mom, size_t nbox, int p) {
+  const size_t stride = 4 * (size_t)(p + 1);
+  for (size_t e = (size_t)blockIdx.x * kTB + threadIdx.x; e < nbox * (p + 1); e += (size_t)gridDim.x * kTB) {
+    const size_t box = e / (p + 1);
+    const int k = (int)(e - box * (p + 1));
+    double2* mb = mom + box * stride;
+    if (k == 0) {
+      mb[3 * (p + 1)] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double ik = 1.0 / (double)k;
+    const double2 a = mb[k], b = mb[(p + 1) + k];
+    mb[3 * (p + 1) + k] = make_double2(a.x * ik, a.y * ik);
+    mb[(p + 1) + k] = make_double2(b.x * ik, b.y * ik);
+  }
+}
+
+// ---------------------------------------------------------------- evaluation
+
+__device__ __forceinline__ void direct_term(double zx, double zy, double sx, double sy, double Fx, double Fy,
+                                            double& ux, double& uy) {
+  const double rx = zx - sx, ry = zy - sy;
+  const double q = rx * rx + ry * ry;
+  const double lg = -0.5 * log_pos(q);
+  const double s = (rx * Fx + ry * Fy) / q;
+  ux = fma(lg, Fx, fma(s, rx, ux));
+  uy = fma(lg, Fy, fma(s, ry, uy));
+}
+
+// One wavefront per (leaf, chunk of 64 of its points); every lane one target.
+__global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, const double* __restrict__ f,
+                                                const double* __restrict__ w, int P, const int32_t* __restrict__ off,
+                                                const int32_t* __restrict__ vid, const int32_t* __restrict__ leafid,
+                                                const int32_t* __restrict__ perm, const int32_t* __restrict__ starts,
+                                                const int32_t* __restrict__ wstart, const Geom* __restrict__ geom,
+                                                int depth, int p, const double2* __restrict__ mom,
+                                                const int32_t* __restrict__ bcount, const Levels lv, double scale,
+                                                double* __restrict__ out) {
+  const int n = 1 << depth;
+  const int nleaf = n * n;
+  const int item = blockIdx.x;
+  if (item >= wstart[nleaf]) return;
+  int lo = 0, hi = nleaf;  // wstart[lo] <= item < wstart[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (wstart[mid] <= item) lo = mid; else hi = mid;
+  }
+  const int leaf = lo;
+  const int s0 = starts[leaf], s1 = starts[leaf + 1];
+  const int slot = s0 + (item - wstart[leaf]) * 64 + (int)threadIdx.x;
+  const bool active = slot < s1;
+  const int i = active ? perm[slot] : perm[s0];
+  const double zx = X[i], zy = X[P + i];
+  const int vi = vid[i];
+  const int ix = leaf / n, iy = leaf % n;
+  const Geom g = *geom;
+  const int stride = 4 * (p + 1);
+  double ux = 0.0, uy = 0.0;
+
+  // expansions of the interaction lists, level by level
+  for (int l = 2; l <= depth; ++l) {
+    const int nl = 1 << l;
+    const int bx = ix >> (depth - l), by = iy >> (depth - l);
+    const double2* ml = mom + lv.mom[l];
+    const int32_t* cl = bcount + lv.box[l];
+    for (int a = -2; a <= 3; ++a) {
+      const int sx = 2 * (bx >> 1) + a;
+      if (sx < 0 || sx >= nl) continue;
+      for (int b = -2; b <= 3; ++b) {
+        const int sy = 2 * (by >> 1) + b;
+        if (sy < 0 || sy >= nl) continue;
+        if (abs(sx - bx) <= 1 && abs(sy - by) <= 1) continue;
+        const int sb = sx * nl + sy;
+        if (cl[sb] == 0) continue;
+        const double2* mb = ml + (size_t)sb * stride;
+        const double2 c = box_center(g, nl, sx, sy);
+        const double2 wv = make_double2(zx - c.x, zy - c.y);
+        const double w2 = wv.x * wv.x + wv.y * wv.y;
+        const double2 t = make_double2(wv.x / w2, -wv.y / w2);
+        // Horner, highest order first
+        double2 aF = make_double2(0.0, 0.0), aFc = aF, aPhi = aF, aPsi = aF;
+        for (int k = p; k >= 1; --k) {
+          aF = cfma(aF, t, mb[3 * (p + 1) + k]);
+          aFc = cfma(aFc, t, mb[(p + 1) + k]);
+          aPhi = cfma(aPhi, t, mb[k]);
+          aPsi = cfma(aPsi, t, mb[2 * (p + 1) + k]);
+        }
+        const double2 M0 = mb[0];
+        aPhi = cfma(aPhi, t, M0);
+        aPsi = cfma(aPsi, t, mb[2 * (p + 1)]);
+        aF = cmul(aF, t);
+        aFc = cmul(aFc, t);
+        const double2 Phi = cmul(aPhi, t), Psi = cmul(aPsi, t);
+        const double lnw = 0.5 * log_pos(w2);
+        // w conj(Phi)
+        const double2 wPhi = cmul(wv, make_double2(Phi.x, -Phi.y));
+        ux += -M0.x * lnw + 0.5 * (aF.x + aFc.x) + 0.5 * M0.x + 0.5 * (wPhi.x - Psi.x);
+        uy += -M0.y * lnw + 0.5 * (aF.y - aFc.y) + 0.5 * M0.y + 0.5 * (wPhi.y + Psi.y);
+      }
+    }
+  }
+  // 3 x 3 leaves directly, own vesicle skipped
+  for (int jx = max(ix - 1, 0); jx <= min(ix + 1, n - 1); ++jx)
+    for (int jy = max(iy - 1, 0); jy <= min(iy + 1, n - 1); ++jy) {
+      const int nl = jx * n + jy;
+      const int e0 = starts[nl], e1 = starts[nl + 1];
+      for (int s = e0; s < e1; ++s) {
+        const int j = perm[s];
+        if (vid[j] == vi) continue;
+        direct_term(zx, zy, X[j], X[P + j], w[j] * f[j], w[j] * f[P + j], ux, uy);
+      }
+    }
+  // own-vesicle sources outside those leaves were in the expansions: take them out
+  const int v0 = off[vi], v1 = off[vi + 1];
+  for (int j = v0; j < v1; ++j) {
+    if (j == i) continue;
+    const int lj = leafid[j];
+    const int jx = lj / n, jy = lj - jx * n;
+    if (abs(jx - ix) <= 1 && abs(jy - iy) <= 1) continue;
+    double dx = 0.0, dy = 0.0;
+    direct_term(zx, zy, X[j], X[P + j], w[j] * f[j], w[j] * f[P + j], dx, dy);
+    ux -= dx;
+    uy -= dy;
+  }
+  if (active) {
+    out[i] = ux * scale;
+    out[P + i] = uy * scale;
+  }
+}
+
+}  // namespace
+
+// Workspace layout shared by the size query and the launcher.
+struct TreeLayout {
+  size_t geom, part, leafid, vid, perm, counts, cursor, starts, wstart, bcount, mom, total;
+};
+
+static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+static TreeLayout tree_layout(int P, int depth, int p) {
+  TreeLayout t;
+  const size_t nleaf = (size_t)1 << (2 * depth);
+  size_t boxes = 0, moms = 0;
+  for (int l = 2; l <= depth; ++l) boxes += (size_t)1 << (2 * l);
+  moms = boxes * 4 * (size_t)(p + 1);
+  size_t o = 0;
+  t.geom = o;       o += align_up(sizeof(double) * 4);
+  t.part = o;       o += align_up(sizeof(double) * 4 * kBBoxBlocks);
+  t.leafid = o;     o += align_up(sizeof(int32_t) * (size_t)P);
+  t.vid = o;        o += align_up(sizeof(int32_t) * (size_t)P);
+  t.perm = o;       o += align_up(sizeof(int32_t) * (size_t)P);
+  t.counts = o;     o += align_up(sizeof(int32_t) * nleaf);
+  t.cursor = o;     o += align_up(sizeof(int32_t) * nleaf);
+  t.starts = o;     o += align_up(sizeof(int32_t) * (nleaf + 1));
+  t.wstart = o;     o += align_up(sizeof(int32_t) * (nleaf + 1));
+  t.bcount = o;     o += align_up(sizeof(int32_t) * (boxes > 0 ? boxes : 1));
+  t.mom = o;        o += align_up(sizeof(double2) * (moms > 0 ? moms : 1));
+  t.total = o;
+  return t;
+}
+
+size_t treecode_workspace_bytes(int P, int depth, int p) { return tree_layout(P, depth, p).total; }
+
+// Everything is built on the device; the launches need no host copy and no synchronisation.
+hipError_t launch_treecode(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
+                           double scale, int p, int depth, double* out, void* ws, void* stream) {
+  if (P == 0) return hipSuccess;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  const TreeLayout t = tree_layout(P, depth, p);
+  Geom* geom = reinterpret_cast<Geom*>(base + t.geom);
+  double* part = reinterpret_cast<double*>(base + t.part);
+  int32_t* leafid = reinterpret_cast<int32_t*>(base + t.leafid);
+  int32_t* vid = reinterpret_cast<int32_t*>(base + t.vid);
+  int32_t* perm = reinterpret_cast<int32_t*>(base + t.perm);
+  int32_t* counts = reinterpret_cast<int32_t*>(base + t.counts);
+  int32_t* cursor = reinterpret_cast<int32_t*>(base + t.cursor);
+  int32_t* starts = reinterpret_cast<int32_t*>(base + t.starts);
+  int32_t* wstart = reinterpret_cast<int32_t*>(base + t.wstart);
+  int32_t* bcount = reinterpret_cast<int32_t*>(base + t.bcount);
+  double2* mom = reinterpret_cast<double2*>(base + t.mom);
+  const int nleaf = 1 << (2 * depth);
+
+  if (depth < 0 || depth > kMaxDepth) return hipErrorInvalidValue;
+  // boxes of level l start at box index sum_{m = 2}^{l-1} 4^m
+  Levels lv = {};
+  size_t acc = 0;
+  for (int l = 2; l <= depth; ++l) {
+    lv.box[l] = acc;
+    lv.mom[l] = acc * 4 * (size_t)(p + 1);
+    acc += (size_t)1 << (2 * l);
+  }
+
+  const int pb = (P + kTB - 1) / kTB < 4096 ? (P + kTB - 1) / kTB : 4096;
+  const int bb = (P + kTB - 1) / kTB < kBBoxBlocks ? (P + kTB - 1) / kTB : kBBoxBlocks;
+  hipLaunchKernelGGL(k_tc_bbox_partial, dim3(bb), dim3(kTB), 0, st, X, P, part);
+  hipLaunchKernelGGL(k_tc_bbox_final, dim3(1), dim3(64), 0, st, part, bb, geom);
+  const int zb = (nleaf + kTB - 1) / kTB < 4096 ? (nleaf + kTB - 1) / kTB : 4096;
+  hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, counts, nleaf);
+  hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, cursor, nleaf);
+  hipLaunchKernelGGL(k_tc_leaf, dim3(pb), dim3(kTB), 0, st, X, P, geom, depth, off, M, leafid, vid, counts);
+  hipLaunchKernelGGL(k_tc_scan, dim3(1), dim3(1024), 0, st, counts, nleaf, starts, wstart);
+  hipLaunchKernelGGL(k_tc_scatter, dim3(pb), dim3(kTB), 0, st, leafid, P, starts, cursor, perm);
+  hipLaunchKernelGGL(k_tc_sort, dim3(nleaf), dim3(64), 0, st, starts, perm);
+  if (depth >= 2) {
+    hipLaunchKernelGGL(k_tc_p2m, dim3(nleaf), dim3(64), 0, st, X, f, w, P, perm, starts, geom, depth, p,
+                       mom + lv.mom[depth], bcount + lv.box[depth]);
+    for (int l = depth - 1; l >= 2; --l) {
+      const int n = 1 << l;
+      const size_t work = (size_t)n * n * (p + 1);
+      const int gb = (int)((work + kTB - 1) / kTB < 4096 ? (work + kTB - 1) / kTB : 4096);
+      hipLaunchKernelGGL(k_tc_m2m, dim3(gb), dim3(kTB), 0, st, geom, n, p, mom + lv.mom[l + 1],
+                         bcount + lv.box[l + 1], mom + lv.mom[l], bcount + lv.box[l]);
+    }
+    const size_t nbox = acc;
+    const size_t work = nbox * (p + 1);
+    const int gb = (int)((work + kTB - 1) / kTB < 4096 ? (work + kTB - 1) / kTB : 4096);
+    hipLaunchKernelGGL(k_tc_finalize, dim3(gb), dim3(kTB), 0, st, mom, nbox, p);
+  }
+  const int items = nleaf + (P + 63) / 64;  // bound on sum over leaves of ceil(count / 64)
+  hipLaunchKernelGGL(k_tc_eval, dim3(items), dim3(64), 0, st, X, f, w, P, off, vid, leafid, perm, starts, wstart, geom,
+                     depth, p, mom, bcount, lv, scale, out);
+  return hipGetLastError();
+}
+
+}  // namespace vesnet
