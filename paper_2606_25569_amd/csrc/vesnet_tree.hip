@@ -34,6 +34,7 @@ struct Geom {
 };
 
 constexpr int kMaxDepth = 10;
+constexpr int kMaxOrder = 48;
 
 // Where each level's boxes start: in boxes (counts) and in complex moment entries.
 struct Levels {
@@ -117,15 +118,23 @@ __global__ __launch_bounds__(kTB) void k_tc_bbox_partial(const double* __restric
   if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_tc_bbox_final(const double* __restrict__ part, int nparts, Geom* __restrict__ geom) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(64) void k_tc_bbox_final(const double* __restrict__ part, int nparts,
+                                                      Geom* __restrict__ geom) {
   double xl = INFINITY, xh = -INFINITY, yl = INFINITY, yh = -INFINITY;
-  for (int b = 0; b < nparts; ++b) {
+  for (int b = threadIdx.x; b < nparts; b += 64) {
     xl = fmin(xl, part[4 * b]);
     xh = fmax(xh, part[4 * b + 1]);
     yl = fmin(yl, part[4 * b + 2]);
     yh = fmax(yh, part[4 * b + 3]);
   }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    xl = fmin(xl, __shfl_xor(xl, m, 64));
+    xh = fmax(xh, __shfl_xor(xh, m, 64));
+    yl = fmin(yl, __shfl_xor(yl, m, 64));
+    yh = fmax(yh, __shfl_xor(yh, m, 64));
+  }
+  if (threadIdx.x != 0) return;
   {
 #pragma clang fp contract(off)
     double side = fmax(xh - xl, yh - yl);
@@ -252,35 +261,46 @@ __device__ __forceinline__ double2 cpow_int(double2 z, int k) {
   return r;
 }
 
-// One wavefront per leaf, lane k = order.
+// One wavefront per leaf, lane k = order; the leaf's points pass through LDS 64 at a time.
 __global__ __launch_bounds__(64) void k_tc_p2m(const double* __restrict__ X, const double* __restrict__ f,
                                                const double* __restrict__ w, int P, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ starts, const Geom* __restrict__ geom,
                                                int depth, int p, double2* __restrict__ mom,
                                                int32_t* __restrict__ bcount) {
+  __shared__ double2 zs[64], Fs[64];
   const int leaf = blockIdx.x;
   const int k = threadIdx.x;
   const int n = 1 << depth;
   const int s0 = starts[leaf], s1 = starts[leaf + 1];
   if (k == 0) bcount[leaf] = s1 - s0;
-  if (k > p) return;
   const double2 c = box_center(*geom, n, leaf / n, leaf % n);
   double2 m0 = make_double2(0.0, 0.0), m1 = m0, m2 = m0;
-  for (int s = s0; s < s1; ++s) {
-    const int j = perm[s];
-    const double2 zeta = make_double2(X[j] - c.x, X[P + j] - c.y);
-    const double2 F = make_double2(w[j] * f[j], w[j] * f[P + j]);
-    const double2 zk = cpow_int(zeta, k);
-    const double2 Fz = cmul(F, zk);
-    m0.x += Fz.x;
-    m0.y += Fz.y;
-    const double2 Fcz = cmul(make_double2(F.x, -F.y), zk);
-    m1.x += Fcz.x;
-    m1.y += Fcz.y;
-    const double2 Pz = cmul(make_double2(zeta.x, -zeta.y), Fz);
-    m2.x += Pz.x;
-    m2.y += Pz.y;
+  for (int c0 = s0; c0 < s1; c0 += 64) {
+    const int cnt = min(64, s1 - c0);
+    __syncthreads();  // the previous chunk is done
+    if (k < cnt) {
+      const int j = perm[c0 + k];
+      zs[k] = make_double2(X[j] - c.x, X[P + j] - c.y);
+      Fs[k] = make_double2(w[j] * f[j], w[j] * f[P + j]);
+    }
+    __syncthreads();
+    if (k <= p) {
+      for (int q = 0; q < cnt; ++q) {
+        const double2 zeta = zs[q], F = Fs[q];
+        const double2 zk = cpow_int(zeta, k);
+        const double2 Fz = cmul(F, zk);
+        m0.x += Fz.x;
+        m0.y += Fz.y;
+        const double2 Fcz = cmul(make_double2(F.x, -F.y), zk);
+        m1.x += Fcz.x;
+        m1.y += Fcz.y;
+        const double2 Pz = cmul(make_double2(zeta.x, -zeta.y), Fz);
+        m2.x += Pz.x;
+        m2.y += Pz.y;
+      }
+    }
   }
+  if (k > p) return;
   double2* mb = mom + (size_t)leaf * 4 * (p + 1);
   mb[k] = m0;
   mb[(p + 1) + k] = m1;
@@ -289,53 +309,57 @@ __global__ __launch_bounds__(64) void k_tc_p2m(const double* __restrict__ X, con
 
 // Parent moments at a level with n boxes per side from the children one level down:
 // M'_k = sum_children sum_{m <= k} C(k, m) d^(k-m) M_m, d = child centre - parent centre; the
-// conj(zeta) F row gains conj(d) times the translated F row.  One thread per (parent, k).
-__global__ __launch_bounds__(kTB) void k_tc_m2m(const Geom* __restrict__ geom, int n, int p,
-                                                const double2* __restrict__ child, const int32_t* __restrict__ ccount,
-                                                double2* __restrict__ parent, int32_t* __restrict__ pcount) {
-  const int nbox = n * n;
+// conj(zeta) F row gains conj(d) times the translated F row.  One wavefront per parent box, lane
+// k = order, the children's three rows staged in LDS.
+__global__ __launch_bounds__(64) void k_tc_m2m(const Geom* __restrict__ geom, int n, int p,
+                                               const double2* __restrict__ child, const int32_t* __restrict__ ccount,
+                                               double2* __restrict__ parent, int32_t* __restrict__ pcount) {
+  __shared__ double2 cm[4][3 * (kMaxOrder + 1)];
+  const int box = blockIdx.x;
+  const int k = threadIdx.x;
+  const int bx = box / n, by = box % n;
   const int stride = 4 * (p + 1);
-  for (int e = blockIdx.x * kTB + threadIdx.x; e < nbox * (p + 1); e += gridDim.x * kTB) {
-    const int box = e / (p + 1), k = e - box * (p + 1);
-    const int bx = box / n, by = box % n;
-    const double wc = geom->side / (double)(2 * n);  // child width
-    double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0;
-    int cnt = 0;
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
-        const int cb = (2 * bx + a) * (2 * n) + (2 * by + b);
-        const int cc = ccount[cb];
-        cnt += cc;
-        if (cc == 0) continue;
-        const double2 d = make_double2(((double)a - 0.5) * wc, ((double)b - 0.5) * wc);
-        const double2* cm = child + (size_t)cb * stride;
-        // sum_m C(k, m) d^(k - m) M_m by Horner in d: (((M_0) d + C(k,1)/C(k,0)...)) -- done directly
-        double2 t0 = make_double2(0.0, 0.0), t1 = t0, t2 = t0;
-        double binom = 1.0;      // C(k, m)
-        double2 dp = cpow_int(d, k);  // d^(k - m) for m = 0
-        const double2 dinv = make_double2(d.x / (d.x * d.x + d.y * d.y), -d.y / (d.x * d.x + d.y * d.y));
-        for (int m = 0; m <= k; ++m) {
-          const double2 coef = make_double2(binom * dp.x, binom * dp.y);
-          t0 = cfma(coef, cm[m], t0);
-          t1 = cfma(coef, cm[(p + 1) + m], t1);
-          t2 = cfma(coef, cm[2 * (p + 1) + m], t2);
-          binom = binom * (double)(k - m) / (double)(m + 1);
-          dp = cmul(dp, dinv);
-        }
-        s0.x += t0.x;
-        s0.y += t0.y;
-        s1.x += t1.x;
-        s1.y += t1.y;
-        const double2 extra = cmul(make_double2(d.x, -d.y), t0);
-        s2.x += t2.x + extra.x;
-        s2.y += t2.y + extra.y;
-      }
-    double2* pm = parent + (size_t)box * stride;
-    pm[k] = s0;
-    pm[(p + 1) + k] = s1;
-    pm[2 * (p + 1) + k] = s2;
-    if (k == 0) pcount[box] = cnt;
+  const double wc = geom->side / (double)(2 * n);  // child width
+  int cnt = 0, cc[4];
+  for (int q = 0; q < 4; ++q) {
+    const int cb = (2 * bx + (q >> 1)) * (2 * n) + (2 * by + (q & 1));
+    cc[q] = ccount[cb];
+    cnt += cc[q];
+    if (cc[q] == 0) continue;
+    for (int e = k; e < 3 * (p + 1); e += 64) cm[q][e] = child[(size_t)cb * stride + e];
   }
+  __syncthreads();
+  if (k == 0) pcount[box] = cnt;
+  if (k > p) return;
+  double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0;
+  for (int q = 0; q < 4; ++q) {
+    if (cc[q] == 0) continue;
+    const double2 d = make_double2(((double)(q >> 1) - 0.5) * wc, ((double)(q & 1) - 0.5) * wc);
+    const double dd = d.x * d.x + d.y * d.y;
+    const double2 dinv = make_double2(d.x / dd, -d.y / dd);
+    double2 t0 = make_double2(0.0, 0.0), t1 = t0, t2 = t0;
+    double binom = 1.0;          // C(k, m)
+    double2 dp = cpow_int(d, k);  // d^(k - m)
+    for (int m = 0; m <= k; ++m) {
+      const double2 coef = make_double2(binom * dp.x, binom * dp.y);
+      t0 = cfma(coef, cm[q][m], t0);
+      t1 = cfma(coef, cm[q][(p + 1) + m], t1);
+      t2 = cfma(coef, cm[q][2 * (p + 1) + m], t2);
+      binom = binom * (double)(k - m) / (double)(m + 1);
+      dp = cmul(dp, dinv);
+    }
+    s0.x += t0.x;
+    s0.y += t0.y;
+    s1.x += t1.x;
+    s1.y += t1.y;
+    const double2 extra = cmul(make_double2(d.x, -d.y), t0);
+    s2.x += t2.x + extra.x;
+    s2.y += t2.y + extra.y;
+  }
+  double2* pm = parent + (size_t)box * stride;
+  pm[k] = s0;
+  pm[(p + 1) + k] = s1;
+  pm[2 * (p + 1) + k] = s2;
 }
 
 // Row 3 = M_k[F] / k and row 1 divided by k (k >= 1), for the log series.
@@ -397,6 +421,10 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
   const Geom g = *geom;
   const int stride = 4 * (p + 1);
   double ux = 0.0, uy = 0.0;
+  // per-wavefront staging: the moments of one box, then chunks of 64 direct sources
+  __shared__ double2 cf[4 * (kMaxOrder + 1)];
+  __shared__ double sx_[64], sy_[64], sfx[64], sfy[64];
+  __shared__ int32_t sv[64];
 
   // expansions of the interaction lists, level by level
   for (int l = 2; l <= depth; ++l) {
@@ -414,6 +442,9 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
         const int sb = sx * nl + sy;
         if (cl[sb] == 0) continue;
         const double2* mb = ml + (size_t)sb * stride;
+        __syncthreads();  // the previous box is done with cf
+        for (int e = threadIdx.x; e < stride; e += 64) cf[e] = mb[e];
+        __syncthreads();
         const double2 c = box_center(g, nl, sx, sy);
         const double2 wv = make_double2(zx - c.x, zy - c.y);
         const double w2 = wv.x * wv.x + wv.y * wv.y;
@@ -421,14 +452,14 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
         // Horner, highest order first
         double2 aF = make_double2(0.0, 0.0), aFc = aF, aPhi = aF, aPsi = aF;
         for (int k = p; k >= 1; --k) {
-          aF = cfma(aF, t, mb[3 * (p + 1) + k]);
-          aFc = cfma(aFc, t, mb[(p + 1) + k]);
-          aPhi = cfma(aPhi, t, mb[k]);
-          aPsi = cfma(aPsi, t, mb[2 * (p + 1) + k]);
+          aF = cfma(aF, t, cf[3 * (p + 1) + k]);
+          aFc = cfma(aFc, t, cf[(p + 1) + k]);
+          aPhi = cfma(aPhi, t, cf[k]);
+          aPsi = cfma(aPsi, t, cf[2 * (p + 1) + k]);
         }
-        const double2 M0 = mb[0];
+        const double2 M0 = cf[0];
         aPhi = cfma(aPhi, t, M0);
-        aPsi = cfma(aPsi, t, mb[2 * (p + 1)]);
+        aPsi = cfma(aPsi, t, cf[2 * (p + 1)]);
         aF = cmul(aF, t);
         aFc = cmul(aFc, t);
         const double2 Phi = cmul(aPhi, t), Psi = cmul(aPsi, t);
@@ -445,10 +476,22 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
     for (int jy = max(iy - 1, 0); jy <= min(iy + 1, n - 1); ++jy) {
       const int nl = jx * n + jy;
       const int e0 = starts[nl], e1 = starts[nl + 1];
-      for (int s = e0; s < e1; ++s) {
-        const int j = perm[s];
-        if (vid[j] == vi) continue;
-        direct_term(zx, zy, X[j], X[P + j], w[j] * f[j], w[j] * f[P + j], ux, uy);
+      for (int c0 = e0; c0 < e1; c0 += 64) {
+        const int cnt = min(64, e1 - c0);
+        __syncthreads();  // the previous chunk is done
+        if ((int)threadIdx.x < cnt) {
+          const int j = perm[c0 + threadIdx.x];
+          sx_[threadIdx.x] = X[j];
+          sy_[threadIdx.x] = X[P + j];
+          sfx[threadIdx.x] = w[j] * f[j];
+          sfy[threadIdx.x] = w[j] * f[P + j];
+          sv[threadIdx.x] = vid[j];
+        }
+        __syncthreads();
+        for (int q = 0; q < cnt; ++q) {
+          if (sv[q] == vi) continue;
+          direct_term(zx, zy, sx_[q], sy_[q], sfx[q], sfy[q], ux, uy);
+        }
       }
     }
   // own-vesicle sources outside those leaves were in the expansions: take them out
@@ -522,7 +565,7 @@ hipError_t launch_treecode(const double* X, const double* f, const double* w, co
   double2* mom = reinterpret_cast<double2*>(base + t.mom);
   const int nleaf = 1 << (2 * depth);
 
-  if (depth < 0 || depth > kMaxDepth) return hipErrorInvalidValue;
+  if (depth < 0 || depth > kMaxDepth || p < 1 || p > kMaxOrder) return hipErrorInvalidValue;
   // boxes of level l start at box index sum_{m = 2}^{l-1} 4^m
   Levels lv = {};
   size_t acc = 0;
@@ -548,9 +591,7 @@ hipError_t launch_treecode(const double* X, const double* f, const double* w, co
                        mom + lv.mom[depth], bcount + lv.box[depth]);
     for (int l = depth - 1; l >= 2; --l) {
       const int n = 1 << l;
-      const size_t work = (size_t)n * n * (p + 1);
-      const int gb = (int)((work + kTB - 1) / kTB < 4096 ? (work + kTB - 1) / kTB : 4096);
-      hipLaunchKernelGGL(k_tc_m2m, dim3(gb), dim3(kTB), 0, st, geom, n, p, mom + lv.mom[l + 1],
+      hipLaunchKernelGGL(k_tc_m2m, dim3(n * n), dim3(64), 0, st, geom, n, p, mom + lv.mom[l + 1],
                          bcount + lv.box[l + 1], mom + lv.mom[l], bcount + lv.box[l]);
     }
     const size_t nbox = acc;
