@@ -198,9 +198,9 @@ VESNET_API int vesnet_near_layers(const double* X, const double* arc_weights, co
                                   int32_t n_vesicles, int32_t n_points, double* layers, void* stream);
 
 /* Workspace of vesnet_rbf_fit: one slot of packed 32 x 32 float64 tiles per concurrently
-   factored vesicle (at most 512 slots).  max_points bounds N_v (1 .. 256); returns 0 when
-   max_points or n_vesicles is out of range.  A smaller workspace of at least one slot also
-   works, with fewer vesicles factored at once. */
+   factored vesicle (one wavefront each; at most 2048 slots, and at most 1 GiB recommended).
+   max_points bounds N_v (1 .. 200); returns 0 when max_points or n_vesicles is out of range.  A
+   smaller workspace of at least one slot also works, with fewer vesicles factored at once. */
 VESNET_API size_t vesnet_rbf_workspace_bytes(int32_t max_points, int32_t n_vesicles);
 
 /* Gaussian radial basis interpolation of the layer velocities (Section 3.3): for each vesicle

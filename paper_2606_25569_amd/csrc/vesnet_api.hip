@@ -295,10 +295,17 @@ extern "C" int vesnet_elastic_force(const double* X, const double* sigma, double
 
 namespace {
 
-constexpr int32_t kRbfMaxPoints = 256;  // 5 x 256 nodes per vesicle
-constexpr int kRbfMaxSlots = 512;       // two fit workgroups per compute unit
+constexpr int32_t kRbfMaxPoints = 200;         // 5 x 200 nodes per vesicle
+constexpr int kRbfMaxSlots = 2048;             // eight one-wavefront fits per compute unit
+constexpr size_t kRbfSlotBudget = (size_t)1 << 30;  // recommended workspace at most 1 GiB
 
-int rbf_slots(int32_t M) { return M < kRbfMaxSlots ? (int)M : kRbfMaxSlots; }
+int rbf_slots(int32_t M, int32_t max_points) {
+  const size_t per = rbf_slot_doubles(max_points) * sizeof(double);
+  size_t k = kRbfSlotBudget / per;
+  if (k < 1) k = 1;
+  if (k > (size_t)kRbfMaxSlots) k = kRbfMaxSlots;
+  return M < (int32_t)k ? (int)M : (int)k;
+}
 
 int check_width(double eps) {
   if (!(eps > 0.0) || !std::isfinite(eps)) return fail(VESNET_ERR_INVALID_ARGUMENT, "width must be > 0 and finite (got %g)", eps);
@@ -324,7 +331,7 @@ extern "C" int vesnet_near_layers(const double* X, const double* w, const int32_
 
 extern "C" size_t vesnet_rbf_workspace_bytes(int32_t max_points, int32_t M) {
   if (max_points < 1 || max_points > kRbfMaxPoints || M < 1) return 0;
-  return (size_t)rbf_slots(M) * rbf_slot_doubles(max_points) * sizeof(double);
+  return (size_t)rbf_slots(M, max_points) * rbf_slot_doubles(max_points) * sizeof(double);
 }
 
 extern "C" int vesnet_rbf_fit(const double* layers, const double* vel, const double* w, const int32_t* off, int32_t M,
@@ -347,7 +354,8 @@ extern "C" int vesnet_rbf_fit(const double* layers, const double* vel, const dou
       overlaps(coeffs, lb, ws, ws_bytes) || overlaps(ws, ws_bytes, layers, lb) || overlaps(ws, ws_bytes, vel, lb))
     return fail(VESNET_ERR_INVALID_ARGUMENT, "coeffs or workspace overlap another array");
   size_t slots = ws_bytes / slot;
-  if (slots > (size_t)rbf_slots(M)) slots = (size_t)rbf_slots(M);
+  if (slots > (size_t)kRbfMaxSlots) slots = kRbfMaxSlots;
+  if (slots > (size_t)M) slots = (size_t)M;
   hipError_t e = launch_rbf_fit(layers, vel, w, off, M, P, max_points, width, coeffs, static_cast<double*>(ws),
                                 (int)slots, stream);
   if (e != hipSuccess) return hip_fail(e, "rbf fit launch");

@@ -5,13 +5,16 @@
 // takes its coefficients from the symmetric positive definite system K c = u, K_ab = phi(|x_a - x_b|),
 // which the paper solves by batched Cholesky factorisation.
 //
-// k_rbf_fit: one workgroup per vesicle factors K = L L^T in float64 by a left-looking blocked
+// k_rbf_fit: one wavefront per vesicle factors K = L L^T in float64 by a left-looking blocked
 // algorithm on 32 x 32 tiles.  The entries of K are recomputed from the node coordinates when a
-// panel needs them, so only L is stored (in a per-workgroup slot of the tile workspace, lower tiles
-// packed).  The two right-hand sides ride along as two extra rows below the matrix (the bordered
-// form [K; u^T]): the same panel updates and triangular solves that produce L's rows produce
-// y = L^{-1} u in them.  A back substitution L^T c = y follows.  The rows are padded to a multiple
-// of 32 with an identity block, which leaves the factor and the solution unchanged.
+// panel needs them, so only L is stored (in a per-wavefront slot of the tile workspace, lower tiles
+// packed).  Each diagonal tile is factored in LDS and inverted, W = L_JJ^{-1}; the tiles below it
+// are then L_IJ = T_IJ W^T, a small GEMM like the panel updates, and W replaces L_JJ in the slot
+// (no later panel reads L_JJ).  The two right-hand sides ride along as two extra rows below the
+// matrix (the bordered form [K; u^T]), so the same steps leave y = L^{-1} u in them; the back
+// substitution L^T c = y then takes c_J = W_JJ^T (y_J - sum_{I>J} L_IJ^T c_I), block by block.  The
+// rows are padded to a multiple of 32 with an identity block, which leaves the factor and the
+// solution unchanged.
 //
 // k_rbf_eval_near: one wavefront per near (target, vesicle) pair sums phi c over the vesicle's nodes
 // and adds the result into the target's velocity.
@@ -27,16 +30,13 @@ namespace {
 
 constexpr int kT = 32;           // tile edge
 constexpr int kLd = kT + 1;      // LDS row stride in doubles (conflict-free column reads)
-constexpr int kCT = 4;           // row tiles per panel chunk
-constexpr int kCR = kT * kCT;    // rows per panel chunk
-constexpr int kFB = 256;         // threads of the fit kernel (4 wavefronts, one per chunk tile)
-constexpr int kMaxNodes = 1280;  // 5 x 256 points
-constexpr int kMaxPad = kMaxNodes;
+constexpr int kFW = 64;          // one wavefront per vesicle
+constexpr int kMaxNodes = 1000;  // 5 x 200 points: the back substitution's 2 x 1024 + 64 doubles fit the LDS pool
 
 __device__ __forceinline__ int clamp_i(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 // Packed lower tiles: tile (I, J), J <= I, at index I (I + 1) / 2 + J; the right-hand-side tile row
-// I = nb follows the same formula.
+// I = nb follows the same formula.  The back substitution's two vectors follow the tiles.
 __device__ __forceinline__ size_t tile_index(int I, int J) { return (size_t)I * (I + 1) / 2 + J; }
 
 struct NodeView {
@@ -62,21 +62,97 @@ __device__ __forceinline__ double bordered_entry(const NodeView& nv, int row, in
   return exp(-(dx * dx + dy * dy) * nv.inv_w2);
 }
 
-__global__ __launch_bounds__(kFB, 2) void k_rbf_fit(const double* __restrict__ layers, const double* __restrict__ vel,
+// 32 x 32 tile from the slot into LDS (row stride kLd): every load is issued before any store.
+__device__ __forceinline__ void stage_tile(double* __restrict__ dst, const double* __restrict__ src, int lane) {
+  double v[kT * kT / kFW];
+#pragma unroll
+  for (int t = 0; t < kT * kT / kFW; ++t) v[t] = src[lane + kFW * t];
+#pragma unroll
+  for (int t = 0; t < kT * kT / kFW; ++t) {
+    const int e = lane + kFW * t;
+    dst[(e >> 5) * kLd + (e & 31)] = v[t];
+  }
+}
+
+// Value of v in lane src (src the same in every lane) by two v_readlane.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// This lane's 4 x 4 block (rows I kT + 4 rg + i, columns J kT + 4 cg + j) of the bordered, padded
+// matrix, with the node coordinates loaded before the Gaussians are formed.
+__device__ __forceinline__ void entry_block(const NodeView& nv, int I, int J, int rg, int cg, double (&acc)[4][4]) {
+  const int r0 = I * kT + rg * 4, c0 = J * kT + cg * 4;
+  if (r0 >= nv.npad) {  // right-hand-side rows: u_x, u_y, then zeros
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = r0 + i - nv.npad, col = c0 + j;
+        acc[i][j] = (col >= nv.n || q > 1) ? 0.0 : (q == 0 ? nv.ux[col] : nv.uy[col]);
+      }
+    return;
+  }
+  double xr[4], yr[4], xc[4], yc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = min(r0 + i, nv.n - 1), col = min(c0 + i, nv.n - 1);
+    xr[i] = nv.x[row];
+    yr[i] = nv.y[row];
+    xc[i] = nv.x[col];
+    yc[i] = nv.y[col];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = r0 + i, col = c0 + j;
+      if (row >= nv.n || col >= nv.n) {
+        acc[i][j] = row == col ? 1.0 : 0.0;
+      } else {
+        const double dx = xr[i] - xc[j], dy = yr[i] - yc[j];
+        acc[i][j] = exp(-(dx * dx + dy * dy) * nv.inv_w2);
+      }
+    }
+}
+
+// acc[i][j] += sign * sum_m Ar[(4 rg + i), m] Bc[(4 cg + j), m] over one 32-wide k-range.
+__device__ __forceinline__ void tile_gemm(double (&acc)[4][4], const double* __restrict__ Ar,
+                                          const double* __restrict__ Bc, int rg, int cg, double sign) {
+#pragma unroll 4
+  for (int m = 0; m < kT; ++m) {
+    double a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = sign * Ar[(rg * 4 + i) * kLd + m];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = Bc[(cg * 4 + j) * kLd + m];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+  }
+}
+
+__global__ __launch_bounds__(kFW, 2) void k_rbf_fit(const double* __restrict__ layers, const double* __restrict__ vel,
                                                  const double* __restrict__ w, const int32_t* __restrict__ off,
                                                  int M, int P, int nmax, double eps, double* __restrict__ coeffs,
-                                                 double* __restrict__ tiles, size_t slot_doubles) {
-  __shared__ double A[kCR * kLd];   // panel rows of L (GEMM operand), then the chunk being finished
-  __shared__ double B[kT * kLd];    // diagonal tile row of L (GEMM operand)
-  __shared__ double Ljj[kT * kLd];  // factored diagonal tile of the current panel
-  __shared__ double dinv[kT];       // 1 / L_jj[c][c]
-  __shared__ double cv[2 * kMaxPad];
-  __shared__ double red[4 * 64];
+                                                 double* __restrict__ tiles, size_t slot_doubles,
+                                                 size_t slot_tile_doubles) {
+  // LDS: A (row operand, then the tile being finished) and B (L_Jk, or W = L_JJ^{-1} re-staged from the
+  // slot for the tiles below the diagonal); the back substitution reuses the pool for its two vectors
+  // (2 npad <= 2048) and one exchange row.  Two tiles (17 KB) let eight wavefronts share a CU.
+  __shared__ double pool[2 * kT * kLd];
+  double* A = pool;
+  double* B = pool + kT * kLd;
 
-  const int tid = threadIdx.x;
-  const int cg = tid & 7;   // 4 columns: 4 cg .. 4 cg + 3
-  const int rg = tid >> 3;  // 4 rows:    4 rg .. 4 rg + 3 of the chunk
+  const int lane = threadIdx.x;
+  const int cg = lane & 7;   // 4 columns: 4 cg .. 4 cg + 3
+  const int rg = lane >> 3;  // 4 rows:    4 rg .. 4 rg + 3
   double* slot = tiles + (size_t)blockIdx.x * slot_doubles;
+  (void)slot_tile_doubles;
   const size_t P5 = (size_t)5 * P;
 
   for (int v = blockIdx.x; v < M; v += gridDim.x) {
@@ -88,7 +164,7 @@ __global__ __launch_bounds__(kFB, 2) void k_rbf_fit(const double* __restrict__ l
     double* cx = coeffs + (size_t)5 * j0;
     double* cy = coeffs + P5 + (size_t)5 * j0;
     if (npts > nmax) {
-      for (int a = tid; a < n; a += kFB) {
+      for (int a = lane; a < n; a += kFW) {
         cx[a] = NAN;
         cy[a] = NAN;
       }
@@ -105,138 +181,118 @@ __global__ __launch_bounds__(kFB, 2) void k_rbf_fit(const double* __restrict__ l
     nv.npad = nb * kT;
     nv.inv_w2 = 1.0 / ((eps * h) * (eps * h));
 
-    // ---- factorisation, panel by panel
+    // ---- factorisation, panel by panel; tile row nb holds the right-hand sides
     for (int J = 0; J < nb; ++J) {
-      for (int I0 = J; I0 <= nb; I0 += kCT) {
-        const int ntile = min(kCT, nb + 1 - I0);
-        const bool active = rg * 4 < ntile * kT;  // whole wavefronts drop out together
+      for (int I = J; I <= nb; ++I) {
         double acc[4][4];
+        entry_block(nv, I, J, rg, cg, acc);
+        // T = A - sum_{k < J} L(I, k) L(J, k)^T
+        for (int k = 0; k < J; ++k) {
+          __syncthreads();  // A and B are free
+          stage_tile(B, slot + tile_index(J, k) * (kT * kT), lane);
+          if (I != J) stage_tile(A, slot + tile_index(I, k) * (kT * kT), lane);
+          __syncthreads();
+          tile_gemm(acc, I != J ? A : B, B, rg, cg, -1.0);
+        }
+        __syncthreads();  // A is free
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
-            acc[i][j] = active ? bordered_entry(nv, I0 * kT + rg * 4 + i, J * kT + cg * 4 + j) : 0.0;
-        // T = A - sum_{k < J} L(rows, k) L(J, k)^T
-        for (int k = 0; k < J; ++k) {
-          __syncthreads();  // A and B are free
-          for (int e = tid; e < ntile * kT * kT; e += kFB) {
-            const int r = e >> 5, c = e & 31;
-            A[r * kLd + c] = slot[tile_index(I0 + (r >> 5), k) * (kT * kT) + (r & 31) * kT + c];
+          for (int j = 0; j < 4; ++j) A[(rg * 4 + i) * kLd + cg * 4 + j] = acc[i][j];
+        __syncthreads();
+        double* dst = slot + tile_index(I, J) * (kT * kT);
+        if (I == J) {
+          // Cholesky of the diagonal tile with lane i holding row i in registers (lanes 32..63
+          // repeat lanes 0..31): column j takes s_i = T[i][j] - sum_{m<j} L[i][m] L[j][m], row j
+          // read from lane j; L[j][j] = sqrt(s_j) and L[i][j] = s_i / L[j][j] below it.
+          const int i = lane & (kT - 1);
+          double row[kT];
+#pragma unroll
+          for (int c = 0; c < kT; ++c) row[c] = A[i * kLd + c];
+#pragma unroll
+          for (int j = 0; j < kT; ++j) {
+            double sj = row[j];
+#pragma unroll
+            for (int m = 0; m < j; ++m) sj = fma(-row[m], lane_bcast(row[m], j), sj);
+            const double d = sqrt(lane_bcast(sj, j));
+            const double di = 1.0 / d;
+            row[j] = i > j ? sj * di : (i == j ? d : 0.0);
           }
-          for (int e = tid; e < kT * kT; e += kFB) B[(e >> 5) * kLd + (e & 31)] = slot[tile_index(J, k) * (kT * kT) + e];
+          if (lane < kT) {
+#pragma unroll
+            for (int c = 0; c < kT; ++c) A[i * kLd + c] = row[c];
+          }
           __syncthreads();
-          if (active) {
-#pragma unroll 4
-            for (int m = 0; m < kT; ++m) {
-              double a[4], b[4];
+          // W = L^{-1} with lane i holding column i: W[r][i] = (delta_ri - sum_{m<r} L[r][m] W[m][i]) / L[r][r],
+          // L read from LDS (the same address in every lane); W goes to the slot in place of L_JJ
+          double wc[kT];
 #pragma unroll
-              for (int i = 0; i < 4; ++i) a[i] = A[(rg * 4 + i) * kLd + m];
+          for (int r = 0; r < kT; ++r) {
+            double t = i == r ? 1.0 : 0.0;
 #pragma unroll
-              for (int j = 0; j < 4; ++j) b[j] = B[(cg * 4 + j) * kLd + m];
-#pragma unroll
-              for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(-a[i], b[j], acc[i][j]);
-            }
+            for (int m = 0; m < r; ++m) t = fma(-A[r * kLd + m], wc[m], t);
+            wc[r] = t / A[r * kLd + r];
           }
-        }
-        __syncthreads();  // A is free: it now holds the chunk
-        if (active) {
+          if (lane < kT) {
+#pragma unroll
+            for (int r = 0; r < kT; ++r) B[r * kLd + lane] = wc[r];
+          }
+          __syncthreads();
+          for (int e = lane; e < kT * kT; e += kFW) dst[e] = B[(e >> 5) * kLd + (e & 31)];
+          __syncthreads();
+        } else {
+          // L_IJ = T W^T, W staged into B from the slot
+          {
+            const double* wsrc = slot + tile_index(J, J) * (kT * kT);
+            for (int e = lane; e < kT * kT; e += kFW) B[(e >> 5) * kLd + (e & 31)] = wsrc[e];
+          }
+          __syncthreads();
+          double out[4][4];
 #pragma unroll
           for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) A[(rg * 4 + i) * kLd + cg * 4 + j] = acc[i][j];
-        }
-        __syncthreads();
-        if (I0 == J) {
-          // unblocked Cholesky of the diagonal tile (chunk rows 0..31), in place.  Step c updates the
-          // trailing lower triangle with the unscaled column c and the pivot A_cc (one barrier per
-          // step); the columns are scaled by 1 / sqrt(pivot) once all steps are done.
-          for (int c = 0; c < kT; ++c) {
-            const double rp = 1.0 / A[c * kLd + c];
-            for (int e = tid; e < kT * kT; e += kFB) {
-              const int r = e >> 5, s2 = e & 31;
-              if (s2 > c && r >= s2) A[r * kLd + s2] = fma(-A[r * kLd + c] * rp, A[s2 * kLd + c], A[r * kLd + s2]);
-            }
-            __syncthreads();
-          }
-          if (tid < kT) dinv[tid] = 1.0 / sqrt(A[tid * kLd + tid]);
-          __syncthreads();
-          for (int e = tid; e < kT * kT; e += kFB) {
-            const int r = e >> 5, s2 = e & 31;
-            const double l = s2 > r ? 0.0 : A[r * kLd + s2] * dinv[s2];
-            Ljj[r * kLd + s2] = l;
-          }
-          __syncthreads();
-          for (int e = tid; e < kT * kT; e += kFB) A[(e >> 5) * kLd + (e & 31)] = Ljj[(e >> 5) * kLd + (e & 31)];
-          __syncthreads();
-        }
-        // triangular solve of the chunk's other rows: x L_jj^T = t, one thread per row
-        const int r = tid;
-        const int rlo = I0 == J ? kT : 0;
-        if (r >= rlo && r < ntile * kT) {
-          double x[kT];
+            for (int j = 0; j < 4; ++j) out[i][j] = 0.0;
+          tile_gemm(out, A, B, rg, cg, 1.0);
 #pragma unroll
-          for (int c = 0; c < kT; ++c) x[c] = A[r * kLd + c];
-          // column by column: x_c is final once scaled, then removed from the later unknowns
-          // (independent updates rather than one dependent chain per unknown)
+          for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int c = 0; c < kT; ++c) {
-            x[c] *= dinv[c];
-#pragma unroll
-            for (int m = c + 1; m < kT; ++m) x[m] = fma(-x[c], Ljj[m * kLd + c], x[m]);
-          }
-#pragma unroll
-          for (int c = 0; c < kT; ++c) A[r * kLd + c] = x[c];
-        }
-        __syncthreads();
-        for (int e = tid; e < ntile * kT * kT; e += kFB) {
-          const int rr = e >> 5, c = e & 31;
-          slot[tile_index(I0 + (rr >> 5), J) * (kT * kT) + (rr & 31) * kT + c] = A[rr * kLd + c];
+            for (int j = 0; j < 4; ++j) dst[(rg * 4 + i) * kT + cg * 4 + j] = out[i][j];
         }
       }
     }
     __syncthreads();
 
-    // ---- back substitution L^T c = y; y sits in rows 0, 1 of the tile row nb
-    for (int e = tid; e < 2 * nv.npad; e += kFB) {
+    // ---- back substitution: c_J = W_JJ^T (y_J - sum_{I > J} L_IJ^T c_I); y in rows 0, 1 of tile row nb
+    double* cv = pool;                    // [2][npad]
+    double* zx = pool + 2 * nv.npad;      // [2][32]
+    for (int e = lane; e < 2 * nv.npad; e += kFW) {
       const int q = e / nv.npad, a = e - q * nv.npad;
       cv[e] = slot[tile_index(nb, a >> 5) * (kT * kT) + q * kT + (a & 31)];
     }
     __syncthreads();
-    const int comb = tid & 63;  // (right-hand side q, column c)
-    const int q = comb >> 5, c = comb & 31;
-    const int part = tid >> 6;
+    const int q = lane >> 5, c = lane & 31;
     for (int J = nb - 1; J >= 0; --J) {
-      // z = y_J - sum_{I > J} L(I, J)^T c_I, rows split over the four wavefronts
-      double s = 0.0;
-      for (int I = J + 1 + part; I < nb; I += 4) {
+      double z = cv[q * nv.npad + J * kT + c];
+      for (int I = J + 1; I < nb; ++I) {
         const double* Lt = slot + tile_index(I, J) * (kT * kT);
         const double* cI = cv + q * nv.npad + I * kT;
-        for (int rr = 0; rr < kT; ++rr) s = fma(Lt[rr * kT + c], cI[rr], s);
+#pragma unroll 8
+        for (int r = 0; r < kT; ++r) z = fma(-Lt[r * kT + c], cI[r], z);
       }
-      red[part * 64 + comb] = s;
-      for (int e = tid; e < kT * kT; e += kFB)
-        Ljj[(e >> 5) * kLd + (e & 31)] = slot[tile_index(J, J) * (kT * kT) + e];
+      zx[q * kT + c] = z;
       __syncthreads();
-      if (tid < 64) {
-        double z = cv[q * nv.npad + J * kT + c] - (((red[comb] + red[64 + comb]) + red[128 + comb]) + red[192 + comb]);
-        // L_jj^T x = z, last unknown first; lane (q, c) owns x_c
-        double xc = 0.0;
-        for (int k = kT - 1; k >= 0; --k) {
-          const double xk = __shfl(z, q * 32 + k, 64) / Ljj[k * kLd + k];
-          if (c == k) xc = xk;
-          if (c < k) z = fma(-Ljj[k * kLd + c], xk, z);
-        }
-        cv[q * nv.npad + J * kT + c] = xc;
-      }
+      const double* Wjj = slot + tile_index(J, J) * (kT * kT);
+      double x = 0.0;
+#pragma unroll 8
+      for (int r = 0; r < kT; ++r) x = fma(Wjj[r * kT + c], zx[q * kT + r], x);
+      cv[q * nv.npad + J * kT + c] = x;
       __syncthreads();
     }
-    for (int a = tid; a < n; a += kFB) {
+    for (int a = lane; a < n; a += kFW) {
       cx[a] = cv[a];
       cy[a] = cv[nv.npad + a];
     }
-    __syncthreads();  // cv and the slot are reused by the next vesicle
+    __syncthreads();  // the slot and LDS are reused by the next vesicle
   }
 }
 
@@ -290,9 +346,14 @@ __global__ __launch_bounds__(kEB) void k_rbf_eval_near(const double* __restrict_
 
 }  // namespace
 
-size_t rbf_slot_doubles(int nmax) {
+static size_t rbf_slot_tile_doubles(int nmax) {
   const int nb = (5 * nmax + kT - 1) / kT;
   return (size_t)nb * (nb + 3) / 2 * (kT * kT);
+}
+
+size_t rbf_slot_doubles(int nmax) {
+  const int nb = (5 * nmax + kT - 1) / kT;
+  return rbf_slot_tile_doubles(nmax) + (size_t)2 * nb * kT;
 }
 
 hipError_t launch_rbf_fit(const double* layers, const double* vel, const double* w, const int32_t* off, int M, int P,
@@ -300,8 +361,8 @@ hipError_t launch_rbf_fit(const double* layers, const double* vel, const double*
   if (M == 0 || P == 0) return hipSuccess;
   if (5 * nmax > kMaxNodes || slots < 1) return hipErrorInvalidValue;
   const int grid = M < slots ? M : slots;
-  hipLaunchKernelGGL(k_rbf_fit, dim3(grid), dim3(kFB), 0, reinterpret_cast<hipStream_t>(stream), layers, vel, w, off,
-                     M, P, nmax, eps, coeffs, tiles, rbf_slot_doubles(nmax));
+  hipLaunchKernelGGL(k_rbf_fit, dim3(grid), dim3(kFW), 0, reinterpret_cast<hipStream_t>(stream), layers, vel, w, off,
+                     M, P, nmax, eps, coeffs, tiles, rbf_slot_doubles(nmax), rbf_slot_tile_doubles(nmax));
   return hipGetLastError();
 }
 

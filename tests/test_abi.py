@@ -185,17 +185,19 @@ def test_near_layers_and_rbf_reject(L):
     assert lib.vesnet_near_layers(None, None, None, 0, 0, None, None) == 0
     # workspace query: out-of-range max_points or vesicle count gives 0
     assert lib.vesnet_rbf_workspace_bytes(0, 4) == 0
-    assert lib.vesnet_rbf_workspace_bytes(257, 4) == 0
+    assert lib.vesnet_rbf_workspace_bytes(201, 4) == 0
     assert lib.vesnet_rbf_workspace_bytes(32, 0) == 0
     slot = lib.vesnet_rbf_workspace_bytes(32, 1)
     assert slot > 0 and lib.vesnet_rbf_workspace_bytes(32, 4) == 4 * slot
-    assert lib.vesnet_rbf_workspace_bytes(32, 100000) == 512 * slot
+    assert lib.vesnet_rbf_workspace_bytes(32, 100000) == 2048 * slot          # 2048 slots of 160 KB
+    big = lib.vesnet_rbf_workspace_bytes(200, 1)
+    assert lib.vesnet_rbf_workspace_bytes(200, 100000) == (2 ** 30 // big) * big  # capped at 1 GiB
     fit = lambda **k: lib.vesnet_rbf_fit(k.get("lay", lay), vel, w, off, 2, 10, k.get("nmax", 32),
                                          k.get("width", 1.0), k.get("co", co), k.get("ws", ws),
                                          k.get("wsb", slot), None)
     assert fit(width=0.0) == -1
     assert fit(width=float("inf")) == -1
-    assert fit(nmax=300) == -2
+    assert fit(nmax=201) == -2
     assert fit(lay=None) == -1
     assert fit(wsb=slot - 1) == -3
     assert fit(ws=None) == -3

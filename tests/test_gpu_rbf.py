@@ -104,7 +104,7 @@ def test_rbf_fit_and_eval_parity(width):
     coefficients solve K c = u with a backward error of a stable Cholesky solve."""
     import torch
     import paper_2606_25569_amd as V
-    sizes = [3, 7, 0, 32, 33, 64, 100, 128, 256]
+    sizes = [3, 7, 0, 32, 33, 64, 100, 128, 200]
     X, w, off, layers, h, U, L, wd, coeffs = _fit_case(sizes, 31, width)
     c_gpu = coeffs.cpu().numpy()
     c_ref = NR.rbf_fit(layers, U, w, off, width)
