@@ -392,6 +392,39 @@ __device__ __forceinline__ void direct_term(double zx, double zy, double sx, dou
   uy = fma(lg, Fy, fma(s, ry, uy));
 }
 
+// Walk over the interaction lists of a leaf (ix, iy), levels 2..depth, candidates in a fixed order;
+// the same in every lane.  Yields the non-empty boxes (level, sx, sy).
+struct ListWalk {
+  int l, a, b;
+};
+
+// First box of level l >= 2 when levels 2, 3, ... are stored one after another: sum_{m=2}^{l-1} 4^m.
+__device__ __forceinline__ size_t level_box_base(int l) { return (((size_t)1 << (2 * l)) - 16) / 3; }
+
+__device__ __forceinline__ bool next_box(ListWalk& s, int depth, int ix, int iy, const int32_t* __restrict__ bcount,
+                                         int& lo, int& sxo, int& syo) {
+  while (s.l <= depth) {
+    const int l = s.l, nl = 1 << l;
+    const int bx = ix >> (depth - l), by = iy >> (depth - l);
+    const int sx = 2 * (bx >> 1) + s.a, sy = 2 * (by >> 1) + s.b;
+    if (++s.b > 3) {
+      s.b = -2;
+      if (++s.a > 3) {
+        s.a = -2;
+        ++s.l;
+      }
+    }
+    if (sx < 0 || sx >= nl || sy < 0 || sy >= nl) continue;
+    if (abs(sx - bx) <= 1 && abs(sy - by) <= 1) continue;
+    if (bcount[level_box_base(l) + (size_t)sx * nl + sy] == 0) continue;
+    lo = l;
+    sxo = sx;
+    syo = sy;
+    return true;
+  }
+  return false;
+}
+
 // One wavefront per (leaf, chunk of 64 of its points); every lane one target.
 __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, const double* __restrict__ f,
                                                 const double* __restrict__ w, int P, const int32_t* __restrict__ off,
@@ -399,7 +432,7 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ starts,
                                                 const int32_t* __restrict__ wstart, const Geom* __restrict__ geom,
                                                 int depth, int p, const double2* __restrict__ mom,
-                                                const int32_t* __restrict__ bcount, const Levels lv, double scale,
+                                                const int32_t* __restrict__ bcount, double scale,
                                                 double* __restrict__ out) {
   const int n = 1 << depth;
   const int nleaf = n * n;
@@ -422,53 +455,64 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
   const int stride = 4 * (p + 1);
   double ux = 0.0, uy = 0.0;
   // per-wavefront staging: the moments of one box, then chunks of 64 direct sources
-  __shared__ double2 cf[4 * (kMaxOrder + 1)];
+  __shared__ double2 cf[4 * 64];  // 4 (p + 1) <= 196 entries used; padded for whole-wave copies
   __shared__ double sx_[64], sy_[64], sfx[64], sfy[64];
   __shared__ int32_t sv[64];
 
-  // expansions of the interaction lists, level by level
-  for (int l = 2; l <= depth; ++l) {
-    const int nl = 1 << l;
-    const int bx = ix >> (depth - l), by = iy >> (depth - l);
-    const double2* ml = mom + lv.mom[l];
-    const int32_t* cl = bcount + lv.box[l];
-    for (int a = -2; a <= 3; ++a) {
-      const int sx = 2 * (bx >> 1) + a;
-      if (sx < 0 || sx >= nl) continue;
-      for (int b = -2; b <= 3; ++b) {
-        const int sy = 2 * (by >> 1) + b;
-        if (sy < 0 || sy >= nl) continue;
-        if (abs(sx - bx) <= 1 && abs(sy - by) <= 1) continue;
-        const int sb = sx * nl + sy;
-        if (cl[sb] == 0) continue;
-        const double2* mb = ml + (size_t)sb * stride;
-        __syncthreads();  // the previous box is done with cf
-        for (int e = threadIdx.x; e < stride; e += 64) cf[e] = mb[e];
-        __syncthreads();
-        const double2 c = box_center(g, nl, sx, sy);
-        const double2 wv = make_double2(zx - c.x, zy - c.y);
-        const double w2 = wv.x * wv.x + wv.y * wv.y;
-        const double2 t = make_double2(wv.x / w2, -wv.y / w2);
-        // Horner, highest order first
-        double2 aF = make_double2(0.0, 0.0), aFc = aF, aPhi = aF, aPsi = aF;
-        for (int k = p; k >= 1; --k) {
-          aF = cfma(aF, t, cf[3 * (p + 1) + k]);
-          aFc = cfma(aFc, t, cf[(p + 1) + k]);
-          aPhi = cfma(aPhi, t, cf[k]);
-          aPsi = cfma(aPsi, t, cf[2 * (p + 1) + k]);
-        }
-        const double2 M0 = cf[0];
-        aPhi = cfma(aPhi, t, M0);
-        aPsi = cfma(aPsi, t, cf[2 * (p + 1)]);
-        aF = cmul(aF, t);
-        aFc = cmul(aFc, t);
-        const double2 Phi = cmul(aPhi, t), Psi = cmul(aPsi, t);
-        const double lnw = 0.5 * log_pos(w2);
-        // w conj(Phi)
-        const double2 wPhi = cmul(wv, make_double2(Phi.x, -Phi.y));
-        ux += -M0.x * lnw + 0.5 * (aF.x + aFc.x) + 0.5 * M0.x + 0.5 * (wPhi.x - Psi.x);
-        uy += -M0.y * lnw + 0.5 * (aF.y - aFc.y) + 0.5 * M0.y + 0.5 * (wPhi.y + Psi.y);
+  // expansions of the interaction lists: box by box, the next box's moments loaded into registers
+  // while the current one is evaluated from LDS
+  // four entries per lane: 4 x 64 >= 4 (kMaxOrder + 1); the moment array has 256 spare entries
+  double2 n0 = make_double2(0.0, 0.0), n1 = n0, n2 = n0, n3 = n0;
+  ListWalk it = {2, -2, -2};
+  int nl_ = 0, nsx = 0, nsy = 0;
+  bool have = next_box(it, depth, ix, iy, bcount, nl_, nsx, nsy);
+  if (have) {
+    const double2* mb = mom + (level_box_base(nl_) + (size_t)nsx * (1 << nl_) + nsy) * stride;
+    n0 = mb[threadIdx.x];
+    n1 = mb[threadIdx.x + 64];
+    n2 = mb[threadIdx.x + 128];
+    n3 = mb[threadIdx.x + 192];
+  }
+  while (have) {
+    __syncthreads();  // the previous box is done with cf
+    cf[threadIdx.x] = n0;
+    cf[threadIdx.x + 64] = n1;
+    cf[threadIdx.x + 128] = n2;
+    cf[threadIdx.x + 192] = n3;
+    __syncthreads();
+    const int l = nl_, sx = nsx, sy = nsy;
+    have = next_box(it, depth, ix, iy, bcount, nl_, nsx, nsy);
+    if (have) {
+      const double2* mb = mom + (level_box_base(nl_) + (size_t)nsx * (1 << nl_) + nsy) * stride;
+      n0 = mb[threadIdx.x];
+      n1 = mb[threadIdx.x + 64];
+      n2 = mb[threadIdx.x + 128];
+      n3 = mb[threadIdx.x + 192];
+    }
+    {
+      const double2 c = box_center(g, 1 << l, sx, sy);
+      const double2 wv = make_double2(zx - c.x, zy - c.y);
+      const double w2 = wv.x * wv.x + wv.y * wv.y;
+      const double2 t = make_double2(wv.x / w2, -wv.y / w2);
+      // Horner, highest order first
+      double2 aF = make_double2(0.0, 0.0), aFc = aF, aPhi = aF, aPsi = aF;
+      for (int k = p; k >= 1; --k) {
+        aF = cfma(aF, t, cf[3 * (p + 1) + k]);
+        aFc = cfma(aFc, t, cf[(p + 1) + k]);
+        aPhi = cfma(aPhi, t, cf[k]);
+        aPsi = cfma(aPsi, t, cf[2 * (p + 1) + k]);
       }
+      const double2 M0 = cf[0];
+      aPhi = cfma(aPhi, t, M0);
+      aPsi = cfma(aPsi, t, cf[2 * (p + 1)]);
+      aF = cmul(aF, t);
+      aFc = cmul(aFc, t);
+      const double2 Phi = cmul(aPhi, t), Psi = cmul(aPsi, t);
+      const double lnw = 0.5 * log_pos(w2);
+      // w conj(Phi)
+      const double2 wPhi = cmul(wv, make_double2(Phi.x, -Phi.y));
+      ux += -M0.x * lnw + 0.5 * (aF.x + aFc.x) + 0.5 * M0.x + 0.5 * (wPhi.x - Psi.x);
+      uy += -M0.y * lnw + 0.5 * (aF.y - aFc.y) + 0.5 * M0.y + 0.5 * (wPhi.y + Psi.y);
     }
   }
   // 3 x 3 leaves directly, own vesicle skipped
@@ -538,7 +582,7 @@ static TreeLayout tree_layout(int P, int depth, int p) {
   t.starts = o;     o += align_up(sizeof(int32_t) * (nleaf + 1));
   t.wstart = o;     o += align_up(sizeof(int32_t) * (nleaf + 1));
   t.bcount = o;     o += align_up(sizeof(int32_t) * (boxes > 0 ? boxes : 1));
-  t.mom = o;        o += align_up(sizeof(double2) * (moms > 0 ? moms : 1));
+  t.mom = o;        o += align_up(sizeof(double2) * (moms + 256));  // 256 spare entries: whole-wave copies
   t.total = o;
   return t;
 }
@@ -601,7 +645,7 @@ hipError_t launch_treecode(const double* X, const double* f, const double* w, co
   }
   const int items = nleaf + (P + 63) / 64;  // bound on sum over leaves of ceil(count / 64)
   hipLaunchKernelGGL(k_tc_eval, dim3(items), dim3(64), 0, st, X, f, w, P, off, vid, leafid, perm, starts, wstart, geom,
-                     depth, p, mom, bcount, lv, scale, out);
+                     depth, p, mom, bcount, scale, out);
   return hipGetLastError();
 }
 
