@@ -539,7 +539,7 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
       }
     }
   // own-vesicle sources outside those leaves were in the expansions: take them out
-  const int v0 = off[vi], v1 = off[vi + 1];
+  const int v0 = clamp_i(off[vi], 0, P), v1 = max(v0, clamp_i(off[vi + 1], 0, P));  // offsets never trusted
   for (int j = v0; j < v1; ++j) {
     if (j == i) continue;
     const int lj = leafid[j];
