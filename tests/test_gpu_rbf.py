@@ -221,3 +221,58 @@ def test_rbf_full_size_sampled():
         worst = max(worst, err / tol)
         assert err <= tol, (v, err, tol)
     say(f"rbf 2000x32 sampled: worst err/tol {worst:.2e}")
+
+
+def test_near_field_chain_graph_replay():
+    """Layers, fit and interpolation launch kernels only: captured in one HIP graph, every replay
+    (with eager work in between) equals the eager chain bit for bit."""
+    import torch
+    import paper_2606_25569_amd as V
+    from paper_2606_25569_amd import _lib as L
+    from paper_2606_25569_amd.farfield import _ptr
+    s = S.rsa_suspension(81, 60, 32, 0.35, gap=0.02)
+    X, f, w = dev_inputs(s)
+    part = V.Partition(s.offsets, "cuda")
+    P, M = s.n_points, s.n_vesicles
+    u, pairs = V.farfield_nearmasked(X, X, f, w, part, s.mu, "fp64")
+    assert pairs.shape[0] > 0
+    pairs = pairs.contiguous()
+    layers = V.near_layers(X, w, part)
+    vel = torch.tensor(S.smooth_field(82, layers.cpu().numpy()), device="cuda")
+    lib = L.lib()
+    rws = torch.empty(lib.vesnet_rbf_workspace_bytes(32, M), dtype=torch.uint8, device="cuda")
+    lay = torch.empty_like(layers)
+    coeffs = torch.empty_like(layers)
+    out = torch.empty_like(u)
+    cnt = torch.tensor([pairs.shape[0]], dtype=torch.int32, device="cuda")
+
+    def chain(stream):
+        sp = stream.cuda_stream
+        out.copy_(u)
+        L.check(lib.vesnet_near_layers(_ptr(X), _ptr(w), _ptr(part.device), M, P, _ptr(lay), sp))
+        L.check(lib.vesnet_rbf_fit(_ptr(lay), _ptr(vel), _ptr(w), _ptr(part.device), M, P, 32, 1.0, _ptr(coeffs),
+                                   _ptr(rws), rws.numel(), sp))
+        L.check(lib.vesnet_rbf_eval_near(_ptr(lay), _ptr(coeffs), _ptr(w), _ptr(part.device), M, P, 1.0, _ptr(X), P,
+                                         _ptr(pairs), _ptr(cnt), pairs.shape[0], _ptr(out), sp))
+
+    chain(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    eager = out.clone()
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(st):
+        chain(st)
+        with torch.cuda.graph(g, stream=st):
+            chain(st)
+    torch.cuda.current_stream().wait_stream(st)
+    # a target near several vesicles adds their interpolants in atomic order: compare to rounding
+    scale = float(eager.abs().max())
+    for k in range(3):
+        out.fill_(float(k) + 3.0)
+        V.farfield_forward(X, X, f, w, part, s.mu, "fp64")  # unrelated eager work in between
+        g.replay()
+        torch.cuda.synchronize()
+        err = float((out - eager).abs().max()) / scale
+        assert err <= 1e-14, (k, err)
+    say("near-field chain: 3 graph replays equal the eager chain")

@@ -97,3 +97,34 @@ def test_treecode_full_size_sampled():
     say(f"treecode 2000x128 depth 6 order 30: err vs oracle {err_o:.2e}, vs exact {err_x:.2e} of max|u|")
     assert err_o <= 1e-12
     assert err_x <= 1e-7
+
+
+def test_treecode_deterministic_and_graph_replay(susp):
+    """Leaves of at most 2048 points give bit-identical results on every call; the call launches
+    kernels only (no allocation, memset or host synchronisation), so it can be captured in a HIP
+    graph, and every replay (with eager work in between) equals the eager result bit for bit."""
+    import torch
+    import paper_2606_25569_amd as V
+    from paper_2606_25569_amd import _lib as L
+    X, f, w = dev_inputs(susp)
+    part = V.Partition(susp.offsets, "cuda")
+    ws = torch.empty(L.lib().vesnet_treecode_workspace_bytes(susp.n_points, 3, 16), dtype=torch.uint8, device="cuda")
+    out = torch.empty((2, susp.n_points), dtype=torch.float64, device="cuda")
+    eager = V.farfield_treecode(X, f, w, part, susp.mu, 16, 3, out=out, workspace=ws).clone()
+    again = V.farfield_treecode(X, f, w, part, susp.mu, 16, 3, out=torch.empty_like(out), workspace=ws)
+    assert torch.equal(eager, again)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        V.farfield_treecode(X, f, w, part, susp.mu, 16, 3, out=out, workspace=ws)  # warm-up on the side stream
+        with torch.cuda.graph(g, stream=s):
+            V.farfield_treecode(X, f, w, part, susp.mu, 16, 3, out=out, workspace=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    for k in range(3):
+        out.fill_(float(k) - 7.0)
+        V.farfield_forward(X, X, f, w, part, susp.mu, "fp64")  # unrelated eager work in between
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), k
+    say("treecode: deterministic, 3 graph replays equal the eager call")
