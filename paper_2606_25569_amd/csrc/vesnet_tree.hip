@@ -9,6 +9,9 @@
 //   -M_0[F] ln|w| + 1/2 sum_{k=1}^p (M_k[F] t^k + conj(M_k[conj F] t^k)) / k + M_0[F] / 2
 //   + (w conj(Phi) - conj(Psi)) / 2,   Phi = sum_{k=0}^p M_k[F] t^(k+1),  Psi = sum_k M_k[conj(zeta) F] t^(k+1).
 //
+// The evaluation merges the conj-F log series and Psi into one series D, and writes w conj(Phi) as
+// (w / conj w) conj(E), E = sum_k M_k[F] t^k: three Horner chains per box.
+//
 // Tree: a uniform quadtree of depth L over the bounding square of the points.  Leaf moments come
 // from the points (k_tc_p2m), coarser ones by exact binomial translation (k_tc_m2m).  A target takes,
 // at each level l = 2..L, the interaction list of its level-l ancestor (children of the parent's
@@ -362,21 +365,26 @@ __global__ __launch_bounds__(64) void k_tc_m2m(const Geom* __restrict__ geom, in
   pm[2 * (p + 1) + k] = s2;
 }
 
-// Row 3 = M_k[F] / k and row 1 divided by k (k >= 1), for the log series.
+// After all translations: row 3 = M_k[F] / k (k >= 1) for the log series of F, and row 2 = D_k, the
+// coefficients of t^(k+1) in (S[conj F] - Psi) / 2: D_k = (M_{k+1}[conj F] / (k+1) - M_k[conj(zeta) F]) / 2,
+// D_p = -M_p[conj(zeta) F] / 2.  The evaluation then needs three series instead of four.
 __global__ __launch_bounds__(kTB) void k_tc_finalize(double2* __restrict__ mom, size_t nbox, int p) {
   const size_t stride = 4 * (size_t)(p + 1);
   for (size_t e = (size_t)blockIdx.x * kTB + threadIdx.x; e < nbox * (p + 1); e += (size_t)gridDim.x * kTB) {
     const size_t box = e / (p + 1);
     const int k = (int)(e - box * (p + 1));
     double2* mb = mom + box * stride;
-    if (k == 0) {
-      mb[3 * (p + 1)] = make_double2(0.0, 0.0);
-      continue;
+    const double2 a = mb[k];
+    mb[3 * (p + 1) + k] = k == 0 ? make_double2(0.0, 0.0) : make_double2(a.x / (double)k, a.y / (double)k);
+    const double2 psi = mb[2 * (p + 1) + k];
+    double2 d = make_double2(-0.5 * psi.x, -0.5 * psi.y);
+    if (k < p) {
+      const double2 b = mb[(p + 1) + k + 1];
+      const double ik = 0.5 / (double)(k + 1);
+      d.x = fma(b.x, ik, d.x);
+      d.y = fma(b.y, ik, d.y);
     }
-    const double ik = 1.0 / (double)k;
-    const double2 a = mb[k], b = mb[(p + 1) + k];
-    mb[3 * (p + 1) + k] = make_double2(a.x * ik, a.y * ik);
-    mb[(p + 1) + k] = make_double2(b.x * ik, b.y * ik);
+    mb[2 * (p + 1) + k] = d;
   }
 }
 
@@ -494,25 +502,25 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
       const double2 wv = make_double2(zx - c.x, zy - c.y);
       const double w2 = wv.x * wv.x + wv.y * wv.y;
       const double2 t = make_double2(wv.x / w2, -wv.y / w2);
-      // Horner, highest order first
-      double2 aF = make_double2(0.0, 0.0), aFc = aF, aPhi = aF, aPsi = aF;
+      // Three series in t, highest order first:
+      //   S = sum_{k>=1} M_k[F] / k t^k,  D = sum_k D_k t^(k+1),  E = sum_k M_k[F] t^k;
+      // the box contributes S/2 + M_0/2 - M_0 ln|w| + conj(D) + (w / conj w) conj(E) / 2.
+      double2 aS = make_double2(0.0, 0.0), aD = aS, aE = aS;
       for (int k = p; k >= 1; --k) {
-        aF = cfma(aF, t, cf[3 * (p + 1) + k]);
-        aFc = cfma(aFc, t, cf[(p + 1) + k]);
-        aPhi = cfma(aPhi, t, cf[k]);
-        aPsi = cfma(aPsi, t, cf[2 * (p + 1) + k]);
+        aS = cfma(aS, t, cf[3 * (p + 1) + k]);
+        aD = cfma(aD, t, cf[2 * (p + 1) + k]);
+        aE = cfma(aE, t, cf[k]);
       }
       const double2 M0 = cf[0];
-      aPhi = cfma(aPhi, t, M0);
-      aPsi = cfma(aPsi, t, cf[2 * (p + 1)]);
-      aF = cmul(aF, t);
-      aFc = cmul(aFc, t);
-      const double2 Phi = cmul(aPhi, t), Psi = cmul(aPsi, t);
+      aD = cfma(aD, t, cf[2 * (p + 1)]);
+      aE = cfma(aE, t, M0);
+      aS = cmul(aS, t);
+      aD = cmul(aD, t);
       const double lnw = 0.5 * log_pos(w2);
-      // w conj(Phi)
-      const double2 wPhi = cmul(wv, make_double2(Phi.x, -Phi.y));
-      ux += -M0.x * lnw + 0.5 * (aF.x + aFc.x) + 0.5 * M0.x + 0.5 * (wPhi.x - Psi.x);
-      uy += -M0.y * lnw + 0.5 * (aF.y - aFc.y) + 0.5 * M0.y + 0.5 * (wPhi.y + Psi.y);
+      const double2 rot = make_double2((wv.x * wv.x - wv.y * wv.y) / w2, 2.0 * wv.x * wv.y / w2);  // w / conj w
+      const double2 pe = cmul(rot, make_double2(aE.x, -aE.y));
+      ux += 0.5 * aS.x + 0.5 * M0.x - M0.x * lnw + aD.x + 0.5 * pe.x;
+      uy += 0.5 * aS.y + 0.5 * M0.y - M0.y * lnw - aD.y + 0.5 * pe.y;
     }
   }
   // 3 x 3 leaves directly, own vesicle skipped
