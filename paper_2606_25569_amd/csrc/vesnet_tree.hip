@@ -55,10 +55,19 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 t, double2 c) {
   return make_double2(fma(a.x, t.x, fma(-a.y, t.y, c.x)), fma(a.x, t.y, fma(a.y, t.x, c.y)));
 }
 
+// 1 / x for finite x != 0: the hardware estimate refined by two Newton steps (each doubles the correct
+// bits; the result is within an ulp or so of the correctly rounded quotient).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // Natural log of a finite q > 0, in about 20 FP64 operations: q = m 2^e with m in [1/sqrt 2, sqrt 2),
 // ln m = 2 atanh(s) = 2 sum_k s^(2k+1) / (2k+1), s = (m - 1) / (m + 1), |s| <= 0.1716; the terms
 // after s^21 are below 3e-17 of ln m.  ln 2 is split into a 32-bit high part (exact products with e)
-// and a low part.  Measured against 40-digit references: at most 2 ulp.
+// and a low part.  Against 40-digit references the series with an exact quotient stays within 2 ulp;
+// the refined reciprocal adds at most about one more.
 __device__ __forceinline__ double log_pos(double q) {
   constexpr double kLn2Hi = 6.93147180369123816490e-01;
   constexpr double kLn2Lo = 1.90821492927058770002e-10;
@@ -68,7 +77,7 @@ __device__ __forceinline__ double log_pos(double q) {
     m *= 2.0;
     --e;
   }
-  const double s = (m - 1.0) / (m + 1.0);
+  const double s = (m - 1.0) * recip(m + 1.0);
   const double s2 = s * s;
   double pol = 1.0 / 21.0;
   pol = fma(pol, s2, 1.0 / 19.0);
@@ -264,13 +273,17 @@ __device__ __forceinline__ double2 cpow_int(double2 z, int k) {
   return r;
 }
 
-// One wavefront per leaf, lane k = order; the leaf's points pass through LDS 64 at a time.
+// One wavefront per leaf, lane k = order.  The leaf's points pass through LDS 32 at a time, each with
+// its powers zeta^0 .. zeta^p (by repeated multiplication), so lane k reads zeta^k instead of forming it.
+constexpr int kP2MChunk = 32;
+
 __global__ __launch_bounds__(64) void k_tc_p2m(const double* __restrict__ X, const double* __restrict__ f,
                                                const double* __restrict__ w, int P, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ starts, const Geom* __restrict__ geom,
                                                int depth, int p, double2* __restrict__ mom,
                                                int32_t* __restrict__ bcount) {
-  __shared__ double2 zs[64], Fs[64];
+  __shared__ double2 pw[kP2MChunk][kMaxOrder + 1];
+  __shared__ double2 Fs[kP2MChunk], Zc[kP2MChunk];
   const int leaf = blockIdx.x;
   const int k = threadIdx.x;
   const int n = 1 << depth;
@@ -278,26 +291,31 @@ __global__ __launch_bounds__(64) void k_tc_p2m(const double* __restrict__ X, con
   if (k == 0) bcount[leaf] = s1 - s0;
   const double2 c = box_center(*geom, n, leaf / n, leaf % n);
   double2 m0 = make_double2(0.0, 0.0), m1 = m0, m2 = m0;
-  for (int c0 = s0; c0 < s1; c0 += 64) {
-    const int cnt = min(64, s1 - c0);
+  for (int c0 = s0; c0 < s1; c0 += kP2MChunk) {
+    const int cnt = min(kP2MChunk, s1 - c0);
     __syncthreads();  // the previous chunk is done
     if (k < cnt) {
       const int j = perm[c0 + k];
-      zs[k] = make_double2(X[j] - c.x, X[P + j] - c.y);
+      const double2 zeta = make_double2(X[j] - c.x, X[P + j] - c.y);
       Fs[k] = make_double2(w[j] * f[j], w[j] * f[P + j]);
+      Zc[k] = make_double2(zeta.x, -zeta.y);
+      double2 z = make_double2(1.0, 0.0);
+      for (int m = 0; m <= p; ++m) {
+        pw[k][m] = z;
+        z = cmul(z, zeta);
+      }
     }
     __syncthreads();
     if (k <= p) {
       for (int q = 0; q < cnt; ++q) {
-        const double2 zeta = zs[q], F = Fs[q];
-        const double2 zk = cpow_int(zeta, k);
+        const double2 F = Fs[q], zk = pw[q][k];
         const double2 Fz = cmul(F, zk);
         m0.x += Fz.x;
         m0.y += Fz.y;
         const double2 Fcz = cmul(make_double2(F.x, -F.y), zk);
         m1.x += Fcz.x;
         m1.y += Fcz.y;
-        const double2 Pz = cmul(make_double2(zeta.x, -zeta.y), Fz);
+        const double2 Pz = cmul(Zc[q], Fz);
         m2.x += Pz.x;
         m2.y += Pz.y;
       }
@@ -395,7 +413,7 @@ __device__ __forceinline__ void direct_term(double zx, double zy, double sx, dou
   const double rx = zx - sx, ry = zy - sy;
   const double q = rx * rx + ry * ry;
   const double lg = -0.5 * log_pos(q);
-  const double s = (rx * Fx + ry * Fy) / q;
+  const double s = (rx * Fx + ry * Fy) * recip(q);
   ux = fma(lg, Fx, fma(s, rx, ux));
   uy = fma(lg, Fy, fma(s, ry, uy));
 }
