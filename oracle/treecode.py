@@ -107,6 +107,45 @@ def interaction_offsets():
     return [(a, b) for a in range(-2, 4) for b in range(-2, 4)]
 
 
+def near_part(tree, z, F, ves, offsets, target):
+    """Direct part (times 4 pi mu) shared by every tree method here: the sources of the 3 x 3 leaves
+    around each target's leaf, own vesicle skipped, minus the own-vesicle sources outside those leaves
+    (which the expansions included).  Zero at targets not selected."""
+    P = z.size
+    depth = tree.depth
+    u = np.zeros(P, complex)
+    # 3 x 3 leaves, own vesicle skipped
+    n = 1 << depth
+    leaf = tree.ix * n + tree.iy
+    order_ = np.argsort(leaf, kind="stable")
+    starts = np.searchsorted(leaf[order_], np.arange(n * n + 1))
+    for lx in range(n):
+        for ly in range(n):
+            tgt = order_[starts[lx * n + ly]:starts[lx * n + ly + 1]]
+            tgt = tgt[target[tgt]]
+            if tgt.size == 0:
+                continue
+            src = np.concatenate([order_[starts[jx * n + jy]:starts[jx * n + jy + 1]]
+                                  for jx in range(max(lx - 1, 0), min(lx + 2, n))
+                                  for jy in range(max(ly - 1, 0), min(ly + 2, n))])
+            keep = ves[src][None, :] != ves[tgt][:, None]
+            Fm = np.where(keep, F[src][None, :], 0.0)
+            zs = np.where(keep, z[src][None, :], z[tgt][:, None] + 1.0)  # masked terms: F = 0, r = 1
+            u[tgt] += direct_terms(z[tgt][:, None], zs, Fm)
+    # own-vesicle sources that the expansions included: subtract them exactly
+    for v in range(len(offsets) - 1):
+        a, b = int(offsets[v]), int(offsets[v + 1])
+        if b - a < 2 or not target[a:b].any():
+            continue
+        far = (np.abs(tree.ix[a:b, None] - tree.ix[None, a:b]) > 1) | (np.abs(tree.iy[a:b, None] - tree.iy[None, a:b]) > 1)
+        if not far.any():
+            continue
+        Fm = np.where(far, F[None, a:b], 0.0)
+        zs = np.where(far, z[None, a:b], z[a:b, None] + 1.0)
+        u[a:b] -= direct_terms(z[a:b, None], zs, Fm)
+    return u
+
+
 def treecode(X, f, w, offsets, mu, order, depth, sel=None):
     """Treecode far field of all points on themselves, own vesicle excluded: (2, P), or
     (2, len(sel)) at the targets sel only (the tree and moments still use every point)."""
@@ -140,35 +179,7 @@ def treecode(X, f, w, offsets, mu, order, depth, sel=None):
                 continue
             s = sx[ok] * n + sy[ok]
             u[ok] += far_terms(z[ok] - centers[s], MF[s], MFc[s], MPsi[s])
-    # direct part: 3 x 3 leaves, own vesicle skipped
-    n = 1 << depth
-    leaf = tree.ix * n + tree.iy
-    order_ = np.argsort(leaf, kind="stable")
-    starts = np.searchsorted(leaf[order_], np.arange(n * n + 1))
-    for lx in range(n):
-        for ly in range(n):
-            tgt = order_[starts[lx * n + ly]:starts[lx * n + ly + 1]]
-            tgt = tgt[target[tgt]]
-            if tgt.size == 0:
-                continue
-            src = np.concatenate([order_[starts[jx * n + jy]:starts[jx * n + jy + 1]]
-                                  for jx in range(max(lx - 1, 0), min(lx + 2, n))
-                                  for jy in range(max(ly - 1, 0), min(ly + 2, n))])
-            keep = ves[src][None, :] != ves[tgt][:, None]
-            Fm = np.where(keep, F[src][None, :], 0.0)
-            zs = np.where(keep, z[src][None, :], z[tgt][:, None] + 1.0)  # masked terms: F = 0, r = 1
-            u[tgt] += direct_terms(z[tgt][:, None], zs, Fm)
-    # own-vesicle sources that the expansions included: subtract them exactly
-    for v in range(len(offsets) - 1):
-        a, b = int(offsets[v]), int(offsets[v + 1])
-        if b - a < 2 or not target[a:b].any():
-            continue
-        far = (np.abs(tree.ix[a:b, None] - tree.ix[None, a:b]) > 1) | (np.abs(tree.iy[a:b, None] - tree.iy[None, a:b]) > 1)
-        if not far.any():
-            continue
-        Fm = np.where(far, F[None, a:b], 0.0)
-        zs = np.where(far, z[None, a:b], z[a:b, None] + 1.0)
-        u[a:b] -= direct_terms(z[a:b, None], zs, Fm)
+    u += near_part(tree, z, F, ves, offsets, target)
     u /= 4.0 * np.pi * mu
     if sel is not None:
         u = u[np.asarray(sel)]

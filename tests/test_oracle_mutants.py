@@ -99,6 +99,18 @@ PY_MUTANTS = [
      "((np.abs(sx - bx) > 0) | (np.abs(sy - by) > 0))\n            ok &= target", "test_oracle_treecode.py"),
     ("treecode: own vesicle not subtracted", "treecode.py", "u[a:b] -= direct_terms(", "u[a:b] += 0 * direct_terms(",
      "test_oracle_treecode.py"),
+    ("fmm: Taylor sign of the inverse powers dropped", "fmm.py", "out[:, l] = (-1.0) ** l * np.sum(",
+     "out[:, l] = np.sum(", "test_oracle_fmm.py"),
+    ("fmm: binomial index off by one", "fmm.py", "float(comb(mm + l - 1, l))", "float(comb(mm + l, l))",
+     "test_oracle_fmm.py"),
+    ("fmm: log coefficient sign", "fmm.py", "lam * (-1.0) ** (l - 1) * Dinv ** l / l",
+     "lam * (-1.0) ** l * Dinv ** l / l", "test_oracle_fmm.py"),
+    ("fmm: G moments about the box centre", "fmm.py", "MG = box_moments(z, np.conj(z) * F,",
+     "MG = box_moments(z, np.conj(z - centers[box]) * F,", "test_oracle_fmm.py"),
+    ("fmm: constant term dropped", "fmm.py", " + 0.5 * K[row]", "", "test_oracle_fmm.py"),
+    ("fmm: Phi paired with the offset from the box centre", "fmm.py", "0.5 * z[idx] * np.conj(Pv)",
+     "0.5 * zeta * np.conj(Pv)", "test_oracle_fmm.py"),
+    ("fmm: Q not conjugated", "fmm.py", "- 0.5 * np.conj(Qv)", "- 0.5 * Qv", "test_oracle_fmm.py"),
     ("spectral: derivative sign", "spectral.py", "1j * k * np.fft.fft(v", "-1j * k * np.fft.fft(v",
      "test_oracle_spectral.py"),
     ("spectral: tension without 1/J", "spectral.py", "tension = spectral_derivative(sigma * xs) / J",
@@ -115,7 +127,7 @@ PY_MUTANTS = [
 def test_planted_python_oracle_mistake_is_caught(tmp_path, name, module, orig, bad, pins):
     pkg = tmp_path / "oracle"
     pkg.mkdir()
-    for f in ("__init__.py", "spectral.py", "nearfield_rbf.py", "treecode.py", "oracle.py", "vesnet_oracle.c",
+    for f in ("__init__.py", "spectral.py", "nearfield_rbf.py", "treecode.py", "fmm.py", "oracle.py", "vesnet_oracle.c",
               "libvesnet_oracle.so"):
         if os.path.exists(os.path.join(ROOT, "oracle", f)):
             shutil.copy2(os.path.join(ROOT, "oracle", f), pkg / f)  # keeps mtimes: no rebuild of the C oracle
