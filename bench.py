@@ -432,8 +432,9 @@ def bench_nearfield(args):
 
 
 def _treecode_work(X, sizes, depth):
-    """Work of one treecode evaluation from its tree: (target, non-empty far box) evaluations and
-    direct pairs with other vesicles' points in the 3 x 3 leaves (own vesicle assumed inside them)."""
+    """Work of one treecode evaluation from its tree: (target, non-empty far box) evaluations,
+    direct pairs with other vesicles' points in the 3 x 3 leaves (own vesicle assumed inside them),
+    and the fast multipole method's (non-empty target box, non-empty source box) translations."""
     import numpy as np
     x, y = X
     side = max(x.max() - x.min(), y.max() - y.min())
@@ -442,21 +443,26 @@ def _treecode_work(X, sizes, depth):
     n = 1 << depth
     ix = np.clip(np.floor((x - x0) / (side / n)), 0, n - 1).astype(np.int64)
     iy = np.clip(np.floor((y - y0) / (side / n)), 0, n - 1).astype(np.int64)
-    n_box = 0
+    n_box = n_m2l = 0
     for l in range(2, depth + 1):
         nl = 1 << l
         bx, by = ix >> (depth - l), iy >> (depth - l)
         occ = np.bincount(bx * nl + by, minlength=nl * nl) > 0
+        tb = np.flatnonzero(occ)
+        tx, ty = tb // nl, tb % nl
         for a in range(-2, 4):
             for b in range(-2, 4):
                 sx, sy = 2 * (bx >> 1) + a, 2 * (by >> 1) + b
                 ok = (sx >= 0) & (sx < nl) & (sy >= 0) & (sy < nl) & ((np.abs(sx - bx) > 1) | (np.abs(sy - by) > 1))
                 n_box += int(occ[np.where(ok, sx * nl + sy, 0)][ok].sum())
+                sx, sy = 2 * (tx >> 1) + a, 2 * (ty >> 1) + b
+                ok = (sx >= 0) & (sx < nl) & (sy >= 0) & (sy < nl) & ((np.abs(sx - tx) > 1) | (np.abs(sy - ty) > 1))
+                n_m2l += int(occ[np.where(ok, sx * nl + sy, 0)][ok].sum())
     cnt = np.bincount(ix * n + iy, minlength=n * n).reshape(n, n)
     pad = np.pad(cnt, 1)
     near = sum(pad[1 + a:1 + a + n, 1 + b:1 + b + n] for a in (-1, 0, 1) for b in (-1, 0, 1))
     n_direct = int(near[ix, iy].sum() - np.repeat(sizes, sizes).sum())
-    return n_box, n_direct
+    return n_box, n_direct, n_m2l
 
 
 def bench_treecode(args):
@@ -487,11 +493,11 @@ def bench_treecode(args):
     exact = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu, select=sel)
     t_oracle = time.time() - t0
     scale = float(np.abs(exact).max())
-    n_box, n_direct = _treecode_work(s.X, s.sizes(), depth)
-    rec = {"workload": "treecode far field of the dense suspension: 2000 vesicles x 128 points (256000), "
-                       f"uniform quadtree depth {depth}, FP64",
-           "far_box_evaluations": n_box, "direct_pairs": n_direct,
-           "n_points": P, "cross_vesicle_pairs": pairs, "depth": depth, "orders": {}}
+    n_box, n_direct, n_m2l = _treecode_work(s.X, s.sizes(), depth)
+    rec = {"workload": "treecode and fast multipole far field of the dense suspension: 2000 vesicles x 128 "
+                       f"points (256000), uniform quadtree depth {depth}, FP64",
+           "far_box_evaluations": n_box, "direct_pairs": n_direct, "m2l_translations": n_m2l,
+           "n_points": P, "cross_vesicle_pairs": pairs, "depth": depth, "orders": {}, "fmm_orders": {}}
     for order in (20, 30, 40):
         ws = torch.empty(lib.vesnet_treecode_workspace_bytes(P, depth, order), dtype=torch.uint8, device=dev)
         fn = lambda: V.farfield_treecode(X, f, w, part, s.mu, order, depth, out=out, workspace=ws)
@@ -505,6 +511,14 @@ def bench_treecode(args):
                                 "algorithmic_tflops_fp64": flops / (ms * 1e-3) / 1e12,
                                 "frac_of_fp64_peak": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
         log(f"[bench] treecode order {order}: {ms:.3f} ms, err {err:.2e} of max|u| on {sel.size} targets")
+        ws = torch.empty(lib.vesnet_fmm_workspace_bytes(P, depth, order), dtype=torch.uint8, device=dev)
+        fn = lambda: V.farfield_fmm(X, f, w, part, s.mu, order, depth, out=out, workspace=ws)
+        ms = _time(fn, args.steps, stream)
+        fn()
+        torch.cuda.synchronize()
+        err = float(np.abs(out.cpu().numpy()[:, sel] - exact).max() / scale)
+        rec["fmm_orders"][order] = {"ms": ms, "max_rel_err_vs_exact": err, "equivalent_pairs_per_s": pairs / (ms * 1e-3)}
+        log(f"[bench] fmm order {order}: {ms:.3f} ms, err {err:.2e} of max|u| on {sel.size} targets")
     wsd = torch.empty(V.workspace_bytes(P, M, "fp32c"), dtype=torch.uint8, device=dev)
     ms_direct = _time(lambda: V.farfield_forward(X, X, f, w, part, s.mu, "fp32c", out=out, workspace=wsd), 5, stream)
     rec["direct_fp32c_ms"] = ms_direct

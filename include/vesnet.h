@@ -258,6 +258,26 @@ VESNET_API int vesnet_farfield_treecode(const double* points, const double* forc
                                         double mu, int32_t order, int32_t depth, double* out, void* workspace,
                                         size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------------------------------ fast multipole far field */
+
+/* The fast multipole method the paper names as the route to O(M) cost and leaves out of scope
+   (Section 4.1), on the treecode's tree, interaction lists, direct part and own-vesicle exclusion:
+   instead of evaluating every far box's truncated multipole series at every target, each box's
+   series is converted once into a Taylor polynomial of the same order about the centre of every
+   box whose interaction list holds it, the polynomials are re-centred down the tree, and each target
+   evaluates only its leaf's polynomial.  The far work becomes O(boxes x order^2) instead of
+   O(points x boxes per list x order).  Accuracy: at the same order about 2 to 4 times the treecode's
+   error (order 30: about 5e-12 relative to max|u| on dense suspensions); everything in float64.
+   Deterministic under the same condition as the treecode.
+     arguments, layouts, ownership and errors as vesnet_farfield_treecode;
+     workspace : device, vesnet_fmm_workspace_bytes(P, depth, order) bytes (the treecode's plus
+                 3 (order+1) complex numbers per box and a binomial table) */
+VESNET_API size_t vesnet_fmm_workspace_bytes(int32_t n_points, int32_t depth, int32_t order);
+VESNET_API int vesnet_farfield_fmm(const double* points, const double* force_density, const double* arc_weights,
+                                   const int32_t* vesicle_offsets, int32_t n_vesicles, int32_t n_points, double mu,
+                                   int32_t order, int32_t depth, double* out, void* workspace, size_t workspace_bytes,
+                                   void* stream);
+
 /* ------------------------------------------------------------------ batched */
 
 /* S independent suspensions concatenated point-wise and vesicle-wise.

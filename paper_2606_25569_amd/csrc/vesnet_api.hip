@@ -426,6 +426,34 @@ extern "C" int vesnet_farfield_treecode(const double* X, const double* f, const 
   return ok();
 }
 
+extern "C" size_t vesnet_fmm_workspace_bytes(int32_t P, int32_t depth, int32_t order) {
+  if (P < 0 || P > kMaxPoints || depth < 0 || depth > kTreeMaxDepth || order < 1 || order > kTreeMaxOrder) return 0;
+  return fmm_workspace_bytes(P, depth, order);
+}
+
+extern "C" int vesnet_farfield_fmm(const double* X, const double* f, const double* w, const int32_t* off, int32_t M,
+                                   int32_t P, double mu, int32_t order, int32_t depth, double* out, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  int rc = check_sizes(P, M);
+  if (rc) return rc;
+  if ((rc = check_mu(mu))) return rc;
+  if (order < 1 || order > kTreeMaxOrder)
+    return fail(VESNET_ERR_UNSUPPORTED, "order = %d outside 1..%d", order, kTreeMaxOrder);
+  if (depth < 0 || depth > kTreeMaxDepth)
+    return fail(VESNET_ERR_UNSUPPORTED, "depth = %d outside 0..%d", depth, kTreeMaxDepth);
+  if (P == 0) return ok();
+  if (!X || !f || !w || !off || !out) return fail(VESNET_ERR_INVALID_ARGUMENT, "a required pointer is NULL");
+  if ((rc = check_workspace(ws, ws_bytes, fmm_workspace_bytes(P, depth, order)))) return rc;
+  const size_t vb = (size_t)2 * P * sizeof(double);
+  if (overlaps(out, vb, X, vb) || overlaps(out, vb, f, vb) || overlaps(out, vb, w, (size_t)P * sizeof(double)) ||
+      overlaps(out, vb, off, (size_t)(M + 1) * sizeof(int32_t)) || overlaps(out, vb, ws, ws_bytes) ||
+      overlaps(ws, ws_bytes, X, vb) || overlaps(ws, ws_bytes, f, vb) || overlaps(ws, ws_bytes, w, (size_t)P * sizeof(double)))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "out or workspace overlap another array");
+  hipError_t e = launch_fmm(X, f, w, off, M, P, 1.0 / (4.0 * kPi * mu), order, depth, out, ws, stream);
+  if (e != hipSuccess) return hip_fail(e, "fast multipole launch");
+  return ok();
+}
+
 // ============================================================================ near-field masked
 
 extern "C" int vesnet_farfield_stokeslet_nearmasked(const double* targets, const double* sources, const double* f,

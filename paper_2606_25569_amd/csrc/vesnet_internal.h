@@ -63,6 +63,10 @@ hipError_t launch_rbf_eval_near(const double* layers, const double* coeffs, cons
 size_t treecode_workspace_bytes(int P, int depth, int p);
 hipError_t launch_treecode(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
                            double scale, int p, int depth, double* out, void* ws, void* stream);
+// Fast multipole far field on the same tree: workspace size and the whole build + evaluation.
+size_t fmm_workspace_bytes(int P, int depth, int p);
+hipError_t launch_fmm(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
+                      double scale, int p, int depth, double* out, void* ws, void* stream);
 hipError_t launch_plan(const int32_t* sus_off, int S, int M, const PreparedView& pv, int tile, const PlanView& pl,
                        void* stream);
 hipError_t launch_batched(int prec, int T, int B, bool lds, int grid, const double* tg, int P, int M,

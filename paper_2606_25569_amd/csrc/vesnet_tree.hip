@@ -100,6 +100,9 @@ __device__ __forceinline__ double2 box_center(const Geom& g, int n, int bx, int 
   return make_double2(g.x0 + ((double)bx + 0.5) * wl, g.y0 + ((double)by + 0.5) * wl);
 }
 
+// First box of level l >= 2 when levels 2, 3, ... are stored one after another: sum_{m=2}^{l-1} 4^m.
+__device__ __forceinline__ size_t level_box_base(int l) { return (((size_t)1 << (2 * l)) - 16) / 3; }
+
 // ---------------------------------------------------------------- tree construction
 
 __global__ __launch_bounds__(kTB) void k_tc_bbox_partial(const double* __restrict__ X, int P,
@@ -406,6 +409,192 @@ __global__ __launch_bounds__(kTB) void k_tc_finalize(double2* __restrict__ mom, 
   }
 }
 
+// ---------------------------------------------------------------- fast multipole translations
+//
+// Local expansion of a box T (centre c_T, zeta = z - c_T): three rows of (p + 1) complex Taylor
+// coefficients A, B, C such that the far field (times 4 pi mu) of everything in the interaction lists
+// of T and of its ancestors is
+//     u = -A(zeta)/2 - conj(B(zeta))/2 + zeta conj(C(zeta))/2.
+// A source box S, d = c_S - c_T, t = 1/d, enters through its multipole series in powers of (z - c_S)^-1:
+//   A: log sum of F,  lambda = M_0[F],       a_m = -M_m[F]/m                      (m = 1..p);
+//   C: Cauchy sum Phi,                       a_m = M_{m-1}[F]                     (m = 1..p+1);
+//   B: log sum of conj F plus Psi,  lambda = M_0[conj F],  a_m = -M_m[conj F]/m + M_{m-1}[conj(zeta) F],
+//      plus conj(d) times C (the term that re-centres conj(zeta_j) from c_S to c_T).
+// With (z - c_S)^-m = (-t)^m sum_l C(m + l - 1, l) t^l zeta^l and log(z - c_S) = log(-d) - sum_{l>=1} t^l zeta^l / l,
+// the coefficient of zeta^l is t^l (sum_m C(m + l - 1, l) (-t)^m a_m - lambda / l), and for l = 0
+// lambda ln|d| + sum_m (-t)^m a_m: the imaginary part of log(-d) cancels between A and conj(B) because
+// M_0[conj F] = conj(M_0[F]).  Each source box's constant M_0[F]/2 goes into A_0 as -M_0[F].
+// A child inherits its parent's expansion re-centred by e = c_child - c_parent:
+//   X_l += sum_{m>=l} C(m, l) e^(m-l) X_m  for A, B, C, and B additionally -conj(e) times the shifted C.
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// T[m][l] = C(m + l - 1, l) for m = 0..p+1, l = 0..p (row 0: 1, 0, 0, ...), row stride p + 1, by Pascal's
+// rule T[m][l] = T[m-1][l] + T[m][l-1] along anti-diagonals: sums of integers, exact below 2^53.  The
+// same table holds C(m, l) = T[m - l + 1][l].  One wavefront, lane = l.
+__global__ __launch_bounds__(64) void k_fmm_binom(int p, double* __restrict__ tab) {
+  __shared__ double prev[64];
+  const int l = threadIdx.x;
+  double v = l == 0 ? 1.0 : 0.0;  // T[0][l]
+  if (l <= p) tab[l] = v;
+  for (int s = 1; s <= 2 * p + 1; ++s) {
+    prev[l] = v;  // this lane's latest entry, T[s - 1 - l][l]
+    __syncthreads();
+    const int m = s - l;
+    if (l <= p && m >= 1 && m <= p + 1) {
+      v += l > 0 ? prev[l - 1] : 0.0;  // + T[m][l - 1], written by lane l - 1 one step earlier
+      tab[m * (p + 1) + l] = v;
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int kM2LWaves = 4;  // target boxes per workgroup; they share the binomial table in LDS
+
+// Interaction-list contributions to the local expansion of every non-empty box of levels 2..depth (one
+// launch for all levels).  One wavefront per target box: lane m scales the source's coefficient a_m by
+// (-t)^m into LDS, then lane l forms sum_m C(m + l - 1, l) (-t)^m a_m for the three series.
+__global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restrict__ geom, int depth, int p,
+                                                           const double2* __restrict__ mom,
+                                                           const int32_t* __restrict__ bcount,
+                                                           const double* __restrict__ tab, size_t nbox,
+                                                           double2* __restrict__ loc) {
+  __shared__ double T[(kMaxOrder + 2) * (kMaxOrder + 1)];
+  __shared__ double2 st[kM2LWaves][3][kMaxOrder + 2];
+  const int nt = (p + 2) * (p + 1);
+  for (int e = threadIdx.x; e < nt; e += 64 * kM2LWaves) T[e] = tab[e];
+  __syncthreads();  // the only workgroup barrier: waves below synchronise among their own lanes
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t box = (size_t)blockIdx.x * kM2LWaves + wv;
+  if (box >= nbox || bcount[box] == 0) return;
+  int l = 2;
+  while (l < depth && box >= level_box_base(l + 1)) ++l;
+  const int n = 1 << l;
+  const size_t base = level_box_base(l);
+  const int b = (int)(box - base);
+  const int bx = b / n, by = b - (b / n) * n;
+  const double wl = geom->side / (double)n;
+  const int stride = 4 * (p + 1);
+  const double inv = lane > 0 ? 1.0 / (double)lane : 0.0;  // 1/m and 1/l: lane = m in the scaling, l after
+  double2* sA = st[wv][0];
+  double2* sP = st[wv][1];
+  double2* sQ = st[wv][2];
+  double2 accA = make_double2(0.0, 0.0), accB = accA, accC = accA;
+  for (int a = -2; a <= 3; ++a)
+    for (int c = -2; c <= 3; ++c) {
+      const int sx = 2 * (bx >> 1) + a, sy = 2 * (by >> 1) + c;
+      if (sx < 0 || sx >= n || sy < 0 || sy >= n) continue;
+      if (abs(sx - bx) <= 1 && abs(sy - by) <= 1) continue;
+      const size_t sb = base + (size_t)sx * n + sy;
+      if (bcount[sb] == 0) continue;
+      const double2 d = make_double2((double)(sx - bx) * wl, (double)(sy - by) * wl);
+      const double dd = d.x * d.x + d.y * d.y;
+      const double rdd = recip(dd);
+      const double2 mt = make_double2(-d.x * rdd, d.y * rdd);  // -t = -1/d
+      const double2 pw = cpow_int(mt, lane);                   // (-t)^lane
+      const double2* ms = mom + sb * stride;
+      if (lane >= 1 && lane <= p + 1) {
+        const double2 Fm1 = ms[lane - 1];
+        double2 aA = make_double2(0.0, 0.0), aQ = ms[2 * (p + 1) + lane - 1];
+        if (lane <= p) {
+          const double2 Fm = ms[lane], Cm = ms[(p + 1) + lane];
+          aA = make_double2(-Fm.x * inv, -Fm.y * inv);
+          aQ.x = fma(-Cm.x, inv, aQ.x);
+          aQ.y = fma(-Cm.y, inv, aQ.y);
+        }
+        sA[lane] = cmul(aA, pw);
+        sP[lane] = cmul(Fm1, pw);
+        sQ[lane] = cmul(aQ, pw);
+      }
+      wave_sync();
+      if (lane <= p) {
+        double2 xA = make_double2(0.0, 0.0), xP = xA, xQ = xA;
+        for (int m = 1; m <= p + 1; ++m) {
+          const double cb = T[m * (p + 1) + lane];
+          const double2 qa = sA[m], qp = sP[m], qq = sQ[m];
+          xA.x = fma(cb, qa.x, xA.x);
+          xA.y = fma(cb, qa.y, xA.y);
+          xP.x = fma(cb, qp.x, xP.x);
+          xP.y = fma(cb, qp.y, xP.y);
+          xQ.x = fma(cb, qq.x, xQ.x);
+          xQ.y = fma(cb, qq.y, xQ.y);
+        }
+        const double2 lamA = ms[0], lamQ = ms[p + 1];
+        double2 bA, bP, bQ;
+        if (lane == 0) {
+          const double lnd = 0.5 * log_pos(dd);
+          bA = make_double2(fma(lamA.x, lnd, xA.x), fma(lamA.y, lnd, xA.y));
+          bP = xP;
+          bQ = make_double2(fma(lamQ.x, lnd, xQ.x), fma(lamQ.y, lnd, xQ.y));
+        } else {
+          const double2 tl = (lane & 1) ? make_double2(-pw.x, -pw.y) : pw;  // t^l = (-1)^l (-t)^l
+          bA = cmul(tl, make_double2(fma(-lamA.x, inv, xA.x), fma(-lamA.y, inv, xA.y)));
+          bP = cmul(tl, xP);
+          bQ = cmul(tl, make_double2(fma(-lamQ.x, inv, xQ.x), fma(-lamQ.y, inv, xQ.y)));
+        }
+        accA.x += bA.x;
+        accA.y += bA.y;
+        accC.x += bP.x;
+        accC.y += bP.y;
+        const double2 sh = cmul(make_double2(d.x, -d.y), bP);
+        accB.x += bQ.x + sh.x;
+        accB.y += bQ.y + sh.y;
+        if (lane == 0) {
+          accA.x -= lamA.x;
+          accA.y -= lamA.y;
+        }
+      }
+      wave_sync();  // the staging is rewritten for the next source box
+    }
+  if (lane <= p) {
+    double2* lb = loc + box * 3 * (p + 1);
+    lb[lane] = accA;
+    lb[(p + 1) + lane] = accB;
+    lb[2 * (p + 1) + lane] = accC;
+  }
+}
+
+// Adds the parent's local expansion, re-centred, to every non-empty box of level l (n = 2^l per side).
+// One wavefront per box, lane = order, the parent's three rows staged in LDS.
+__global__ __launch_bounds__(64) void k_fmm_l2l(const Geom* __restrict__ geom, int n, int p,
+                                               const int32_t* __restrict__ bcount, const double* __restrict__ tab,
+                                               const double2* __restrict__ parent, double2* __restrict__ child) {
+  __shared__ double2 pl[3 * (kMaxOrder + 1)];
+  const int box = blockIdx.x;
+  if (bcount[box] == 0) return;
+  const int k = threadIdx.x;
+  const int bx = box / n, by = box % n;
+  const int rows = 3 * (p + 1);
+  const size_t pbox = (size_t)(bx >> 1) * (n >> 1) + (by >> 1);
+  for (int e = k; e < rows; e += 64) pl[e] = parent[pbox * rows + e];
+  __syncthreads();
+  if (k > p) return;
+  const double wl = geom->side / (double)n;
+  const double2 e = make_double2(((double)(bx & 1) - 0.5) * wl, ((double)(by & 1) - 0.5) * wl);
+  double2 sA = make_double2(0.0, 0.0), sB = sA, sC = sA;
+  double2 ej = make_double2(1.0, 0.0);  // e^j
+  for (int j = 0; j <= p - k; ++j) {
+    const double cb = tab[(j + 1) * (p + 1) + k];  // C(k + j, k)
+    const double2 ce = make_double2(cb * ej.x, cb * ej.y);
+    sA = cfma(ce, pl[k + j], sA);
+    sB = cfma(ce, pl[(p + 1) + k + j], sB);
+    sC = cfma(ce, pl[2 * (p + 1) + k + j], sC);
+    ej = cmul(ej, e);
+  }
+  const double2 sh = cmul(make_double2(e.x, -e.y), sC);
+  double2* cb_ = child + (size_t)box * rows;
+  double2 v = cb_[k];
+  cb_[k] = make_double2(v.x + sA.x, v.y + sA.y);
+  v = cb_[(p + 1) + k];
+  cb_[(p + 1) + k] = make_double2(v.x + sB.x - sh.x, v.y + sB.y - sh.y);
+  v = cb_[2 * (p + 1) + k];
+  cb_[2 * (p + 1) + k] = make_double2(v.x + sC.x, v.y + sC.y);
+}
+
 // ---------------------------------------------------------------- evaluation
 
 __device__ __forceinline__ void direct_term(double zx, double zy, double sx, double sy, double Fx, double Fy,
@@ -423,9 +612,6 @@ __device__ __forceinline__ void direct_term(double zx, double zy, double sx, dou
 struct ListWalk {
   int l, a, b;
 };
-
-// First box of level l >= 2 when levels 2, 3, ... are stored one after another: sum_{m=2}^{l-1} 4^m.
-__device__ __forceinline__ size_t level_box_base(int l) { return (((size_t)1 << (2 * l)) - 16) / 3; }
 
 __device__ __forceinline__ bool next_box(ListWalk& s, int depth, int ix, int iy, const int32_t* __restrict__ bcount,
                                          int& lo, int& sxo, int& syo) {
@@ -451,15 +637,18 @@ __device__ __forceinline__ bool next_box(ListWalk& s, int depth, int ix, int iy,
   return false;
 }
 
-// One wavefront per (leaf, chunk of 64 of its points); every lane one target.
+// One wavefront per (leaf, chunk of 64 of its points); every lane one target.  The far part is the
+// treecode's walk over the interaction lists (kFmm false: mom holds the finalised moments) or the leaf's
+// local expansion (kFmm true: loc holds it); the direct part and the own-vesicle correction are shared.
+template <bool kFmm>
 __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, const double* __restrict__ f,
                                                 const double* __restrict__ w, int P, const int32_t* __restrict__ off,
                                                 const int32_t* __restrict__ vid, const int32_t* __restrict__ leafid,
                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ starts,
                                                 const int32_t* __restrict__ wstart, const Geom* __restrict__ geom,
                                                 int depth, int p, const double2* __restrict__ mom,
-                                                const int32_t* __restrict__ bcount, double scale,
-                                                double* __restrict__ out) {
+                                                const double2* __restrict__ loc, const int32_t* __restrict__ bcount,
+                                                double scale, double* __restrict__ out) {
   const int n = 1 << depth;
   const int nleaf = n * n;
   const int item = blockIdx.x;
@@ -485,29 +674,33 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
   __shared__ double sx_[64], sy_[64], sfx[64], sfy[64];
   __shared__ int32_t sv[64];
 
-  // expansions of the interaction lists: box by box, the next box's moments loaded into registers
-  // while the current one is evaluated from LDS
-  // four entries per lane: 4 x 64 >= 4 (kMaxOrder + 1); the moment array has 256 spare entries
-  double2 n0 = make_double2(0.0, 0.0), n1 = n0, n2 = n0, n3 = n0;
-  ListWalk it = {2, -2, -2};
-  int nl_ = 0, nsx = 0, nsy = 0;
-  bool have = next_box(it, depth, ix, iy, bcount, nl_, nsx, nsy);
-  if (have) {
-    const double2* mb = mom + (level_box_base(nl_) + (size_t)nsx * (1 << nl_) + nsy) * stride;
-    n0 = mb[threadIdx.x];
-    n1 = mb[threadIdx.x + 64];
-    n2 = mb[threadIdx.x + 128];
-    n3 = mb[threadIdx.x + 192];
-  }
-  while (have) {
-    __syncthreads();  // the previous box is done with cf
-    cf[threadIdx.x] = n0;
-    cf[threadIdx.x + 64] = n1;
-    cf[threadIdx.x + 128] = n2;
-    cf[threadIdx.x + 192] = n3;
-    __syncthreads();
-    const int l = nl_, sx = nsx, sy = nsy;
-    have = next_box(it, depth, ix, iy, bcount, nl_, nsx, nsy);
+  if constexpr (kFmm) {
+    // the leaf's local expansion: u += -A(zeta)/2 - conj(B(zeta))/2 + zeta conj(C(zeta))/2
+    if (depth >= 2) {
+      const double2* lb = loc + (level_box_base(depth) + (size_t)leaf) * 3 * (p + 1);
+      cf[threadIdx.x] = lb[threadIdx.x];  // 3 x 64 >= 3 (kMaxOrder + 1); the array has 192 spare entries
+      cf[threadIdx.x + 64] = lb[threadIdx.x + 64];
+      cf[threadIdx.x + 128] = lb[threadIdx.x + 128];
+      __syncthreads();
+      const double2 c = box_center(g, n, ix, iy);
+      const double2 zt = make_double2(zx - c.x, zy - c.y);
+      double2 A = cf[p], B = cf[2 * p + 1], C = cf[3 * p + 2];
+      for (int k = p - 1; k >= 0; --k) {
+        A = cfma(A, zt, cf[k]);
+        B = cfma(B, zt, cf[(p + 1) + k]);
+        C = cfma(C, zt, cf[2 * (p + 1) + k]);
+      }
+      ux += -0.5 * A.x - 0.5 * B.x + 0.5 * (zt.x * C.x + zt.y * C.y);
+      uy += -0.5 * A.y + 0.5 * B.y + 0.5 * (zt.y * C.x - zt.x * C.y);
+    }
+  } else {
+    // expansions of the interaction lists: box by box, the next box's moments loaded into registers
+    // while the current one is evaluated from LDS
+    // four entries per lane: 4 x 64 >= 4 (kMaxOrder + 1); the moment array has 256 spare entries
+    double2 n0 = make_double2(0.0, 0.0), n1 = n0, n2 = n0, n3 = n0;
+    ListWalk it = {2, -2, -2};
+    int nl_ = 0, nsx = 0, nsy = 0;
+    bool have = next_box(it, depth, ix, iy, bcount, nl_, nsx, nsy);
     if (have) {
       const double2* mb = mom + (level_box_base(nl_) + (size_t)nsx * (1 << nl_) + nsy) * stride;
       n0 = mb[threadIdx.x];
@@ -515,30 +708,47 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
       n2 = mb[threadIdx.x + 128];
       n3 = mb[threadIdx.x + 192];
     }
-    {
-      const double2 c = box_center(g, 1 << l, sx, sy);
-      const double2 wv = make_double2(zx - c.x, zy - c.y);
-      const double w2 = wv.x * wv.x + wv.y * wv.y;
-      const double2 t = make_double2(wv.x / w2, -wv.y / w2);
-      // Three series in t, highest order first:
-      //   S = sum_{k>=1} M_k[F] / k t^k,  D = sum_k D_k t^(k+1),  E = sum_k M_k[F] t^k;
-      // the box contributes S/2 + M_0/2 - M_0 ln|w| + conj(D) + (w / conj w) conj(E) / 2.
-      double2 aS = make_double2(0.0, 0.0), aD = aS, aE = aS;
-      for (int k = p; k >= 1; --k) {
-        aS = cfma(aS, t, cf[3 * (p + 1) + k]);
-        aD = cfma(aD, t, cf[2 * (p + 1) + k]);
-        aE = cfma(aE, t, cf[k]);
+    while (have) {
+      __syncthreads();  // the previous box is done with cf
+      cf[threadIdx.x] = n0;
+      cf[threadIdx.x + 64] = n1;
+      cf[threadIdx.x + 128] = n2;
+      cf[threadIdx.x + 192] = n3;
+      __syncthreads();
+      const int l = nl_, sx = nsx, sy = nsy;
+      have = next_box(it, depth, ix, iy, bcount, nl_, nsx, nsy);
+      if (have) {
+        const double2* mb = mom + (level_box_base(nl_) + (size_t)nsx * (1 << nl_) + nsy) * stride;
+        n0 = mb[threadIdx.x];
+        n1 = mb[threadIdx.x + 64];
+        n2 = mb[threadIdx.x + 128];
+        n3 = mb[threadIdx.x + 192];
       }
-      const double2 M0 = cf[0];
-      aD = cfma(aD, t, cf[2 * (p + 1)]);
-      aE = cfma(aE, t, M0);
-      aS = cmul(aS, t);
-      aD = cmul(aD, t);
-      const double lnw = 0.5 * log_pos(w2);
-      const double2 rot = make_double2((wv.x * wv.x - wv.y * wv.y) / w2, 2.0 * wv.x * wv.y / w2);  // w / conj w
-      const double2 pe = cmul(rot, make_double2(aE.x, -aE.y));
-      ux += 0.5 * aS.x + 0.5 * M0.x - M0.x * lnw + aD.x + 0.5 * pe.x;
-      uy += 0.5 * aS.y + 0.5 * M0.y - M0.y * lnw - aD.y + 0.5 * pe.y;
+      {
+        const double2 c = box_center(g, 1 << l, sx, sy);
+        const double2 wv = make_double2(zx - c.x, zy - c.y);
+        const double w2 = wv.x * wv.x + wv.y * wv.y;
+        const double2 t = make_double2(wv.x / w2, -wv.y / w2);
+        // Three series in t, highest order first:
+        //   S = sum_{k>=1} M_k[F] / k t^k,  D = sum_k D_k t^(k+1),  E = sum_k M_k[F] t^k;
+        // the box contributes S/2 + M_0/2 - M_0 ln|w| + conj(D) + (w / conj w) conj(E) / 2.
+        double2 aS = make_double2(0.0, 0.0), aD = aS, aE = aS;
+        for (int k = p; k >= 1; --k) {
+          aS = cfma(aS, t, cf[3 * (p + 1) + k]);
+          aD = cfma(aD, t, cf[2 * (p + 1) + k]);
+          aE = cfma(aE, t, cf[k]);
+        }
+        const double2 M0 = cf[0];
+        aD = cfma(aD, t, cf[2 * (p + 1)]);
+        aE = cfma(aE, t, M0);
+        aS = cmul(aS, t);
+        aD = cmul(aD, t);
+        const double lnw = 0.5 * log_pos(w2);
+        const double2 rot = make_double2((wv.x * wv.x - wv.y * wv.y) / w2, 2.0 * wv.x * wv.y / w2);  // w / conj w
+        const double2 pe = cmul(rot, make_double2(aE.x, -aE.y));
+        ux += 0.5 * aS.x + 0.5 * M0.x - M0.x * lnw + aD.x + 0.5 * pe.x;
+        uy += 0.5 * aS.y + 0.5 * M0.y - M0.y * lnw - aD.y + 0.5 * pe.y;
+      }
     }
   }
   // 3 x 3 leaves directly, own vesicle skipped
@@ -584,19 +794,20 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
 
 }  // namespace
 
-// Workspace layout shared by the size query and the launcher.
+// Workspace layout shared by the size queries and the launchers; the fast multipole method adds the
+// local expansions (3 rows per box) and the binomial table.
 struct TreeLayout {
-  size_t geom, part, leafid, vid, perm, counts, cursor, starts, wstart, bcount, mom, total;
+  size_t geom, part, leafid, vid, perm, counts, cursor, starts, wstart, bcount, mom, loc, tab, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
-static TreeLayout tree_layout(int P, int depth, int p) {
+static TreeLayout tree_layout(int P, int depth, int p, bool fmm) {
   TreeLayout t;
   const size_t nleaf = (size_t)1 << (2 * depth);
-  size_t boxes = 0, moms = 0;
+  size_t boxes = 0;
   for (int l = 2; l <= depth; ++l) boxes += (size_t)1 << (2 * l);
-  moms = boxes * 4 * (size_t)(p + 1);
+  const size_t moms = boxes * 4 * (size_t)(p + 1);
   size_t o = 0;
   t.geom = o;       o += align_up(sizeof(double) * 4);
   t.part = o;       o += align_up(sizeof(double) * 4 * kBBoxBlocks);
@@ -609,69 +820,132 @@ static TreeLayout tree_layout(int P, int depth, int p) {
   t.wstart = o;     o += align_up(sizeof(int32_t) * (nleaf + 1));
   t.bcount = o;     o += align_up(sizeof(int32_t) * (boxes > 0 ? boxes : 1));
   t.mom = o;        o += align_up(sizeof(double2) * (moms + 256));  // 256 spare entries: whole-wave copies
+  t.loc = o;
+  t.tab = o;
+  if (fmm) {
+    t.loc = o;      o += align_up(sizeof(double2) * (boxes * 3 * (size_t)(p + 1) + 192));  // 192 spare: as above
+    t.tab = o;      o += align_up(sizeof(double) * (size_t)(p + 2) * (p + 1));
+  }
   t.total = o;
   return t;
 }
 
-size_t treecode_workspace_bytes(int P, int depth, int p) { return tree_layout(P, depth, p).total; }
+size_t treecode_workspace_bytes(int P, int depth, int p) { return tree_layout(P, depth, p, false).total; }
+size_t fmm_workspace_bytes(int P, int depth, int p) { return tree_layout(P, depth, p, true).total; }
+
+namespace {
+
+struct TreeRun {
+  Geom* geom;
+  double* part;
+  int32_t *leafid, *vid, *perm, *counts, *cursor, *starts, *wstart, *bcount;
+  double2 *mom, *loc;
+  double* tab;
+  Levels lv;       // first box and first moment entry of every level
+  size_t nbox;     // boxes of levels 2..depth
+};
+
+TreeRun tree_run(void* ws, const TreeLayout& t, int depth, int p) {
+  char* base = static_cast<char*>(ws);
+  TreeRun r;
+  r.geom = reinterpret_cast<Geom*>(base + t.geom);
+  r.part = reinterpret_cast<double*>(base + t.part);
+  r.leafid = reinterpret_cast<int32_t*>(base + t.leafid);
+  r.vid = reinterpret_cast<int32_t*>(base + t.vid);
+  r.perm = reinterpret_cast<int32_t*>(base + t.perm);
+  r.counts = reinterpret_cast<int32_t*>(base + t.counts);
+  r.cursor = reinterpret_cast<int32_t*>(base + t.cursor);
+  r.starts = reinterpret_cast<int32_t*>(base + t.starts);
+  r.wstart = reinterpret_cast<int32_t*>(base + t.wstart);
+  r.bcount = reinterpret_cast<int32_t*>(base + t.bcount);
+  r.mom = reinterpret_cast<double2*>(base + t.mom);
+  r.loc = reinterpret_cast<double2*>(base + t.loc);
+  r.tab = reinterpret_cast<double*>(base + t.tab);
+  r.lv = {};
+  size_t acc = 0;
+  for (int l = 2; l <= depth; ++l) {  // boxes of level l start at box index sum_{m = 2}^{l-1} 4^m
+    r.lv.box[l] = acc;
+    r.lv.mom[l] = acc * 4 * (size_t)(p + 1);
+    acc += (size_t)1 << (2 * l);
+  }
+  r.nbox = acc;
+  return r;
+}
+
+// Tree over the points (root square, leaves, leaf order) and the moments of every box of levels
+// 2..depth (leaves from the points, coarser levels by translation).
+void launch_upward(const double* X, const double* f, const double* w, const int32_t* off, int M, int P, int p,
+                   int depth, const TreeRun& r, hipStream_t st) {
+  const int nleaf = 1 << (2 * depth);
+  const int pb = (P + kTB - 1) / kTB < 4096 ? (P + kTB - 1) / kTB : 4096;
+  const int bb = (P + kTB - 1) / kTB < kBBoxBlocks ? (P + kTB - 1) / kTB : kBBoxBlocks;
+  hipLaunchKernelGGL(k_tc_bbox_partial, dim3(bb), dim3(kTB), 0, st, X, P, r.part);
+  hipLaunchKernelGGL(k_tc_bbox_final, dim3(1), dim3(64), 0, st, r.part, bb, r.geom);
+  const int zb = (nleaf + kTB - 1) / kTB < 4096 ? (nleaf + kTB - 1) / kTB : 4096;
+  hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, r.counts, nleaf);
+  hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, r.cursor, nleaf);
+  hipLaunchKernelGGL(k_tc_leaf, dim3(pb), dim3(kTB), 0, st, X, P, r.geom, depth, off, M, r.leafid, r.vid, r.counts);
+  hipLaunchKernelGGL(k_tc_scan, dim3(1), dim3(1024), 0, st, r.counts, nleaf, r.starts, r.wstart);
+  hipLaunchKernelGGL(k_tc_scatter, dim3(pb), dim3(kTB), 0, st, r.leafid, P, r.starts, r.cursor, r.perm);
+  hipLaunchKernelGGL(k_tc_sort, dim3(nleaf), dim3(64), 0, st, r.starts, r.perm);
+  if (depth < 2) return;
+  hipLaunchKernelGGL(k_tc_p2m, dim3(nleaf), dim3(64), 0, st, X, f, w, P, r.perm, r.starts, r.geom, depth, p,
+                     r.mom + r.lv.mom[depth], r.bcount + r.lv.box[depth]);
+  for (int l = depth - 1; l >= 2; --l) {
+    const int n = 1 << l;
+    hipLaunchKernelGGL(k_tc_m2m, dim3(n * n), dim3(64), 0, st, r.geom, n, p, r.mom + r.lv.mom[l + 1],
+                       r.bcount + r.lv.box[l + 1], r.mom + r.lv.mom[l], r.bcount + r.lv.box[l]);
+  }
+}
+
+template <bool kFmm>
+void launch_eval(const double* X, const double* f, const double* w, const int32_t* off, int P, int p, int depth,
+                 double scale, const TreeRun& r, double* out, hipStream_t st) {
+  const int nleaf = 1 << (2 * depth);
+  const int items = nleaf + (P + 63) / 64;  // bound on sum over leaves of ceil(count / 64)
+  hipLaunchKernelGGL(k_tc_eval<kFmm>, dim3(items), dim3(64), 0, st, X, f, w, P, off, r.vid, r.leafid, r.perm,
+                     r.starts, r.wstart, r.geom, depth, p, r.mom, r.loc, r.bcount, scale, out);
+}
+
+}  // namespace
 
 // Everything is built on the device; the launches need no host copy and no synchronisation.
 hipError_t launch_treecode(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
                            double scale, int p, int depth, double* out, void* ws, void* stream) {
   if (P == 0) return hipSuccess;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
-  const TreeLayout t = tree_layout(P, depth, p);
-  Geom* geom = reinterpret_cast<Geom*>(base + t.geom);
-  double* part = reinterpret_cast<double*>(base + t.part);
-  int32_t* leafid = reinterpret_cast<int32_t*>(base + t.leafid);
-  int32_t* vid = reinterpret_cast<int32_t*>(base + t.vid);
-  int32_t* perm = reinterpret_cast<int32_t*>(base + t.perm);
-  int32_t* counts = reinterpret_cast<int32_t*>(base + t.counts);
-  int32_t* cursor = reinterpret_cast<int32_t*>(base + t.cursor);
-  int32_t* starts = reinterpret_cast<int32_t*>(base + t.starts);
-  int32_t* wstart = reinterpret_cast<int32_t*>(base + t.wstart);
-  int32_t* bcount = reinterpret_cast<int32_t*>(base + t.bcount);
-  double2* mom = reinterpret_cast<double2*>(base + t.mom);
-  const int nleaf = 1 << (2 * depth);
-
   if (depth < 0 || depth > kMaxDepth || p < 1 || p > kMaxOrder) return hipErrorInvalidValue;
-  // boxes of level l start at box index sum_{m = 2}^{l-1} 4^m
-  Levels lv = {};
-  size_t acc = 0;
-  for (int l = 2; l <= depth; ++l) {
-    lv.box[l] = acc;
-    lv.mom[l] = acc * 4 * (size_t)(p + 1);
-    acc += (size_t)1 << (2 * l);
-  }
-
-  const int pb = (P + kTB - 1) / kTB < 4096 ? (P + kTB - 1) / kTB : 4096;
-  const int bb = (P + kTB - 1) / kTB < kBBoxBlocks ? (P + kTB - 1) / kTB : kBBoxBlocks;
-  hipLaunchKernelGGL(k_tc_bbox_partial, dim3(bb), dim3(kTB), 0, st, X, P, part);
-  hipLaunchKernelGGL(k_tc_bbox_final, dim3(1), dim3(64), 0, st, part, bb, geom);
-  const int zb = (nleaf + kTB - 1) / kTB < 4096 ? (nleaf + kTB - 1) / kTB : 4096;
-  hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, counts, nleaf);
-  hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, cursor, nleaf);
-  hipLaunchKernelGGL(k_tc_leaf, dim3(pb), dim3(kTB), 0, st, X, P, geom, depth, off, M, leafid, vid, counts);
-  hipLaunchKernelGGL(k_tc_scan, dim3(1), dim3(1024), 0, st, counts, nleaf, starts, wstart);
-  hipLaunchKernelGGL(k_tc_scatter, dim3(pb), dim3(kTB), 0, st, leafid, P, starts, cursor, perm);
-  hipLaunchKernelGGL(k_tc_sort, dim3(nleaf), dim3(64), 0, st, starts, perm);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const TreeRun r = tree_run(ws, tree_layout(P, depth, p, false), depth, p);
+  launch_upward(X, f, w, off, M, P, p, depth, r, st);
   if (depth >= 2) {
-    hipLaunchKernelGGL(k_tc_p2m, dim3(nleaf), dim3(64), 0, st, X, f, w, P, perm, starts, geom, depth, p,
-                       mom + lv.mom[depth], bcount + lv.box[depth]);
-    for (int l = depth - 1; l >= 2; --l) {
-      const int n = 1 << l;
-      hipLaunchKernelGGL(k_tc_m2m, dim3(n * n), dim3(64), 0, st, geom, n, p, mom + lv.mom[l + 1],
-                         bcount + lv.box[l + 1], mom + lv.mom[l], bcount + lv.box[l]);
-    }
-    const size_t nbox = acc;
-    const size_t work = nbox * (p + 1);
+    const size_t work = r.nbox * (p + 1);
     const int gb = (int)((work + kTB - 1) / kTB < 4096 ? (work + kTB - 1) / kTB : 4096);
-    hipLaunchKernelGGL(k_tc_finalize, dim3(gb), dim3(kTB), 0, st, mom, nbox, p);
+    hipLaunchKernelGGL(k_tc_finalize, dim3(gb), dim3(kTB), 0, st, r.mom, r.nbox, p);
   }
-  const int items = nleaf + (P + 63) / 64;  // bound on sum over leaves of ceil(count / 64)
-  hipLaunchKernelGGL(k_tc_eval, dim3(items), dim3(64), 0, st, X, f, w, P, off, vid, leafid, perm, starts, wstart, geom,
-                     depth, p, mom, bcount, scale, out);
+  launch_eval<false>(X, f, w, off, P, p, depth, scale, r, out, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_fmm(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
+                      double scale, int p, int depth, double* out, void* ws, void* stream) {
+  if (P == 0) return hipSuccess;
+  if (depth < 0 || depth > kMaxDepth || p < 1 || p > kMaxOrder) return hipErrorInvalidValue;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const TreeRun r = tree_run(ws, tree_layout(P, depth, p, true), depth, p);
+  launch_upward(X, f, w, off, M, P, p, depth, r, st);
+  if (depth >= 2) {
+    hipLaunchKernelGGL(k_fmm_binom, dim3(1), dim3(64), 0, st, p, r.tab);
+    const int gb = (int)((r.nbox + kM2LWaves - 1) / kM2LWaves);
+    hipLaunchKernelGGL(k_fmm_m2l, dim3(gb), dim3(64 * kM2LWaves), 0, st, r.geom, depth, p, r.mom, r.bcount, r.tab,
+                       r.nbox, r.loc);
+    const size_t rows = 3 * (size_t)(p + 1);
+    for (int l = 3; l <= depth; ++l) {
+      const int n = 1 << l;
+      hipLaunchKernelGGL(k_fmm_l2l, dim3(n * n), dim3(64), 0, st, r.geom, n, p, r.bcount + r.lv.box[l], r.tab,
+                         r.loc + r.lv.box[l - 1] * rows, r.loc + r.lv.box[l] * rows);
+    }
+  }
+  launch_eval<true>(X, f, w, off, P, p, depth, scale, r, out, st);
   return hipGetLastError();
 }
 

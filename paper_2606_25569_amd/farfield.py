@@ -186,6 +186,26 @@ def farfield_treecode(X, force_density, arc_weights, partition, mu, order=30, de
     return out
 
 
+def farfield_fmm(X, force_density, arc_weights, partition, mu, order=30, depth=None, out=None, workspace=None):
+    """Fast multipole far field of the points X on themselves (own vesicle excluded), on the
+    treecode's tree: local expansions of the given order (default depth as the treecode's)."""
+    part = as_partition(partition)
+    P, M = part.n_points, part.n_vesicles
+    _check_vec("X", X, P)
+    _check_vec("force_density", force_density, P)
+    _check_w(arc_weights, P)
+    lib = L.lib()
+    depth = int(lib.vesnet_treecode_default_depth(P)) if depth is None else int(depth)
+    if out is None:
+        out = torch.empty((2, P), dtype=torch.float64, device=X.device)
+    if workspace is None:
+        workspace = _workspace(lib.vesnet_fmm_workspace_bytes(P, depth, int(order)), X.device)
+    L.check(lib.vesnet_farfield_fmm(_ptr(X), _ptr(force_density), _ptr(arc_weights), _ptr(part.device), M, P,
+                                    float(mu), int(order), depth, _ptr(out), _ptr(workspace), workspace.numel(),
+                                    _stream()))
+    return out
+
+
 def near_layers(X, arc_weights, partition):
     """CreateNearLayers (Section 3.3): the five layers of every vesicle, membrane points moved along
     the outward normal by (-h, -h/2, 0, h/2, h) h_v; returns (2, 5P) with vesicle v's 5 N_v nodes at

@@ -24,7 +24,7 @@ def _declared():
 def test_every_declared_symbol_is_exported(L):
     lib = L.lib()
     names = _declared()
-    assert len(names) == 25, names
+    assert len(names) == 27, names
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(L.EXPORTED)
@@ -211,6 +211,37 @@ def test_near_layers_and_rbf_reject(L):
     assert ev(out=None) == -1
     assert ev(out=_p(FAKE + 0x8000000 + 8)) == -1  # out overlaps the targets
     assert ev(cap=0) == 0 and ev(nt=0) == 0
+
+
+@pytest.mark.parametrize("method", ["treecode", "fmm"])
+def test_tree_methods_reject(L, method):
+    """Treecode and fast multipole entry points: workspace queries give 0 out of range, and the
+    calls refuse bad orders, depths, viscosities, NULLs, short workspaces and overlaps."""
+    lib = L.lib()
+    wsq = getattr(lib, f"vesnet_{method}_workspace_bytes")
+    run = getattr(lib, f"vesnet_farfield_{method}")
+    assert lib.vesnet_treecode_default_depth(0) == 0
+    assert lib.vesnet_treecode_default_depth(64) == 0
+    assert lib.vesnet_treecode_default_depth(65) == 1
+    assert lib.vesnet_treecode_default_depth(256000) == 6
+    assert wsq(100, 3, 0) == 0 and wsq(100, 3, 49) == 0 and wsq(100, -1, 8) == 0 and wsq(100, 11, 8) == 0
+    assert wsq(-1, 3, 8) == 0
+    need = wsq(100, 3, 8)
+    assert need > 0
+    if method == "fmm":  # the treecode's workspace plus the local expansions and the binomial table
+        assert need > lib.vesnet_treecode_workspace_bytes(100, 3, 8)
+    X, f, w, off = _p(FAKE), _p(FAKE + 0x100000), _p(FAKE + 0x200000), _p(FAKE + 0x300000)
+    out, ws = _p(FAKE + 0x400000), _p(FAKE + 0x1000000)
+    call = lambda **k: run(k.get("X", X), f, w, off, 2, 100, k.get("mu", 1.0), k.get("order", 8), k.get("depth", 3),
+                           k.get("out", out), k.get("ws", ws), k.get("wsb", need), None)
+    assert call(order=0) == -2 and call(order=49) == -2
+    assert call(depth=-1) == -2 and call(depth=11) == -2
+    assert call(mu=0.0) == -1 and call(mu=float("nan")) == -1
+    assert call(X=None) == -1 and call(out=None) == -1
+    assert call(wsb=need - 1) == -3 and call(ws=None) == -3
+    assert call(out=_p(FAKE + 8)) == -1                      # out overlaps the points
+    assert call(ws=_p(FAKE + 0x400000 + 64)) == -1           # workspace overlaps out
+    assert run(None, None, None, None, 0, 0, 1.0, 8, 3, None, None, 0, None) == 0  # empty: no-op
 
 
 def test_product_package_has_no_cpu_fallback():
