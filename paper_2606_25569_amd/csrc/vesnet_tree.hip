@@ -93,6 +93,37 @@ __device__ __forceinline__ double log_pos(double q) {
   return fma((double)e, kLn2Hi, fma((double)e, kLn2Lo, 2.0 * s * pol));
 }
 
+// Table of the reduced log below: entry i (mantissa interval [1 + i/64, 1 + (i+1)/64)) holds a 10-bit
+// approximation a of 1 / (1 + (i + 0.5) / 64) and -ln a (from log_pos).  One entry per lane.
+constexpr int kLogTab = 64;
+__device__ __forceinline__ double2 log_tab_entry(int i) {
+  const double c = 1.0 + ((double)i + 0.5) / 64.0;
+  const double a = rint(512.0 / c) / 512.0;
+  return make_double2(a, -log_pos(a));
+}
+
+// Natural log of a finite q > 0 with the table: q = m 2^e, m in [1, 2); r = m a - 1 (exact product, one
+// rounding), |r| < 0.009, ln m = -ln a + log1p(r), log1p by its series through r^7 (the next term is
+// below 5e-18); ln 2 in a high and a low part as in log_pos.  About 20 operations, no division.
+__device__ __forceinline__ double log_reduced(double q, const double2* __restrict__ tab) {
+  constexpr double kLn2Hi = 6.93147180369123816490e-01;
+  constexpr double kLn2Lo = 1.90821492927058770002e-10;
+  int e;
+  const double m = 2.0 * frexp(q, &e);
+  const int i = clamp_i((int)fma(m, 64.0, -64.0), 0, kLogTab - 1);
+  const double2 t = tab[i];
+  const double r = fma(m, t.x, -1.0);
+  double pol = 1.0 / 7.0;
+  pol = fma(pol, r, -1.0 / 6.0);
+  pol = fma(pol, r, 1.0 / 5.0);
+  pol = fma(pol, r, -1.0 / 4.0);
+  pol = fma(pol, r, 1.0 / 3.0);
+  pol = fma(pol, r, -0.5);
+  pol = fma(pol, r, 1.0);
+  const double ed = (double)(e - 1);
+  return fma(ed, kLn2Hi, fma(ed, kLn2Lo, fma(r, pol, t.y)));
+}
+
 // Box centre at a level with n boxes per side (contraction off: the same bits as the plain formula).
 __device__ __forceinline__ double2 box_center(const Geom& g, int n, int bx, int by) {
 #pragma clang fp contract(off)
@@ -194,9 +225,10 @@ __global__ __launch_bounds__(kTB) void k_tc_leaf(const double* __restrict__ X, i
   }
 }
 
-// Exclusive scans of the leaf occupancies (starts) and of their 64-point chunks (wave starts).
+// Exclusive scans of the leaf occupancies (starts) and of their chunks of 2^cshift targets (wave starts).
 __global__ __launch_bounds__(1024) void k_tc_scan(const int32_t* __restrict__ counts, int nleaf,
-                                                  int32_t* __restrict__ starts, int32_t* __restrict__ wstart) {
+                                                  int32_t* __restrict__ starts, int32_t* __restrict__ wstart,
+                                                  int cshift) {
   __shared__ int32_t sa[1024];
   __shared__ int32_t sb[1024];
   const int t = threadIdx.x;
@@ -205,31 +237,30 @@ __global__ __launch_bounds__(1024) void k_tc_scan(const int32_t* __restrict__ co
   int32_t a = 0, b = 0;
   for (int i = b0; i < b1; ++i) {
     a += counts[i];
-    b += (counts[i] + 63) >> 6;
+    b += (counts[i] + (1 << cshift) - 1) >> cshift;
   }
+  const int32_t own_a = a, own_b = b;
   sa[t] = a;
   sb[t] = b;
   __syncthreads();
-  if (t == 0) {
-    int32_t ra = 0, rb = 0;
-    for (int k = 0; k < 1024; ++k) {
-      const int32_t xa = sa[k], xb = sb[k];
-      sa[k] = ra;
-      sb[k] = rb;
-      ra += xa;
-      rb += xb;
-    }
-    starts[nleaf] = ra;
-    wstart[nleaf] = rb;
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan of the segment sums (Hillis-Steele)
+    const int32_t xa = t >= d ? sa[t - d] : 0, xb = t >= d ? sb[t - d] : 0;
+    __syncthreads();
+    sa[t] += xa;
+    sb[t] += xb;
+    __syncthreads();
   }
-  __syncthreads();
-  a = sa[t];
-  b = sb[t];
+  if (t == 1023) {
+    starts[nleaf] = sa[t];
+    wstart[nleaf] = sb[t];
+  }
+  a = sa[t] - own_a;  // exclusive
+  b = sb[t] - own_b;
   for (int i = b0; i < b1; ++i) {
     starts[i] = a;
     wstart[i] = b;
     a += counts[i];
-    b += (counts[i] + 63) >> 6;
+    b += (counts[i] + (1 << cshift) - 1) >> cshift;
   }
 }
 
@@ -331,59 +362,80 @@ __global__ __launch_bounds__(64) void k_tc_p2m(const double* __restrict__ X, con
   mb[2 * (p + 1) + k] = m2;
 }
 
+// 1 / (m + 1), m = 0..kMaxOrder: the binomial recurrence below multiplies instead of dividing.
+__constant__ double kRecip[kMaxOrder + 1] = {
+    1.0 / 1,  1.0 / 2,  1.0 / 3,  1.0 / 4,  1.0 / 5,  1.0 / 6,  1.0 / 7,  1.0 / 8,  1.0 / 9,  1.0 / 10,
+    1.0 / 11, 1.0 / 12, 1.0 / 13, 1.0 / 14, 1.0 / 15, 1.0 / 16, 1.0 / 17, 1.0 / 18, 1.0 / 19, 1.0 / 20,
+    1.0 / 21, 1.0 / 22, 1.0 / 23, 1.0 / 24, 1.0 / 25, 1.0 / 26, 1.0 / 27, 1.0 / 28, 1.0 / 29, 1.0 / 30,
+    1.0 / 31, 1.0 / 32, 1.0 / 33, 1.0 / 34, 1.0 / 35, 1.0 / 36, 1.0 / 37, 1.0 / 38, 1.0 / 39, 1.0 / 40,
+    1.0 / 41, 1.0 / 42, 1.0 / 43, 1.0 / 44, 1.0 / 45, 1.0 / 46, 1.0 / 47, 1.0 / 48, 1.0 / 49};
+
 // Parent moments at a level with n boxes per side from the children one level down:
 // M'_k = sum_children sum_{m <= k} C(k, m) d^(k-m) M_m, d = child centre - parent centre; the
-// conj(zeta) F row gains conj(d) times the translated F row.  One wavefront per parent box, lane
-// k = order, the children's three rows staged in LDS.
-__global__ __launch_bounds__(64) void k_tc_m2m(const Geom* __restrict__ geom, int n, int p,
-                                               const double2* __restrict__ child, const int32_t* __restrict__ ccount,
-                                               double2* __restrict__ parent, int32_t* __restrict__ pcount) {
+// conj(zeta) F row gains conj(d) times the translated F row.  One workgroup per parent box, wave q
+// translates child q (lane k = order, the child's three rows staged in LDS), and the four results
+// are added in child order.  C(k, m + 1) = C(k, m) (k - m) / (m + 1) is an integer below 2^53 for
+// k <= 48, so rounding the product with the reciprocal to the nearest integer gives it exactly.
+__global__ __launch_bounds__(256) void k_tc_m2m(const Geom* __restrict__ geom, int n, int p,
+                                                const double2* __restrict__ child, const int32_t* __restrict__ ccount,
+                                                double2* __restrict__ parent, int32_t* __restrict__ pcount) {
   __shared__ double2 cm[4][3 * (kMaxOrder + 1)];
   const int box = blockIdx.x;
-  const int k = threadIdx.x;
+  const int q = threadIdx.x >> 6, k = threadIdx.x & 63;
   const int bx = box / n, by = box % n;
   const int stride = 4 * (p + 1);
   const double wc = geom->side / (double)(2 * n);  // child width
-  int cnt = 0, cc[4];
-  for (int q = 0; q < 4; ++q) {
-    const int cb = (2 * bx + (q >> 1)) * (2 * n) + (2 * by + (q & 1));
-    cc[q] = ccount[cb];
-    cnt += cc[q];
-    if (cc[q] == 0) continue;
+  const int cb = (2 * bx + (q >> 1)) * (2 * n) + (2 * by + (q & 1));
+  const int cnt = ccount[cb];
+  if (cnt > 0)
     for (int e = k; e < 3 * (p + 1); e += 64) cm[q][e] = child[(size_t)cb * stride + e];
-  }
   __syncthreads();
-  if (k == 0) pcount[box] = cnt;
-  if (k > p) return;
-  double2 s0 = make_double2(0.0, 0.0), s1 = s0, s2 = s0;
-  for (int q = 0; q < 4; ++q) {
-    if (cc[q] == 0) continue;
+  double2 t0 = make_double2(0.0, 0.0), t1 = t0, t2 = t0;
+  if (cnt > 0 && k <= p) {
     const double2 d = make_double2(((double)(q >> 1) - 0.5) * wc, ((double)(q & 1) - 0.5) * wc);
     const double dd = d.x * d.x + d.y * d.y;
     const double2 dinv = make_double2(d.x / dd, -d.y / dd);
-    double2 t0 = make_double2(0.0, 0.0), t1 = t0, t2 = t0;
-    double binom = 1.0;          // C(k, m)
+    double binom = 1.0;           // C(k, m)
     double2 dp = cpow_int(d, k);  // d^(k - m)
     for (int m = 0; m <= k; ++m) {
       const double2 coef = make_double2(binom * dp.x, binom * dp.y);
       t0 = cfma(coef, cm[q][m], t0);
       t1 = cfma(coef, cm[q][(p + 1) + m], t1);
       t2 = cfma(coef, cm[q][2 * (p + 1) + m], t2);
-      binom = binom * (double)(k - m) / (double)(m + 1);
+      binom = rint(binom * (double)(k - m) * kRecip[m]);
       dp = cmul(dp, dinv);
     }
-    s0.x += t0.x;
-    s0.y += t0.y;
-    s1.x += t1.x;
-    s1.y += t1.y;
     const double2 extra = cmul(make_double2(d.x, -d.y), t0);
-    s2.x += t2.x + extra.x;
-    s2.y += t2.y + extra.y;
+    t2.x += extra.x;
+    t2.y += extra.y;
   }
-  double2* pm = parent + (size_t)box * stride;
-  pm[k] = s0;
-  pm[(p + 1) + k] = s1;
-  pm[2 * (p + 1) + k] = s2;
+  __syncthreads();  // every wave is done reading its child
+  if (k <= p) {     // each wave's row of LDS now holds its three results
+    cm[q][k] = t0;
+    cm[q][(p + 1) + k] = t1;
+    cm[q][2 * (p + 1) + k] = t2;
+  }
+  __syncthreads();
+  if (q == 0) {
+    int tot = 0;
+    for (int c = 0; c < 4; ++c) tot += ccount[(2 * bx + (c >> 1)) * (2 * n) + (2 * by + (c & 1))];
+    if (k == 0) pcount[box] = tot;
+    if (k <= p) {
+      double2 s0 = cm[0][k], s1 = cm[0][(p + 1) + k], s2 = cm[0][2 * (p + 1) + k];
+      for (int c = 1; c < 4; ++c) {
+        s0.x += cm[c][k].x;
+        s0.y += cm[c][k].y;
+        s1.x += cm[c][(p + 1) + k].x;
+        s1.y += cm[c][(p + 1) + k].y;
+        s2.x += cm[c][2 * (p + 1) + k].x;
+        s2.y += cm[c][2 * (p + 1) + k].y;
+      }
+      double2* pm = parent + (size_t)box * stride;
+      pm[k] = s0;
+      pm[(p + 1) + k] = s1;
+      pm[2 * (p + 1) + k] = s2;
+    }
+  }
 }
 
 // After all translations: row 3 = M_k[F] / k (k >= 1) for the log series of F, and row 2 = D_k, the
@@ -453,24 +505,44 @@ __global__ __launch_bounds__(64) void k_fmm_binom(int p, double* __restrict__ ta
   }
 }
 
-constexpr int kM2LWaves = 4;  // target boxes per workgroup; they share the binomial table in LDS
+constexpr int kM2LWaves = 4;  // waves per target box; source box k of the list goes to wave k mod 4
+
+// Dynamic LDS of k_fmm_m2l: the binomial table, then per wave three staging vectors (A, Phi and B
+// series) of max(G (p + 2), 64) complex numbers, G = floor(64 / (p + 1)).
+__host__ __device__ inline int m2l_groups(int p) { return 64 / (p + 1); }
+__host__ __device__ inline int m2l_stage(int p) {
+  const int g = m2l_groups(p) * (p + 2);
+  return g > 64 ? g : 64;
+}
+__host__ __device__ inline int m2l_table_doubles(int p) { return ((p + 2) * (p + 1) + 1) / 2 * 2; }  // 16-byte multiple
+inline size_t m2l_lds_bytes(int p) {
+  return sizeof(double) * (size_t)m2l_table_doubles(p) + sizeof(double2) * (size_t)kM2LWaves * 3 * m2l_stage(p);
+}
 
 // Interaction-list contributions to the local expansion of every non-empty box of levels 2..depth (one
-// launch for all levels).  One wavefront per target box: lane m scales the source's coefficient a_m by
-// (-t)^m into LDS, then lane l forms sum_m C(m + l - 1, l) (-t)^m a_m for the three series.
+// launch for all levels, one workgroup per target box).  Lanes form G groups of p + 1; each group takes
+// one source box at a time: lane j of the group scales a_(j+1) by (-t)^(j+1) into LDS, then forms
+// sum_m C(m + j - 1, j) (-t)^m a_m for order l = j of the three series.  The partial expansions of all
+// groups and waves are added in a fixed order at the end.
 __global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restrict__ geom, int depth, int p,
                                                            const double2* __restrict__ mom,
                                                            const int32_t* __restrict__ bcount,
-                                                           const double* __restrict__ tab, size_t nbox,
-                                                           double2* __restrict__ loc) {
-  __shared__ double T[(kMaxOrder + 2) * (kMaxOrder + 1)];
-  __shared__ double2 st[kM2LWaves][3][kMaxOrder + 2];
-  const int nt = (p + 2) * (p + 1);
+                                                           const double* __restrict__ tab, double2* __restrict__ loc) {
+  extern __shared__ double smem[];
+  const size_t box = blockIdx.x;
+  if (bcount[box] == 0) return;  // the whole workgroup
+  const int np = p + 1;
+  const int G = m2l_groups(p), stage = m2l_stage(p);
+  double* T = smem;
+  double2* st = reinterpret_cast<double2*>(smem + m2l_table_doubles(p));
+  const int nt = (p + 2) * np;
   for (int e = threadIdx.x; e < nt; e += 64 * kM2LWaves) T[e] = tab[e];
-  __syncthreads();  // the only workgroup barrier: waves below synchronise among their own lanes
+  __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const size_t box = (size_t)blockIdx.x * kM2LWaves + wv;
-  if (box >= nbox || bcount[box] == 0) return;
+  const int g = lane / np, j = lane - g * np;  // group, order within the group; g >= G: idle lane
+  double2* sA = st + (size_t)wv * 3 * stage;
+  double2* sP = sA + stage;
+  double2* sQ = sP + stage;
   int l = 2;
   while (l < depth && box >= level_box_base(l + 1)) ++l;
   const int n = 1 << l;
@@ -478,83 +550,113 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restri
   const int b = (int)(box - base);
   const int bx = b / n, by = b - (b / n) * n;
   const double wl = geom->side / (double)n;
-  const int stride = 4 * (p + 1);
-  const double inv = lane > 0 ? 1.0 / (double)lane : 0.0;  // 1/m and 1/l: lane = m in the scaling, l after
-  double2* sA = st[wv][0];
-  double2* sP = st[wv][1];
-  double2* sQ = st[wv][2];
+  const int stride = 4 * np;
+  const double inv_m = 1.0 / (double)(j + 1);          // 1/m, m = j + 1
+  const double inv_l = j > 0 ? 1.0 / (double)j : 0.0;  // 1/l, l = j
   double2 accA = make_double2(0.0, 0.0), accB = accA, accC = accA;
-  for (int a = -2; a <= 3; ++a)
-    for (int c = -2; c <= 3; ++c) {
-      const int sx = 2 * (bx >> 1) + a, sy = 2 * (by >> 1) + c;
+  int cand = 0, k = 0;  // next candidate of the 6 x 6 block; non-empty sources seen so far
+  for (;;) {
+    // this wave's next batch: up to G non-empty sources, group g takes the g-th
+    int nb = 0, msx = 0, msy = 0;
+    while (nb < G && cand < 36) {
+      const int sx = 2 * (bx >> 1) + cand / 6 - 2, sy = 2 * (by >> 1) + cand % 6 - 2;
+      ++cand;
       if (sx < 0 || sx >= n || sy < 0 || sy >= n) continue;
       if (abs(sx - bx) <= 1 && abs(sy - by) <= 1) continue;
-      const size_t sb = base + (size_t)sx * n + sy;
-      if (bcount[sb] == 0) continue;
-      const double2 d = make_double2((double)(sx - bx) * wl, (double)(sy - by) * wl);
-      const double dd = d.x * d.x + d.y * d.y;
-      const double rdd = recip(dd);
-      const double2 mt = make_double2(-d.x * rdd, d.y * rdd);  // -t = -1/d
-      const double2 pw = cpow_int(mt, lane);                   // (-t)^lane
-      const double2* ms = mom + sb * stride;
-      if (lane >= 1 && lane <= p + 1) {
-        const double2 Fm1 = ms[lane - 1];
-        double2 aA = make_double2(0.0, 0.0), aQ = ms[2 * (p + 1) + lane - 1];
-        if (lane <= p) {
-          const double2 Fm = ms[lane], Cm = ms[(p + 1) + lane];
-          aA = make_double2(-Fm.x * inv, -Fm.y * inv);
-          aQ.x = fma(-Cm.x, inv, aQ.x);
-          aQ.y = fma(-Cm.y, inv, aQ.y);
-        }
-        sA[lane] = cmul(aA, pw);
-        sP[lane] = cmul(Fm1, pw);
-        sQ[lane] = cmul(aQ, pw);
+      if (bcount[base + (size_t)sx * n + sy] == 0) continue;
+      if ((k++ & (kM2LWaves - 1)) != wv) continue;
+      if (g == nb) {
+        msx = sx;
+        msy = sy;
       }
-      wave_sync();
-      if (lane <= p) {
-        double2 xA = make_double2(0.0, 0.0), xP = xA, xQ = xA;
-        for (int m = 1; m <= p + 1; ++m) {
-          const double cb = T[m * (p + 1) + lane];
-          const double2 qa = sA[m], qp = sP[m], qq = sQ[m];
-          xA.x = fma(cb, qa.x, xA.x);
-          xA.y = fma(cb, qa.y, xA.y);
-          xP.x = fma(cb, qp.x, xP.x);
-          xP.y = fma(cb, qp.y, xP.y);
-          xQ.x = fma(cb, qq.x, xQ.x);
-          xQ.y = fma(cb, qq.y, xQ.y);
-        }
-        const double2 lamA = ms[0], lamQ = ms[p + 1];
-        double2 bA, bP, bQ;
-        if (lane == 0) {
-          const double lnd = 0.5 * log_pos(dd);
-          bA = make_double2(fma(lamA.x, lnd, xA.x), fma(lamA.y, lnd, xA.y));
-          bP = xP;
-          bQ = make_double2(fma(lamQ.x, lnd, xQ.x), fma(lamQ.y, lnd, xQ.y));
-        } else {
-          const double2 tl = (lane & 1) ? make_double2(-pw.x, -pw.y) : pw;  // t^l = (-1)^l (-t)^l
-          bA = cmul(tl, make_double2(fma(-lamA.x, inv, xA.x), fma(-lamA.y, inv, xA.y)));
-          bP = cmul(tl, xP);
-          bQ = cmul(tl, make_double2(fma(-lamQ.x, inv, xQ.x), fma(-lamQ.y, inv, xQ.y)));
-        }
-        accA.x += bA.x;
-        accA.y += bA.y;
-        accC.x += bP.x;
-        accC.y += bP.y;
-        const double2 sh = cmul(make_double2(d.x, -d.y), bP);
-        accB.x += bQ.x + sh.x;
-        accB.y += bQ.y + sh.y;
-        if (lane == 0) {
-          accA.x -= lamA.x;
-          accA.y -= lamA.y;
-        }
-      }
-      wave_sync();  // the staging is rewritten for the next source box
+      ++nb;
     }
-  if (lane <= p) {
-    double2* lb = loc + box * 3 * (p + 1);
-    lb[lane] = accA;
-    lb[(p + 1) + lane] = accB;
-    lb[2 * (p + 1) + lane] = accC;
+    if (nb == 0) break;
+    const bool on = g < nb;
+    const double2 d = make_double2((double)(msx - bx) * wl, (double)(msy - by) * wl);
+    const double dd = on ? d.x * d.x + d.y * d.y : 1.0;
+    const double rdd = recip(dd);
+    const double2 mt = make_double2(-d.x * rdd, d.y * rdd);  // -t = -1/d
+    const double2 pl = cpow_int(mt, j);                      // (-t)^l, l = j
+    const double2 pm = cmul(pl, mt);                         // (-t)^m, m = j + 1
+    const double2* ms = mom + (base + (size_t)msx * n + msy) * stride;
+    double2* qA = sA + g * (p + 2);
+    double2* qP = sP + g * (p + 2);
+    double2* qQ = sQ + g * (p + 2);
+    if (on) {
+      double2 aA = make_double2(0.0, 0.0), aQ = ms[2 * np + j];
+      if (j < p) {
+        const double2 Fm = ms[j + 1], Cm = ms[np + j + 1];
+        aA = make_double2(-Fm.x * inv_m, -Fm.y * inv_m);
+        aQ.x = fma(-Cm.x, inv_m, aQ.x);
+        aQ.y = fma(-Cm.y, inv_m, aQ.y);
+      }
+      qA[j + 1] = cmul(aA, pm);
+      qP[j + 1] = cmul(ms[j], pm);
+      qQ[j + 1] = cmul(aQ, pm);
+    }
+    wave_sync();
+    if (on) {
+      double2 xA = make_double2(0.0, 0.0), xP = xA, xQ = xA;
+#pragma unroll 2
+      for (int m = 1; m <= np; ++m) {
+        const double cb = T[m * np + j];
+        const double2 va = qA[m], vp = qP[m], vq = qQ[m];
+        xA.x = fma(cb, va.x, xA.x);
+        xA.y = fma(cb, va.y, xA.y);
+        xP.x = fma(cb, vp.x, xP.x);
+        xP.y = fma(cb, vp.y, xP.y);
+        xQ.x = fma(cb, vq.x, xQ.x);
+        xQ.y = fma(cb, vq.y, xQ.y);
+      }
+      const double2 lamA = ms[0], lamQ = ms[np];
+      double2 bA, bP, bQ;
+      if (j == 0) {
+        const double lnd = 0.5 * log_pos(dd);
+        bA = make_double2(fma(lamA.x, lnd, xA.x) - lamA.x, fma(lamA.y, lnd, xA.y) - lamA.y);  // - M_0[F]: constant
+        bP = xP;
+        bQ = make_double2(fma(lamQ.x, lnd, xQ.x), fma(lamQ.y, lnd, xQ.y));
+      } else {
+        const double2 tl = (j & 1) ? make_double2(-pl.x, -pl.y) : pl;  // t^l = (-1)^l (-t)^l
+        bA = cmul(tl, make_double2(fma(-lamA.x, inv_l, xA.x), fma(-lamA.y, inv_l, xA.y)));
+        bP = cmul(tl, xP);
+        bQ = cmul(tl, make_double2(fma(-lamQ.x, inv_l, xQ.x), fma(-lamQ.y, inv_l, xQ.y)));
+      }
+      accA.x += bA.x;
+      accA.y += bA.y;
+      accC.x += bP.x;
+      accC.y += bP.y;
+      const double2 sh = cmul(make_double2(d.x, -d.y), bP);  // + conj(d) Phi
+      accB.x += bQ.x + sh.x;
+      accB.y += bQ.y + sh.y;
+    }
+    wave_sync();  // the staging is rewritten by the next batch
+  }
+  // partial expansions of every group of every wave, added in a fixed order
+  __syncthreads();
+  sA[lane] = accA;
+  sP[lane] = accB;
+  sQ[lane] = accC;
+  __syncthreads();
+  if (threadIdx.x < np) {
+    const int t = threadIdx.x;
+    double2 rA = make_double2(0.0, 0.0), rB = rA, rC = rA;
+    for (int w = 0; w < kM2LWaves; ++w) {
+      const double2* r = st + (size_t)w * 3 * stage;
+      for (int q = 0; q < G; ++q) {
+        const double2 a = r[q * np + t], bb = r[stage + q * np + t], c = r[2 * stage + q * np + t];
+        rA.x += a.x;
+        rA.y += a.y;
+        rB.x += bb.x;
+        rB.y += bb.y;
+        rC.x += c.x;
+        rC.y += c.y;
+      }
+    }
+    double2* lb = loc + box * 3 * np;
+    lb[t] = rA;
+    lb[np + t] = rB;
+    lb[2 * np + t] = rC;
   }
 }
 
@@ -598,10 +700,10 @@ __global__ __launch_bounds__(64) void k_fmm_l2l(const Geom* __restrict__ geom, i
 // ---------------------------------------------------------------- evaluation
 
 __device__ __forceinline__ void direct_term(double zx, double zy, double sx, double sy, double Fx, double Fy,
-                                            double& ux, double& uy) {
+                                            const double2* __restrict__ ltab, double& ux, double& uy) {
   const double rx = zx - sx, ry = zy - sy;
   const double q = rx * rx + ry * ry;
-  const double lg = -0.5 * log_pos(q);
+  const double lg = -0.5 * log_reduced(q, ltab);
   const double s = (rx * Fx + ry * Fy) * recip(q);
   ux = fma(lg, Fx, fma(s, rx, ux));
   uy = fma(lg, Fy, fma(s, ry, uy));
@@ -637,18 +739,23 @@ __device__ __forceinline__ bool next_box(ListWalk& s, int depth, int ix, int iy,
   return false;
 }
 
-// One wavefront per (leaf, chunk of 64 of its points); every lane one target.  The far part is the
+// Targets per wavefront of the evaluation: the treecode's far part costs the same per wavefront whatever
+// its target count, so it takes 64; the fast multipole method's is a short polynomial per target and
+// takes 32, twice the wavefronts to hide the direct part's latencies.
+template <bool kFmm> constexpr int eval_chunk_shift() { return kFmm ? 5 : 6; }
+
+// One wavefront per (leaf, chunk of kChunk of its points); every lane one target.  The far part is the
 // treecode's walk over the interaction lists (kFmm false: mom holds the finalised moments) or the leaf's
-// local expansion (kFmm true: loc holds it); the direct part and the own-vesicle correction are shared.
+// local expansion (kFmm true: loc holds it); the direct part is shared.
 template <bool kFmm>
 __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, const double* __restrict__ f,
-                                                const double* __restrict__ w, int P, const int32_t* __restrict__ off,
-                                                const int32_t* __restrict__ vid, const int32_t* __restrict__ leafid,
+                                                const double* __restrict__ w, int P, const int32_t* __restrict__ vid,
                                                 const int32_t* __restrict__ perm, const int32_t* __restrict__ starts,
                                                 const int32_t* __restrict__ wstart, const Geom* __restrict__ geom,
                                                 int depth, int p, const double2* __restrict__ mom,
                                                 const double2* __restrict__ loc, const int32_t* __restrict__ bcount,
                                                 double scale, double* __restrict__ out) {
+  constexpr int kChunk = 1 << eval_chunk_shift<kFmm>();
   const int n = 1 << depth;
   const int nleaf = n * n;
   const int item = blockIdx.x;
@@ -660,7 +767,17 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
   }
   const int leaf = lo;
   const int s0 = starts[leaf], s1 = starts[leaf + 1];
-  const int slot = s0 + (item - wstart[leaf]) * 64 + (int)threadIdx.x;
+  // A chunk of at most 32 targets splits the wave into S = 64 / K lane groups (K = the target count
+  // rounded up to a power of two): lane = g K + t takes target t, and in the direct part every S-th
+  // source from g on; the groups' direct sums are added at the end.  The far part is the same in every
+  // group.
+  const int lane = threadIdx.x;
+  const int base = s0 + (item - wstart[leaf]) * kChunk;
+  const int tcnt = min(kChunk, s1 - base);
+  int K = 1;
+  while (K < tcnt) K <<= 1;
+  const int S = 64 / K;
+  const int slot = base + (lane & (K - 1));
   const bool active = slot < s1;
   const int i = active ? perm[slot] : perm[s0];
   const double zx = X[i], zy = X[P + i];
@@ -673,6 +790,8 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
   __shared__ double2 cf[4 * 64];  // 4 (p + 1) <= 196 entries used; padded for whole-wave copies
   __shared__ double sx_[64], sy_[64], sfx[64], sfy[64];
   __shared__ int32_t sv[64];
+  __shared__ double2 ltab[kLogTab];
+  ltab[threadIdx.x] = log_tab_entry(threadIdx.x);  // read after the first barrier below
 
   if constexpr (kFmm) {
     // the leaf's local expansion: u += -A(zeta)/2 - conj(B(zeta))/2 + zeta conj(C(zeta))/2
@@ -752,6 +871,7 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
     }
   }
   // 3 x 3 leaves directly, own vesicle skipped
+  double dx = 0.0, dy = 0.0;
   for (int jx = max(ix - 1, 0); jx <= min(ix + 1, n - 1); ++jx)
     for (int jy = max(iy - 1, 0); jy <= min(iy + 1, n - 1); ++jy) {
       const int nl = jx * n + jy;
@@ -768,27 +888,93 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
           sv[threadIdx.x] = vid[j];
         }
         __syncthreads();
-        for (int q = 0; q < cnt; ++q) {
-          if (sv[q] == vi) continue;
-          direct_term(zx, zy, sx_[q], sy_[q], sfx[q], sfy[q], ux, uy);
+        // the next source's data is read while the current one is evaluated
+        int q = lane / K;
+        const int qq = q < cnt ? q : 0;
+        double nx = sx_[qq], ny = sy_[qq], nfx = sfx[qq], nfy = sfy[qq];
+        int nv = sv[qq];
+        for (; q < cnt; q += S) {
+          const double cx = nx, cy = ny, cfx = nfx, cfy = nfy;
+          const int cv = nv;
+          const int qn = q + S < cnt ? q + S : q;
+          nx = sx_[qn];
+          ny = sy_[qn];
+          nfx = sfx[qn];
+          nfy = sfy[qn];
+          nv = sv[qn];
+          if (cv != vi) direct_term(zx, zy, cx, cy, cfx, cfy, ltab, dx, dy);
         }
       }
     }
-  // own-vesicle sources outside those leaves were in the expansions: take them out
-  const int v0 = clamp_i(off[vi], 0, P), v1 = max(v0, clamp_i(off[vi + 1], 0, P));  // offsets never trusted
-  for (int j = v0; j < v1; ++j) {
-    if (j == i) continue;
-    const int lj = leafid[j];
-    const int jx = lj / n, jy = lj - jx * n;
-    if (abs(jx - ix) <= 1 && abs(jy - iy) <= 1) continue;
-    double dx = 0.0, dy = 0.0;
-    direct_term(zx, zy, X[j], X[P + j], w[j] * f[j], w[j] * f[P + j], dx, dy);
-    ux -= dx;
-    uy -= dy;
+  for (int o = K; o < 64; o <<= 1) {  // groups' direct sums, pairwise in a fixed order
+    dx += __shfl_down(dx, o);
+    dy += __shfl_down(dy, o);
   }
-  if (active) {
-    out[i] = ux * scale;
-    out[P + i] = uy * scale;
+  if (active && lane < K) {
+    out[i] = (ux + dx) * scale;
+    out[P + i] = (uy + dy) * scale;
+  }
+}
+
+// Own-vesicle sources outside the 3 x 3 leaves around a target were in the expansions: their direct terms
+// are subtracted from the finished velocity.  One wavefront per vesicle, targets 64 at a time, the
+// vesicle's points (coordinates, weighted force, leaf) staged in LDS in chunks.  Few sources of a chunk
+// are far from a given target, and different ones for different lanes: each lane first lists its far
+// sources, then the wave evaluates the lists side by side (as many steps as the longest list).
+constexpr int kOwnChunk = 128;
+
+__global__ __launch_bounds__(64) void k_tc_own(const double* __restrict__ X, const double* __restrict__ f,
+                                               const double* __restrict__ w, int P, const int32_t* __restrict__ off,
+                                               const int32_t* __restrict__ leafid, int depth, double scale,
+                                               double* __restrict__ out) {
+  __shared__ double sx_[kOwnChunk], sy_[kOwnChunk], sfx[kOwnChunk], sfy[kOwnChunk];
+  __shared__ int32_t sl[kOwnChunk];
+  __shared__ uint8_t lst[kOwnChunk][64];  // lst[k][lane]: the k-th far source of the lane's target
+  __shared__ double2 ltab[kLogTab];
+  const int v = blockIdx.x;
+  const int v0 = clamp_i(off[v], 0, P), v1 = max(v0, clamp_i(off[v + 1], 0, P));  // offsets never trusted
+  if (v1 - v0 < 2) return;
+  const int lane = threadIdx.x;
+  ltab[lane] = log_tab_entry(lane);  // read after the first barrier below
+  const int mask = (1 << depth) - 1;
+  for (int t0 = v0; t0 < v1; t0 += 64) {
+    const int i = t0 + lane;
+    const bool act = i < v1;
+    const int ii = act ? i : v0;
+    const double zx = X[ii], zy = X[P + ii];
+    const int li = leafid[ii];
+    const int ix = li >> depth, iy = li & mask;
+    double ux = 0.0, uy = 0.0;
+    for (int c0 = v0; c0 < v1; c0 += kOwnChunk) {
+      const int cnt = min(kOwnChunk, v1 - c0);
+      __syncthreads();  // the previous chunk is done
+      for (int q = lane; q < cnt; q += 64) {
+        const int j = c0 + q;
+        sx_[q] = X[j];
+        sy_[q] = X[P + j];
+        sfx[q] = w[j] * f[j];
+        sfy[q] = w[j] * f[P + j];
+        sl[q] = leafid[j];
+      }
+      __syncthreads();
+      int nf = 0;
+      for (int q = 0; q < cnt; ++q) {
+        const int lj = sl[q];
+        if (abs((lj >> depth) - ix) > 1 || abs((lj & mask) - iy) > 1) lst[nf++][lane] = (uint8_t)q;  // far
+      }
+      int most = nf;  // longest list of the wave
+      for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+      for (int k = 0; k < most; ++k) {
+        if (k < nf) {
+          const int q = lst[k][lane];
+          direct_term(zx, zy, sx_[q], sy_[q], sfx[q], sfy[q], ltab, ux, uy);
+        }
+      }
+    }
+    if (act) {
+      out[i] -= ux * scale;
+      out[P + i] -= uy * scale;
+    }
   }
 }
 
@@ -875,7 +1061,7 @@ TreeRun tree_run(void* ws, const TreeLayout& t, int depth, int p) {
 // Tree over the points (root square, leaves, leaf order) and the moments of every box of levels
 // 2..depth (leaves from the points, coarser levels by translation).
 void launch_upward(const double* X, const double* f, const double* w, const int32_t* off, int M, int P, int p,
-                   int depth, const TreeRun& r, hipStream_t st) {
+                   int depth, int cshift, const TreeRun& r, hipStream_t st) {
   const int nleaf = 1 << (2 * depth);
   const int pb = (P + kTB - 1) / kTB < 4096 ? (P + kTB - 1) / kTB : 4096;
   const int bb = (P + kTB - 1) / kTB < kBBoxBlocks ? (P + kTB - 1) / kTB : kBBoxBlocks;
@@ -885,7 +1071,7 @@ void launch_upward(const double* X, const double* f, const double* w, const int3
   hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, r.counts, nleaf);
   hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, r.cursor, nleaf);
   hipLaunchKernelGGL(k_tc_leaf, dim3(pb), dim3(kTB), 0, st, X, P, r.geom, depth, off, M, r.leafid, r.vid, r.counts);
-  hipLaunchKernelGGL(k_tc_scan, dim3(1), dim3(1024), 0, st, r.counts, nleaf, r.starts, r.wstart);
+  hipLaunchKernelGGL(k_tc_scan, dim3(1), dim3(1024), 0, st, r.counts, nleaf, r.starts, r.wstart, cshift);
   hipLaunchKernelGGL(k_tc_scatter, dim3(pb), dim3(kTB), 0, st, r.leafid, P, r.starts, r.cursor, r.perm);
   hipLaunchKernelGGL(k_tc_sort, dim3(nleaf), dim3(64), 0, st, r.starts, r.perm);
   if (depth < 2) return;
@@ -893,18 +1079,22 @@ void launch_upward(const double* X, const double* f, const double* w, const int3
                      r.mom + r.lv.mom[depth], r.bcount + r.lv.box[depth]);
   for (int l = depth - 1; l >= 2; --l) {
     const int n = 1 << l;
-    hipLaunchKernelGGL(k_tc_m2m, dim3(n * n), dim3(64), 0, st, r.geom, n, p, r.mom + r.lv.mom[l + 1],
+    hipLaunchKernelGGL(k_tc_m2m, dim3(n * n), dim3(256), 0, st, r.geom, n, p, r.mom + r.lv.mom[l + 1],
                        r.bcount + r.lv.box[l + 1], r.mom + r.lv.mom[l], r.bcount + r.lv.box[l]);
   }
 }
 
 template <bool kFmm>
-void launch_eval(const double* X, const double* f, const double* w, const int32_t* off, int P, int p, int depth,
+void launch_eval(const double* X, const double* f, const double* w, const int32_t* off, int M, int P, int p, int depth,
                  double scale, const TreeRun& r, double* out, hipStream_t st) {
   const int nleaf = 1 << (2 * depth);
-  const int items = nleaf + (P + 63) / 64;  // bound on sum over leaves of ceil(count / 64)
-  hipLaunchKernelGGL(k_tc_eval<kFmm>, dim3(items), dim3(64), 0, st, X, f, w, P, off, r.vid, r.leafid, r.perm,
-                     r.starts, r.wstart, r.geom, depth, p, r.mom, r.loc, r.bcount, scale, out);
+  constexpr int kChunk = 1 << eval_chunk_shift<kFmm>();
+  const int items = nleaf + (P + kChunk - 1) / kChunk;  // bound on sum over leaves of ceil(count / kChunk)
+  hipLaunchKernelGGL(k_tc_eval<kFmm>, dim3(items), dim3(64), 0, st, X, f, w, P, r.vid, r.perm, r.starts, r.wstart,
+                     r.geom, depth, p, r.mom, r.loc, r.bcount, scale, out);
+  // without expansions (depth < 2) every own-vesicle source is in the 3 x 3 leaves
+  if (depth >= 2)
+    hipLaunchKernelGGL(k_tc_own, dim3(M), dim3(64), 0, st, X, f, w, P, off, r.leafid, depth, scale, out);
 }
 
 }  // namespace
@@ -916,13 +1106,13 @@ hipError_t launch_treecode(const double* X, const double* f, const double* w, co
   if (depth < 0 || depth > kMaxDepth || p < 1 || p > kMaxOrder) return hipErrorInvalidValue;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const TreeRun r = tree_run(ws, tree_layout(P, depth, p, false), depth, p);
-  launch_upward(X, f, w, off, M, P, p, depth, r, st);
+  launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<false>(), r, st);
   if (depth >= 2) {
     const size_t work = r.nbox * (p + 1);
     const int gb = (int)((work + kTB - 1) / kTB < 4096 ? (work + kTB - 1) / kTB : 4096);
     hipLaunchKernelGGL(k_tc_finalize, dim3(gb), dim3(kTB), 0, st, r.mom, r.nbox, p);
   }
-  launch_eval<false>(X, f, w, off, P, p, depth, scale, r, out, st);
+  launch_eval<false>(X, f, w, off, M, P, p, depth, scale, r, out, st);
   return hipGetLastError();
 }
 
@@ -932,12 +1122,11 @@ hipError_t launch_fmm(const double* X, const double* f, const double* w, const i
   if (depth < 0 || depth > kMaxDepth || p < 1 || p > kMaxOrder) return hipErrorInvalidValue;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const TreeRun r = tree_run(ws, tree_layout(P, depth, p, true), depth, p);
-  launch_upward(X, f, w, off, M, P, p, depth, r, st);
+  launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<true>(), r, st);
   if (depth >= 2) {
     hipLaunchKernelGGL(k_fmm_binom, dim3(1), dim3(64), 0, st, p, r.tab);
-    const int gb = (int)((r.nbox + kM2LWaves - 1) / kM2LWaves);
-    hipLaunchKernelGGL(k_fmm_m2l, dim3(gb), dim3(64 * kM2LWaves), 0, st, r.geom, depth, p, r.mom, r.bcount, r.tab,
-                       r.nbox, r.loc);
+    hipLaunchKernelGGL(k_fmm_m2l, dim3((unsigned)r.nbox), dim3(64 * kM2LWaves), m2l_lds_bytes(p), st, r.geom, depth, p,
+                       r.mom, r.bcount, r.tab, r.loc);
     const size_t rows = 3 * (size_t)(p + 1);
     for (int l = 3; l <= depth; ++l) {
       const int n = 1 << l;
@@ -945,7 +1134,7 @@ hipError_t launch_fmm(const double* X, const double* f, const double* w, const i
                          r.loc + r.lv.box[l - 1] * rows, r.loc + r.lv.box[l] * rows);
     }
   }
-  launch_eval<true>(X, f, w, off, P, p, depth, scale, r, out, st);
+  launch_eval<true>(X, f, w, off, M, P, p, depth, scale, r, out, st);
   return hipGetLastError();
 }
 
