@@ -193,15 +193,16 @@ __global__ __launch_bounds__(64) void k_tc_bbox_final(const double* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kTB) void k_tc_zero(int32_t* __restrict__ a, int n) {
-  for (int i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) a[i] = 0;
+__global__ __launch_bounds__(kTB) void k_tc_zero(int32_t* __restrict__ a, int32_t* __restrict__ b, int n) {
+  for (int i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) {
+    a[i] = 0;
+    b[i] = 0;
+  }
 }
 
-// Leaf of every point, leaf occupancy, vesicle id of every point.
+// Leaf of every point and leaf occupancy.
 __global__ __launch_bounds__(kTB) void k_tc_leaf(const double* __restrict__ X, int P, const Geom* __restrict__ geom,
-                                                 int depth, const int32_t* __restrict__ off, int M,
-                                                 int32_t* __restrict__ leafid, int32_t* __restrict__ vid,
-                                                 int32_t* __restrict__ counts) {
+                                                 int depth, int32_t* __restrict__ leafid, int32_t* __restrict__ counts) {
   const Geom g = *geom;
   const int n = 1 << depth;
   for (int j = blockIdx.x * kTB + threadIdx.x; j < P; j += gridDim.x * kTB) {
@@ -215,14 +216,14 @@ __global__ __launch_bounds__(kTB) void k_tc_leaf(const double* __restrict__ X, i
     const int leaf = ix * n + iy;
     leafid[j] = leaf;
     atomicAdd(counts + leaf, 1);
-    // vesicle of j: the last v with off[v] <= j
-    int lo = 0, hi = M;  // off[lo] <= j < off[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (off[mid] <= j) lo = mid; else hi = mid;
-    }
-    vid[j] = lo;
   }
+}
+
+// Vesicle id of every point: one workgroup per vesicle writes its index over its range (offsets clamped).
+__global__ __launch_bounds__(kTB) void k_tc_vid(const int32_t* __restrict__ off, int P, int32_t* __restrict__ vid) {
+  const int v = blockIdx.x;
+  const int v0 = clamp_i(off[v], 0, P), v1 = max(v0, clamp_i(off[v + 1], 0, P));
+  for (int j = v0 + (int)threadIdx.x; j < v1; j += kTB) vid[j] = v;
 }
 
 // Exclusive scans of the leaf occupancies (starts) and of their chunks of 2^cshift targets (wave starts).
@@ -485,214 +486,304 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// T[m][l] = C(m + l - 1, l) for m = 0..p+1, l = 0..p (row 0: 1, 0, 0, ...), row stride p + 1, by Pascal's
-// rule T[m][l] = T[m-1][l] + T[m][l-1] along anti-diagonals: sums of integers, exact below 2^53.  The
-// same table holds C(m, l) = T[m - l + 1][l].  One wavefront, lane = l.
+// Binomial table T[m][l] = C(m + l - 1, l) for m = 1..p+1, l = 0..p, zero elsewhere, over rows m = 0..kTabM-1
+// and columns l = 0..63 (stride kTabL): the whole zero-padded range the matrix-core tiles read.  Row 0 holds
+// 1, 0, 0, ... while it is built (the start of the recurrence) and zeros once done.  Pascal's rule
+// T[m][l] = T[m-1][l] + T[m][l-1] runs along anti-diagonals: sums of integers, exact below 2^53.  The same
+// table holds C(m, l) = T[m - l + 1][l].  One wavefront, lane = l.
+constexpr int kTabL = 64;
+constexpr int kTabM = 4 * ((kMaxOrder + 1 + 3) / 4) + 1;  // m up to 4 ceil((p + 1) / 4)
+
 __global__ __launch_bounds__(64) void k_fmm_binom(int p, double* __restrict__ tab) {
   __shared__ double prev[64];
   const int l = threadIdx.x;
+  for (int m = 0; m < kTabM; ++m) tab[m * kTabL + l] = 0.0;
   double v = l == 0 ? 1.0 : 0.0;  // T[0][l]
-  if (l <= p) tab[l] = v;
   for (int s = 1; s <= 2 * p + 1; ++s) {
     prev[l] = v;  // this lane's latest entry, T[s - 1 - l][l]
     __syncthreads();
     const int m = s - l;
     if (l <= p && m >= 1 && m <= p + 1) {
       v += l > 0 ? prev[l - 1] : 0.0;  // + T[m][l - 1], written by lane l - 1 one step earlier
-      tab[m * (p + 1) + l] = v;
+      tab[m * kTabL + l] = v;
     }
     __syncthreads();
   }
 }
 
-constexpr int kM2LWaves = 4;  // waves per target box; source box k of the list goes to wave k mod 4
+typedef double double4v __attribute__((ext_vector_type(4)));
 
-// Dynamic LDS of k_fmm_m2l: the binomial table, then per wave three staging vectors (A, Phi and B
-// series) of max(G (p + 2), 64) complex numbers, G = floor(64 / (p + 1)).
-__host__ __device__ inline int m2l_groups(int p) { return 64 / (p + 1); }
-__host__ __device__ inline int m2l_stage(int p) {
-  const int g = m2l_groups(p) * (p + 2);
-  return g > 64 ? g : 64;
+// Dynamic LDS of k_fmm_m2l for order p, KS = ceil((p + 1) / 4) steps of four m and RT = ceil((p + 1) / 16)
+// tiles of 16 orders: the binomial tile T[m - 1][l] (4 KS x 16 RT, shared), the source list, and per wave
+// the scaled coefficients X[v][m - 1][s] of its batch (3 series x 4 KS x 8 sources, complex; also the
+// final exchange of 3 x 64 sums), the powers (-t_s)^l (8 sources x 4 KS, complex), and per source
+// lambda_A, lambda_B (complex) and ln|d|.
+constexpr int kM2LBatch = 8;  // source boxes per batch: 8 complex columns fill one 16-column tile
+constexpr int kM2LWaves = 1;  // at most this many waves per target box: wave w takes batches w, w + W, ...
+__host__ __device__ inline int m2l_ksteps(int p) { return (p + 1 + 3) / 4; }
+__host__ __device__ inline int m2l_rtiles(int p) { return (p + 1 + 15) / 16; }
+__host__ __device__ inline int m2l_tsize(int p) { return (4 * m2l_ksteps(p) * 16 * m2l_rtiles(p) + 1) / 2; }  // double2
+__host__ __device__ inline int m2l_wsize(int p) {  // per wave, in double2
+  const int mm = 4 * m2l_ksteps(p);
+  const int x = 3 * mm * kM2LBatch > 3 * 64 ? 3 * mm * kM2LBatch : 3 * 64;
+  return x + kM2LBatch * mm + 2 * kM2LBatch + kM2LBatch / 2;  // X, powers, lambdas, ln|d|
 }
-__host__ __device__ inline int m2l_table_doubles(int p) { return ((p + 2) * (p + 1) + 1) / 2 * 2; }  // 16-byte multiple
-inline size_t m2l_lds_bytes(int p) {
-  return sizeof(double) * (size_t)m2l_table_doubles(p) + sizeof(double2) * (size_t)kM2LWaves * 3 * m2l_stage(p);
+inline size_t m2l_lds_bytes(int p, int waves) {
+  return sizeof(double2) * ((size_t)m2l_tsize(p) + 36 + (size_t)waves * m2l_wsize(p));
+}
+// Waves per target box: as many as fit 64 KB of LDS, at most kM2LWaves.
+inline int m2l_waves(int p) {
+  int w = kM2LWaves;
+  while (w > 1 && m2l_lds_bytes(p, w) > 65536) --w;
+  return w;
 }
 
 // Interaction-list contributions to the local expansion of every non-empty box of levels 2..depth (one
-// launch for all levels, one workgroup per target box).  Lanes form G groups of p + 1; each group takes
-// one source box at a time: lane j of the group scales a_(j+1) by (-t)^(j+1) into LDS, then forms
-// sum_m C(m + j - 1, j) (-t)^m a_m for order l = j of the three series.  The partial expansions of all
-// groups and waves are added in a fixed order at the end.
+// launch for all levels, one workgroup per target box), on the matrix cores.  For a source box s at
+// d_s = c_s - c_T, t_s = 1/d_s, and each series v (A, Phi, and B with the conj(d) Phi term folded in,
+// conj(d_s) being a constant factor per source), the coefficient of zeta^l is
+//   t_s^l (sum_{m=1}^{p+1} C(m + l - 1, l) X_v[m][s] - lambda_v / l),   X_v[m][s] = a_v(m) (-t_s)^m,
+// (l = 0: sum_m X_v[m][s] + lambda_v ln|d_s|).  The sums over m are the product D = X^T T with
+// X^T: (16 columns: 8 sources x re, im) x m and T: m x l, in 16 x 16 x 4 FP64 steps: the columns of a tile
+// are one series of eight sources, source c's real part in row (c mod 4) + 8 (c / 4) and its imaginary part
+// four rows below, so that every lane (l = lane mod 16, q = lane / 16) receives both parts of sources q and
+// q + 4 for its order l and scales them itself.  Sources go eight at a time, in the fixed candidate order,
+// to the waves in turn; at the end the sums of the four waves and of the four lanes of every order are added
+// in (wave, q) order.  RT = ceil((p + 1) / 16).
+template <int RT>
 __global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restrict__ geom, int depth, int p,
                                                            const double2* __restrict__ mom,
                                                            const int32_t* __restrict__ bcount,
                                                            const double* __restrict__ tab, double2* __restrict__ loc) {
-  extern __shared__ double smem[];
+  extern __shared__ double2 sm[];
   const size_t box = blockIdx.x;
   if (bcount[box] == 0) return;  // the whole workgroup
-  const int np = p + 1;
-  const int G = m2l_groups(p), stage = m2l_stage(p);
-  double* T = smem;
-  double2* st = reinterpret_cast<double2*>(smem + m2l_table_doubles(p));
-  const int nt = (p + 2) * np;
-  for (int e = threadIdx.x; e < nt; e += 64 * kM2LWaves) T[e] = tab[e];
-  __syncthreads();
+  const int nw = blockDim.x >> 6;  // waves of this workgroup
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int g = lane / np, j = lane - g * np;  // group, order within the group; g >= G: idle lane
-  double2* sA = st + (size_t)wv * 3 * stage;
-  double2* sP = sA + stage;
-  double2* sQ = sP + stage;
-  int l = 2;
-  while (l < depth && box >= level_box_base(l + 1)) ++l;
-  const int n = 1 << l;
-  const size_t base = level_box_base(l);
+  const int np = p + 1;
+  const int KS = m2l_ksteps(p), MM = 4 * KS;
+  constexpr int TL = 16 * RT;                                    // orders per table row
+  double* Tt = reinterpret_cast<double*>(sm);                    // [MM][TL]
+  int32_t* lst = reinterpret_cast<int32_t*>(sm + m2l_tsize(p));  // [36][2]: source box coordinates
+  double2* X = sm + m2l_tsize(p) + 36 + (size_t)wv * m2l_wsize(p);  // this wave's [3][MM][8]
+  double2* pw = X + (m2l_wsize(p) - kM2LBatch * MM - 2 * kM2LBatch - kM2LBatch / 2);  // [8][MM]: (-t_s)^l
+  double2* lam = pw + kM2LBatch * MM;                            // [8][2]: lambda_A, lambda_B
+  double* lnd = reinterpret_cast<double*>(lam + 2 * kM2LBatch);  // [8]
+  for (int e = threadIdx.x; e < MM * TL; e += blockDim.x) Tt[e] = tab[(size_t)(e / TL + 1) * kTabL + e % TL];
+  int l2 = 2;
+  while (l2 < depth && box >= level_box_base(l2 + 1)) ++l2;
+  const int n = 1 << l2;
+  const size_t base = level_box_base(l2);
   const int b = (int)(box - base);
   const int bx = b / n, by = b - (b / n) * n;
   const double wl = geom->side / (double)n;
   const int stride = 4 * np;
-  const double inv_m = 1.0 / (double)(j + 1);          // 1/m, m = j + 1
-  const double inv_l = j > 0 ? 1.0 / (double)j : 0.0;  // 1/l, l = j
-  double2 accA = make_double2(0.0, 0.0), accB = accA, accC = accA;
-  int cand = 0, k = 0;  // next candidate of the 6 x 6 block; non-empty sources seen so far
-  for (;;) {
-    // this wave's next batch: up to G non-empty sources, group g takes the g-th
-    int nb = 0, msx = 0, msy = 0;
-    while (nb < G && cand < 36) {
-      const int sx = 2 * (bx >> 1) + cand / 6 - 2, sy = 2 * (by >> 1) + cand % 6 - 2;
-      ++cand;
-      if (sx < 0 || sx >= n || sy < 0 || sy >= n) continue;
-      if (abs(sx - bx) <= 1 && abs(sy - by) <= 1) continue;
-      if (bcount[base + (size_t)sx * n + sy] == 0) continue;
-      if ((k++ & (kM2LWaves - 1)) != wv) continue;
-      if (g == nb) {
-        msx = sx;
-        msy = sy;
-      }
-      ++nb;
+  // the interaction list's non-empty boxes in the fixed candidate order: lane c examines candidate c
+  int ns;
+  {
+    const int sx = 2 * (bx >> 1) + lane / 6 - 2, sy = 2 * (by >> 1) + lane % 6 - 2;
+    bool ok = lane < 36 && sx >= 0 && sx < n && sy >= 0 && sy < n && (abs(sx - bx) > 1 || abs(sy - by) > 1);
+    if (ok) ok = bcount[base + (size_t)sx * n + sy] != 0;
+    const unsigned long long mask = __ballot(ok);
+    ns = __popcll(mask);
+    if (wv == 0 && ok) {
+      const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+      lst[2 * rank] = sx;
+      lst[2 * rank + 1] = sy;
     }
-    if (nb == 0) break;
-    const bool on = g < nb;
-    const double2 d = make_double2((double)(msx - bx) * wl, (double)(msy - by) * wl);
-    const double dd = on ? d.x * d.x + d.y * d.y : 1.0;
-    const double rdd = recip(dd);
-    const double2 mt = make_double2(-d.x * rdd, d.y * rdd);  // -t = -1/d
-    const double2 pl = cpow_int(mt, j);                      // (-t)^l, l = j
-    const double2 pm = cmul(pl, mt);                         // (-t)^m, m = j + 1
-    const double2* ms = mom + (base + (size_t)msx * n + msy) * stride;
-    double2* qA = sA + g * (p + 2);
-    double2* qP = sP + g * (p + 2);
-    double2* qQ = sQ + g * (p + 2);
-    if (on) {
-      double2 aA = make_double2(0.0, 0.0), aQ = ms[2 * np + j];
-      if (j < p) {
-        const double2 Fm = ms[j + 1], Cm = ms[np + j + 1];
-        aA = make_double2(-Fm.x * inv_m, -Fm.y * inv_m);
-        aQ.x = fma(-Cm.x, inv_m, aQ.x);
-        aQ.y = fma(-Cm.y, inv_m, aQ.y);
+  }
+  __syncthreads();  // table and list ready; below, each wave synchronises its own lanes only
+  const int j = lane & 15, q = lane >> 4;  // result lanes: order j (+ 16 rt), sources q and q + 4
+  const int ai = lane & 15, ak = lane >> 4;  // operand lanes: column / order ai, step row ak
+  const int acol = (ai & 3) + 4 * (ai >> 3), apart = (ai >> 2) & 1;  // column ai: source acol, re or im
+  double2 acc[3][RT];
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) acc[v][rt] = make_double2(0.0, 0.0);
+  for (int b0 = wv * kM2LBatch; b0 < ns; b0 += nw * kM2LBatch) {
+    const int nb = min(kM2LBatch, ns - b0);
+    // scaling: lane takes source s = lane mod 8 and m = 1 + lane / 8, then every eighth m
+    {
+      const int s = lane & 7;
+      const bool valid = s < nb;
+      const int sx = valid ? lst[2 * (b0 + s)] : bx + 2, sy = valid ? lst[2 * (b0 + s) + 1] : by;
+      const double2 d = make_double2((double)(sx - bx) * wl, (double)(sy - by) * wl);
+      const double dd = d.x * d.x + d.y * d.y;
+      const double rdd = recip(dd);
+      const double2 mt = make_double2(-d.x * rdd, d.y * rdd);  // -t
+      const double2* ms = mom + (base + (size_t)(valid ? sx : 0) * n + (valid ? sy : 0)) * stride;
+      const int m0 = 1 + (lane >> 3);
+      // every moment load first, at indices clamped into the rows (values outside are discarded), so
+      // that they are all in flight together
+      double2 Fm1[2 * RT], Fm[2 * RT], Cm[2 * RT], Pm1[2 * RT];
+#pragma unroll
+      for (int it = 0; it < 2 * RT; ++it) {
+        const int mc = min(m0 + 8 * it, np), mp = min(mc, p);
+        Fm1[it] = ms[mc - 1];
+        Fm[it] = ms[mp];
+        Cm[it] = ms[np + mp];
+        Pm1[it] = ms[2 * np + mc - 1];
       }
-      qA[j + 1] = cmul(aA, pm);
-      qP[j + 1] = cmul(ms[j], pm);
-      qQ[j + 1] = cmul(aQ, pm);
+      double2 pl = cpow_int(mt, m0 - 1);  // (-t)^(m-1)
+      const double2 step = cpow_int(mt, 8);
+#pragma unroll
+      for (int it = 0; it < 2 * RT; ++it) {  // m = m0 + 8 it; MM <= 16 RT
+        const int m = m0 + 8 * it;
+        if (m <= MM) {
+          pw[s * MM + (m - 1)] = valid ? pl : make_double2(0.0, 0.0);
+          const bool use = valid && m <= np;
+          const double2 pm = cmul(pl, mt);  // (-t)^m
+          const double im = m <= p ? kRecip[m - 1] : 0.0;  // the A and conj-F series stop at order p
+          const double2 aA = make_double2(-Fm[it].x * im, -Fm[it].y * im);
+          const double2 aQ = make_double2(fma(-Cm[it].x, im, Pm1[it].x), fma(-Cm[it].y, im, Pm1[it].y));
+          const double2 sh = cmul(make_double2(d.x, -d.y), Fm1[it]);  // conj(d) Phi folded into B
+          const double2 zero = make_double2(0.0, 0.0);
+          X[(0 * MM + (m - 1)) * kM2LBatch + s] = use ? cmul(aA, pm) : zero;
+          X[(1 * MM + (m - 1)) * kM2LBatch + s] = use ? cmul(Fm1[it], pm) : zero;
+          X[(2 * MM + (m - 1)) * kM2LBatch + s] = use ? cmul(make_double2(aQ.x + sh.x, aQ.y + sh.y), pm) : zero;
+        }
+        pl = cmul(pl, step);
+      }
+      if (lane < kM2LBatch) {  // lane = s, m0 = 1: the first load of the loop above read M_0[F]
+        const double2 lq = ms[np];
+        lam[2 * s] = valid ? Fm1[0] : make_double2(0.0, 0.0);
+        lam[2 * s + 1] = valid ? lq : make_double2(0.0, 0.0);
+        lnd[s] = valid ? 0.5 * log_pos(dd) : 0.0;
+      }
     }
     wave_sync();
-    if (on) {
-      double2 xA = make_double2(0.0, 0.0), xP = xA, xQ = xA;
-#pragma unroll 2
-      for (int m = 1; m <= np; ++m) {
-        const double cb = T[m * np + j];
-        const double2 va = qA[m], vp = qP[m], vq = qQ[m];
-        xA.x = fma(cb, va.x, xA.x);
-        xA.y = fma(cb, va.y, xA.y);
-        xP.x = fma(cb, vp.x, xP.x);
-        xP.y = fma(cb, vp.y, xP.y);
-        xQ.x = fma(cb, vq.x, xQ.x);
-        xQ.y = fma(cb, vq.y, xQ.y);
-      }
-      const double2 lamA = ms[0], lamQ = ms[np];
-      double2 bA, bP, bQ;
-      if (j == 0) {
-        const double lnd = 0.5 * log_pos(dd);
-        bA = make_double2(fma(lamA.x, lnd, xA.x) - lamA.x, fma(lamA.y, lnd, xA.y) - lamA.y);  // - M_0[F]: constant
-        bP = xP;
-        bQ = make_double2(fma(lamQ.x, lnd, xQ.x), fma(lamQ.y, lnd, xQ.y));
-      } else {
-        const double2 tl = (j & 1) ? make_double2(-pl.x, -pl.y) : pl;  // t^l = (-1)^l (-t)^l
-        bA = cmul(tl, make_double2(fma(-lamA.x, inv_l, xA.x), fma(-lamA.y, inv_l, xA.y)));
-        bP = cmul(tl, xP);
-        bQ = cmul(tl, make_double2(fma(-lamQ.x, inv_l, xQ.x), fma(-lamQ.y, inv_l, xQ.y)));
-      }
-      accA.x += bA.x;
-      accA.y += bA.y;
-      accC.x += bP.x;
-      accC.y += bP.y;
-      const double2 sh = cmul(make_double2(d.x, -d.y), bP);  // + conj(d) Phi
-      accB.x += bQ.x + sh.x;
-      accB.y += bQ.y + sh.y;
+    // D[v][rt] = sum over m of the batch's columns times the binomials, three series and RT order tiles
+    // issued together at every step
+    const double* Xd = reinterpret_cast<const double*>(X);
+    double4v D[3][RT];
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) D[v][rt] = (double4v){0.0, 0.0, 0.0, 0.0};
+    for (int ks = 0; ks < KS; ++ks) {
+      const int mi = 4 * ks + ak;  // m - 1
+      double av[3], bv[RT];
+#pragma unroll
+      for (int v = 0; v < 3; ++v) av[v] = Xd[2 * ((v * MM + mi) * kM2LBatch + acol) + apart];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) bv[rt] = Tt[mi * TL + ai + 16 * rt];
+#pragma unroll
+      for (int v = 0; v < 3; ++v)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) D[v][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[v], bv[rt], D[v][rt], 0, 0, 0);
     }
+#pragma unroll
+    for (int v = 0; v < 3; ++v)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int l = j + 16 * rt;
+        if (l > p) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int s = q + 4 * h;
+          const double2 y = make_double2(D[v][rt][2 * h], D[v][rt][2 * h + 1]);
+          const double2 lv = v == 0 ? lam[2 * s] : (v == 2 ? lam[2 * s + 1] : make_double2(0.0, 0.0));
+          double2 bv2;
+          if (l == 0) {
+            bv2 = make_double2(fma(lv.x, lnd[s], y.x), fma(lv.y, lnd[s], y.y));
+            if (v == 0) {  // the source's constant M_0[F] / 2, as -M_0[F] in A_0
+              bv2.x -= lv.x;
+              bv2.y -= lv.y;
+            }
+          } else {
+            const double2 pwl = pw[s * MM + l];
+            const double2 tl = (l & 1) ? make_double2(-pwl.x, -pwl.y) : pwl;  // t^l = (-1)^l (-t)^l
+            const double il = kRecip[l - 1];
+            bv2 = cmul(tl, make_double2(fma(-lv.x, il, y.x), fma(-lv.y, il, y.y)));
+          }
+          acc[v][rt].x += bv2.x;
+          acc[v][rt].y += bv2.y;
+        }
+      }
     wave_sync();  // the staging is rewritten by the next batch
   }
-  // partial expansions of every group of every wave, added in a fixed order
-  __syncthreads();
-  sA[lane] = accA;
-  sP[lane] = accB;
-  sQ[lane] = accC;
-  __syncthreads();
-  if (threadIdx.x < np) {
-    const int t = threadIdx.x;
-    double2 rA = make_double2(0.0, 0.0), rB = rA, rC = rA;
-    for (int w = 0; w < kM2LWaves; ++w) {
-      const double2* r = st + (size_t)w * 3 * stage;
-      for (int q = 0; q < G; ++q) {
-        const double2 a = r[q * np + t], bb = r[stage + q * np + t], c = r[2 * stage + q * np + t];
-        rA.x += a.x;
-        rA.y += a.y;
-        rB.x += bb.x;
-        rB.y += bb.y;
-        rC.x += c.x;
-        rC.y += c.y;
+  // the sums of every wave and of the four lanes of every order, added in (wave, q) order; each wave's
+  // X carries its sums
+  double2* lb = loc + box * 3 * np;
+  double2* X0 = sm + m2l_tsize(p) + 36;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+    for (int v = 0; v < 3; ++v) X[v * 64 + lane] = acc[v][rt];
+    __syncthreads();
+    const int l = lane + 16 * rt;
+    if (wv == 0 && lane < 16 && l <= p) {
+      for (int v = 0; v < 3; ++v) {
+        double2 r = make_double2(0.0, 0.0);
+        for (int w = 0; w < nw; ++w)
+          for (int qq = 0; qq < 4; ++qq) {
+            const double2 x = X0[(size_t)w * m2l_wsize(p) + v * 64 + lane + 16 * qq];
+            r.x += x.x;
+            r.y += x.y;
+          }
+        lb[(v == 0 ? 0 : (v == 1 ? 2 : 1)) * np + l] = r;  // series A, Phi, B -> rows A, B, C
       }
     }
-    double2* lb = loc + box * 3 * np;
-    lb[t] = rA;
-    lb[np + t] = rB;
-    lb[2 * np + t] = rC;
+    __syncthreads();
   }
 }
 
-// Adds the parent's local expansion, re-centred, to every non-empty box of level l (n = 2^l per side).
-// One wavefront per box, lane = order, the parent's three rows staged in LDS.
-__global__ __launch_bounds__(64) void k_fmm_l2l(const Geom* __restrict__ geom, int n, int p,
-                                               const int32_t* __restrict__ bcount, const double* __restrict__ tab,
-                                               const double2* __restrict__ parent, double2* __restrict__ child) {
+// Completes the local expansion of every non-empty leaf: its own interaction-list part plus the part of
+// each ancestor (levels 2..depth-1), re-centred from the ancestor's centre straight to the leaf's (the
+// re-centring of a polynomial is exact, so one shift per ancestor equals the chain through the levels).
+// With e = c_leaf - c_anc: X_k += sum_{m>=k} C(m, k) e^(m-k) X_m for A, B, C, and B also -conj(e) times the
+// shifted C.  One wavefront per leaf, lane = order k, the ancestors' rows staged in LDS one at a time; the
+// binomials follow their recurrence (C(48, 24) < 2^53: rounding the product with the reciprocal to the
+// nearest integer gives each one exactly).
+__global__ __launch_bounds__(64) void k_fmm_l2l(const Geom* __restrict__ geom, int depth, int p,
+                                               const int32_t* __restrict__ bcount, double2* __restrict__ loc) {
   __shared__ double2 pl[3 * (kMaxOrder + 1)];
-  const int box = blockIdx.x;
-  if (bcount[box] == 0) return;
+  const int n = 1 << depth;
+  const int leaf = blockIdx.x;
+  const size_t lbox = level_box_base(depth) + (size_t)leaf;
+  if (bcount[lbox] == 0) return;
   const int k = threadIdx.x;
-  const int bx = box / n, by = box % n;
+  const int bx = leaf / n, by = leaf % n;
   const int rows = 3 * (p + 1);
-  const size_t pbox = (size_t)(bx >> 1) * (n >> 1) + (by >> 1);
-  for (int e = k; e < rows; e += 64) pl[e] = parent[pbox * rows + e];
-  __syncthreads();
-  if (k > p) return;
-  const double wl = geom->side / (double)n;
-  const double2 e = make_double2(((double)(bx & 1) - 0.5) * wl, ((double)(by & 1) - 0.5) * wl);
+  const double wL = geom->side / (double)n;
   double2 sA = make_double2(0.0, 0.0), sB = sA, sC = sA;
-  double2 ej = make_double2(1.0, 0.0);  // e^j
-  for (int j = 0; j <= p - k; ++j) {
-    const double cb = tab[(j + 1) * (p + 1) + k];  // C(k + j, k)
-    const double2 ce = make_double2(cb * ej.x, cb * ej.y);
-    sA = cfma(ce, pl[k + j], sA);
-    sB = cfma(ce, pl[(p + 1) + k + j], sB);
-    sC = cfma(ce, pl[2 * (p + 1) + k + j], sC);
-    ej = cmul(ej, e);
+  for (int l = 2; l < depth; ++l) {
+    const int sh = depth - l;
+    const int ax = bx >> sh, ay = by >> sh;
+    const size_t abox = level_box_base(l) + (size_t)ax * (1 << l) + ay;
+    __syncthreads();  // the previous ancestor is done
+    for (int e = k; e < rows; e += 64) pl[e] = loc[abox * rows + e];
+    __syncthreads();
+    if (k > p) continue;
+    // leaf centre - ancestor centre = ((b + 1/2) - (a + 1/2) 2^sh) wL per coordinate: exact before the product
+    const double2 e = make_double2(((double)bx + 0.5 - ((double)ax + 0.5) * (double)(1 << sh)) * wL,
+                                   ((double)by + 0.5 - ((double)ay + 0.5) * (double)(1 << sh)) * wL);
+    double2 tA = make_double2(0.0, 0.0), tB = tA, tC = tA;
+    double2 ej = make_double2(1.0, 0.0);  // e^j
+    double cb = 1.0;                      // C(k + j, k): integers below 2^53, each step exact after rounding
+    for (int j = 0; j <= p - k; ++j) {
+      const double2 ce = make_double2(cb * ej.x, cb * ej.y);
+      tA = cfma(ce, pl[k + j], tA);
+      tB = cfma(ce, pl[(p + 1) + k + j], tB);
+      tC = cfma(ce, pl[2 * (p + 1) + k + j], tC);
+      ej = cmul(ej, e);
+      cb = rint(cb * (double)(k + j + 1) * kRecip[j]);  // C(k + j + 1, k) = C(k + j, k) (k + j + 1) / (j + 1)
+    }
+    const double2 shc = cmul(make_double2(e.x, -e.y), tC);
+    sA.x += tA.x;
+    sA.y += tA.y;
+    sB.x += tB.x - shc.x;
+    sB.y += tB.y - shc.y;
+    sC.x += tC.x;
+    sC.y += tC.y;
   }
-  const double2 sh = cmul(make_double2(e.x, -e.y), sC);
-  double2* cb_ = child + (size_t)box * rows;
+  if (k > p) return;
+  double2* cb_ = loc + lbox * rows;
   double2 v = cb_[k];
   cb_[k] = make_double2(v.x + sA.x, v.y + sA.y);
   v = cb_[(p + 1) + k];
-  cb_[(p + 1) + k] = make_double2(v.x + sB.x - sh.x, v.y + sB.y - sh.y);
+  cb_[(p + 1) + k] = make_double2(v.x + sB.x, v.y + sB.y);
   v = cb_[2 * (p + 1) + k];
   cb_[2 * (p + 1) + k] = make_double2(v.x + sC.x, v.y + sC.y);
 }
@@ -917,28 +1008,30 @@ __global__ __launch_bounds__(64) void k_tc_eval(const double* __restrict__ X, co
 }
 
 // Own-vesicle sources outside the 3 x 3 leaves around a target were in the expansions: their direct terms
-// are subtracted from the finished velocity.  One wavefront per vesicle, targets 64 at a time, the
-// vesicle's points (coordinates, weighted force, leaf) staged in LDS in chunks.  Few sources of a chunk
-// are far from a given target, and different ones for different lanes: each lane first lists its far
-// sources, then the wave evaluates the lists side by side (as many steps as the longest list).
+// are subtracted from the finished velocity.  One workgroup of two wavefronts per vesicle, targets 128 at a
+// time, the vesicle's points (coordinates, weighted force, leaf) staged in LDS in chunks.  Few sources of a
+// chunk are far from a given target, and different ones for different lanes: each lane first lists its far
+// sources, then each wavefront evaluates its lanes' lists side by side (as many steps as its longest list).
 constexpr int kOwnChunk = 128;
+constexpr int kOwnThreads = 128;
 
-__global__ __launch_bounds__(64) void k_tc_own(const double* __restrict__ X, const double* __restrict__ f,
-                                               const double* __restrict__ w, int P, const int32_t* __restrict__ off,
-                                               const int32_t* __restrict__ leafid, int depth, double scale,
-                                               double* __restrict__ out) {
+__global__ __launch_bounds__(kOwnThreads) void k_tc_own(const double* __restrict__ X, const double* __restrict__ f,
+                                                        const double* __restrict__ w, int P,
+                                                        const int32_t* __restrict__ off,
+                                                        const int32_t* __restrict__ leafid, int depth, double scale,
+                                                        double* __restrict__ out) {
   __shared__ double sx_[kOwnChunk], sy_[kOwnChunk], sfx[kOwnChunk], sfy[kOwnChunk];
   __shared__ int32_t sl[kOwnChunk];
-  __shared__ uint8_t lst[kOwnChunk][64];  // lst[k][lane]: the k-th far source of the lane's target
+  __shared__ uint8_t lst[kOwnChunk][kOwnThreads];  // lst[k][thread]: the k-th far source of its target
   __shared__ double2 ltab[kLogTab];
   const int v = blockIdx.x;
   const int v0 = clamp_i(off[v], 0, P), v1 = max(v0, clamp_i(off[v + 1], 0, P));  // offsets never trusted
   if (v1 - v0 < 2) return;
-  const int lane = threadIdx.x;
-  ltab[lane] = log_tab_entry(lane);  // read after the first barrier below
+  const int t = threadIdx.x;
+  if (t < kLogTab) ltab[t] = log_tab_entry(t);  // read after the first barrier below
   const int mask = (1 << depth) - 1;
-  for (int t0 = v0; t0 < v1; t0 += 64) {
-    const int i = t0 + lane;
+  for (int t0 = v0; t0 < v1; t0 += kOwnThreads) {
+    const int i = t0 + t;
     const bool act = i < v1;
     const int ii = act ? i : v0;
     const double zx = X[ii], zy = X[P + ii];
@@ -948,7 +1041,7 @@ __global__ __launch_bounds__(64) void k_tc_own(const double* __restrict__ X, con
     for (int c0 = v0; c0 < v1; c0 += kOwnChunk) {
       const int cnt = min(kOwnChunk, v1 - c0);
       __syncthreads();  // the previous chunk is done
-      for (int q = lane; q < cnt; q += 64) {
+      for (int q = t; q < cnt; q += kOwnThreads) {
         const int j = c0 + q;
         sx_[q] = X[j];
         sy_[q] = X[P + j];
@@ -958,15 +1051,16 @@ __global__ __launch_bounds__(64) void k_tc_own(const double* __restrict__ X, con
       }
       __syncthreads();
       int nf = 0;
+#pragma unroll 8
       for (int q = 0; q < cnt; ++q) {
         const int lj = sl[q];
-        if (abs((lj >> depth) - ix) > 1 || abs((lj & mask) - iy) > 1) lst[nf++][lane] = (uint8_t)q;  // far
+        if (abs((lj >> depth) - ix) > 1 || abs((lj & mask) - iy) > 1) lst[nf++][t] = (uint8_t)q;  // far
       }
-      int most = nf;  // longest list of the wave
+      int most = nf;  // longest list of the wavefront
       for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
       for (int k = 0; k < most; ++k) {
         if (k < nf) {
-          const int q = lst[k][lane];
+          const int q = lst[k][t];
           direct_term(zx, zy, sx_[q], sy_[q], sfx[q], sfy[q], ltab, ux, uy);
         }
       }
@@ -1010,7 +1104,7 @@ static TreeLayout tree_layout(int P, int depth, int p, bool fmm) {
   t.tab = o;
   if (fmm) {
     t.loc = o;      o += align_up(sizeof(double2) * (boxes * 3 * (size_t)(p + 1) + 192));  // 192 spare: as above
-    t.tab = o;      o += align_up(sizeof(double) * (size_t)(p + 2) * (p + 1));
+    t.tab = o;      o += align_up(sizeof(double) * (size_t)kTabM * kTabL);
   }
   t.total = o;
   return t;
@@ -1068,9 +1162,9 @@ void launch_upward(const double* X, const double* f, const double* w, const int3
   hipLaunchKernelGGL(k_tc_bbox_partial, dim3(bb), dim3(kTB), 0, st, X, P, r.part);
   hipLaunchKernelGGL(k_tc_bbox_final, dim3(1), dim3(64), 0, st, r.part, bb, r.geom);
   const int zb = (nleaf + kTB - 1) / kTB < 4096 ? (nleaf + kTB - 1) / kTB : 4096;
-  hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, r.counts, nleaf);
-  hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, r.cursor, nleaf);
-  hipLaunchKernelGGL(k_tc_leaf, dim3(pb), dim3(kTB), 0, st, X, P, r.geom, depth, off, M, r.leafid, r.vid, r.counts);
+  hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, r.counts, r.cursor, nleaf);
+  hipLaunchKernelGGL(k_tc_leaf, dim3(pb), dim3(kTB), 0, st, X, P, r.geom, depth, r.leafid, r.counts);
+  hipLaunchKernelGGL(k_tc_vid, dim3(M), dim3(kTB), 0, st, off, P, r.vid);
   hipLaunchKernelGGL(k_tc_scan, dim3(1), dim3(1024), 0, st, r.counts, nleaf, r.starts, r.wstart, cshift);
   hipLaunchKernelGGL(k_tc_scatter, dim3(pb), dim3(kTB), 0, st, r.leafid, P, r.starts, r.cursor, r.perm);
   hipLaunchKernelGGL(k_tc_sort, dim3(nleaf), dim3(64), 0, st, r.starts, r.perm);
@@ -1094,7 +1188,7 @@ void launch_eval(const double* X, const double* f, const double* w, const int32_
                      r.geom, depth, p, r.mom, r.loc, r.bcount, scale, out);
   // without expansions (depth < 2) every own-vesicle source is in the 3 x 3 leaves
   if (depth >= 2)
-    hipLaunchKernelGGL(k_tc_own, dim3(M), dim3(64), 0, st, X, f, w, P, off, r.leafid, depth, scale, out);
+    hipLaunchKernelGGL(k_tc_own, dim3(M), dim3(kOwnThreads), 0, st, X, f, w, P, off, r.leafid, depth, scale, out);
 }
 
 }  // namespace
@@ -1125,13 +1219,18 @@ hipError_t launch_fmm(const double* X, const double* f, const double* w, const i
   launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<true>(), r, st);
   if (depth >= 2) {
     hipLaunchKernelGGL(k_fmm_binom, dim3(1), dim3(64), 0, st, p, r.tab);
-    hipLaunchKernelGGL(k_fmm_m2l, dim3((unsigned)r.nbox), dim3(64 * kM2LWaves), m2l_lds_bytes(p), st, r.geom, depth, p,
-                       r.mom, r.bcount, r.tab, r.loc);
-    const size_t rows = 3 * (size_t)(p + 1);
-    for (int l = 3; l <= depth; ++l) {
-      const int n = 1 << l;
-      hipLaunchKernelGGL(k_fmm_l2l, dim3(n * n), dim3(64), 0, st, r.geom, n, p, r.bcount + r.lv.box[l], r.tab,
-                         r.loc + r.lv.box[l - 1] * rows, r.loc + r.lv.box[l] * rows);
+    const int nw = m2l_waves(p);
+    const dim3 g((unsigned)r.nbox), bl(64 * nw);
+    const size_t lds = m2l_lds_bytes(p, nw);
+    switch (m2l_rtiles(p)) {
+      case 1: hipLaunchKernelGGL(k_fmm_m2l<1>, g, bl, lds, st, r.geom, depth, p, r.mom, r.bcount, r.tab, r.loc); break;
+      case 2: hipLaunchKernelGGL(k_fmm_m2l<2>, g, bl, lds, st, r.geom, depth, p, r.mom, r.bcount, r.tab, r.loc); break;
+      case 3: hipLaunchKernelGGL(k_fmm_m2l<3>, g, bl, lds, st, r.geom, depth, p, r.mom, r.bcount, r.tab, r.loc); break;
+      default: hipLaunchKernelGGL(k_fmm_m2l<4>, g, bl, lds, st, r.geom, depth, p, r.mom, r.bcount, r.tab, r.loc); break;
+    }
+    if (depth >= 3) {
+      const int nleaf = 1 << (2 * depth);
+      hipLaunchKernelGGL(k_fmm_l2l, dim3(nleaf), dim3(64), 0, st, r.geom, depth, p, r.bcount, r.loc);
     }
   }
   launch_eval<true>(X, f, w, off, M, P, p, depth, scale, r, out, st);
