@@ -1,6 +1,7 @@
-// Treecode far field on gfx950: the far-field sum of eq. (single_layer) at O(P log P) cost.  The
-// paper evaluates the sum directly and leaves fast summation out of scope (Section 4.1); this is
-// a fast, approximate alternative with its own accuracy contract (order p of the expansions).
+// Tree far fields on gfx950: the far-field sum of eq. (single_layer) at O(P log P) (treecode) and O(P)
+// (fast multipole method) cost.  The paper evaluates the sum directly, names the fast multipole method as
+// the route to O(M) cost and leaves fast summation out of scope (Section 4.1); both methods here are fast,
+// approximate alternatives with their own accuracy contract (order p of the expansions).
 //
 // With complex numbers z = x + i y, F_j = w_j (f_x + i f_y)_j, u = u_x + i u_y, each Stokeslet term is
 //   -F_j ln|z - z_j| + F_j / 2 + (z - z_j) conj(F_j / (z - z_j)) / 2,
@@ -9,15 +10,20 @@
 //   -M_0[F] ln|w| + 1/2 sum_{k=1}^p (M_k[F] t^k + conj(M_k[conj F] t^k)) / k + M_0[F] / 2
 //   + (w conj(Phi) - conj(Psi)) / 2,   Phi = sum_{k=0}^p M_k[F] t^(k+1),  Psi = sum_k M_k[conj(zeta) F] t^(k+1).
 //
-// The evaluation merges the conj-F log series and Psi into one series D, and writes w conj(Phi) as
-// (w / conj w) conj(E), E = sum_k M_k[F] t^k: three Horner chains per box.
+// Tree: a uniform quadtree of depth L over the bounding square of the points.  Leaf moments come from
+// the points (k_tc_p2m), coarser ones by exact binomial translation (k_tc_m2m).  A target takes, at each
+// level l = 2..L, the interaction list of its level-l ancestor (children of the parent's 3 x 3
+// neighbourhood not adjacent to the ancestor) through the expansions, and the 3 x 3 leaves around its own
+// directly, skipping its own vesicle; own-vesicle sources outside those leaves, which the expansions
+// included, are subtracted exactly (k_tc_own).  Everything is FP64.
 //
-// Tree: a uniform quadtree of depth L over the bounding square of the points.  Leaf moments come
-// from the points (k_tc_p2m), coarser ones by exact binomial translation (k_tc_m2m).  A target takes,
-// at each level l = 2..L, the interaction list of its level-l ancestor (children of the parent's
-// 3 x 3 neighbourhood not adjacent to the ancestor) through the expansions, and the 3 x 3 leaves
-// around its own directly, skipping its own vesicle; own-vesicle sources outside those leaves,
-// which the expansions included, are subtracted exactly.  Everything is FP64.
+// Treecode: every target evaluates the series of every box of its lists (k_tc_eval<false>); the
+// evaluation merges the conj-F log series and Psi into one series D, and writes w conj(Phi) as
+// (w / conj w) conj(E), E = sum_k M_k[F] t^k: three Horner chains per box.
+// Fast multipole method: each box's series becomes a Taylor polynomial of degree p about the centre of
+// every box whose list holds it (k_fmm_m2l, on the matrix cores), the polynomials of a leaf's ancestors
+// are re-centred onto the leaf (k_fmm_l2l), and every target evaluates its leaf's polynomial
+// (k_tc_eval<true>).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
