@@ -323,8 +323,9 @@ __global__ __launch_bounds__(64) void k_tc_p2m(const double* __restrict__ X, con
                                                const int32_t* __restrict__ starts, const Geom* __restrict__ geom,
                                                int depth, int p, double2* __restrict__ mom,
                                                int32_t* __restrict__ bcount) {
-  __shared__ double2 pw[kP2MChunk][kMaxOrder + 1];
-  __shared__ double2 Fs[kP2MChunk], Zc[kP2MChunk];
+  extern __shared__ double2 p2m_lds[];  // powers [kP2MChunk][p + 1], then F and conj(zeta) of the chunk
+  double2* Fs = p2m_lds + kP2MChunk * (p + 1);
+  double2* Zc = Fs + kP2MChunk;
   const int leaf = blockIdx.x;
   const int k = threadIdx.x;
   const int n = 1 << depth;
@@ -342,14 +343,14 @@ __global__ __launch_bounds__(64) void k_tc_p2m(const double* __restrict__ X, con
       Zc[k] = make_double2(zeta.x, -zeta.y);
       double2 z = make_double2(1.0, 0.0);
       for (int m = 0; m <= p; ++m) {
-        pw[k][m] = z;
+        p2m_lds[k * (p + 1) + m] = z;
         z = cmul(z, zeta);
       }
     }
     __syncthreads();
     if (k <= p) {
       for (int q = 0; q < cnt; ++q) {
-        const double2 F = Fs[q], zk = pw[q][k];
+        const double2 F = Fs[q], zk = p2m_lds[q * (p + 1) + k];
         const double2 Fz = cmul(F, zk);
         m0.x += Fz.x;
         m0.y += Fz.y;
@@ -739,12 +740,12 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restri
 // each ancestor (levels 2..depth-1), re-centred from the ancestor's centre straight to the leaf's (the
 // re-centring of a polynomial is exact, so one shift per ancestor equals the chain through the levels).
 // With e = c_leaf - c_anc: X_k += sum_{m>=k} C(m, k) e^(m-k) X_m for A, B, C, and B also -conj(e) times the
-// shifted C.  One wavefront per leaf, lane = order k, the ancestors' rows staged in LDS one at a time; the
+// shifted C.  One wavefront per leaf, lane = order k, all ancestors' rows staged in LDS together; the
 // binomials follow their recurrence (C(48, 24) < 2^53: rounding the product with the reciprocal to the
 // nearest integer gives each one exactly).
 __global__ __launch_bounds__(64) void k_fmm_l2l(const Geom* __restrict__ geom, int depth, int p,
                                                const int32_t* __restrict__ bcount, double2* __restrict__ loc) {
-  __shared__ double2 pl[3 * (kMaxOrder + 1)];
+  extern __shared__ double2 anc[];  // [depth - 2][3 (p + 1)]
   const int n = 1 << depth;
   const int leaf = blockIdx.x;
   const size_t lbox = level_box_base(depth) + (size_t)leaf;
@@ -753,15 +754,18 @@ __global__ __launch_bounds__(64) void k_fmm_l2l(const Geom* __restrict__ geom, i
   const int bx = leaf / n, by = leaf % n;
   const int rows = 3 * (p + 1);
   const double wL = geom->side / (double)n;
+  for (int e = k; e < (depth - 2) * rows; e += 64) {
+    const int l = 2 + e / rows, sh = depth - l;
+    const size_t abox = level_box_base(l) + (size_t)(bx >> sh) * (1 << l) + (by >> sh);
+    anc[e] = loc[abox * rows + e % rows];
+  }
+  __syncthreads();
+  if (k > p) return;
   double2 sA = make_double2(0.0, 0.0), sB = sA, sC = sA;
   for (int l = 2; l < depth; ++l) {
     const int sh = depth - l;
     const int ax = bx >> sh, ay = by >> sh;
-    const size_t abox = level_box_base(l) + (size_t)ax * (1 << l) + ay;
-    __syncthreads();  // the previous ancestor is done
-    for (int e = k; e < rows; e += 64) pl[e] = loc[abox * rows + e];
-    __syncthreads();
-    if (k > p) continue;
+    const double2* pl = anc + (l - 2) * rows;
     // leaf centre - ancestor centre = ((b + 1/2) - (a + 1/2) 2^sh) wL per coordinate: exact before the product
     const double2 e = make_double2(((double)bx + 0.5 - ((double)ax + 0.5) * (double)(1 << sh)) * wL,
                                    ((double)by + 0.5 - ((double)ay + 0.5) * (double)(1 << sh)) * wL);
@@ -784,7 +788,6 @@ __global__ __launch_bounds__(64) void k_fmm_l2l(const Geom* __restrict__ geom, i
     sC.x += tC.x;
     sC.y += tC.y;
   }
-  if (k > p) return;
   double2* cb_ = loc + lbox * rows;
   double2 v = cb_[k];
   cb_[k] = make_double2(v.x + sA.x, v.y + sA.y);
@@ -1175,7 +1178,8 @@ void launch_upward(const double* X, const double* f, const double* w, const int3
   hipLaunchKernelGGL(k_tc_scatter, dim3(pb), dim3(kTB), 0, st, r.leafid, P, r.starts, r.cursor, r.perm);
   hipLaunchKernelGGL(k_tc_sort, dim3(nleaf), dim3(64), 0, st, r.starts, r.perm);
   if (depth < 2) return;
-  hipLaunchKernelGGL(k_tc_p2m, dim3(nleaf), dim3(64), 0, st, X, f, w, P, r.perm, r.starts, r.geom, depth, p,
+  hipLaunchKernelGGL(k_tc_p2m, dim3(nleaf), dim3(64), sizeof(double2) * (size_t)kP2MChunk * (p + 3), st, X, f, w, P,
+                     r.perm, r.starts, r.geom, depth, p,
                      r.mom + r.lv.mom[depth], r.bcount + r.lv.box[depth]);
   for (int l = depth - 1; l >= 2; --l) {
     const int n = 1 << l;
@@ -1236,7 +1240,8 @@ hipError_t launch_fmm(const double* X, const double* f, const double* w, const i
     }
     if (depth >= 3) {
       const int nleaf = 1 << (2 * depth);
-      hipLaunchKernelGGL(k_fmm_l2l, dim3(nleaf), dim3(64), 0, st, r.geom, depth, p, r.bcount, r.loc);
+      hipLaunchKernelGGL(k_fmm_l2l, dim3(nleaf), dim3(64), sizeof(double2) * (size_t)(depth - 2) * 3 * (p + 1), st,
+                         r.geom, depth, p, r.bcount, r.loc);
     }
   }
   launch_eval<true>(X, f, w, off, M, P, p, depth, scale, r, out, st);
