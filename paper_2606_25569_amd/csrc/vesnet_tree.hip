@@ -604,10 +604,14 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restri
   const int ai = lane & 15, ak = lane >> 4;  // operand lanes: column / order ai, step row ak
   const int acol = (ai & 3) + 4 * (ai >> 3), apart = (ai >> 2) & 1;  // column ai: source acol, re or im
   double2 acc[3][RT];
+  double inv_l[RT];  // 1/l for the lane's orders l = j + 16 rt (0 for l = 0 or beyond p)
 #pragma unroll
-  for (int v = 0; v < 3; ++v)
+  for (int rt = 0; rt < RT; ++rt) {
+    const int l = j + 16 * rt;
+    inv_l[rt] = (l >= 1 && l <= p) ? kRecip[l - 1] : 0.0;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) acc[v][rt] = make_double2(0.0, 0.0);
+    for (int v = 0; v < 3; ++v) acc[v][rt] = make_double2(0.0, 0.0);
+  }
   for (int b0 = wv * kM2LBatch; b0 < ns; b0 += nw * kM2LBatch) {
     const int nb = min(kM2LBatch, ns - b0);
     // scaling: lane takes source s = lane mod 8 and m = 1 + lane / 8, then every eighth m
@@ -632,8 +636,11 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restri
         Cm[it] = ms[np + mp];
         Pm1[it] = ms[2 * np + mc - 1];
       }
-      double2 pl = cpow_int(mt, m0 - 1);  // (-t)^(m-1)
-      const double2 step = cpow_int(mt, 8);
+      const double2 t2 = cmul(mt, mt), t4 = cmul(t2, t2), step = cmul(t4, t4);  // (-t)^2, ^4, ^8
+      const int e0 = m0 - 1;                                                     // 0..7
+      double2 pl = (e0 & 1) ? mt : make_double2(1.0, 0.0);                      // (-t)^(m-1)
+      if (e0 & 2) pl = cmul(pl, t2);
+      if (e0 & 4) pl = cmul(pl, t4);
 #pragma unroll
       for (int it = 0; it < 2 * RT; ++it) {  // m = m0 + 8 it; MM <= 16 RT
         const int m = m0 + 8 * it;
@@ -680,34 +687,38 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restri
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) D[v][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[v], bv[rt], D[v][rt], 0, 0, 0);
     }
+    // scale: every lane owns orders l = j + 16 rt and sources q, q + 4; t^l, 1/l, the lambdas and ln|d|
+    // are shared by the three series
 #pragma unroll
-    for (int v = 0; v < 3; ++v)
+    for (int h = 0; h < 2; ++h) {
+      const int s = q + 4 * h;
+      const double2 lamA = lam[2 * s], lamB = lam[2 * s + 1];
+      const double ld = lnd[s];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         const int l = j + 16 * rt;
         if (l > p) continue;
+        const double2 pwl = pw[s * MM + l];
+        const double sg = (l & 1) ? -1.0 : 1.0;  // t^l = (-1)^l (-t)^l
+        const double2 tl = l == 0 ? make_double2(1.0, 0.0) : make_double2(sg * pwl.x, sg * pwl.y);
+        const double il = inv_l[rt];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int s = q + 4 * h;
+        for (int v = 0; v < 3; ++v) {
           const double2 y = make_double2(D[v][rt][2 * h], D[v][rt][2 * h + 1]);
-          const double2 lv = v == 0 ? lam[2 * s] : (v == 2 ? lam[2 * s + 1] : make_double2(0.0, 0.0));
-          double2 bv2;
-          if (l == 0) {
-            bv2 = make_double2(fma(lv.x, lnd[s], y.x), fma(lv.y, lnd[s], y.y));
-            if (v == 0) {  // the source's constant M_0[F] / 2, as -M_0[F] in A_0
-              bv2.x -= lv.x;
-              bv2.y -= lv.y;
-            }
-          } else {
-            const double2 pwl = pw[s * MM + l];
-            const double2 tl = (l & 1) ? make_double2(-pwl.x, -pwl.y) : pwl;  // t^l = (-1)^l (-t)^l
-            const double il = kRecip[l - 1];
-            bv2 = cmul(tl, make_double2(fma(-lv.x, il, y.x), fma(-lv.y, il, y.y)));
+          const double2 lv = v == 0 ? lamA : (v == 2 ? lamB : make_double2(0.0, 0.0));
+          // l = 0: y + lambda ln|d| (and, for A, the source's constant M_0[F] / 2 as -M_0[F]);
+          // l >= 1: t^l (y - lambda / l)
+          const double2 c0 = make_double2(fma(lv.x, l == 0 ? ld : -il, y.x), fma(lv.y, l == 0 ? ld : -il, y.y));
+          double2 bv2 = cmul(tl, c0);
+          if (v == 0 && l == 0) {
+            bv2.x -= lv.x;
+            bv2.y -= lv.y;
           }
           acc[v][rt].x += bv2.x;
           acc[v][rt].y += bv2.y;
         }
       }
+    }
     wave_sync();  // the staging is rewritten by the next batch
   }
   // the sums of every wave and of the four lanes of every order, added in (wave, q) order; each wave's
