@@ -115,8 +115,9 @@ __device__ __forceinline__ double log_reduced(double q, const double2* __restric
   constexpr double kLn2Hi = 6.93147180369123816490e-01;
   constexpr double kLn2Lo = 1.90821492927058770002e-10;
   int e;
-  const double m = 2.0 * frexp(q, &e);
-  const int i = clamp_i((int)fma(m, 64.0, -64.0), 0, kLogTab - 1);
+  const double mant = frexp(q, &e);  // [0.5, 1): the top six mantissa bits are bits 19..14 of the high word
+  const double m = 2.0 * mant;
+  const int i = (__double2hiint(mant) >> 14) & (kLogTab - 1);  // in range for every input
   const double2 t = tab[i];
   const double r = fma(m, t.x, -1.0);
   double pol = 1.0 / 7.0;
@@ -141,6 +142,32 @@ __device__ __forceinline__ double2 box_center(const Geom& g, int n, int bx, int 
 __device__ __forceinline__ size_t level_box_base(int l) { return (((size_t)1 << (2 * l)) - 16) / 3; }
 
 // ---------------------------------------------------------------- tree construction
+
+// Binomial table T[m][l] = C(m + l - 1, l) for m = 1..p+1, l = 0..p, zero elsewhere, over rows m = 0..kTabM-1
+// and columns l = 0..63 (stride kTabL): the whole zero-padded range the matrix-core tiles read.  Row 0 holds
+// 1, 0, 0, ... while it is built (the start of the recurrence) and zeros once done.  Pascal's rule
+// T[m][l] = T[m-1][l] + T[m][l-1] runs along anti-diagonals: sums of integers, exact below 2^53.  The same
+// table holds C(m, l) = T[m - l + 1][l].  Run by the one wavefront (lane = l) of the bounding-box kernel.
+constexpr int kTabL = 64;
+constexpr int kTabM = 4 * ((kMaxOrder + 1 + 3) / 4) + 1;  // m up to 4 ceil((p + 1) / 4)
+
+__device__ void build_binomials(int p, double* __restrict__ tab) {
+  __shared__ double prev[64];
+  const int l = threadIdx.x;
+  for (int m = 0; m < kTabM; ++m) tab[m * kTabL + l] = 0.0;
+  double v = l == 0 ? 1.0 : 0.0;  // T[0][l]
+  for (int s = 1; s <= 2 * p + 1; ++s) {
+    prev[l] = v;  // this lane's latest entry, T[s - 1 - l][l]
+    __syncthreads();
+    const int m = s - l;
+    if (l <= p && m >= 1 && m <= p + 1) {
+      v += l > 0 ? prev[l - 1] : 0.0;  // + T[m][l - 1], written by lane l - 1 one step earlier
+      tab[m * kTabL + l] = v;
+    }
+    __syncthreads();
+  }
+}
+
 
 __global__ __launch_bounds__(kTB) void k_tc_bbox_partial(const double* __restrict__ X, int P,
                                                          double* __restrict__ part) {
@@ -170,8 +197,10 @@ __global__ __launch_bounds__(kTB) void k_tc_bbox_partial(const double* __restric
   if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Also builds the binomial table of the fast multipole method when tab is not null.
 __global__ __launch_bounds__(64) void k_tc_bbox_final(const double* __restrict__ part, int nparts,
-                                                      Geom* __restrict__ geom) {
+                                                      Geom* __restrict__ geom, int p, double* __restrict__ tab) {
+  if (tab != nullptr) build_binomials(p, tab);
   double xl = INFINITY, xh = -INFINITY, yl = INFINITY, yh = -INFINITY;
   for (int b = threadIdx.x; b < nparts; b += 64) {
     xl = fmin(xl, part[4 * b]);
@@ -206,22 +235,47 @@ __global__ __launch_bounds__(kTB) void k_tc_zero(int32_t* __restrict__ a, int32_
   }
 }
 
+// Within a wavefront, the lanes whose key equals the first pending lane's form a group: one atomic adds the
+// group's size to counter[key] and returns the group's base, and each lane takes base + its rank among the
+// group's lanes.  Consecutive points mostly share a leaf, so a wavefront needs a few atomics instead of 64.
+__device__ __forceinline__ int wave_group_add(bool ok, int key, int32_t* __restrict__ counter) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(ok);
+  int pos = 0;
+  while (todo) {
+    const int leader = __ffsll(todo) - 1;
+    const int lk = __shfl(key, leader);
+    const unsigned long long same = __ballot(ok && key == lk);  // not yet placed: earlier groups had other keys
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter + lk, __popcll(same));
+    base = __shfl(base, leader);
+    if ((same >> lane) & 1ull) pos = base + __popcll(same & ((1ull << lane) - 1ull));
+    todo &= ~same;
+  }
+  return pos;
+}
+
 // Leaf of every point and leaf occupancy.
 __global__ __launch_bounds__(kTB) void k_tc_leaf(const double* __restrict__ X, int P, const Geom* __restrict__ geom,
                                                  int depth, int32_t* __restrict__ leafid, int32_t* __restrict__ counts) {
   const Geom g = *geom;
   const int n = 1 << depth;
-  for (int j = blockIdx.x * kTB + threadIdx.x; j < P; j += gridDim.x * kTB) {
-    int ix, iy;
-    {
+  for (int j0 = blockIdx.x * kTB; j0 < P; j0 += gridDim.x * kTB) {  // the same trip count for every lane
+    const int j = j0 + (int)threadIdx.x;
+    const bool ok = j < P;
+    int leaf = 0;
+    if (ok) {
+      int ix, iy;
+      {
 #pragma clang fp contract(off)
-      const double wl = g.side / (double)n;
-      ix = clamp_i((int)floor((X[j] - g.x0) / wl), 0, n - 1);
-      iy = clamp_i((int)floor((X[P + j] - g.y0) / wl), 0, n - 1);
+        const double wl = g.side / (double)n;
+        ix = clamp_i((int)floor((X[j] - g.x0) / wl), 0, n - 1);
+        iy = clamp_i((int)floor((X[P + j] - g.y0) / wl), 0, n - 1);
+      }
+      leaf = ix * n + iy;
+      leafid[j] = leaf;
     }
-    const int leaf = ix * n + iy;
-    leafid[j] = leaf;
-    atomicAdd(counts + leaf, 1);
+    wave_group_add(ok, leaf, counts);
   }
 }
 
@@ -274,9 +328,12 @@ __global__ __launch_bounds__(1024) void k_tc_scan(const int32_t* __restrict__ co
 __global__ __launch_bounds__(kTB) void k_tc_scatter(const int32_t* __restrict__ leafid, int P,
                                                     const int32_t* __restrict__ starts, int32_t* __restrict__ cursor,
                                                     int32_t* __restrict__ perm) {
-  for (int j = blockIdx.x * kTB + threadIdx.x; j < P; j += gridDim.x * kTB) {
-    const int leaf = leafid[j];
-    perm[starts[leaf] + atomicAdd(cursor + leaf, 1)] = j;
+  for (int j0 = blockIdx.x * kTB; j0 < P; j0 += gridDim.x * kTB) {  // the same trip count for every lane
+    const int j = j0 + (int)threadIdx.x;
+    const bool ok = j < P;
+    const int leaf = ok ? leafid[j] : 0;
+    const int pos = wave_group_add(ok, leaf, cursor);
+    if (ok) perm[starts[leaf] + pos] = j;
   }
 }
 
@@ -491,31 +548,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Binomial table T[m][l] = C(m + l - 1, l) for m = 1..p+1, l = 0..p, zero elsewhere, over rows m = 0..kTabM-1
-// and columns l = 0..63 (stride kTabL): the whole zero-padded range the matrix-core tiles read.  Row 0 holds
-// 1, 0, 0, ... while it is built (the start of the recurrence) and zeros once done.  Pascal's rule
-// T[m][l] = T[m-1][l] + T[m][l-1] runs along anti-diagonals: sums of integers, exact below 2^53.  The same
-// table holds C(m, l) = T[m - l + 1][l].  One wavefront, lane = l.
-constexpr int kTabL = 64;
-constexpr int kTabM = 4 * ((kMaxOrder + 1 + 3) / 4) + 1;  // m up to 4 ceil((p + 1) / 4)
-
-__global__ __launch_bounds__(64) void k_fmm_binom(int p, double* __restrict__ tab) {
-  __shared__ double prev[64];
-  const int l = threadIdx.x;
-  for (int m = 0; m < kTabM; ++m) tab[m * kTabL + l] = 0.0;
-  double v = l == 0 ? 1.0 : 0.0;  // T[0][l]
-  for (int s = 1; s <= 2 * p + 1; ++s) {
-    prev[l] = v;  // this lane's latest entry, T[s - 1 - l][l]
-    __syncthreads();
-    const int m = s - l;
-    if (l <= p && m >= 1 && m <= p + 1) {
-      v += l > 0 ? prev[l - 1] : 0.0;  // + T[m][l - 1], written by lane l - 1 one step earlier
-      tab[m * kTabL + l] = v;
-    }
-    __syncthreads();
-  }
 }
 
 typedef double double4v __attribute__((ext_vector_type(4)));
@@ -1175,12 +1207,12 @@ TreeRun tree_run(void* ws, const TreeLayout& t, int depth, int p) {
 // Tree over the points (root square, leaves, leaf order) and the moments of every box of levels
 // 2..depth (leaves from the points, coarser levels by translation).
 void launch_upward(const double* X, const double* f, const double* w, const int32_t* off, int M, int P, int p,
-                   int depth, int cshift, const TreeRun& r, hipStream_t st) {
+                   int depth, int cshift, bool binomials, const TreeRun& r, hipStream_t st) {
   const int nleaf = 1 << (2 * depth);
   const int pb = (P + kTB - 1) / kTB < 4096 ? (P + kTB - 1) / kTB : 4096;
   const int bb = (P + kTB - 1) / kTB < kBBoxBlocks ? (P + kTB - 1) / kTB : kBBoxBlocks;
   hipLaunchKernelGGL(k_tc_bbox_partial, dim3(bb), dim3(kTB), 0, st, X, P, r.part);
-  hipLaunchKernelGGL(k_tc_bbox_final, dim3(1), dim3(64), 0, st, r.part, bb, r.geom);
+  hipLaunchKernelGGL(k_tc_bbox_final, dim3(1), dim3(64), 0, st, r.part, bb, r.geom, p, binomials ? r.tab : nullptr);
   const int zb = (nleaf + kTB - 1) / kTB < 4096 ? (nleaf + kTB - 1) / kTB : 4096;
   hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, r.counts, r.cursor, nleaf);
   hipLaunchKernelGGL(k_tc_leaf, dim3(pb), dim3(kTB), 0, st, X, P, r.geom, depth, r.leafid, r.counts);
@@ -1221,7 +1253,7 @@ hipError_t launch_treecode(const double* X, const double* f, const double* w, co
   if (depth < 0 || depth > kMaxDepth || p < 1 || p > kMaxOrder) return hipErrorInvalidValue;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const TreeRun r = tree_run(ws, tree_layout(P, depth, p, false), depth, p);
-  launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<false>(), r, st);
+  launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<false>(), false, r, st);
   if (depth >= 2) {
     const size_t work = r.nbox * (p + 1);
     const int gb = (int)((work + kTB - 1) / kTB < 4096 ? (work + kTB - 1) / kTB : 4096);
@@ -1237,9 +1269,8 @@ hipError_t launch_fmm(const double* X, const double* f, const double* w, const i
   if (depth < 0 || depth > kMaxDepth || p < 1 || p > kMaxOrder) return hipErrorInvalidValue;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const TreeRun r = tree_run(ws, tree_layout(P, depth, p, true), depth, p);
-  launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<true>(), r, st);
+  launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<true>(), depth >= 2, r, st);
   if (depth >= 2) {
-    hipLaunchKernelGGL(k_fmm_binom, dim3(1), dim3(64), 0, st, p, r.tab);
     const int nw = m2l_waves(p);
     const dim3 g((unsigned)r.nbox), bl(64 * nw);
     const size_t lds = m2l_lds_bytes(p, nw);
