@@ -783,54 +783,79 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restri
 // each ancestor (levels 2..depth-1), re-centred from the ancestor's centre straight to the leaf's (the
 // re-centring of a polynomial is exact, so one shift per ancestor equals the chain through the levels).
 // With e = c_leaf - c_anc: X_k += sum_{m>=k} C(m, k) e^(m-k) X_m for A, B, C, and B also -conj(e) times the
-// shifted C.  One wavefront per leaf, lane = order k, all ancestors' rows staged in LDS together; the
-// binomials follow their recurrence (C(48, 24) < 2^53: rounding the product with the reciprocal to the
-// nearest integer gives each one exactly).
+// shifted C.  One wavefront per leaf, all ancestors' rows staged in LDS together; lane = (half h, order k):
+// for p + 1 <= 32 the two halves of the wavefront take alternate ancestors and their sums are added at the
+// end, otherwise one half does all.  The binomials follow their recurrence (C(48, 24) < 2^53: rounding the
+// product with the reciprocal to the nearest integer gives each one exactly).
 __global__ __launch_bounds__(64) void k_fmm_l2l(const Geom* __restrict__ geom, int depth, int p,
                                                const int32_t* __restrict__ bcount, double2* __restrict__ loc) {
-  extern __shared__ double2 anc[];  // [depth - 2][3 (p + 1)]
+  extern __shared__ double2 anc[];  // [depth - 2][3 (p + 1)], then 3 x 32 for the halves' exchange
   const int n = 1 << depth;
   const int leaf = blockIdx.x;
   const size_t lbox = level_box_base(depth) + (size_t)leaf;
   if (bcount[lbox] == 0) return;
-  const int k = threadIdx.x;
+  const int lane = threadIdx.x;
   const int bx = leaf / n, by = leaf % n;
   const int rows = 3 * (p + 1);
   const double wL = geom->side / (double)n;
-  for (int e = k; e < (depth - 2) * rows; e += 64) {
+  const int nanc = depth - 2;
+  for (int e = lane; e < nanc * rows; e += 64) {
     const int l = 2 + e / rows, sh = depth - l;
     const size_t abox = level_box_base(l) + (size_t)(bx >> sh) * (1 << l) + (by >> sh);
     anc[e] = loc[abox * rows + e % rows];
   }
   __syncthreads();
-  if (k > p) return;
+  const bool split = p + 1 <= 32;
+  const int h = split ? lane >> 5 : 0, k = split ? lane & 31 : lane;
+  const int hstep = split ? 2 : 1;
   double2 sA = make_double2(0.0, 0.0), sB = sA, sC = sA;
-  for (int l = 2; l < depth; ++l) {
-    const int sh = depth - l;
-    const int ax = bx >> sh, ay = by >> sh;
-    const double2* pl = anc + (l - 2) * rows;
-    // leaf centre - ancestor centre = ((b + 1/2) - (a + 1/2) 2^sh) wL per coordinate: exact before the product
-    const double2 e = make_double2(((double)bx + 0.5 - ((double)ax + 0.5) * (double)(1 << sh)) * wL,
-                                   ((double)by + 0.5 - ((double)ay + 0.5) * (double)(1 << sh)) * wL);
-    double2 tA = make_double2(0.0, 0.0), tB = tA, tC = tA;
-    double2 ej = make_double2(1.0, 0.0);  // e^j
-    double cb = 1.0;                      // C(k + j, k): integers below 2^53, each step exact after rounding
-    for (int j = 0; j <= p - k; ++j) {
-      const double2 ce = make_double2(cb * ej.x, cb * ej.y);
-      tA = cfma(ce, pl[k + j], tA);
-      tB = cfma(ce, pl[(p + 1) + k + j], tB);
-      tC = cfma(ce, pl[2 * (p + 1) + k + j], tC);
-      ej = cmul(ej, e);
-      cb = rint(cb * (double)(k + j + 1) * kRecip[j]);  // C(k + j + 1, k) = C(k + j, k) (k + j + 1) / (j + 1)
+  if (k <= p && (split || lane <= p)) {
+    for (int a = h; a < nanc; a += hstep) {
+      const int l = 2 + a, sh = depth - l;
+      const int ax = bx >> sh, ay = by >> sh;
+      const double2* pl = anc + a * rows;
+      // leaf centre - ancestor centre = ((b + 1/2) - (a + 1/2) 2^sh) wL per coordinate: exact before the product
+      const double2 e = make_double2(((double)bx + 0.5 - ((double)ax + 0.5) * (double)(1 << sh)) * wL,
+                                     ((double)by + 0.5 - ((double)ay + 0.5) * (double)(1 << sh)) * wL);
+      double2 tA = make_double2(0.0, 0.0), tB = tA, tC = tA;
+      double2 ej = make_double2(1.0, 0.0);  // e^j
+      double cb = 1.0;                      // C(k + j, k): integers below 2^53, each step exact after rounding
+      for (int j = 0; j <= p - k; ++j) {
+        const double2 ce = make_double2(cb * ej.x, cb * ej.y);
+        tA = cfma(ce, pl[k + j], tA);
+        tB = cfma(ce, pl[(p + 1) + k + j], tB);
+        tC = cfma(ce, pl[2 * (p + 1) + k + j], tC);
+        ej = cmul(ej, e);
+        cb = rint(cb * (double)(k + j + 1) * kRecip[j]);  // C(k + j + 1, k) = C(k + j, k) (k + j + 1) / (j + 1)
+      }
+      const double2 shc = cmul(make_double2(e.x, -e.y), tC);
+      sA.x += tA.x;
+      sA.y += tA.y;
+      sB.x += tB.x - shc.x;
+      sB.y += tB.y - shc.y;
+      sC.x += tC.x;
+      sC.y += tC.y;
     }
-    const double2 shc = cmul(make_double2(e.x, -e.y), tC);
-    sA.x += tA.x;
-    sA.y += tA.y;
-    sB.x += tB.x - shc.x;
-    sB.y += tB.y - shc.y;
-    sC.x += tC.x;
-    sC.y += tC.y;
   }
+  double2* xch = anc + nanc * rows;
+  if (split) {  // the second half's sums join the first half's
+    if (h == 1) {
+      xch[k] = sA;
+      xch[32 + k] = sB;
+      xch[64 + k] = sC;
+    }
+    __syncthreads();
+    if (h == 1) return;
+    if (k <= p) {
+      sA.x += xch[k].x;
+      sA.y += xch[k].y;
+      sB.x += xch[32 + k].x;
+      sB.y += xch[32 + k].y;
+      sC.x += xch[64 + k].x;
+      sC.y += xch[64 + k].y;
+    }
+  }
+  if (k > p) return;
   double2* cb_ = loc + lbox * rows;
   double2 v = cb_[k];
   cb_[k] = make_double2(v.x + sA.x, v.y + sA.y);
@@ -1282,8 +1307,8 @@ hipError_t launch_fmm(const double* X, const double* f, const double* w, const i
     }
     if (depth >= 3) {
       const int nleaf = 1 << (2 * depth);
-      hipLaunchKernelGGL(k_fmm_l2l, dim3(nleaf), dim3(64), sizeof(double2) * (size_t)(depth - 2) * 3 * (p + 1), st,
-                         r.geom, depth, p, r.bcount, r.loc);
+      hipLaunchKernelGGL(k_fmm_l2l, dim3(nleaf), dim3(64), sizeof(double2) * ((size_t)(depth - 2) * 3 * (p + 1) + 96),
+                         st, r.geom, depth, p, r.bcount, r.loc);
     }
   }
   launch_eval<true>(X, f, w, off, M, P, p, depth, scale, r, out, st);
