@@ -267,7 +267,8 @@ VESNET_API int vesnet_farfield_treecode(const double* points, const double* forc
    box whose interaction list holds it, the polynomials are re-centred down the tree, and each target
    evaluates only its leaf's polynomial.  The far work becomes O(boxes x order^2) instead of
    O(points x boxes per list x order).  Accuracy: at the same order about 2 to 4 times the treecode's
-   error (order 30: about 5e-12 relative to max|u| on dense suspensions); everything in float64.
+   error (order 30: about 1e-11 relative to max|u| on dense suspensions, order 40: 1e-14); everything
+   in float64.
    Deterministic under the same condition as the treecode.
      arguments, layouts, ownership and errors as vesnet_farfield_treecode;
      workspace : device, vesnet_fmm_workspace_bytes(P, depth, order) bytes (the treecode's plus
