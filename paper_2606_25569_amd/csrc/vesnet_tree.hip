@@ -1101,6 +1101,7 @@ __global__ __launch_bounds__(kOwnThreads) void k_tc_own(const double* __restrict
   __shared__ int32_t sl[kOwnChunk];
   __shared__ uint8_t lst[kOwnChunk][kOwnThreads];  // lst[k][thread]: the k-th far source of its target
   __shared__ double2 ltab[kLogTab];
+  __shared__ int bb[kOwnThreads / 64][4];  // per wavefront: min and max leaf column and row of the chunk
   const int v = blockIdx.x;
   const int v0 = clamp_i(off[v], 0, P), v1 = max(v0, clamp_i(off[v + 1], 0, P));  // offsets never trusted
   if (v1 - v0 < 2) return;
@@ -1126,12 +1127,42 @@ __global__ __launch_bounds__(kOwnThreads) void k_tc_own(const double* __restrict
         sfy[q] = w[j] * f[P + j];
         sl[q] = leafid[j];
       }
+      // the chunk's leaf bounding box: a target whose 3 x 3 leaves cover it has no far source here
+      int mnx = 1 << 30, mxx = -1, mny = 1 << 30, mxy = -1;
+      for (int q = t; q < cnt; q += kOwnThreads) {
+        const int lj = leafid[c0 + q];
+        mnx = min(mnx, lj >> depth);
+        mxx = max(mxx, lj >> depth);
+        mny = min(mny, lj & mask);
+        mxy = max(mxy, lj & mask);
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        mnx = min(mnx, __shfl_xor(mnx, o));
+        mxx = max(mxx, __shfl_xor(mxx, o));
+        mny = min(mny, __shfl_xor(mny, o));
+        mxy = max(mxy, __shfl_xor(mxy, o));
+      }
+      if ((t & 63) == 0) {
+        bb[t >> 6][0] = mnx;
+        bb[t >> 6][1] = mxx;
+        bb[t >> 6][2] = mny;
+        bb[t >> 6][3] = mxy;
+      }
       __syncthreads();
+      for (int wv = 0; wv < kOwnThreads / 64; ++wv) {
+        mnx = min(mnx, bb[wv][0]);
+        mxx = max(mxx, bb[wv][1]);
+        mny = min(mny, bb[wv][2]);
+        mxy = max(mxy, bb[wv][3]);
+      }
+      const bool covered = ix - 1 <= mnx && mxx <= ix + 1 && iy - 1 <= mny && mxy <= iy + 1;
       int nf = 0;
+      if (!covered) {
 #pragma unroll 8
-      for (int q = 0; q < cnt; ++q) {
-        const int lj = sl[q];
-        if (abs((lj >> depth) - ix) > 1 || abs((lj & mask) - iy) > 1) lst[nf++][t] = (uint8_t)q;  // far
+        for (int q = 0; q < cnt; ++q) {
+          const int lj = sl[q];
+          if (abs((lj >> depth) - ix) > 1 || abs((lj & mask) - iy) > 1) lst[nf++][t] = (uint8_t)q;  // far
+        }
       }
       int most = nf;  // longest list of the wavefront
       for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
