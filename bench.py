@@ -465,6 +465,18 @@ def _treecode_work(X, sizes, depth):
     return n_box, n_direct, n_m2l
 
 
+def _nonempty_leaves(X, depth):
+    import numpy as np
+    x, y = X
+    side = max(x.max() - x.min(), y.max() - y.min())
+    x0 = 0.5 * (x.min() + x.max()) - 0.5 * side
+    y0 = 0.5 * (y.min() + y.max()) - 0.5 * side
+    n = 1 << depth
+    ix = np.clip(np.floor((x - x0) / (side / n)), 0, n - 1).astype(np.int64)
+    iy = np.clip(np.floor((y - y0) / (side / n)), 0, n - 1).astype(np.int64)
+    return int(np.unique(ix * n + iy).size)
+
+
 def bench_treecode(args):
     """The 2000 x 128 workload by the FP64 treecode (default depth), at several orders, against the
     exact sum on a seeded target sample; the direct FP32-compensated sum timed alongside."""
@@ -494,9 +506,10 @@ def bench_treecode(args):
     t_oracle = time.time() - t0
     scale = float(np.abs(exact).max())
     n_box, n_direct, n_m2l = _treecode_work(s.X, s.sizes(), depth)
+    n_l2l = _nonempty_leaves(s.X, depth) * max(depth - 2, 0)  # (leaf, ancestor) shifts
     rec = {"workload": "treecode and fast multipole far field of the dense suspension: 2000 vesicles x 128 "
                        f"points (256000), uniform quadtree depth {depth}, FP64",
-           "far_box_evaluations": n_box, "direct_pairs": n_direct, "m2l_translations": n_m2l,
+           "far_box_evaluations": n_box, "direct_pairs": n_direct, "m2l_translations": n_m2l, "l2l_shifts": n_l2l,
            "n_points": P, "cross_vesicle_pairs": pairs, "depth": depth, "orders": {}, "fmm_orders": {}}
     for order in (20, 30, 40):
         ws = torch.empty(lib.vesnet_treecode_workspace_bytes(P, depth, order), dtype=torch.uint8, device=dev)
@@ -517,7 +530,13 @@ def bench_treecode(args):
         fn()
         torch.cuda.synchronize()
         err = float(np.abs(out.cpu().numpy()[:, sel] - exact).max() / scale)
-        rec["fmm_orders"][order] = {"ms": ms, "max_rel_err_vs_exact": err, "equivalent_pairs_per_s": pairs / (ms * 1e-3)}
+        # M2L 3 series x (p+1)^2 complex-by-real MACs (4 flops) per translation; L2L 3 series x (p+1)(p+2)/2
+        # complex FMAs (8 flops) per (leaf, ancestor); L2P three complex Horner chains (12p flops) per target
+        fflops = (12 * (order + 1) ** 2 * n_m2l + 12 * (order + 1) * (order + 2) * n_l2l + 12 * order * P
+                  + FLOPS_PER_PAIR * n_direct)
+        rec["fmm_orders"][order] = {"ms": ms, "max_rel_err_vs_exact": err, "equivalent_pairs_per_s": pairs / (ms * 1e-3),
+                                    "algorithmic_tflops_fp64": fflops / (ms * 1e-3) / 1e12,
+                                    "frac_of_fp64_peak": fflops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS}
         log(f"[bench] fmm order {order}: {ms:.3f} ms, err {err:.2e} of max|u| on {sel.size} targets")
     wsd = torch.empty(V.workspace_bytes(P, M, "fp32c"), dtype=torch.uint8, device=dev)
     ms_direct = _time(lambda: V.farfield_forward(X, X, f, w, part, s.mu, "fp32c", out=out, workspace=wsd), 5, stream)
