@@ -553,32 +553,27 @@ __device__ __forceinline__ void wave_sync() {
 typedef double double4v __attribute__((ext_vector_type(4)));
 
 // Dynamic LDS of k_fmm_m2l for order p, KS = ceil((p + 1) / 4) steps of four m and RT = ceil((p + 1) / 16)
-// tiles of 16 orders: the binomial tile T[m - 1][l] (4 KS x 16 RT, shared), the source list, and per wave
-// the scaled coefficients X[v][m - 1][s] of its batch (3 series x 4 KS x 8 sources, complex; also the
-// final exchange of 3 x 64 sums), the powers (-t_s)^l (8 sources x 4 KS, complex), and per source
-// lambda_A, lambda_B (complex) and ln|d|.
+// tiles of 16 orders: the binomial tile T[m - 1][l] (4 KS x 16 RT), the source list, the scaled coefficients
+// X[v][m - 1][s] of a batch (3 series x 4 KS x 8 sources, complex; also the final exchange of 3 x 64 sums),
+// the powers (-t_s)^l (8 sources x 4 KS, complex), and per source lambda_A, lambda_B (complex) and ln|d|.
+// (Splitting a box's batches over several waves, or taking one series at a time to save registers, both
+// measured slower: the first is limited by LDS occupancy, the second loses independent MFMA chains.)
 constexpr int kM2LBatch = 8;  // source boxes per batch: 8 complex columns fill one 16-column tile
-constexpr int kM2LWaves = 1;  // at most this many waves per target box: wave w takes batches w, w + W, ...
 __host__ __device__ inline int m2l_ksteps(int p) { return (p + 1 + 3) / 4; }
 __host__ __device__ inline int m2l_rtiles(int p) { return (p + 1 + 15) / 16; }
 __host__ __device__ inline int m2l_tsize(int p) { return (4 * m2l_ksteps(p) * 16 * m2l_rtiles(p) + 1) / 2; }  // double2
-__host__ __device__ inline int m2l_wsize(int p) {  // per wave, in double2
+__host__ __device__ inline int m2l_xsize(int p) {  // in double2
   const int mm = 4 * m2l_ksteps(p);
-  const int x = 3 * mm * kM2LBatch > 3 * 64 ? 3 * mm * kM2LBatch : 3 * 64;
-  return x + kM2LBatch * mm + 2 * kM2LBatch + kM2LBatch / 2;  // X, powers, lambdas, ln|d|
+  return 3 * mm * kM2LBatch > 3 * 64 ? 3 * mm * kM2LBatch : 3 * 64;
 }
-inline size_t m2l_lds_bytes(int p, int waves) {
-  return sizeof(double2) * ((size_t)m2l_tsize(p) + 36 + (size_t)waves * m2l_wsize(p));
-}
-// Waves per target box: as many as fit 64 KB of LDS, at most kM2LWaves.
-inline int m2l_waves(int p) {
-  int w = kM2LWaves;
-  while (w > 1 && m2l_lds_bytes(p, w) > 65536) --w;
-  return w;
+inline size_t m2l_lds_bytes(int p) {
+  const int mm = 4 * m2l_ksteps(p);
+  return sizeof(double2) * ((size_t)m2l_tsize(p) + 36 + m2l_xsize(p) + (size_t)kM2LBatch * mm + 2 * kM2LBatch +
+                            kM2LBatch / 2);
 }
 
 // Interaction-list contributions to the local expansion of every non-empty box of levels 2..depth (one
-// launch for all levels, one workgroup per target box), on the matrix cores.  For a source box s at
+// launch for all levels, one wavefront per target box), on the matrix cores.  For a source box s at
 // d_s = c_s - c_T, t_s = 1/d_s, and each series v (A, Phi, and B with the conj(d) Phi term folded in,
 // conj(d_s) being a constant factor per source), the coefficient of zeta^l is
 //   t_s^l (sum_{m=1}^{p+1} C(m + l - 1, l) X_v[m][s] - lambda_v / l),   X_v[m][s] = a_v(m) (-t_s)^m,
@@ -586,26 +581,24 @@ inline int m2l_waves(int p) {
 // X^T: (16 columns: 8 sources x re, im) x m and T: m x l, in 16 x 16 x 4 FP64 steps: the columns of a tile
 // are one series of eight sources, source c's real part in row (c mod 4) + 8 (c / 4) and its imaginary part
 // four rows below, so that every lane (l = lane mod 16, q = lane / 16) receives both parts of sources q and
-// q + 4 for its order l and scales them itself.  Sources go eight at a time, in the fixed candidate order,
-// to the waves in turn; at the end the sums of the four waves and of the four lanes of every order are added
-// in (wave, q) order.  RT = ceil((p + 1) / 16).
+// q + 4 for its order l and scales them itself.  Sources go eight at a time, in the fixed candidate order;
+// at the end the sums of the four lanes of every order are added in q order.  RT = ceil((p + 1) / 16).
 template <int RT>
-__global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restrict__ geom, int depth, int p,
+__global__ __launch_bounds__(64) void k_fmm_m2l(const Geom* __restrict__ geom, int depth, int p,
                                                            const double2* __restrict__ mom,
                                                            const int32_t* __restrict__ bcount,
                                                            const double* __restrict__ tab, double2* __restrict__ loc) {
   extern __shared__ double2 sm[];
   const size_t box = blockIdx.x;
-  if (bcount[box] == 0) return;  // the whole workgroup
-  const int nw = blockDim.x >> 6;  // waves of this workgroup
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (bcount[box] == 0) return;
+  const int lane = threadIdx.x;
   const int np = p + 1;
   const int KS = m2l_ksteps(p), MM = 4 * KS;
   constexpr int TL = 16 * RT;                                    // orders per table row
   double* Tt = reinterpret_cast<double*>(sm);                    // [MM][TL]
   int32_t* lst = reinterpret_cast<int32_t*>(sm + m2l_tsize(p));  // [36][2]: source box coordinates
-  double2* X = sm + m2l_tsize(p) + 36 + (size_t)wv * m2l_wsize(p);  // this wave's [3][MM][8]
-  double2* pw = X + (m2l_wsize(p) - kM2LBatch * MM - 2 * kM2LBatch - kM2LBatch / 2);  // [8][MM]: (-t_s)^l
+  double2* X = sm + m2l_tsize(p) + 36;                           // [3][MM][8]
+  double2* pw = X + m2l_xsize(p);                                // [8][MM]: (-t_s)^l
   double2* lam = pw + kM2LBatch * MM;                            // [8][2]: lambda_A, lambda_B
   double* lnd = reinterpret_cast<double*>(lam + 2 * kM2LBatch);  // [8]
   for (int e = threadIdx.x; e < MM * TL; e += blockDim.x) Tt[e] = tab[(size_t)(e / TL + 1) * kTabL + e % TL];
@@ -625,13 +618,13 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restri
     if (ok) ok = bcount[base + (size_t)sx * n + sy] != 0;
     const unsigned long long mask = __ballot(ok);
     ns = __popcll(mask);
-    if (wv == 0 && ok) {
+    if (ok) {
       const int rank = __popcll(mask & ((1ull << lane) - 1ull));
       lst[2 * rank] = sx;
       lst[2 * rank + 1] = sy;
     }
   }
-  __syncthreads();  // table and list ready; below, each wave synchronises its own lanes only
+  wave_sync();  // table and list ready
   const int j = lane & 15, q = lane >> 4;  // result lanes: order j (+ 16 rt), sources q and q + 4
   const int ai = lane & 15, ak = lane >> 4;  // operand lanes: column / order ai, step row ak
   const int acol = (ai & 3) + 4 * (ai >> 3), apart = (ai >> 2) & 1;  // column ai: source acol, re or im
@@ -644,7 +637,7 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restri
 #pragma unroll
     for (int v = 0; v < 3; ++v) acc[v][rt] = make_double2(0.0, 0.0);
   }
-  for (int b0 = wv * kM2LBatch; b0 < ns; b0 += nw * kM2LBatch) {
+  for (int b0 = 0; b0 < ns; b0 += kM2LBatch) {
     const int nb = min(kM2LBatch, ns - b0);
     // scaling: lane takes source s = lane mod 8 and m = 1 + lane / 8, then every eighth m
     {
@@ -753,29 +746,25 @@ __global__ __launch_bounds__(64 * kM2LWaves) void k_fmm_m2l(const Geom* __restri
     }
     wave_sync();  // the staging is rewritten by the next batch
   }
-  // the sums of every wave and of the four lanes of every order, added in (wave, q) order; each wave's
-  // X carries its sums
+  // the sums of the four lanes of every order, added in q order; X is reused for the exchange
   double2* lb = loc + box * 3 * np;
-  double2* X0 = sm + m2l_tsize(p) + 36;
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
     for (int v = 0; v < 3; ++v) X[v * 64 + lane] = acc[v][rt];
-    __syncthreads();
+    wave_sync();
     const int l = lane + 16 * rt;
-    if (wv == 0 && lane < 16 && l <= p) {
+    if (lane < 16 && l <= p) {
       for (int v = 0; v < 3; ++v) {
-        double2 r = make_double2(0.0, 0.0);
-        for (int w = 0; w < nw; ++w)
-          for (int qq = 0; qq < 4; ++qq) {
-            const double2 x = X0[(size_t)w * m2l_wsize(p) + v * 64 + lane + 16 * qq];
-            r.x += x.x;
-            r.y += x.y;
-          }
+        double2 r = X[v * 64 + lane];
+        for (int qq = 1; qq < 4; ++qq) {
+          r.x += X[v * 64 + lane + 16 * qq].x;
+          r.y += X[v * 64 + lane + 16 * qq].y;
+        }
         lb[(v == 0 ? 0 : (v == 1 ? 2 : 1)) * np + l] = r;  // series A, Phi, B -> rows A, B, C
       }
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
@@ -1327,9 +1316,8 @@ hipError_t launch_fmm(const double* X, const double* f, const double* w, const i
   const TreeRun r = tree_run(ws, tree_layout(P, depth, p, true), depth, p);
   launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<true>(), depth >= 2, r, st);
   if (depth >= 2) {
-    const int nw = m2l_waves(p);
-    const dim3 g((unsigned)r.nbox), bl(64 * nw);
-    const size_t lds = m2l_lds_bytes(p, nw);
+    const dim3 g((unsigned)r.nbox), bl(64);
+    const size_t lds = m2l_lds_bytes(p);
     switch (m2l_rtiles(p)) {
       case 1: hipLaunchKernelGGL(k_fmm_m2l<1>, g, bl, lds, st, r.geom, depth, p, r.mom, r.bcount, r.tab, r.loc); break;
       case 2: hipLaunchKernelGGL(k_fmm_m2l<2>, g, bl, lds, st, r.geom, depth, p, r.mom, r.bcount, r.tab, r.loc); break;
