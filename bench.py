@@ -541,6 +541,25 @@ def bench_treecode(args):
     wsd = torch.empty(V.workspace_bytes(P, M, "fp32c"), dtype=torch.uint8, device=dev)
     ms_direct = _time(lambda: V.farfield_forward(X, X, f, w, part, s.mu, "fp32c", out=out, workspace=wsd), 5, stream)
     rec["direct_fp32c_ms"] = ms_direct
+    # scaling in P: the fast multipole method, order 30 at the default depth, on twice the points
+    s2 = S.load_config(2)
+    P2 = s2.n_points
+    X2, f2, w2 = (torch.tensor(a, device=dev) for a in (s2.X, s2.f, s2.w))
+    part2 = V.Partition(s2.offsets, dev)
+    depth2 = int(lib.vesnet_treecode_default_depth(P2))
+    out2 = torch.empty((2, P2), dtype=torch.float64, device=dev)
+    ws2 = torch.empty(lib.vesnet_fmm_workspace_bytes(P2, depth2, 30), dtype=torch.uint8, device=dev)
+    fn2 = lambda: V.farfield_fmm(X2, f2, w2, part2, s2.mu, 30, depth2, out=out2, workspace=ws2)
+    ms2 = _time(fn2, args.steps, stream)
+    fn2()
+    torch.cuda.synchronize()
+    sel2 = np.sort(np.random.default_rng(S.config_seed(2, 7)).choice(P2, 1000, replace=False))
+    exact2 = O.farfield_suspension(s2.X, s2.f, s2.w, s2.offsets, s2.mu, select=sel2)
+    err2 = float(np.abs(out2.cpu().numpy()[:, sel2] - exact2).max() / np.abs(exact2).max())
+    rec["fmm_scaling"] = {"workload": "8000 vesicles x 64 points (512000), force-free", "depth": depth2, "order": 30,
+                          "ms": ms2, "max_rel_err_vs_exact": err2, "cross_vesicle_pairs": s2.cross_pairs(),
+                          "equivalent_pairs_per_s": s2.cross_pairs() / (ms2 * 1e-3)}
+    log(f"[bench] fmm 8000 x 64, depth {depth2}, order 30: {ms2:.3f} ms, err {err2:.2e} of max|u| on {sel2.size} targets")
     rec["oracle_sample"] = {"targets": int(sel.size), "seconds": t_oracle}
     log(f"[bench] direct FP32-compensated sum: {ms_direct:.3f} ms")
     print(json.dumps(rec), flush=True)
