@@ -546,7 +546,7 @@ def bench_treecode(args):
     P2 = s2.n_points
     X2, f2, w2 = (torch.tensor(a, device=dev) for a in (s2.X, s2.f, s2.w))
     part2 = V.Partition(s2.offsets, dev)
-    depth2 = int(lib.vesnet_treecode_default_depth(P2))
+    depth2 = int(lib.vesnet_fmm_default_depth(P2, 30))
     out2 = torch.empty((2, P2), dtype=torch.float64, device=dev)
     ws2 = torch.empty(lib.vesnet_fmm_workspace_bytes(P2, depth2, 30), dtype=torch.uint8, device=dev)
     fn2 = lambda: V.farfield_fmm(X2, f2, w2, part2, s2.mu, 30, depth2, out=out2, workspace=ws2)

@@ -273,6 +273,10 @@ VESNET_API int vesnet_farfield_treecode(const double* points, const double* forc
      arguments, layouts, ownership and errors as vesnet_farfield_treecode;
      workspace : device, vesnet_fmm_workspace_bytes(P, depth, order) bytes (the treecode's plus
                  3 (order+1) complex numbers per box and a binomial table) */
+/* Default depth of the fast multipole method: leaves of at most about 64 points up to order 32 and 128
+   above, where the M2L work (order^2 per pair of boxes) outweighs the direct part (measured best on the
+   2000 x 128 and 8000 x 64 suspensions at orders 30 and 40). */
+VESNET_API int32_t vesnet_fmm_default_depth(int32_t n_points, int32_t order);
 VESNET_API size_t vesnet_fmm_workspace_bytes(int32_t n_points, int32_t depth, int32_t order);
 VESNET_API int vesnet_farfield_fmm(const double* points, const double* force_density, const double* arc_weights,
                                    const int32_t* vesicle_offsets, int32_t n_vesicles, int32_t n_points, double mu,

@@ -26,7 +26,8 @@ EXPORTED = (
     "vesnet_backward_workspace_bytes", "vesnet_farfield_stokeslet_backward", "vesnet_autotune",
     "vesnet_farfield_stokeslet_nearmasked", "vesnet_elastic_force", "vesnet_near_layers",
     "vesnet_rbf_workspace_bytes", "vesnet_rbf_fit", "vesnet_rbf_eval_near", "vesnet_treecode_default_depth",
-    "vesnet_treecode_workspace_bytes", "vesnet_farfield_treecode", "vesnet_fmm_workspace_bytes", "vesnet_farfield_fmm",
+    "vesnet_treecode_workspace_bytes", "vesnet_farfield_treecode", "vesnet_fmm_default_depth", "vesnet_fmm_workspace_bytes",
+    "vesnet_farfield_fmm",
 )
 
 
@@ -90,6 +91,7 @@ def lib():
         "vesnet_treecode_default_depth": ([I32], I32),
         "vesnet_treecode_workspace_bytes": ([I32, I32, I32], SZ),
         "vesnet_farfield_treecode": ([P, P, P, P, I32, I32, D, I32, I32, P, P, SZ, P], INT),
+        "vesnet_fmm_default_depth": ([I32, I32], I32),
         "vesnet_fmm_workspace_bytes": ([I32, I32, I32], SZ),
         "vesnet_farfield_fmm": ([P, P, P, P, I32, I32, D, I32, I32, P, P, SZ, P], INT),
         "vesnet_autotune": ([P, P, P, P, P, I32, I32, INT, P, I32, P, D, P, INT, INT, P, SZ, P, CFG,

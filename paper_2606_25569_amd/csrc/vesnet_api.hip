@@ -426,6 +426,14 @@ extern "C" int vesnet_farfield_treecode(const double* X, const double* f, const 
   return ok();
 }
 
+extern "C" int32_t vesnet_fmm_default_depth(int32_t P, int32_t order) {
+  // leaves of about 64 points, or 128 above order 32, where M2L (p^2 per box pair) outweighs the direct part
+  const int64_t cap = order > 32 ? 128 : 64;
+  int32_t L = 0;
+  while (L < kTreeMaxDepth && (int64_t)P > cap << (2 * L)) ++L;
+  return L;
+}
+
 extern "C" size_t vesnet_fmm_workspace_bytes(int32_t P, int32_t depth, int32_t order) {
   if (P < 0 || P > kMaxPoints || depth < 0 || depth > kTreeMaxDepth || order < 1 || order > kTreeMaxOrder) return 0;
   return fmm_workspace_bytes(P, depth, order);

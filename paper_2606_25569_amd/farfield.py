@@ -188,14 +188,14 @@ def farfield_treecode(X, force_density, arc_weights, partition, mu, order=30, de
 
 def farfield_fmm(X, force_density, arc_weights, partition, mu, order=30, depth=None, out=None, workspace=None):
     """Fast multipole far field of the points X on themselves (own vesicle excluded), on the
-    treecode's tree: local expansions of the given order (default depth as the treecode's)."""
+    treecode's tree: local expansions of the given order (default depth: vesnet_fmm_default_depth)."""
     part = as_partition(partition)
     P, M = part.n_points, part.n_vesicles
     _check_vec("X", X, P)
     _check_vec("force_density", force_density, P)
     _check_w(arc_weights, P)
     lib = L.lib()
-    depth = int(lib.vesnet_treecode_default_depth(P)) if depth is None else int(depth)
+    depth = int(lib.vesnet_fmm_default_depth(P, int(order))) if depth is None else int(depth)
     if out is None:
         out = torch.empty((2, P), dtype=torch.float64, device=X.device)
     if workspace is None:

@@ -24,7 +24,7 @@ def _declared():
 def test_every_declared_symbol_is_exported(L):
     lib = L.lib()
     names = _declared()
-    assert len(names) == 27, names
+    assert len(names) == 28, names
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(L.EXPORTED)
@@ -224,6 +224,9 @@ def test_tree_methods_reject(L, method):
     assert lib.vesnet_treecode_default_depth(64) == 0
     assert lib.vesnet_treecode_default_depth(65) == 1
     assert lib.vesnet_treecode_default_depth(256000) == 6
+    assert lib.vesnet_fmm_default_depth(256000, 30) == 6 and lib.vesnet_fmm_default_depth(256000, 40) == 6
+    assert lib.vesnet_fmm_default_depth(512000, 30) == 7 and lib.vesnet_fmm_default_depth(512000, 40) == 6
+    assert lib.vesnet_fmm_default_depth(0, 30) == 0 and lib.vesnet_fmm_default_depth(10 ** 9, 8) == 10
     assert wsq(100, 3, 0) == 0 and wsq(100, 3, 49) == 0 and wsq(100, -1, 8) == 0 and wsq(100, 11, 8) == 0
     assert wsq(-1, 3, 8) == 0
     need = wsq(100, 3, 8)
