@@ -283,6 +283,32 @@ VESNET_API int vesnet_farfield_fmm(const double* points, const double* force_den
                                    int32_t order, int32_t depth, double* out, void* workspace, size_t workspace_bytes,
                                    void* stream);
 
+/* The fast multipole far field with the near-field masking of Algorithm 4: as
+   vesnet_farfield_stokeslet_nearmasked, vesicle v (not the target's own) is near target i when
+   min_j |x_i - x_j| <= h_v = sum_j w_j / N_v, decided here in float64 on squared distances.  Every
+   near pair (i, v) is stored into near_pairs[2k], near_pairs[2k+1] in unspecified order, and v's
+   exact direct sum at x_i is subtracted from the fast multipole result, so that out is the masked
+   far field with the fast multipole method's truncation error.  The result does not depend on the
+   order of the list.
+   Near vesicles are found in the 3 x 3 leaves around the target's leaf, which holds every point
+   within h_v while h_v <= side / 2^depth (side: the larger extent of the points).
+   *near_count (device int32) receives:
+     >= 0: the number of near pairs; when it exceeds near_capacity, only the first near_capacity
+           were stored, but out is masked completely;
+     -1:   a target had more than 16 near vesicles (out is not masked completely);
+     -2:   some h_v exceeds the leaf width (use a smaller depth; out is not masked completely).
+     near_pairs : device int32 [near_capacity][2] (may be NULL if capacity is 0)
+     workspace  : device, vesnet_fmm_nearmasked_workspace_bytes(P, M, depth, order) bytes
+   Other arguments as vesnet_farfield_fmm. */
+VESNET_API size_t vesnet_fmm_nearmasked_workspace_bytes(int32_t n_points, int32_t n_vesicles, int32_t depth,
+                                                        int32_t order);
+VESNET_API int vesnet_farfield_fmm_nearmasked(const double* points, const double* force_density,
+                                              const double* arc_weights, const int32_t* vesicle_offsets,
+                                              int32_t n_vesicles, int32_t n_points, double mu, int32_t order,
+                                              int32_t depth, double* out, int32_t* near_pairs, int32_t near_capacity,
+                                              int32_t* near_count, void* workspace, size_t workspace_bytes,
+                                              void* stream);
+
 /* ------------------------------------------------------------------ batched */
 
 /* S independent suspensions concatenated point-wise and vesicle-wise.

@@ -27,7 +27,7 @@ EXPORTED = (
     "vesnet_farfield_stokeslet_nearmasked", "vesnet_elastic_force", "vesnet_near_layers",
     "vesnet_rbf_workspace_bytes", "vesnet_rbf_fit", "vesnet_rbf_eval_near", "vesnet_treecode_default_depth",
     "vesnet_treecode_workspace_bytes", "vesnet_farfield_treecode", "vesnet_fmm_default_depth", "vesnet_fmm_workspace_bytes",
-    "vesnet_farfield_fmm",
+    "vesnet_farfield_fmm", "vesnet_fmm_nearmasked_workspace_bytes", "vesnet_farfield_fmm_nearmasked",
 )
 
 
@@ -94,6 +94,8 @@ def lib():
         "vesnet_fmm_default_depth": ([I32, I32], I32),
         "vesnet_fmm_workspace_bytes": ([I32, I32, I32], SZ),
         "vesnet_farfield_fmm": ([P, P, P, P, I32, I32, D, I32, I32, P, P, SZ, P], INT),
+        "vesnet_fmm_nearmasked_workspace_bytes": ([I32, I32, I32, I32], SZ),
+        "vesnet_farfield_fmm_nearmasked": ([P, P, P, P, I32, I32, D, I32, I32, P, P, I32, P, P, SZ, P], INT),
         "vesnet_autotune": ([P, P, P, P, P, I32, I32, INT, P, I32, P, D, P, INT, INT, P, SZ, P, CFG,
                              ctypes.POINTER(ctypes.c_float)], INT),
     }

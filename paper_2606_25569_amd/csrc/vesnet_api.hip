@@ -462,6 +462,50 @@ extern "C" int vesnet_farfield_fmm(const double* X, const double* f, const doubl
   return ok();
 }
 
+extern "C" size_t vesnet_fmm_nearmasked_workspace_bytes(int32_t P, int32_t M, int32_t depth, int32_t order) {
+  if (P < 0 || P > kMaxPoints || M < 0 || depth < 0 || depth > kTreeMaxDepth || order < 1 || order > kTreeMaxOrder)
+    return 0;
+  return fmm_near_workspace_bytes(P, M > 0 ? M : 1, depth, order);
+}
+
+extern "C" int vesnet_farfield_fmm_nearmasked(const double* X, const double* f, const double* w, const int32_t* off,
+                                              int32_t M, int32_t P, double mu, int32_t order, int32_t depth,
+                                              double* out, int32_t* near_pairs, int32_t near_capacity,
+                                              int32_t* near_count, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_sizes(P, M);
+  if (rc) return rc;
+  if ((rc = check_mu(mu))) return rc;
+  if (order < 1 || order > kTreeMaxOrder)
+    return fail(VESNET_ERR_UNSUPPORTED, "order = %d outside 1..%d", order, kTreeMaxOrder);
+  if (depth < 0 || depth > kTreeMaxDepth)
+    return fail(VESNET_ERR_UNSUPPORTED, "depth = %d outside 0..%d", depth, kTreeMaxDepth);
+  if (!near_count) return fail(VESNET_ERR_INVALID_ARGUMENT, "near_count is NULL");
+  if (near_capacity < 0) return fail(VESNET_ERR_INVALID_ARGUMENT, "near_capacity = %d < 0", near_capacity);
+  if (near_capacity > 0 && !near_pairs)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "near_pairs is NULL but near_capacity = %d", near_capacity);
+  if (P == 0) {
+    hipError_t e = launch_zero_count(near_count, stream);
+    return e == hipSuccess ? ok() : hip_fail(e, "near count clear");
+  }
+  if (!X || !f || !w || !off || !out) return fail(VESNET_ERR_INVALID_ARGUMENT, "a required pointer is NULL");
+  if ((rc = check_workspace(ws, ws_bytes, fmm_near_workspace_bytes(P, M, depth, order)))) return rc;
+  const size_t vb = (size_t)2 * P * sizeof(double);
+  const size_t pb = (size_t)2 * near_capacity * sizeof(int32_t);
+  if (overlaps(out, vb, X, vb) || overlaps(out, vb, f, vb) || overlaps(out, vb, w, (size_t)P * sizeof(double)) ||
+      overlaps(out, vb, off, (size_t)(M + 1) * sizeof(int32_t)) || overlaps(out, vb, ws, ws_bytes) ||
+      overlaps(ws, ws_bytes, X, vb) || overlaps(ws, ws_bytes, f, vb) || overlaps(ws, ws_bytes, w, (size_t)P * sizeof(double)))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "out or workspace overlap another array");
+  if (overlaps(near_pairs, pb, out, vb) || overlaps(near_pairs, pb, ws, ws_bytes) ||
+      overlaps(near_count, sizeof(int32_t), out, vb) || overlaps(near_count, sizeof(int32_t), ws, ws_bytes) ||
+      overlaps(near_count, sizeof(int32_t), near_pairs, pb) || overlaps(near_pairs, pb, X, vb) ||
+      overlaps(near_pairs, pb, f, vb))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "near-field outputs overlap other arrays");
+  hipError_t e = launch_fmm_nearmasked(X, f, w, off, M, P, 1.0 / (4.0 * kPi * mu), order, depth, out, near_pairs,
+                                       near_capacity, near_count, ws, stream);
+  if (e != hipSuccess) return hip_fail(e, "fast multipole near-masked launch");
+  return ok();
+}
+
 // ============================================================================ near-field masked
 
 extern "C" int vesnet_farfield_stokeslet_nearmasked(const double* targets, const double* sources, const double* f,

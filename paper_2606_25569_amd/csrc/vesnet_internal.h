@@ -67,6 +67,13 @@ hipError_t launch_treecode(const double* X, const double* f, const double* w, co
 size_t fmm_workspace_bytes(int P, int depth, int p);
 hipError_t launch_fmm(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
                       double scale, int p, int depth, double* out, void* ws, void* stream);
+// Sets a device int32 to zero with a kernel (so that callers may capture it in a graph).
+hipError_t launch_zero_count(int32_t* count, void* stream);
+// The same with near-field masking of Algorithm 4 and the near-pair list.
+size_t fmm_near_workspace_bytes(int P, int M, int depth, int p);
+hipError_t launch_fmm_nearmasked(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
+                                 double scale, int p, int depth, double* out, int32_t* pairs, int capacity,
+                                 int32_t* count, void* ws, void* stream);
 hipError_t launch_plan(const int32_t* sus_off, int S, int M, const PreparedView& pv, int tile, const PlanView& pl,
                        void* stream);
 hipError_t launch_batched(int prec, int T, int B, bool lds, int grid, const double* tg, int P, int M,

@@ -280,10 +280,30 @@ __global__ __launch_bounds__(kTB) void k_tc_leaf(const double* __restrict__ X, i
 }
 
 // Vesicle id of every point: one workgroup per vesicle writes its index over its range (offsets clamped).
-__global__ __launch_bounds__(kTB) void k_tc_vid(const int32_t* __restrict__ off, int P, int32_t* __restrict__ vid) {
+// With h2 given, also the squared near-field radius h_v^2 of every vesicle, h_v = sum_j w_j / N_v (the
+// mean arclength spacing, summed in a fixed order), and bit 1 of *flag when h_v exceeds the leaf width
+// (then a point within h_v of a target may lie outside its 3 x 3 leaves).
+__global__ __launch_bounds__(kTB) void k_tc_vid(const int32_t* __restrict__ off, int P, int32_t* __restrict__ vid,
+                                                const double* __restrict__ w, const Geom* __restrict__ geom,
+                                                int depth, double* __restrict__ h2, int32_t* __restrict__ flag) {
   const int v = blockIdx.x;
   const int v0 = clamp_i(off[v], 0, P), v1 = max(v0, clamp_i(off[v + 1], 0, P));
   for (int j = v0 + (int)threadIdx.x; j < v1; j += kTB) vid[j] = v;
+  if (h2 == nullptr) return;
+  __shared__ double red[kTB];
+  double a = 0.0;
+  for (int j = v0 + (int)threadIdx.x; j < v1; j += kTB) a += w[j];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = kTB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double h = v1 > v0 ? red[0] / (double)(v1 - v0) : 0.0;
+    h2[v] = h * h;
+    if (h > geom->side / (double)(1 << depth)) atomicOr(flag, 2);
+  }
 }
 
 // Exclusive scans of the leaf occupancies (starts) and of their chunks of 2^cshift targets (wave starts).
@@ -1169,17 +1189,138 @@ __global__ __launch_bounds__(kOwnThreads) void k_tc_own(const double* __restrict
   }
 }
 
+// Near-field masking of Algorithm 4 on the fast multipole result: vesicle v (not the target's own) is near
+// target i when min_j |x_i - x_j| <= h_v (the rule of the direct masked sum, decided here in FP64 on
+// squared distances).  With every h_v at most the leaf width, all such points lie in the 3 x 3 leaves around
+// the target's leaf, which one wavefront per (leaf, chunk of 32 targets) scans with the sources staged in
+// LDS; each lane keeps the distinct near vesicles of its target (at most kNearMax, else bit 0 of *flag).
+// The lane then takes them in ascending order, stores each pair (i, v) at the next slot of the list, and
+// subtracts v's exact direct sum at x_i from out[i]: the FMM had included v through the direct part or the
+// expansions, and the difference leaves the masked far field with the FMM's truncation error.
+constexpr int kNearMax = 16;
+
+__global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, const double* __restrict__ f,
+                                                const double* __restrict__ w, int P, int M,
+                                                const int32_t* __restrict__ off,
+                                                const int32_t* __restrict__ vid, const int32_t* __restrict__ perm,
+                                                const int32_t* __restrict__ starts,
+                                                const int32_t* __restrict__ wstart, int depth,
+                                                const double* __restrict__ h2, double scale, double* __restrict__ out,
+                                                int32_t* __restrict__ pairs, int capacity, int32_t* __restrict__ count,
+                                                int32_t* __restrict__ flag) {
+  constexpr int kChunk = 1 << eval_chunk_shift<true>();
+  __shared__ double sx_[64], sy_[64], sh[64];
+  __shared__ int32_t sv[64];
+  __shared__ double2 ltab[kLogTab];
+  const int n = 1 << depth;
+  const int nleaf = n * n;
+  const int item = blockIdx.x;
+  if (item >= wstart[nleaf]) return;
+  int lo = 0, hi = nleaf;  // wstart[lo] <= item < wstart[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (wstart[mid] <= item) lo = mid; else hi = mid;
+  }
+  const int leaf = lo;
+  const int lane = threadIdx.x;
+  ltab[lane] = log_tab_entry(lane);  // read after the barriers below
+  const int s0 = starts[leaf], s1 = starts[leaf + 1];
+  const int slot = s0 + (item - wstart[leaf]) * kChunk + lane;
+  const bool active = lane < kChunk && slot < s1;
+  const int i = active ? perm[slot] : perm[s0];
+  const double zx = X[i], zy = X[P + i];
+  const int vi = clamp_i(vid[i], 0, M - 1);
+  const int ix = leaf / n, iy = leaf % n;
+  int nv[kNearMax];
+  int nn = 0;
+  bool over = false;
+  for (int jx = max(ix - 1, 0); jx <= min(ix + 1, n - 1); ++jx)
+    for (int jy = max(iy - 1, 0); jy <= min(iy + 1, n - 1); ++jy) {
+      const int nl = jx * n + jy;
+      const int e0 = starts[nl], e1 = starts[nl + 1];
+      for (int c0 = e0; c0 < e1; c0 += 64) {
+        const int cnt = min(64, e1 - c0);
+        __syncthreads();  // the previous chunk is done
+        if (lane < cnt) {
+          const int j = perm[c0 + lane];
+          const int vj = clamp_i(vid[j], 0, M - 1);  // ids index the per-vesicle arrays: never trusted
+          sx_[lane] = X[j];
+          sy_[lane] = X[P + j];
+          sv[lane] = vj;
+          sh[lane] = h2[vj];
+        }
+        __syncthreads();
+        if (!active) continue;
+        for (int q = 0; q < cnt; ++q) {
+          const int vq = sv[q];
+          if (vq == vi) continue;
+          const double rx = zx - sx_[q], ry = zy - sy_[q];
+          if (rx * rx + ry * ry > sh[q]) continue;
+          bool seen = false;
+#pragma unroll
+          for (int k = 0; k < kNearMax; ++k) seen |= k < nn && nv[k] == vq;
+          if (seen) continue;
+          if (nn == kNearMax) {
+            over = true;
+            continue;
+          }
+#pragma unroll
+          for (int k = 0; k < kNearMax; ++k)
+            if (k == nn) nv[k] = vq;
+          ++nn;
+        }
+      }
+    }
+  if (!active) return;
+  if (over) atomicOr(flag, 1);
+  // ascending vesicle order: the subtraction order, and so the result, does not depend on the scan
+#pragma unroll
+  for (int a = 1; a < kNearMax; ++a)
+#pragma unroll
+    for (int b = kNearMax - 1; b >= a; --b)
+      if (b < nn && nv[b - 1] > nv[b]) {
+        const int t = nv[b - 1];
+        nv[b - 1] = nv[b];
+        nv[b] = t;
+      }
+  double ux = 0.0, uy = 0.0;
+#pragma unroll
+  for (int k = 0; k < kNearMax; ++k) {
+    if (k >= nn) break;
+    const int v = nv[k];
+    const int slotp = atomicAdd(count, 1);
+    if (slotp < capacity) {
+      pairs[2 * slotp] = i;
+      pairs[2 * slotp + 1] = v;
+    }
+    const int v0 = clamp_i(off[v], 0, P), v1 = max(v0, clamp_i(off[v + 1], 0, P));
+    for (int j = v0; j < v1; ++j) direct_term(zx, zy, X[j], X[P + j], w[j] * f[j], w[j] * f[P + j], ltab, ux, uy);
+  }
+  if (nn > 0) {
+    out[i] -= ux * scale;
+    out[P + i] -= uy * scale;
+  }
+}
+
+// The list's status: a negative count when the masking could not be completed (see k_fmm_near and k_tc_vid).
+__global__ __launch_bounds__(64) void k_fmm_near_status(const int32_t* __restrict__ flag, int32_t* __restrict__ count) {
+  if (threadIdx.x != 0) return;
+  const int32_t fl = *flag;
+  if (fl & 2) *count = -2;
+  else if (fl & 1) *count = -1;
+}
+
 }  // namespace
 
 // Workspace layout shared by the size queries and the launchers; the fast multipole method adds the
 // local expansions (3 rows per box) and the binomial table.
 struct TreeLayout {
-  size_t geom, part, leafid, vid, perm, counts, cursor, starts, wstart, bcount, mom, loc, tab, total;
+  size_t geom, part, leafid, vid, perm, counts, cursor, starts, wstart, bcount, mom, loc, tab, h2, flag, total;
 };
 
 static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
-static TreeLayout tree_layout(int P, int depth, int p, bool fmm) {
+static TreeLayout tree_layout(int P, int depth, int p, bool fmm, int near_M = 0) {
   TreeLayout t;
   const size_t nleaf = (size_t)1 << (2 * depth);
   size_t boxes = 0;
@@ -1203,12 +1344,19 @@ static TreeLayout tree_layout(int P, int depth, int p, bool fmm) {
     t.loc = o;      o += align_up(sizeof(double2) * (boxes * 3 * (size_t)(p + 1) + 192));  // 192 spare: as above
     t.tab = o;      o += align_up(sizeof(double) * (size_t)kTabM * kTabL);
   }
+  t.h2 = o;
+  t.flag = o;
+  if (near_M > 0) {  // near-field masking: h_v^2 of every vesicle and a status word
+    t.h2 = o;       o += align_up(sizeof(double) * (size_t)near_M);
+    t.flag = o;     o += align_up(sizeof(int32_t));
+  }
   t.total = o;
   return t;
 }
 
 size_t treecode_workspace_bytes(int P, int depth, int p) { return tree_layout(P, depth, p, false).total; }
 size_t fmm_workspace_bytes(int P, int depth, int p) { return tree_layout(P, depth, p, true).total; }
+size_t fmm_near_workspace_bytes(int P, int M, int depth, int p) { return tree_layout(P, depth, p, true, M).total; }
 
 namespace {
 
@@ -1218,6 +1366,8 @@ struct TreeRun {
   int32_t *leafid, *vid, *perm, *counts, *cursor, *starts, *wstart, *bcount;
   double2 *mom, *loc;
   double* tab;
+  double* h2;
+  int32_t* flag;
   Levels lv;       // first box and first moment entry of every level
   size_t nbox;     // boxes of levels 2..depth
 };
@@ -1238,6 +1388,8 @@ TreeRun tree_run(void* ws, const TreeLayout& t, int depth, int p) {
   r.mom = reinterpret_cast<double2*>(base + t.mom);
   r.loc = reinterpret_cast<double2*>(base + t.loc);
   r.tab = reinterpret_cast<double*>(base + t.tab);
+  r.h2 = reinterpret_cast<double*>(base + t.h2);
+  r.flag = reinterpret_cast<int32_t*>(base + t.flag);
   r.lv = {};
   size_t acc = 0;
   for (int l = 2; l <= depth; ++l) {  // boxes of level l start at box index sum_{m = 2}^{l-1} 4^m
@@ -1252,7 +1404,7 @@ TreeRun tree_run(void* ws, const TreeLayout& t, int depth, int p) {
 // Tree over the points (root square, leaves, leaf order) and the moments of every box of levels
 // 2..depth (leaves from the points, coarser levels by translation).
 void launch_upward(const double* X, const double* f, const double* w, const int32_t* off, int M, int P, int p,
-                   int depth, int cshift, bool binomials, const TreeRun& r, hipStream_t st) {
+                   int depth, int cshift, bool binomials, bool near, const TreeRun& r, hipStream_t st) {
   const int nleaf = 1 << (2 * depth);
   const int pb = (P + kTB - 1) / kTB < 4096 ? (P + kTB - 1) / kTB : 4096;
   const int bb = (P + kTB - 1) / kTB < kBBoxBlocks ? (P + kTB - 1) / kTB : kBBoxBlocks;
@@ -1261,7 +1413,8 @@ void launch_upward(const double* X, const double* f, const double* w, const int3
   const int zb = (nleaf + kTB - 1) / kTB < 4096 ? (nleaf + kTB - 1) / kTB : 4096;
   hipLaunchKernelGGL(k_tc_zero, dim3(zb), dim3(kTB), 0, st, r.counts, r.cursor, nleaf);
   hipLaunchKernelGGL(k_tc_leaf, dim3(pb), dim3(kTB), 0, st, X, P, r.geom, depth, r.leafid, r.counts);
-  hipLaunchKernelGGL(k_tc_vid, dim3(M), dim3(kTB), 0, st, off, P, r.vid);
+  hipLaunchKernelGGL(k_tc_vid, dim3(M), dim3(kTB), 0, st, off, P, r.vid, w, r.geom, depth, near ? r.h2 : nullptr,
+                     r.flag);
   hipLaunchKernelGGL(k_tc_scan, dim3(1), dim3(1024), 0, st, r.counts, nleaf, r.starts, r.wstart, cshift);
   hipLaunchKernelGGL(k_tc_scatter, dim3(pb), dim3(kTB), 0, st, r.leafid, P, r.starts, r.cursor, r.perm);
   hipLaunchKernelGGL(k_tc_sort, dim3(nleaf), dim3(64), 0, st, r.starts, r.perm);
@@ -1298,7 +1451,7 @@ hipError_t launch_treecode(const double* X, const double* f, const double* w, co
   if (depth < 0 || depth > kMaxDepth || p < 1 || p > kMaxOrder) return hipErrorInvalidValue;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const TreeRun r = tree_run(ws, tree_layout(P, depth, p, false), depth, p);
-  launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<false>(), false, r, st);
+  launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<false>(), false, false, r, st);
   if (depth >= 2) {
     const size_t work = r.nbox * (p + 1);
     const int gb = (int)((work + kTB - 1) / kTB < 4096 ? (work + kTB - 1) / kTB : 4096);
@@ -1308,13 +1461,12 @@ hipError_t launch_treecode(const double* X, const double* f, const double* w, co
   return hipGetLastError();
 }
 
-hipError_t launch_fmm(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
-                      double scale, int p, int depth, double* out, void* ws, void* stream) {
-  if (P == 0) return hipSuccess;
-  if (depth < 0 || depth > kMaxDepth || p < 1 || p > kMaxOrder) return hipErrorInvalidValue;
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const TreeRun r = tree_run(ws, tree_layout(P, depth, p, true), depth, p);
-  launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<true>(), depth >= 2, r, st);
+static hipError_t run_fmm(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
+                          double scale, int p, int depth, double* out, void* ws, hipStream_t st, bool near,
+                          int32_t* pairs, int capacity, int32_t* count) {
+  const TreeRun r = tree_run(ws, tree_layout(P, depth, p, true, near ? M : 0), depth, p);
+  if (near) hipLaunchKernelGGL(k_tc_zero, dim3(1), dim3(kTB), 0, st, count, r.flag, 1);
+  launch_upward(X, f, w, off, M, P, p, depth, eval_chunk_shift<true>(), depth >= 2, near, r, st);
   if (depth >= 2) {
     const dim3 g((unsigned)r.nbox), bl(64);
     const size_t lds = m2l_lds_bytes(p);
@@ -1331,7 +1483,37 @@ hipError_t launch_fmm(const double* X, const double* f, const double* w, const i
     }
   }
   launch_eval<true>(X, f, w, off, M, P, p, depth, scale, r, out, st);
+  if (near) {
+    constexpr int kChunk = 1 << eval_chunk_shift<true>();
+    const int nleaf = 1 << (2 * depth);
+    const int items = nleaf + (P + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_fmm_near, dim3(items), dim3(64), 0, st, X, f, w, P, M, off, r.vid, r.perm, r.starts, r.wstart,
+                       depth, r.h2, scale, out, pairs, capacity, count, r.flag);
+    hipLaunchKernelGGL(k_fmm_near_status, dim3(1), dim3(64), 0, st, r.flag, count);
+  }
   return hipGetLastError();
+}
+
+hipError_t launch_fmm(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
+                      double scale, int p, int depth, double* out, void* ws, void* stream) {
+  if (P == 0) return hipSuccess;
+  if (depth < 0 || depth > kMaxDepth || p < 1 || p > kMaxOrder) return hipErrorInvalidValue;
+  return run_fmm(X, f, w, off, M, P, scale, p, depth, out, ws, reinterpret_cast<hipStream_t>(stream), false, nullptr,
+                 0, nullptr);
+}
+
+hipError_t launch_zero_count(int32_t* count, void* stream) {
+  hipLaunchKernelGGL(k_tc_zero, dim3(1), dim3(kTB), 0, reinterpret_cast<hipStream_t>(stream), count, count, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_fmm_nearmasked(const double* X, const double* f, const double* w, const int32_t* off, int M, int P,
+                                 double scale, int p, int depth, double* out, int32_t* pairs, int capacity,
+                                 int32_t* count, void* ws, void* stream) {
+  if (P == 0) return hipSuccess;
+  if (depth < 0 || depth > kMaxDepth || p < 1 || p > kMaxOrder) return hipErrorInvalidValue;
+  return run_fmm(X, f, w, off, M, P, scale, p, depth, out, ws, reinterpret_cast<hipStream_t>(stream), true, pairs,
+                 capacity, count);
 }
 
 }  // namespace vesnet

@@ -206,6 +206,40 @@ def farfield_fmm(X, force_density, arc_weights, partition, mu, order=30, depth=N
     return out
 
 
+def farfield_fmm_nearmasked(X, force_density, arc_weights, partition, mu, order=30, depth=None, capacity=None):
+    """Fast multipole far field with the near-field masking of Algorithm 4, and the near pairs.
+
+    Returns (out (2, P), pairs (n, 2) int32 device tensor of (target, vesicle), unordered).  The
+    list is re-run with a larger capacity when the first pass overflows (one host
+    synchronisation).  Raises when the masking could not be completed (a target with more than 16
+    near vesicles, or a spacing h_v above the leaf width: pass a smaller depth)."""
+    part = as_partition(partition)
+    P, M = part.n_points, part.n_vesicles
+    _check_vec("X", X, P)
+    _check_vec("force_density", force_density, P)
+    _check_w(arc_weights, P)
+    lib = L.lib()
+    depth = int(lib.vesnet_fmm_default_depth(P, int(order))) if depth is None else int(depth)
+    dev = X.device
+    out = torch.empty((2, P), dtype=torch.float64, device=dev)
+    cap = int(capacity) if capacity is not None else max(1024, 4 * P)
+    ws = _workspace(lib.vesnet_fmm_nearmasked_workspace_bytes(P, M, depth, int(order)), dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    while True:
+        pairs = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        L.check(lib.vesnet_farfield_fmm_nearmasked(_ptr(X), _ptr(force_density), _ptr(arc_weights), _ptr(part.device),
+                                                   M, P, float(mu), int(order), depth, _ptr(out), _ptr(pairs), cap,
+                                                   _ptr(count), _ptr(ws), ws.numel(), _stream()))
+        n = int(count.item())
+        if n == -1:
+            raise L.VesnetError(L.ERR_UNSUPPORTED, "a target has more than 16 near vesicles")
+        if n == -2:
+            raise L.VesnetError(L.ERR_UNSUPPORTED, f"a vesicle's arclength spacing exceeds the leaf width at depth {depth}")
+        if n <= cap:
+            return out, pairs[:n]
+        cap = n
+
+
 def near_layers(X, arc_weights, partition):
     """CreateNearLayers (Section 3.3): the five layers of every vesicle, membrane points moved along
     the outward normal by (-h, -h/2, 0, h/2, h) h_v; returns (2, 5P) with vesicle v's 5 N_v nodes at

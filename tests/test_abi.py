@@ -24,7 +24,7 @@ def _declared():
 def test_every_declared_symbol_is_exported(L):
     lib = L.lib()
     names = _declared()
-    assert len(names) == 28, names
+    assert len(names) == 30, names
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(L.EXPORTED)
@@ -245,6 +245,27 @@ def test_tree_methods_reject(L, method):
     assert call(out=_p(FAKE + 8)) == -1                      # out overlaps the points
     assert call(ws=_p(FAKE + 0x400000 + 64)) == -1           # workspace overlaps out
     assert run(None, None, None, None, 0, 0, 1.0, 8, 3, None, None, 0, None) == 0  # empty: no-op
+
+
+def test_fmm_nearmasked_rejects(L):
+    lib = L.lib()
+    wsq = lib.vesnet_fmm_nearmasked_workspace_bytes
+    assert wsq(100, 4, 3, 0) == 0 and wsq(100, 4, 11, 8) == 0 and wsq(-1, 4, 3, 8) == 0
+    need = wsq(100, 4, 3, 8)
+    assert need > lib.vesnet_fmm_workspace_bytes(100, 3, 8)  # plus h_v^2 and a status word
+    X, f, w, off = _p(FAKE), _p(FAKE + 0x100000), _p(FAKE + 0x200000), _p(FAKE + 0x300000)
+    out, ws = _p(FAKE + 0x400000), _p(FAKE + 0x1000000)
+    pairs, cnt = _p(FAKE + 0x2000000), _p(FAKE + 0x2100000)
+    call = lambda **k: lib.vesnet_farfield_fmm_nearmasked(X, f, w, off, 4, 100, 1.0, k.get("order", 8), 3,
+                                                          k.get("out", out), k.get("pairs", pairs), k.get("cap", 16),
+                                                          k.get("cnt", cnt), ws, k.get("wsb", need), None)
+    assert call(order=49) == -2
+    assert call(cnt=None) == -1
+    assert call(cap=-1) == -1
+    assert call(pairs=None) == -1
+    assert call(wsb=need - 1) == -3
+    assert call(pairs=_p(FAKE + 0x400000 + 16)) == -1  # the list overlaps out
+    assert call(cnt=_p(FAKE + 0x2000000 + 8)) == -1    # the count overlaps the list
 
 
 def test_product_package_has_no_cpu_fallback():

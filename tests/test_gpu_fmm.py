@@ -137,3 +137,73 @@ def test_fmm_deterministic_and_graph_replay(susp):
         torch.cuda.synchronize()
         assert torch.equal(out, eager), k
     say("fmm: deterministic, 3 graph replays equal the eager call")
+
+
+def _fmm_masked_ref(s, order, depth):
+    """Fast-multipole oracle minus the near vesicles' exact sums (the plain direct oracle minus the masked one)."""
+    plain = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    masked, pairs = O.nearmasked_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    return FM.fmm(s.X, s.f, s.w, s.offsets, s.mu, order, depth) - (plain - masked), pairs
+
+
+@pytest.mark.parametrize("depth,order", [(0, 8), (2, 12), (3, 20), (4, 30)])
+def test_fmm_nearmasked_parity(depth, order):
+    """Dense suspension at gap 0.02 (every distance at least 1e-5 relative away from the spacing): the near
+    pairs equal the oracle's exactly, and the masked field equals the fast-multipole oracle minus the near
+    vesicles' exact sums within 1e-12 of max|u|."""
+    import torch
+    import paper_2606_25569_amd as V
+    from tests.gpu_util import near_margin
+    s = S.rsa_suspension(33, 120, 32, 0.40, gap=0.02)
+    assert near_margin(s) > 1e-5
+    ref, pairs_ref = _fmm_masked_ref(s, order, depth)
+    assert pairs_ref.shape[0] > 20
+    X, f, w = dev_inputs(s)
+    out, pairs = V.farfield_fmm_nearmasked(X, f, w, s.offsets, s.mu, order, depth)
+    torch.cuda.synchronize()
+    got = {tuple(p) for p in pairs.cpu().numpy().tolist()}
+    err, _ = rel_err(out.cpu().numpy(), ref)
+    say(f"fmm nearmasked depth={depth} order={order}: err vs oracle {err:.2e}, {len(got)} near pairs")
+    assert got == {tuple(p) for p in pairs_ref.tolist()}
+    assert len(got) == pairs.shape[0]  # no pair twice
+    assert err <= 1e-12
+
+
+def test_fmm_nearmasked_small_list_and_determinism():
+    """A list smaller than the pairs reports the full count and still masks completely: out equals the
+    full-list call bit for bit, and repeated calls agree bit for bit."""
+    import torch
+    import paper_2606_25569_amd as V
+    from paper_2606_25569_amd import _lib as L
+    s = S.rsa_suspension(34, 60, 32, 0.40, gap=0.02)
+    X, f, w = dev_inputs(s)
+    part = V.Partition(s.offsets, "cuda")
+    full, pairs = V.farfield_fmm_nearmasked(X, f, w, part, s.mu, 16, 3)
+    again, _ = V.farfield_fmm_nearmasked(X, f, w, part, s.mu, 16, 3)
+    assert torch.equal(full, again)
+    lib = L.lib()
+    P, M = s.n_points, len(s.offsets) - 1
+    ws = torch.empty(lib.vesnet_fmm_nearmasked_workspace_bytes(P, M, 3, 16), dtype=torch.uint8, device="cuda")
+    out = torch.empty((2, P), dtype=torch.float64, device="cuda")
+    small = torch.empty((3, 2), dtype=torch.int32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int32, device="cuda")
+    L.check(lib.vesnet_farfield_fmm_nearmasked(X.data_ptr(), f.data_ptr(), w.data_ptr(), part.device.data_ptr(), M, P,
+                                               float(s.mu), 16, 3, out.data_ptr(), small.data_ptr(), 3,
+                                               count.data_ptr(), ws.data_ptr(), ws.numel(),
+                                               torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert int(count.item()) == pairs.shape[0] > 3
+    assert torch.equal(out, full)
+
+
+def test_fmm_nearmasked_spacing_above_leaf_width_is_reported():
+    """At depth 8 over 60 vesicles the leaves (about 0.06 wide) are narrower than the spacing (0.2): the
+    count is -2 and the binding raises."""
+    import torch
+    import paper_2606_25569_amd as V
+    from paper_2606_25569_amd import _lib as L
+    s = S.rsa_suspension(34, 60, 32, 0.40, gap=0.02)
+    X, f, w = dev_inputs(s)
+    with pytest.raises(L.VesnetError, match="leaf width"):
+        V.farfield_fmm_nearmasked(X, f, w, s.offsets, s.mu, 8, 8)
+    torch.cuda.synchronize()
