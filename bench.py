@@ -403,9 +403,37 @@ def bench_nearfield(args):
         fit()
         ev()
 
+    # the same step with the masked far field by the fast multipole method (FP64, order 30)
+    order = 30
+    depth = lib.vesnet_fmm_default_depth(P, order)
+    fws = torch.empty(lib.vesnet_fmm_nearmasked_workspace_bytes(P, M, depth, order), dtype=torch.uint8, device=dev)
+    out_f = torch.empty_like(out)
+    pairs_f = torch.empty_like(pairs)
+    count_f = torch.zeros_like(count)
+
+    def far_fmm():
+        L.check(lib.vesnet_farfield_fmm_nearmasked(_ptr(X), _ptr(f), _ptr(w), _ptr(part.device), M, P, s.mu, order,
+                                                   depth, _ptr(out_f), _ptr(pairs_f), cap, _ptr(count_f), _ptr(fws),
+                                                   fws.numel(), sp))
+
+    def ev_fmm():
+        L.check(lib.vesnet_rbf_eval_near(_ptr(layers), _ptr(coeffs), _ptr(w), _ptr(part.device), M, P, width, _ptr(X),
+                                         P, _ptr(pairs_f), _ptr(count_f), cap, _ptr(out_f), sp))
+
+    def step_fmm():
+        far_fmm()
+        lay()
+        fit()
+        ev_fmm()
+
+    far_fmm()
+    torch.cuda.synchronize()
+    assert int(count_f.item()) == n_near, (int(count_f.item()), n_near)
+    fmm_diff = float((out_f - out).abs().max() / out.abs().max())  # both masked, before interpolation
     log(f"[bench] nearfield 2000x32: P={P}, {n_near} near pairs ({time.time() - t0:.1f}s)")
     times = {k: _time(fn, args.steps, stream) for k, fn in
-             (("far_masked", far), ("layers", lay), ("rbf_fit", fit), ("rbf_eval", ev), ("step", step))}
+             (("far_masked", far), ("layers", lay), ("rbf_fit", fit), ("rbf_eval", ev), ("step", step),
+              ("far_masked_fmm", far_fmm), ("step_fmm", step_fmm))}
     n = 5 * N
     fit_flops = M * (n ** 3 / 3 + 4 * n * n)  # Cholesky and two triangular solves of two right-hand sides
     pairs_far = s.cross_pairs()
@@ -420,13 +448,15 @@ def bench_nearfield(args):
         NR.vesicle_fit(lay_h[:, a:b], vel_h[:, a:b], width * s.w[s.offsets[v]:s.offsets[v + 1]].mean())
     cpu_fit_vps = sample / (time.time() - tc)
     rec = {"workload": "near field: 2000 vesicles x 32 points at 30% area fraction (gap >= 0.1 < h), "
-                       "FP32-compensated masked far field + FP64 layers, RBF fit (width h) and interpolation",
+                       "FP32-compensated masked far field + FP64 layers, RBF fit (width h) and interpolation; "
+                       f"step_fmm: the masked far field by the fast multipole method (FP64, order {order}, depth {depth})",
            "n_points": P, "near_pairs": n_near, "ms": times,
            "far_masked_pairs_per_s": pairs_far / (times["far_masked"] * 1e-3),
            "rbf_fit": {"vesicles_per_s": M / (times["rbf_fit"] * 1e-3), "algorithmic_tflops_fp64": fit_flops / (times["rbf_fit"] * 1e-3) / 1e12,
                        "frac_of_fp64_peak": fit_flops / (times["rbf_fit"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
                        "oracle_numpy_vesicles_per_s": cpu_fit_vps},
-           "rbf_eval_pairs_per_s": n_near / (times["rbf_eval"] * 1e-3)}
+           "rbf_eval_pairs_per_s": n_near / (times["rbf_eval"] * 1e-3),
+           "far_masked_fmm_vs_direct_rel_diff": fmm_diff}
     log(f"[bench] nearfield: " + ", ".join(f"{k} {v:.3f} ms" for k, v in times.items()))
     print(json.dumps(rec), flush=True)
 

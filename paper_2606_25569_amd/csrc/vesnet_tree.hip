@@ -1192,12 +1192,29 @@ __global__ __launch_bounds__(kOwnThreads) void k_tc_own(const double* __restrict
 // Near-field masking of Algorithm 4 on the fast multipole result: vesicle v (not the target's own) is near
 // target i when min_j |x_i - x_j| <= h_v (the rule of the direct masked sum, decided here in FP64 on
 // squared distances).  With every h_v at most the leaf width, all such points lie in the 3 x 3 leaves around
-// the target's leaf, which one wavefront per (leaf, chunk of 32 targets) scans with the sources staged in
-// LDS; each lane keeps the distinct near vesicles of its target (at most kNearMax, else bit 0 of *flag).
-// The lane then takes them in ascending order, stores each pair (i, v) at the next slot of the list, and
-// subtracts v's exact direct sum at x_i from out[i]: the FMM had included v through the direct part or the
-// expansions, and the difference leaves the masked far field with the FMM's truncation error.
+// the target's leaf.  One wavefront per (leaf, chunk of 32 targets) stages those leaves' points in LDS; lanes
+// t and t + 32 scan alternate points for target t, each keeping the distinct near vesicles it meets (at most
+// kNearMax, else bit 0 of *flag), and lane t merges the two sets and sorts them ascending.  One atomic per
+// wavefront reserves the pair slots.  The whole wavefront then takes the near vesicles of each target in
+// turn, 64 points at a time, and subtracts their exact direct sum at x_i from out[i]: the FMM had included v
+// through the direct part or the expansions, and the difference leaves the masked far field with the FMM's
+// truncation error.  The lane partials are combined by a butterfly, so the result is deterministic.
 constexpr int kNearMax = 16;
+
+__device__ __forceinline__ void near_insert(int (&nv)[kNearMax], int& nn, bool& over, int v) {
+  bool seen = false;
+#pragma unroll
+  for (int k = 0; k < kNearMax; ++k) seen |= k < nn && nv[k] == v;
+  if (seen) return;
+  if (nn == kNearMax) {
+    over = true;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < kNearMax; ++k)
+    if (k == nn) nv[k] = v;
+  ++nn;
+}
 
 __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, const double* __restrict__ f,
                                                 const double* __restrict__ w, int P, int M,
@@ -1209,9 +1226,12 @@ __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, c
                                                 int32_t* __restrict__ pairs, int capacity, int32_t* __restrict__ count,
                                                 int32_t* __restrict__ flag) {
   constexpr int kChunk = 1 << eval_chunk_shift<true>();
+  static_assert(kChunk == 32, "two lanes per target");
   __shared__ double sx_[64], sy_[64], sh[64];
   __shared__ int32_t sv[64];
   __shared__ double2 ltab[kLogTab];
+  __shared__ int32_t mlist[kChunk][kNearMax + 1];
+  __shared__ int32_t mcount[kChunk];
   const int n = 1 << depth;
   const int nleaf = n * n;
   const int item = blockIdx.x;
@@ -1223,10 +1243,11 @@ __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, c
   }
   const int leaf = lo;
   const int lane = threadIdx.x;
+  const int t = lane & (kChunk - 1), half = lane >> 5;
   ltab[lane] = log_tab_entry(lane);  // read after the barriers below
   const int s0 = starts[leaf], s1 = starts[leaf + 1];
-  const int slot = s0 + (item - wstart[leaf]) * kChunk + lane;
-  const bool active = lane < kChunk && slot < s1;
+  const int slot = s0 + (item - wstart[leaf]) * kChunk + t;
+  const bool active = slot < s1;
   const int i = active ? perm[slot] : perm[s0];
   const double zx = X[i], zy = X[P + i];
   const int vi = clamp_i(vid[i], 0, M - 1);
@@ -1251,54 +1272,84 @@ __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, c
         }
         __syncthreads();
         if (!active) continue;
-        for (int q = 0; q < cnt; ++q) {
-          const int vq = sv[q];
-          if (vq == vi) continue;
+#pragma unroll 4
+        for (int q = half; q < cnt; q += 2) {
           const double rx = zx - sx_[q], ry = zy - sy_[q];
-          if (rx * rx + ry * ry > sh[q]) continue;
-          bool seen = false;
-#pragma unroll
-          for (int k = 0; k < kNearMax; ++k) seen |= k < nn && nv[k] == vq;
-          if (seen) continue;
-          if (nn == kNearMax) {
-            over = true;
-            continue;
-          }
-#pragma unroll
-          for (int k = 0; k < kNearMax; ++k)
-            if (k == nn) nv[k] = vq;
-          ++nn;
+          const int vq = sv[q];
+          if (!(rx * rx + ry * ry > sh[q]) && vq != vi) near_insert(nv, nn, over, vq);
         }
       }
     }
-  if (!active) return;
-  if (over) atomicOr(flag, 1);
-  // ascending vesicle order: the subtraction order, and so the result, does not depend on the scan
+  // merge the upper half's sets into the lower half's
+  if (half == 1) {
 #pragma unroll
-  for (int a = 1; a < kNearMax; ++a)
-#pragma unroll
-    for (int b = kNearMax - 1; b >= a; --b)
-      if (b < nn && nv[b - 1] > nv[b]) {
-        const int t = nv[b - 1];
-        nv[b - 1] = nv[b];
-        nv[b] = t;
-      }
-  double ux = 0.0, uy = 0.0;
-#pragma unroll
-  for (int k = 0; k < kNearMax; ++k) {
-    if (k >= nn) break;
-    const int v = nv[k];
-    const int slotp = atomicAdd(count, 1);
-    if (slotp < capacity) {
-      pairs[2 * slotp] = i;
-      pairs[2 * slotp + 1] = v;
-    }
-    const int v0 = clamp_i(off[v], 0, P), v1 = max(v0, clamp_i(off[v + 1], 0, P));
-    for (int j = v0; j < v1; ++j) direct_term(zx, zy, X[j], X[P + j], w[j] * f[j], w[j] * f[P + j], ltab, ux, uy);
+    for (int k = 0; k < kNearMax; ++k)
+      if (k < nn) mlist[t][k] = nv[k];
+    mcount[t] = nn;
+    nn = 0;
   }
-  if (nn > 0) {
-    out[i] -= ux * scale;
-    out[P + i] -= uy * scale;
+  __syncthreads();
+  if (half == 0) {
+    const int m = mcount[t];
+    for (int k = 0; k < m; ++k) near_insert(nv, nn, over, mlist[t][k]);
+    // ascending vesicle order: the subtraction order, and so the result, does not depend on the scan
+#pragma unroll
+    for (int a = 1; a < kNearMax; ++a)
+#pragma unroll
+      for (int b = kNearMax - 1; b >= a; --b)
+        if (b < nn && nv[b - 1] > nv[b]) {
+          const int tmp = nv[b - 1];
+          nv[b - 1] = nv[b];
+          nv[b] = tmp;
+        }
+  }
+  if (__ballot(over) != 0 && lane == 0) atomicOr(flag, 1);
+  int incl = nn;  // inclusive prefix of the pair counts over the wavefront (zero in the upper half)
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  const int total = __shfl(incl, 63);
+  if (total == 0) return;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(count, total);
+  base = __shfl(base, 0);
+  if (half == 0) {
+    const int b0 = base + incl - nn;
+#pragma unroll
+    for (int k = 0; k < kNearMax; ++k)
+      if (k < nn) {
+        if (b0 + k < capacity) {
+          pairs[2 * (b0 + k)] = i;
+          pairs[2 * (b0 + k) + 1] = nv[k];
+        }
+        mlist[t][k] = nv[k];
+      }
+    mcount[t] = nn;
+  }
+  __syncthreads();
+  unsigned long long todo = __ballot(half == 0 && nn > 0);
+  while (todo) {
+    const int tt = __ffsll(todo) - 1;
+    todo &= todo - 1;
+    const double tx = __shfl(zx, tt), ty = __shfl(zy, tt);
+    const int it = __shfl(i, tt);
+    const int m = mcount[tt];
+    double ux = 0.0, uy = 0.0;
+    for (int k = 0; k < m; ++k) {
+      const int v = mlist[tt][k];
+      const int v0 = clamp_i(off[v], 0, P), v1 = max(v0, clamp_i(off[v + 1], 0, P));
+      for (int j = v0 + lane; j < v1; j += 64)
+        direct_term(tx, ty, X[j], X[P + j], w[j] * f[j], w[j] * f[P + j], ltab, ux, uy);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      ux += __shfl_xor(ux, o);
+      uy += __shfl_xor(uy, o);
+    }
+    if (lane == 0) {
+      out[it] -= ux * scale;
+      out[P + it] -= uy * scale;
+    }
   }
 }
 
