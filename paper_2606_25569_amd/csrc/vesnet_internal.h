@@ -10,6 +10,14 @@ namespace vesnet {
 
 enum Prec { P64 = 0, P32C = 1, P32N = 2 };
 
+// Orders the LDS accesses of one wavefront around this point (a workgroup of one wavefront needs no
+// s_barrier: its LDS instructions execute in issue order).  Global memory is not ordered by it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Mean arclength spacing h_v = sum_j w_j / n of the n weights w[0..n-1], formed by one
 // whole wavefront (all 64 lanes call it with the same arguments) in a fixed order, so
 // that every kernel that needs h_v gets the same bits.

@@ -181,25 +181,28 @@ __global__ __launch_bounds__(kFW, 2) void k_rbf_fit(const double* __restrict__ l
     nv.npad = nb * kT;
     nv.inv_w2 = 1.0 / ((eps * h) * (eps * h));
 
-    // ---- factorisation, panel by panel; tile row nb holds the right-hand sides
+    // ---- factorisation, panel by panel; tile row nb holds the right-hand sides.  The workgroup is one
+    // wavefront, so LDS needs only wave_sync; a tile stored to the slot is read back in later panels
+    // only, after the panel's closing barrier has waited for the stores.
+    double wreg[kT * kT / kFW];  // W = L_JJ^{-1} of the current panel, element lane + kFW t (row-major)
     for (int J = 0; J < nb; ++J) {
       for (int I = J; I <= nb; ++I) {
         double acc[4][4];
         entry_block(nv, I, J, rg, cg, acc);
         // T = A - sum_{k < J} L(I, k) L(J, k)^T
         for (int k = 0; k < J; ++k) {
-          __syncthreads();  // A and B are free
+          wave_sync();  // A and B are free
           stage_tile(B, slot + tile_index(J, k) * (kT * kT), lane);
           if (I != J) stage_tile(A, slot + tile_index(I, k) * (kT * kT), lane);
-          __syncthreads();
+          wave_sync();
           tile_gemm(acc, I != J ? A : B, B, rg, cg, -1.0);
         }
-        __syncthreads();  // A is free
+        wave_sync();  // A is free
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j) A[(rg * 4 + i) * kLd + cg * 4 + j] = acc[i][j];
-        __syncthreads();
+        wave_sync();
         double* dst = slot + tile_index(I, J) * (kT * kT);
         if (I == J) {
           // Cholesky of the diagonal tile with lane i holding row i in registers (lanes 32..63
@@ -209,6 +212,7 @@ __global__ __launch_bounds__(kFW, 2) void k_rbf_fit(const double* __restrict__ l
           double row[kT];
 #pragma unroll
           for (int c = 0; c < kT; ++c) row[c] = A[i * kLd + c];
+          double rinv = 0.0;  // 1 / L[i][i]
 #pragma unroll
           for (int j = 0; j < kT; ++j) {
             double sj = row[j];
@@ -217,36 +221,44 @@ __global__ __launch_bounds__(kFW, 2) void k_rbf_fit(const double* __restrict__ l
             const double d = sqrt(lane_bcast(sj, j));
             const double di = 1.0 / d;
             row[j] = i > j ? sj * di : (i == j ? d : 0.0);
+            if (i == j) rinv = di;
           }
           if (lane < kT) {
 #pragma unroll
             for (int c = 0; c < kT; ++c) A[i * kLd + c] = row[c];
+            A[i * kLd + kT] = rinv;  // the row's padding entry
           }
-          __syncthreads();
+          wave_sync();
           // W = L^{-1} with lane i holding column i: W[r][i] = (delta_ri - sum_{m<r} L[r][m] W[m][i]) / L[r][r],
-          // L read from LDS (the same address in every lane); W goes to the slot in place of L_JJ
+          // L and 1 / L[r][r] read from LDS (the same address in every lane); W goes to the slot in place
+          // of L_JJ and stays in registers for the tiles below
           double wc[kT];
 #pragma unroll
           for (int r = 0; r < kT; ++r) {
             double t = i == r ? 1.0 : 0.0;
 #pragma unroll
             for (int m = 0; m < r; ++m) t = fma(-A[r * kLd + m], wc[m], t);
-            wc[r] = t / A[r * kLd + r];
+            wc[r] = t * A[r * kLd + kT];
           }
           if (lane < kT) {
 #pragma unroll
             for (int r = 0; r < kT; ++r) B[r * kLd + lane] = wc[r];
           }
-          __syncthreads();
-          for (int e = lane; e < kT * kT; e += kFW) dst[e] = B[(e >> 5) * kLd + (e & 31)];
-          __syncthreads();
-        } else {
-          // L_IJ = T W^T, W staged into B from the slot
-          {
-            const double* wsrc = slot + tile_index(J, J) * (kT * kT);
-            for (int e = lane; e < kT * kT; e += kFW) B[(e >> 5) * kLd + (e & 31)] = wsrc[e];
+          wave_sync();
+#pragma unroll
+          for (int t = 0; t < kT * kT / kFW; ++t) {
+            const int e = lane + kFW * t;
+            wreg[t] = B[(e >> 5) * kLd + (e & 31)];
+            dst[e] = wreg[t];
           }
-          __syncthreads();
+        } else {
+          // L_IJ = T W^T, W written into B from the registers
+#pragma unroll
+          for (int t = 0; t < kT * kT / kFW; ++t) {
+            const int e = lane + kFW * t;
+            B[(e >> 5) * kLd + (e & 31)] = wreg[t];
+          }
+          wave_sync();
           double out[4][4];
 #pragma unroll
           for (int i = 0; i < 4; ++i)
@@ -259,34 +271,49 @@ __global__ __launch_bounds__(kFW, 2) void k_rbf_fit(const double* __restrict__ l
             for (int j = 0; j < 4; ++j) dst[(rg * 4 + i) * kT + cg * 4 + j] = out[i][j];
         }
       }
+      __syncthreads();  // the panel's tiles are stored before later panels read them
     }
-    __syncthreads();
 
-    // ---- back substitution: c_J = W_JJ^T (y_J - sum_{I > J} L_IJ^T c_I); y in rows 0, 1 of tile row nb
+    // ---- back substitution: c_J = W_JJ^T (y_J - sum_{I > J} L_IJ^T c_I); y in rows 0, 1 of tile row nb.
+    // Lane (q, c) takes column c of each tile for right-hand side q, all 32 loads of a tile at once.
+    // The tiles go in the order J = nb-1 .. 0, within J the L_IJ for I = J+1 .. nb-1 and then W_JJ.
     double* cv = pool;                    // [2][npad]
     double* zx = pool + 2 * nv.npad;      // [2][32]
     for (int e = lane; e < 2 * nv.npad; e += kFW) {
       const int q = e / nv.npad, a = e - q * nv.npad;
       cv[e] = slot[tile_index(nb, a >> 5) * (kT * kT) + q * kT + (a & 31)];
     }
-    __syncthreads();
-    const int q = lane >> 5, c = lane & 31;
-    for (int J = nb - 1; J >= 0; --J) {
+    wave_sync();
+    {
+      const int q = lane >> 5, c = lane & 31;
+      int I = nb - 1, J = nb - 1;  // I == J: the tile W_JJ
       double z = cv[q * nv.npad + J * kT + c];
-      for (int I = J + 1; I < nb; ++I) {
-        const double* Lt = slot + tile_index(I, J) * (kT * kT);
-        const double* cI = cv + q * nv.npad + I * kT;
-#pragma unroll 8
-        for (int r = 0; r < kT; ++r) z = fma(-Lt[r * kT + c], cI[r], z);
+      while (true) {
+        double col[kT];
+        {
+          const double* Lt = slot + tile_index(I, J) * (kT * kT);
+#pragma unroll
+          for (int r = 0; r < kT; ++r) col[r] = Lt[r * kT + c];
+        }
+        if (I == J) {
+          zx[q * kT + c] = z;
+          wave_sync();
+          double x = 0.0;
+#pragma unroll
+          for (int r = 0; r < kT; ++r) x = fma(col[r], zx[q * kT + r], x);
+          cv[q * nv.npad + J * kT + c] = x;
+          wave_sync();
+          if (J == 0) break;
+          --J;
+          I = J + 1 < nb ? J + 1 : J;
+          z = cv[q * nv.npad + J * kT + c];
+        } else {
+          const double* cI = cv + q * nv.npad + I * kT;
+#pragma unroll
+          for (int r = 0; r < kT; ++r) z = fma(-col[r], cI[r], z);
+          I = I + 1 < nb ? I + 1 : J;
+        }
       }
-      zx[q * kT + c] = z;
-      __syncthreads();
-      const double* Wjj = slot + tile_index(J, J) * (kT * kT);
-      double x = 0.0;
-#pragma unroll 8
-      for (int r = 0; r < kT; ++r) x = fma(Wjj[r * kT + c], zx[q * kT + r], x);
-      cv[q * nv.npad + J * kT + c] = x;
-      __syncthreads();
     }
     for (int a = lane; a < n; a += kFW) {
       cx[a] = cv[a];

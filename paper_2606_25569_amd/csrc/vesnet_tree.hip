@@ -564,12 +564,6 @@ __global__ __launch_bounds__(kTB) void k_tc_finalize(double2* __restrict__ mom, 
 // A child inherits its parent's expansion re-centred by e = c_child - c_parent:
 //   X_l += sum_{m>=l} C(m, l) e^(m-l) X_m  for A, B, C, and B additionally -conj(e) times the shifted C.
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 typedef double double4v __attribute__((ext_vector_type(4)));
 
 // Dynamic LDS of k_fmm_m2l for order p, KS = ceil((p + 1) / 4) steps of four m and RT = ceil((p + 1) / 16)
