@@ -82,57 +82,74 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
-// This lane's 4 x 4 block (rows I kT + 4 rg + i, columns J kT + 4 cg + j) of the bordered, padded
-// matrix, with the node coordinates loaded before the Gaussians are formed.
-__device__ __forceinline__ void entry_block(const NodeView& nv, int I, int J, int rg, int cg, double (&acc)[4][4]) {
-  const int r0 = I * kT + rg * 4, c0 = J * kT + cg * 4;
+// The 32 x 32 tile products run on the FP64 matrix cores (v_mfma_f64_16x16x4f64), as four 16 x 16 blocks
+// (R, C).  Accumulator layout: lane l holds column 16 C + (l & 15) and rows 16 R + (l >> 4) + 4 q,
+// q = 0..3, of the tile.  Operands: the A operand's element (i, k) and the B operand's element (k, j)
+// sit in lane i + 16 k and lane j + 16 k.
+typedef double double4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int acc_row(int lane, int R, int q) { return R * 16 + (lane >> 4) + 4 * q; }
+__device__ __forceinline__ int acc_col(int lane, int C) { return C * 16 + (lane & 15); }
+
+// This lane's entries (accumulator layout) of tile (I, J) of the bordered, padded matrix, with the
+// node coordinates loaded before the Gaussians are formed.
+__device__ __forceinline__ void entry_block(const NodeView& nv, int I, int J, int lane, double4v (&acc)[2][2]) {
+  const int r0 = I * kT, c0 = J * kT;
   if (r0 >= nv.npad) {  // right-hand-side rows: u_x, u_y, then zeros
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int R = 0; R < 2; ++R)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int q = r0 + i - nv.npad, col = c0 + j;
-        acc[i][j] = (col >= nv.n || q > 1) ? 0.0 : (q == 0 ? nv.ux[col] : nv.uy[col]);
-      }
+      for (int C = 0; C < 2; ++C)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int qq = r0 + acc_row(lane, R, q) - nv.npad, col = c0 + acc_col(lane, C);
+          acc[R][C][q] = (col >= nv.n || qq > 1) ? 0.0 : (qq == 0 ? nv.ux[col] : nv.uy[col]);
+        }
     return;
   }
-  double xr[4], yr[4], xc[4], yc[4];
+  double xr[2][4], yr[2][4], xc[2], yc[2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int row = min(r0 + i, nv.n - 1), col = min(c0 + i, nv.n - 1);
-    xr[i] = nv.x[row];
-    yr[i] = nv.y[row];
-    xc[i] = nv.x[col];
-    yc[i] = nv.y[col];
+  for (int R = 0; R < 2; ++R)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = min(r0 + acc_row(lane, R, q), nv.n - 1);
+      xr[R][q] = nv.x[row];
+      yr[R][q] = nv.y[row];
+    }
+#pragma unroll
+  for (int C = 0; C < 2; ++C) {
+    const int col = min(c0 + acc_col(lane, C), nv.n - 1);
+    xc[C] = nv.x[col];
+    yc[C] = nv.y[col];
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int R = 0; R < 2; ++R)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = r0 + i, col = c0 + j;
-      if (row >= nv.n || col >= nv.n) {
-        acc[i][j] = row == col ? 1.0 : 0.0;
-      } else {
-        const double dx = xr[i] - xc[j], dy = yr[i] - yc[j];
-        acc[i][j] = exp(-(dx * dx + dy * dy) * nv.inv_w2);
+    for (int C = 0; C < 2; ++C)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = r0 + acc_row(lane, R, q), col = c0 + acc_col(lane, C);
+        if (row >= nv.n || col >= nv.n) {
+          acc[R][C][q] = row == col ? 1.0 : 0.0;
+        } else {
+          const double dx = xr[R][q] - xc[C], dy = yr[R][q] - yc[C];
+          acc[R][C][q] = exp(-(dx * dx + dy * dy) * nv.inv_w2);
+        }
       }
-    }
 }
 
-// acc[i][j] += sign * sum_m Ar[(4 rg + i), m] Bc[(4 cg + j), m] over one 32-wide k-range.
-__device__ __forceinline__ void tile_gemm(double (&acc)[4][4], const double* __restrict__ Ar,
-                                          const double* __restrict__ Bc, int rg, int cg, double sign) {
-#pragma unroll 4
-  for (int m = 0; m < kT; ++m) {
-    double a[4], b[4];
+// acc += sign * Ar Bc^T over one 32-wide k-range (Ar, Bc: 32 x 32 tiles in LDS, row stride kLd).
+__device__ __forceinline__ void tile_gemm(double4v (&acc)[2][2], const double* __restrict__ Ar,
+                                          const double* __restrict__ Bc, int lane, double sign) {
+  const int i = lane & 15, k = lane >> 4;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = sign * Ar[(rg * 4 + i) * kLd + m];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = Bc[(cg * 4 + j) * kLd + m];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+  for (int s = 0; s < kT / 4; ++s) {
+    const double a0 = sign * Ar[i * kLd + 4 * s + k], a1 = sign * Ar[(16 + i) * kLd + 4 * s + k];
+    const double b0 = Bc[i * kLd + 4 * s + k], b1 = Bc[(16 + i) * kLd + 4 * s + k];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
   }
 }
 
@@ -149,8 +166,6 @@ __global__ __launch_bounds__(kFW, 2) void k_rbf_fit(const double* __restrict__ l
   double* B = pool + kT * kLd;
 
   const int lane = threadIdx.x;
-  const int cg = lane & 7;   // 4 columns: 4 cg .. 4 cg + 3
-  const int rg = lane >> 3;  // 4 rows:    4 rg .. 4 rg + 3
   double* slot = tiles + (size_t)blockIdx.x * slot_doubles;
   (void)slot_tile_doubles;
   const size_t P5 = (size_t)5 * P;
@@ -187,21 +202,23 @@ __global__ __launch_bounds__(kFW, 2) void k_rbf_fit(const double* __restrict__ l
     double wreg[kT * kT / kFW];  // W = L_JJ^{-1} of the current panel, element lane + kFW t (row-major)
     for (int J = 0; J < nb; ++J) {
       for (int I = J; I <= nb; ++I) {
-        double acc[4][4];
-        entry_block(nv, I, J, rg, cg, acc);
+        double4v acc[2][2];
+        entry_block(nv, I, J, lane, acc);
         // T = A - sum_{k < J} L(I, k) L(J, k)^T
         for (int k = 0; k < J; ++k) {
           wave_sync();  // A and B are free
           stage_tile(B, slot + tile_index(J, k) * (kT * kT), lane);
           if (I != J) stage_tile(A, slot + tile_index(I, k) * (kT * kT), lane);
           wave_sync();
-          tile_gemm(acc, I != J ? A : B, B, rg, cg, -1.0);
+          tile_gemm(acc, I != J ? A : B, B, lane, -1.0);
         }
         wave_sync();  // A is free
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int R = 0; R < 2; ++R)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) A[(rg * 4 + i) * kLd + cg * 4 + j] = acc[i][j];
+          for (int C = 0; C < 2; ++C)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) A[acc_row(lane, R, q) * kLd + acc_col(lane, C)] = acc[R][C][q];
         wave_sync();
         double* dst = slot + tile_index(I, J) * (kT * kT);
         if (I == J) {
@@ -259,16 +276,18 @@ __global__ __launch_bounds__(kFW, 2) void k_rbf_fit(const double* __restrict__ l
             B[(e >> 5) * kLd + (e & 31)] = wreg[t];
           }
           wave_sync();
-          double out[4][4];
+          double4v out[2][2];
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int R = 0; R < 2; ++R)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) out[i][j] = 0.0;
-          tile_gemm(out, A, B, rg, cg, 1.0);
+            for (int C = 0; C < 2; ++C) out[R][C] = double4v{0.0, 0.0, 0.0, 0.0};
+          tile_gemm(out, A, B, lane, 1.0);
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int R = 0; R < 2; ++R)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) dst[(rg * 4 + i) * kT + cg * 4 + j] = out[i][j];
+            for (int C = 0; C < 2; ++C)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) dst[acc_row(lane, R, q) * kT + acc_col(lane, C)] = out[R][C][q];
         }
       }
       __syncthreads();  // the panel's tiles are stored before later panels read them
