@@ -235,8 +235,11 @@ __global__ __launch_bounds__(kFW, 2) void k_rbf_fit(const double* __restrict__ l
             double sj = row[j];
 #pragma unroll
             for (int m = 0; m < j; ++m) sj = fma(-row[m], lane_bcast(row[m], j), sj);
-            const double d = sqrt(lane_bcast(sj, j));
-            const double di = 1.0 / d;
+            const double s2 = lane_bcast(sj, j);
+            double di = __builtin_amdgcn_rsq(s2);  // 1 / sqrt(s2), refined by two Newton steps
+            di = fma(0.5 * di, fma(-s2 * di, di, 1.0), di);
+            di = fma(0.5 * di, fma(-s2 * di, di, 1.0), di);
+            const double d = s2 * di;
             row[j] = i > j ? sj * di : (i == j ? d : 0.0);
             if (i == j) rinv = di;
           }
