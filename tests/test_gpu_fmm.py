@@ -64,9 +64,8 @@ def test_fmm_within_truncation_bound(susp, exact, depth, order):
     assert np.all(err <= b + 1e-12 * np.abs(exact).max())
 
 
-def test_fmm_ragged_partition_and_big_leaves():
-    """Vesicles of 0 .. 130 points (one empty, one single point), and at depth 0 one leaf of every
-    point (more than 2048 points: the unsorted-leaf path)."""
+def _ragged():
+    """Vesicles of 0 .. 130 points (empty ones, and single points whose spacing h_v = 2 pi) on a grid 4 apart."""
     rng = np.random.default_rng(9)
     sizes = [0, 1, 7, 33, 64, 130, 0, 90] * 8
     Xs, fs, ws, off = [], [], [], [0]
@@ -78,8 +77,14 @@ def test_fmm_ragged_partition_and_big_leaves():
         fs.append(rng.normal(size=(2, n)))
         ws.append(np.full(n, 2 * np.pi / max(n, 1)))
         off.append(off[-1] + n)
-    s = S.Suspension(X=np.concatenate(Xs, 1), f=np.concatenate(fs, 1), w=np.concatenate(ws), offsets=np.asarray(off, np.int32),
-                     mu=0.7, box=24.0, centers=None, axes=None, angles=None)
+    return S.Suspension(X=np.concatenate(Xs, 1), f=np.concatenate(fs, 1), w=np.concatenate(ws),
+                        offsets=np.asarray(off, np.int32), mu=0.7, box=24.0, centers=None, axes=None, angles=None)
+
+
+def test_fmm_ragged_partition_and_big_leaves():
+    """Vesicles of 0 .. 130 points (one empty, one single point), and at depth 0 one leaf of every
+    point (more than 2048 points: the unsorted-leaf path)."""
+    s = _ragged()
     exact = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
     assert s.n_points > 2048
     for depth in (0, 2, 3):
@@ -207,3 +212,39 @@ def test_fmm_nearmasked_spacing_above_leaf_width_is_reported():
     with pytest.raises(L.VesnetError, match="leaf width"):
         V.farfield_fmm_nearmasked(X, f, w, s.offsets, s.mu, 8, 8)
     torch.cuda.synchronize()
+
+
+def test_fmm_nearmasked_ragged_and_empty():
+    """The ragged partition (empty vesicles, single points with h_v = 2 pi, leaves of more than 64 points):
+    at depths 0-2 (leaves at least 10 wide) the pairs and the field match the oracles; at depth 3 (leaves
+    5.1 wide) the spacing is reported.  No points at all: count 0."""
+    import torch
+    import paper_2606_25569_amd as V
+    from paper_2606_25569_amd import _lib as L
+    from tests.gpu_util import near_margin
+    s = _ragged()
+    assert near_margin(s) > 1e-5
+    X, f, w = dev_inputs(s)
+    for depth in (0, 1, 2):
+        ref, pairs_ref = _fmm_masked_ref(s, 24, depth)
+        out, pairs = V.farfield_fmm_nearmasked(X, f, w, s.offsets, s.mu, 24, depth)
+        torch.cuda.synchronize()
+        got = {tuple(p) for p in pairs.cpu().numpy().tolist()}
+        err, _ = rel_err(out.cpu().numpy(), ref)
+        say(f"fmm nearmasked ragged depth={depth}: err vs oracle {err:.2e}, {len(got)} near pairs")
+        assert got == {tuple(p) for p in pairs_ref.tolist()} and len(got) == pairs.shape[0] > 1000
+        assert err <= 1e-12
+    with pytest.raises(L.VesnetError, match="leaf width"):
+        V.farfield_fmm_nearmasked(X, f, w, s.offsets, s.mu, 24, 3)
+    torch.cuda.synchronize()
+    lib = L.lib()
+    off = torch.zeros(3, dtype=torch.int32, device="cuda")  # two empty vesicles
+    count = torch.full((1,), 5, dtype=torch.int32, device="cuda")
+    nothing = torch.empty((2, 0), dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(1, lib.vesnet_fmm_nearmasked_workspace_bytes(0, 2, 2, 8)), dtype=torch.uint8, device="cuda")
+    L.check(lib.vesnet_farfield_fmm_nearmasked(nothing.data_ptr(), nothing.data_ptr(), nothing.data_ptr(),
+                                               off.data_ptr(), 2, 0, 1.0, 8, 2, nothing.data_ptr(), None, 0,
+                                               count.data_ptr(), ws.data_ptr(), ws.numel(),
+                                               torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert int(count.item()) == 0
