@@ -249,20 +249,43 @@ __global__ __launch_bounds__(kFW, 2) void k_rbf_fit(const double* __restrict__ l
             A[i * kLd + kT] = rinv;  // the row's padding entry
           }
           wave_sync();
-          // W = L^{-1} with lane i holding column i: W[r][i] = (delta_ri - sum_{m<r} L[r][m] W[m][i]) / L[r][r],
-          // L and 1 / L[r][r] read from LDS (the same address in every lane); W goes to the slot in place
-          // of L_JJ and stays in registers for the tiles below
-          double wc[kT];
+          // W = L^{-1} by 16 x 16 blocks.  W11 = L11^{-1} (lanes 0..15, column i) and W22 = L22^{-1} (lanes
+          // 16..31, column i - 16) at once: W[r][i] = (delta_ri - sum_{m<r} L[r][m] W[m][i]) / L[r][r], with
+          // L and 1 / L[r][r] read from LDS (the same address in each half).  Then W21 = -W22 (L21 W11) on
+          // the matrix cores: the accumulator of L21 W11 is already in the B-operand layout of the second
+          // product.  W goes to the slot in place of L_JJ and stays in registers for the tiles below.
+          {
+            const int o = lane & 16, ic = lane & 15;  // block offset, column within the block
+            double wc[16];
 #pragma unroll
-          for (int r = 0; r < kT; ++r) {
-            double t = i == r ? 1.0 : 0.0;
+            for (int r = 0; r < 16; ++r) {
+              double t = ic == r ? 1.0 : 0.0;
 #pragma unroll
-            for (int m = 0; m < r; ++m) t = fma(-A[r * kLd + m], wc[m], t);
-            wc[r] = t * A[r * kLd + kT];
+              for (int m = 0; m < r; ++m) t = fma(-A[(o + r) * kLd + o + m], wc[m], t);
+              wc[r] = t * A[(o + r) * kLd + kT];
+            }
+            if (lane < kT) {
+#pragma unroll
+              for (int r = 0; r < 16; ++r) B[(o + r) * kLd + o + ic] = wc[r];
+              if (o != 0) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) B[r * kLd + 16 + ic] = 0.0;  // W12
+              }
+            }
           }
-          if (lane < kT) {
+          wave_sync();
+          {
+            const int i16 = lane & 15, k4 = lane >> 4;
+            double4v x = {0.0, 0.0, 0.0, 0.0}, w21 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int r = 0; r < kT; ++r) B[r * kLd + lane] = wc[r];
+            for (int s4 = 0; s4 < 4; ++s4)  // X = L21 W11
+              x = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(16 + i16) * kLd + 4 * s4 + k4], B[(4 * s4 + k4) * kLd + i16], x,
+                                                       0, 0, 0);
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)  // W21 = -W22 X
+              w21 = __builtin_amdgcn_mfma_f64_16x16x4f64(-B[(16 + i16) * kLd + 16 + 4 * s4 + k4], x[s4], w21, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) B[(16 + 4 * q + k4) * kLd + i16] = w21[q];
           }
           wave_sync();
 #pragma unroll
