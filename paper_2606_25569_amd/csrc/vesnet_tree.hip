@@ -1186,14 +1186,17 @@ __global__ __launch_bounds__(kOwnThreads) void k_tc_own(const double* __restrict
 // Near-field masking of Algorithm 4 on the fast multipole result: vesicle v (not the target's own) is near
 // target i when min_j |x_i - x_j| <= h_v (the rule of the direct masked sum, decided here in FP64 on
 // squared distances).  With every h_v at most the leaf width, all such points lie in the 3 x 3 leaves around
-// the target's leaf.  One wavefront per (leaf, chunk of 32 targets) stages those leaves' points in LDS; lanes
-// t and t + 32 scan alternate points for target t, each keeping the distinct near vesicles it meets (at most
-// kNearMax, else bit 0 of *flag), and lane t merges the two sets and sorts them ascending.  One atomic per
+// the target's leaf.  One wavefront per (leaf, chunk of 32 targets) stages those leaves' points in LDS, up to
+// kNearStage at a time with every lane's loads issued together (a neighbourhood of that many points costs
+// three rounds of memory latency); lanes t and t + 32 scan alternate points for target t, each keeping the
+// distinct near vesicles it meets (at most kNearMax, else bit 0 of *flag), and lane t merges the two sets
+// and sorts them ascending.  One atomic per
 // wavefront reserves the pair slots.  The whole wavefront then takes the near vesicles of each target in
 // turn, 64 points at a time, and subtracts their exact direct sum at x_i from out[i]: the FMM had included v
 // through the direct part or the expansions, and the difference leaves the masked far field with the FMM's
 // truncation error.  The lane partials are combined by a butterfly, so the result is deterministic.
 constexpr int kNearMax = 16;
+constexpr int kNearStage = 6 * 64;  // points of the 3 x 3 leaves staged at once (six per lane)
 
 __device__ __forceinline__ void near_insert(int (&nv)[kNearMax], int& nn, bool& over, int v) {
   bool seen = false;
@@ -1221,8 +1224,8 @@ __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, c
                                                 int32_t* __restrict__ flag) {
   constexpr int kChunk = 1 << eval_chunk_shift<true>();
   static_assert(kChunk == 32, "two lanes per target");
-  __shared__ double sx_[64], sy_[64], sh[64];
-  __shared__ int32_t sv[64];
+  __shared__ double sx_[kNearStage], sy_[kNearStage], sh[kNearStage];
+  __shared__ int32_t sv[kNearStage];
   __shared__ double2 ltab[kLogTab];
   __shared__ int32_t mlist[kChunk][kNearMax + 1];
   __shared__ int32_t mcount[kChunk];
@@ -1249,31 +1252,53 @@ __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, c
   int nv[kNearMax];
   int nn = 0;
   bool over = false;
-  for (int jx = max(ix - 1, 0); jx <= min(ix + 1, n - 1); ++jx)
-    for (int jy = max(iy - 1, 0); jy <= min(iy + 1, n - 1); ++jy) {
-      const int nl = jx * n + jy;
-      const int e0 = starts[nl], e1 = starts[nl + 1];
-      for (int c0 = e0; c0 < e1; c0 += 64) {
-        const int cnt = min(64, e1 - c0);
-        __syncthreads();  // the previous chunk is done
-        if (lane < cnt) {
-          const int j = perm[c0 + lane];
-          const int vj = clamp_i(vid[j], 0, M - 1);  // ids index the per-vesicle arrays: never trusted
-          sx_[lane] = X[j];
-          sy_[lane] = X[P + j];
-          sv[lane] = vj;
-          sh[lane] = h2[vj];
-        }
-        __syncthreads();
-        if (!active) continue;
-#pragma unroll 4
-        for (int q = half; q < cnt; q += 2) {
-          const double rx = zx - sx_[q], ry = zy - sy_[q];
-          const int vq = sv[q];
-          if (!(rx * rx + ry * ry > sh[q]) && vq != vi) near_insert(nv, nn, over, vq);
-        }
+  // point ranges of the 3 x 3 leaves (empty outside the grid) and their running offsets
+  int lb[9], cum[10];
+  cum[0] = 0;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const int jx = ix + a / 3 - 1, jy = iy + a % 3 - 1;
+    const bool in = jx >= 0 && jx < n && jy >= 0 && jy < n;
+    const int nl = in ? jx * n + jy : 0;
+    lb[a] = in ? starts[nl] : 0;
+    cum[a + 1] = cum[a] + (in ? starts[nl + 1] - lb[a] : 0);
+  }
+  const int nsrc = cum[9];
+  for (int b0 = 0; b0 < nsrc; b0 += kNearStage) {
+    const int cnt = min(kNearStage, nsrc - b0);
+    __syncthreads();  // the previous stage is done
+    int jj[kNearStage / 64];
+#pragma unroll
+    for (int u = 0; u < kNearStage / 64; ++u) {
+      const int e = b0 + lane + 64 * u;
+      int a = 0;
+#pragma unroll
+      for (int c = 1; c < 9; ++c) a += e >= cum[c] ? 1 : 0;
+      jj[u] = e < nsrc ? perm[lb[a] + e - cum[a]] : -1;
+    }
+    int vv[kNearStage / 64];
+#pragma unroll
+    for (int u = 0; u < kNearStage / 64; ++u) {
+      if (jj[u] >= 0) {
+        const int k = lane + 64 * u;
+        sx_[k] = X[jj[u]];
+        sy_[k] = X[P + jj[u]];
+        vv[u] = clamp_i(vid[jj[u]], 0, M - 1);  // ids index the per-vesicle arrays: never trusted
+        sv[k] = vv[u];
       }
     }
+#pragma unroll
+    for (int u = 0; u < kNearStage / 64; ++u)
+      if (jj[u] >= 0) sh[lane + 64 * u] = h2[vv[u]];
+    __syncthreads();
+    if (!active) continue;
+#pragma unroll 4
+    for (int q = half; q < cnt; q += 2) {
+      const double rx = zx - sx_[q], ry = zy - sy_[q];
+      const int vq = sv[q];
+      if (!(rx * rx + ry * ry > sh[q]) && vq != vi) near_insert(nv, nn, over, vq);
+    }
+  }
   // merge the upper half's sets into the lower half's
   if (half == 1) {
 #pragma unroll
