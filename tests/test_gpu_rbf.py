@@ -276,3 +276,25 @@ def test_near_field_chain_graph_replay():
         err = float((out - eager).abs().max()) / scale
         assert err <= 1e-14, (k, err)
     say("near-field chain: 3 graph replays equal the eager chain")
+
+
+def test_rbf_fit_small_workspace_is_bit_identical():
+    """With fewer slots than vesicles each wavefront factors several vesicles in turn, reusing its slot
+    and LDS: one and three slots give the coefficients of the full workspace bit for bit."""
+    import torch
+    from paper_2606_25569_amd import _lib as L
+    sizes = [3, 7, 0, 32, 33, 64, 100, 128, 200]
+    X, w, off, layers, h, U, Ld, wd, full = _fit_case(sizes, 41, 1.0)
+    lib = L.lib()
+    M, P = len(sizes), int(off[-1])
+    part = torch.tensor(off, dtype=torch.int32, device="cuda")
+    Ud = torch.tensor(U, device="cuda")
+    slot = lib.vesnet_rbf_workspace_bytes(200, 1)
+    for slots in (1, 3):
+        ws = torch.empty(slot * slots, dtype=torch.uint8, device="cuda")
+        got = torch.full_like(full, float("nan"))
+        L.check(lib.vesnet_rbf_fit(Ld.data_ptr(), Ud.data_ptr(), wd.data_ptr(), part.data_ptr(), M, P, 200, 1.0,
+                                   got.data_ptr(), ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        assert torch.equal(got, full), slots
+    say("rbf fit: 1 and 3 slots equal the full workspace bit for bit")
