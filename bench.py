@@ -20,6 +20,7 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_PAIR = 19          # sub x2, q: mul+fma, log, rcp, r.F: mul+fma, scale, 2 x (2 fma)
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32
 PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64
+PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
 METRIC = "Stokeslet pair-interactions/s (FP32-comp vs FP64) at ≤1e-5 rel err; % VALU peak"
 
 
@@ -58,9 +59,10 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="T,B,splits[,staging]: fixed launch shape instead of the tuned one (staging 1 = SGPR, 2 = LDS)")
     ap.add_argument("--cpu-sample", type=float, default=0.03, help="fraction of targets the oracle evaluates")
-    ap.add_argument("--workload", default="dense", choices=["dense", "batched", "adjoint", "nearfield", "treecode"],
-                    help="dense: the benchmark line; batched / adjoint / nearfield / treecode: the other forms, "
-                         "reported separately")
+    ap.add_argument("--workload", default="dense",
+                    choices=["dense", "batched", "adjoint", "nearfield", "treecode", "force"],
+                    help="dense: the benchmark line; batched / adjoint / nearfield / treecode / force: the other "
+                         "forms, reported separately")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -90,6 +92,8 @@ def main():
         return bench_nearfield(args)
     if args.workload == "treecode":
         return bench_treecode(args)
+    if args.workload == "force":
+        return bench_force(args)
 
     import paper_2606_25569_amd as V
     from synth import suspension as S
@@ -337,6 +341,63 @@ def bench_adjoint(args):
         rec[prec] = {"forward_ms": tf, "backward_ms": tb, "forward_pairs_per_s": pairs / (tf * 1e-3),
                      "backward_pairs_per_s": pairs / (tb * 1e-3)}
         log(f"[bench] adjoint {prec}: forward {tf:.3f} ms, backward {tb:.3f} ms")
+    print(json.dumps(rec), flush=True)
+
+
+def bench_force(args):
+    """The step before the sum: membrane force f = -kappa_b X_ssss + (sigma X_s)_s and trapezoid weights by
+    spectral derivatives (five circulant N x N derivative products of two components per vesicle:
+    20 N^2 flops per vesicle; 48 B of HBM traffic per point), 2000 vesicles of 128 and of 32 points, with
+    a seeded smooth tension."""
+    import numpy as np
+    import torch
+
+    import paper_2606_25569_amd as V
+    from paper_2606_25569_amd import _lib as L
+    from paper_2606_25569_amd.farfield import _ptr
+    from synth import suspension as S
+
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    lib = L.lib()
+    rec = {"workload": "membrane force and trapezoid weights (spectral derivatives, FP64), kappa_b = 1, "
+                       "seeded tension 1 + 0.1 N(0, 1)", "cases": []}
+    for name, s in (("2000 x 128", S.load_config(1)), ("2000 x 32", S.rsa_suspension(S.config_seed(5), 2000, 32, 0.30))):
+        P, M = s.n_points, s.n_vesicles
+        N = P // M
+        X = torch.tensor(s.X, device=dev)
+        sig_h = 1.0 + 0.1 * np.random.default_rng(S.config_seed(6)).normal(size=P)
+        sig = torch.tensor(sig_h, device=dev)
+        part = V.Partition(s.offsets, dev)
+        f = torch.empty((2, P), dtype=torch.float64, device=dev)
+        w = torch.empty((P,), dtype=torch.float64, device=dev)
+
+        def step():
+            L.check(lib.vesnet_elastic_force(_ptr(X), _ptr(sig), 1.0, _ptr(part.device), M, P, _ptr(f), _ptr(w),
+                                             stream.cuda_stream))
+
+        for _ in range(args.warmup):
+            step()
+        ms = _time(step, args.steps, stream)
+        flops = 20.0 * N * N * M
+        nbytes = 48.0 * P
+        # the oracle (numpy FFT) on a bounded sample of vesicles, for context
+        from oracle import spectral as SP
+        sample = 200
+        j1 = int(s.offsets[sample])
+        t0 = time.time()
+        SP.elastic_force(s.X[:, :j1], sig_h[:j1], 1.0, s.offsets[:sample + 1])
+        cpu_vps = sample / (time.time() - t0)
+        case = {"case": name, "n_points": P, "ms": ms, "points_per_s": P / (ms * 1e-3),
+                "fp64": {"achieved_tflops": flops / (ms * 1e-3) / 1e12,
+                         "frac": flops / (ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS},
+                "hbm": {"achieved_gbps": nbytes / (ms * 1e-3) / 1e9, "frac": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBPS},
+                "cpu_baseline": {"value": cpu_vps, "unit": "vesicles/s", "kind": "oracle",
+                                 "sample": f"{sample} vesicles, numpy FFT, one process"}}
+        rec["cases"].append(case)
+        log(f"[bench] force {name}: {ms * 1e3:.1f} us, {P / (ms * 1e-3):.3e} points/s, "
+            f"{case['fp64']['achieved_tflops']:.2f} TFLOP/s FP64, {case['hbm']['achieved_gbps']:.0f} GB/s; "
+            f"oracle {cpu_vps:.0f} vesicles/s")
     print(json.dumps(rec), flush=True)
 
 
