@@ -58,7 +58,7 @@ extern "C" {
 typedef enum {
   VESNET_OK = 0,
   VESNET_ERR_INVALID_ARGUMENT = -1, /* bad pointer, size, mu, precision, aliasing, offsets */
-  VESNET_ERR_UNSUPPORTED = -2,      /* valid request this build does not implement        */
+  VESNET_ERR_UNSUPPORTED = -2,      /* valid request the library does not implement       */
   VESNET_ERR_WORKSPACE = -3,        /* workspace missing or smaller than required          */
   VESNET_ERR_HIP = -4               /* a HIP runtime call or kernel launch failed          */
 } vesnet_status;
