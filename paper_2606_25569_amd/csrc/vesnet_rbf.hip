@@ -8,9 +8,10 @@
 // k_rbf_fit: one wavefront per vesicle factors K = L L^T in float64 by a left-looking blocked
 // algorithm on 32 x 32 tiles.  The entries of K are recomputed from the node coordinates when a
 // panel needs them, so only L is stored (in a per-wavefront slot of the tile workspace, lower tiles
-// packed).  Each diagonal tile is factored in LDS and inverted, W = L_JJ^{-1}; the tiles below it
-// are then L_IJ = T_IJ W^T, a small GEMM like the panel updates, and W replaces L_JJ in the slot
-// (no later panel reads L_JJ).  The two right-hand sides ride along as two extra rows below the
+// packed).  The tile products (panel updates T = K - sum L L^T, and L_IJ = T_IJ W^T) run on the FP64
+// matrix cores.  Each diagonal tile is factored in registers and inverted, W = L_JJ^{-1}, by 16 x 16
+// blocks; W replaces L_JJ in the slot (no later panel reads L_JJ) and stays in registers for the tiles
+// below it.  The two right-hand sides ride along as two extra rows below the
 // matrix (the bordered form [K; u^T]), so the same steps leave y = L^{-1} u in them; the back
 // substitution L^T c = y then takes c_J = W_JJ^T (y_J - sum_{I>J} L_IJ^T c_I), block by block.  The
 // rows are padded to a multiple of 32 with an identity block, which leaves the factor and the
