@@ -8,10 +8,10 @@
 // d/dalpha exact on the band-limited interpolant of the N points alpha_k = 2 pi k / N.
 // On the grid that operator is the circulant matrix with first column
 //   d_0 = 0,  d_m = (1/2) (-1)^m cot(pi m / N)  (N even),  (1/2) (-1)^m csc(pi m / N)  (N odd),
-// which equals multiplying Fourier mode k by i k with the even-N Nyquist mode dropped.  For the
-// N <= 1024 points of one vesicle a workgroup applies it as a direct O(N^2) sum from LDS (a few
-// microseconds for a whole suspension, negligible beside the pair sum), in float64: the fourth
-// derivative amplifies rounding by up to (N/2)^4.
+// which equals multiplying Fourier mode k by i k with the even-N Nyquist mode dropped.  It is applied as
+// a direct O(N^2) sum from LDS in float64 (the fourth derivative amplifies rounding by up to (N/2)^4):
+// one wavefront per vesicle of up to 64, 128 or 256 points (k_elastic_wave), one workgroup per larger
+// vesicle of up to 1024 points (k_elastic), tens of microseconds for a whole suspension.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
