@@ -84,8 +84,24 @@ typedef struct {
   int32_t accumulate;         /* 1: per-pair sums accumulated with VALU FMAs;
                                  2: (compensated forward only) the four accumulations of each pair
                                     issued to the matrix cores as v_mfma_f32_4x4x1f32 products of
-                                    per-target values and per-source features, which then run
-                                    beside the VALU work                                          */
+                                    per-target values and per-source features (measured slower on
+                                    gfx950: each 4x4x1 product takes about five FMA issue slots
+                                    and does not overlap the VALU work; kept for comparison)      */
+  int32_t pair_form;          /* 0: automatic - vesnet_farfield_stokeslet takes the symmetric form
+                                    when targets == sources (the same pointer), the precision is
+                                    VESNET_FP32_COMPENSATED, accumulate is 1 and the problem is
+                                    large enough (at least four units per compute unit); every
+                                    other call takes the direct form;
+                                 1: direct form - one gather per target over all source vesicles;
+                                 2: symmetric form (compensated only) - each unordered pair of
+                                    points of different vesicles is evaluated once and serves both
+                                    (the Stokeslet is even), halving the logarithms and reciprocals;
+                                    the targets must be the points the workspace was prepared with
+                                    (vesnet_farfield_stokeslet requires targets == sources).
+                                    targets_per_thread (1, 2, 4) sets its block of 1024 T targets;
+                                    block_threads, source_splits and source_staging are unused.
+                                    Its partial sums are added as 64-bit fixed-point integers, so
+                                    the result is bitwise reproducible.                            */
 } vesnet_tile_config;
 
 /* Library version string and the thread-local description of the last error. */
@@ -243,7 +259,9 @@ VESNET_API int vesnet_rbf_eval_near(const double* layers, const double* coeffs, 
    expansions included it).  Cost O(P log P); everything in float64.
    Accuracy: for a box of radius rho seen from distance R, the dropped terms are below
    sum_box |w f| x^(order+1) (1/((order+1)(1-x)) + (1+x)/(2(1-x))) / (4 pi mu), x = rho/R <= 0.55;
-   order 30 gives about 1e-8 relative to max|u| on dense suspensions, order 45 reaches rounding.
+   this bound is the contract.  Measured on the 2000 x 128 suspension at depth 6 (2,000 seeded
+   targets against the exact sum): 8.7e-9 relative to max|u| at order 20, 3.2e-12 at order 30,
+   1.3e-14 at order 40; order 45 reaches rounding.
    Results are deterministic unless a leaf holds more than 2048 points (then its summation order
    follows an atomic scatter).
      points, force_density : device [2][P] float64; arc_weights device [P] float64
@@ -266,9 +284,10 @@ VESNET_API int vesnet_farfield_treecode(const double* points, const double* forc
    series is converted once into a Taylor polynomial of the same order about the centre of every
    box whose interaction list holds it, the polynomials are re-centred down the tree, and each target
    evaluates only its leaf's polynomial.  The far work becomes O(boxes x order^2) instead of
-   O(points x boxes per list x order).  Accuracy: at the same order about 2 to 4 times the treecode's
-   error (order 30: about 1e-11 relative to max|u| on dense suspensions, order 40: 1e-14); everything
-   in float64.
+   O(points x boxes per list x order).  Accuracy: the treecode's bound plus the Taylor truncation of
+   each translated series (the contract); measured at the same order 2 to 4 times the treecode's
+   error (2000 x 128, depth 6: 2.0e-8 at order 20, 1.1e-11 at order 30, 1.2e-14 at order 40 relative
+   to max|u|); everything in float64.
    Deterministic under the same condition as the treecode.
      arguments, layouts, ownership and errors as vesnet_farfield_treecode;
      workspace : device, vesnet_fmm_workspace_bytes(P, depth, order) bytes (the treecode's plus

@@ -40,7 +40,7 @@ class VesnetError(RuntimeError):
 class TileConfig(ctypes.Structure):
     _fields_ = [("targets_per_thread", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("source_splits", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("source_staging", ctypes.c_int32), ("accumulate", ctypes.c_int32)]
+                ("source_staging", ctypes.c_int32), ("accumulate", ctypes.c_int32), ("pair_form", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -49,7 +49,7 @@ class TileConfig(ctypes.Structure):
     def from_dict(cls, d):
         return cls(int(d.get("targets_per_thread", 0)), int(d.get("block_threads", 0)),
                    int(d.get("source_splits", 0)), int(d.get("blocks_per_cu", 0)), int(d.get("source_staging", 0)),
-                   int(d.get("accumulate", 0)))
+                   int(d.get("accumulate", 0)), int(d.get("pair_form", 0)))
 
 
 _lib = None

@@ -10,6 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, "vesnet_kernels.hip"), os.path.join(CSRC, "vesnet_spectral.hip"),
            os.path.join(CSRC, "vesnet_rbf.hip"), os.path.join(CSRC, "vesnet_tree.hip"),
+           os.path.join(CSRC, "vesnet_symmetric.hip"),
            os.path.join(CSRC, "vesnet_api.hip")]
 LIB = os.path.join(HERE, "libvesnet.so")
 

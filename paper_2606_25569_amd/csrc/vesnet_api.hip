@@ -44,15 +44,21 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 size_t rec_bytes(int prec) { return prec == P64 ? sizeof(double4) : sizeof(float4); }
 
-size_t prepared_bytes(int32_t P, int32_t M, int prec) {
-  return align_up((size_t)M * sizeof(int2)) + align_up((size_t)P * sizeof(int32_t)) +
-         align_up((size_t)M * sizeof(double4)) + align_up((size_t)M * sizeof(double)) +
-         align_up((size_t)P * rec_bytes(prec));
+// The forward calls' prepared region of the compensated form also holds the float64 weighted
+// forces and the per-vesicle |F|_1 sums that the symmetric form needs.
+bool fwd_forces(int prec) { return prec == P32C; }
+
+size_t prepared_bytes(int32_t P, int32_t M, int prec, bool forces = false) {
+  size_t b = align_up((size_t)M * sizeof(int2)) + align_up((size_t)P * sizeof(int32_t)) +
+             align_up((size_t)M * sizeof(double4)) + align_up((size_t)M * sizeof(double)) +
+             align_up((size_t)P * rec_bytes(prec));
+  if (forces) b += align_up((size_t)P * sizeof(double2)) + align_up((size_t)M * sizeof(double2));
+  return b;
 }
 
 // Carves the prepared region starting at *cursor (already aligned).
-PreparedView carve_prepared(char*& cursor, int32_t P, int32_t M, int prec) {
-  PreparedView pv;
+PreparedView carve_prepared(char*& cursor, int32_t P, int32_t M, int prec, bool forces = false) {
+  PreparedView pv{};
   pv.vrange = reinterpret_cast<int2*>(cursor);
   cursor += align_up((size_t)M * sizeof(int2));
   pv.vid = reinterpret_cast<int32_t*>(cursor);
@@ -63,7 +69,33 @@ PreparedView carve_prepared(char*& cursor, int32_t P, int32_t M, int prec) {
   cursor += align_up((size_t)M * sizeof(double));
   pv.rec = cursor;
   cursor += align_up((size_t)P * rec_bytes(prec));
+  if (forces) {
+    pv.f64 = reinterpret_cast<double2*>(cursor);
+    cursor += align_up((size_t)P * sizeof(double2));
+    pv.vaux = reinterpret_cast<double2*>(cursor);
+    cursor += align_up((size_t)M * sizeof(double2));
+  }
   return pv;
+}
+
+// The symmetric form's region: cycle table, plan values, cycle net forces, fixed-point sums.
+size_t symmetric_bytes(int32_t P, int32_t M) {
+  return align_up((size_t)sym_max_cycles(P, M) * sizeof(int4)) + align_up(4 * sizeof(int32_t)) +
+         align_up((size_t)sym_max_cycles(P, M) * sizeof(double2)) +
+         align_up((size_t)2 * P * sizeof(unsigned long long));
+}
+
+SymmetricView carve_symmetric(char*& cursor, int32_t P, int32_t M) {
+  SymmetricView sv;
+  sv.cyc = reinterpret_cast<int4*>(cursor);
+  cursor += align_up((size_t)sym_max_cycles(P, M) * sizeof(int4));
+  sv.meta = reinterpret_cast<int32_t*>(cursor);
+  cursor += align_up(4 * sizeof(int32_t));
+  sv.fcyc = reinterpret_cast<double2*>(cursor);
+  cursor += align_up((size_t)sym_max_cycles(P, M) * sizeof(double2));
+  sv.acc = reinterpret_cast<unsigned long long*>(cursor);
+  cursor += align_up((size_t)2 * P * sizeof(unsigned long long));
+  return sv;
 }
 
 char* aligned_base(void* ws) {
@@ -75,7 +107,22 @@ bool valid_precision(int prec) { return prec == VESNET_FP64 || prec == VESNET_FP
 
 struct Shape {
   int T, B, splits, bpc, staging, accumulate;
+  int pair;  // 0 automatic, 1 direct, 2 symmetric
+  int symT;  // targets per thread of the symmetric form (0: too few units for it)
 };
+
+// Targets per thread of the symmetric form: the largest T in {8, 4, 2, 1} that still gives at
+// least four units per compute unit (a unit is one workgroup of 512 threads on one pair of blocks
+// of 512 T points), estimated with vesicles of a multiple of 16 points; 0 when even T = 1 gives
+// fewer.
+int sym_default_T(int32_t P) {
+  for (int T : {8, 4, 2, 1}) {
+    const int64_t cyc = (int64_t)P / 16;
+    const int cb = sym_cycles_per_block(T);
+    if (sym_units((cyc + cb - 1) / cb) >= 1024) return T;
+  }
+  return 0;
+}
 
 // The default launch shape is the one the autotuner picks on the 2000 x 128 suspension
 // (T = 1, 256 threads, LDS staging, VALU accumulation) with enough source chunks for
@@ -93,6 +140,8 @@ Shape default_shape(int32_t P, int32_t M, int prec) {
   int splits = 1;
   while (waves * splits < want && splits < 16) splits *= 2;
   s.splits = std::max(1, std::min<int>(splits, std::max(1, M)));
+  s.pair = 0;
+  s.symT = prec == P32C ? sym_default_T(P) : 0;
   return s;
 }
 
@@ -105,9 +154,14 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     if (cfg->blocks_per_cu) s.bpc = cfg->blocks_per_cu;
     if (cfg->source_staging) s.staging = cfg->source_staging;
     if (cfg->accumulate) s.accumulate = cfg->accumulate;
+    if (cfg->pair_form) s.pair = cfg->pair_form;
+    if (cfg->targets_per_thread) s.symT = cfg->targets_per_thread;
   }
-  if (s.T != 1 && s.T != 2 && s.T != 4)
-    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread must be 1, 2 or 4 (got %d)", s.T);
+  if (s.T != 1 && s.T != 2 && s.T != 4 && !(s.T == 8 && s.pair == 2))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread must be 1, 2 or 4 (8 for the symmetric form; got %d)",
+                s.T);
+  if (s.symT != 1 && s.symT != 2 && s.symT != 4 && s.symT != 8 && s.symT != 0)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread of the symmetric form must be 1, 2, 4 or 8");
   if (s.B != 64 && s.B != 128 && s.B != 256)
     return fail(VESNET_ERR_INVALID_ARGUMENT, "block_threads must be 64, 128 or 256 (got %d)", s.B);
   if (s.splits < 1 || s.splits > kMaxSplits)
@@ -120,13 +174,23 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     return fail(VESNET_ERR_INVALID_ARGUMENT, "accumulate must be 1 or 2 (got %d)", s.accumulate);
   if (s.accumulate == 2 && prec != VESNET_FP32_COMPENSATED)
     return fail(VESNET_ERR_UNSUPPORTED, "matrix-core accumulation exists for the compensated form only");
+  if (s.pair < 0 || s.pair > 2)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "pair_form must be 0, 1 or 2 (got %d)", s.pair);
+  if (s.pair == 2 && prec != VESNET_FP32_COMPENSATED)
+    return fail(VESNET_ERR_UNSUPPORTED, "the symmetric pair form exists for the compensated form only");
+  if (s.pair == 2 && s.accumulate == 2)
+    return fail(VESNET_ERR_UNSUPPORTED, "the symmetric pair form accumulates on the VALU only");
+  if (s.pair == 2 && s.symT == 0) s.symT = 1;
   *out = s;
   return VESNET_OK;
 }
 
+// Forward workspace: prepared region, then the direct form's split partials and the symmetric
+// form's region (both when the form is chosen per call).
 size_t forward_bytes(int32_t P, int32_t M, int prec, const Shape& s) {
-  size_t b = kAlign + prepared_bytes(P, M, prec);
-  if (s.splits > 1) b += align_up((size_t)2 * s.splits * P * sizeof(double));
+  size_t b = kAlign + prepared_bytes(P, M, prec, fwd_forces(prec));
+  if (s.pair != 2 && s.splits > 1) b += align_up((size_t)2 * s.splits * P * sizeof(double));
+  if (prec == P32C && s.pair != 1) b += symmetric_bytes(P, M);
   return b;
 }
 
@@ -209,6 +273,7 @@ extern "C" int vesnet_default_tile_config(int32_t P, int32_t M, int prec, vesnet
   cfg->blocks_per_cu = s.bpc;
   cfg->source_staging = s.staging;
   cfg->accumulate = s.accumulate;
+  cfg->pair_form = s.pair;
   return ok();
 }
 
@@ -226,14 +291,42 @@ extern "C" int vesnet_farfield_prepare(const double* sources, const double* f, c
   int rc = check_forward_args(nullptr, sources, f, w, off, M, P, nullptr, prec, ws, ws_bytes, false, true);
   if (rc) return rc;
   if (P == 0) return ok();
-  const size_t need = kAlign + prepared_bytes(P, M, prec);
+  const size_t need = kAlign + prepared_bytes(P, M, prec, fwd_forces(prec));
   if ((rc = check_workspace(ws, ws_bytes, need))) return rc;
   char* cur = aligned_base(ws);
-  PreparedView pv = carve_prepared(cur, P, M, prec);
+  PreparedView pv = carve_prepared(cur, P, M, prec, fwd_forces(prec));
   hipError_t e = launch_prepare(prec, sources, f, w, off, M, P, pv, stream);
   if (e != hipSuccess) return hip_fail(e, "prepare launch");
   return ok();
 }
+
+namespace {
+
+// Evaluation from a prepared workspace with a resolved shape; symmetric selects the form that
+// evaluates each unordered pair once (targets must be the prepared sources).
+int evaluate_resolved(const double* targets, int32_t M, int32_t P, double mu, double* out, int prec, const Shape& s,
+                      bool symmetric, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_workspace(ws, ws_bytes, forward_bytes(P, M, prec, s)))) return rc;
+  char* cur = aligned_base(ws);
+  PreparedView pv = carve_prepared(cur, P, M, prec, fwd_forces(prec));
+  const double scale = 1.0 / (4.0 * kPi * mu);
+  hipError_t e;
+  if (symmetric) {
+    if (s.pair != 2 && s.splits > 1) cur += align_up((size_t)2 * s.splits * P * sizeof(double));
+    SymmetricView sv = carve_symmetric(cur, P, M);
+    e = launch_forward_symmetric(s.symT, P, M, pv, sv, scale, out, stream);
+    if (e != hipSuccess) return hip_fail(e, "symmetric forward launch");
+  } else {
+    double* partial = s.splits > 1 ? reinterpret_cast<double*>(cur) : nullptr;
+    e = launch_forward(prec, s.T, s.B, s.staging == 2, s.accumulate == 2, s.splits, targets, P, M, pv, scale, out,
+                       partial, stream);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+  }
+  return ok();
+}
+
+}  // namespace
 
 extern "C" int vesnet_farfield_evaluate(const double* targets, const int32_t* off, int32_t M, int32_t P, double mu,
                                         double* out, int prec, const vesnet_tile_config* cfg, void* ws,
@@ -245,15 +338,7 @@ extern "C" int vesnet_farfield_evaluate(const double* targets, const int32_t* of
   if (!out) return fail(VESNET_ERR_INVALID_ARGUMENT, "out is NULL");
   Shape s;
   if ((rc = resolve_shape(cfg, P, M, prec, &s))) return rc;
-  if ((rc = check_workspace(ws, ws_bytes, forward_bytes(P, M, prec, s)))) return rc;
-  char* cur = aligned_base(ws);
-  PreparedView pv = carve_prepared(cur, P, M, prec);
-  double* partial = s.splits > 1 ? reinterpret_cast<double*>(cur) : nullptr;
-  const double scale = 1.0 / (4.0 * kPi * mu);
-  hipError_t e = launch_forward(prec, s.T, s.B, s.staging == 2, s.accumulate == 2, s.splits, targets, P, M, pv,
-                                scale, out, partial, stream);
-  if (e != hipSuccess) return hip_fail(e, "forward launch");
-  return ok();
+  return evaluate_resolved(targets, M, P, mu, out, prec, s, s.pair == 2, ws, ws_bytes, stream);
 }
 
 extern "C" int vesnet_farfield_stokeslet(const double* targets, const double* sources, const double* f,
@@ -267,9 +352,13 @@ extern "C" int vesnet_farfield_stokeslet(const double* targets, const double* so
   if (!out) return fail(VESNET_ERR_INVALID_ARGUMENT, "out is NULL");
   Shape s;
   if ((rc = resolve_shape(cfg, P, M, prec, &s))) return rc;
+  if (s.pair == 2 && targets != sources)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "the symmetric pair form needs targets == sources (one point array)");
+  const bool symmetric =
+      s.pair == 2 || (s.pair == 0 && targets == sources && prec == P32C && s.accumulate == 1 && s.symT > 0);
   if ((rc = check_workspace(ws, ws_bytes, forward_bytes(P, M, prec, s)))) return rc;
   if ((rc = vesnet_farfield_prepare(sources, f, w, off, M, P, prec, ws, ws_bytes, stream))) return rc;
-  return vesnet_farfield_evaluate(targets, off, M, P, mu, out, prec, cfg, ws, ws_bytes, stream);
+  return evaluate_resolved(targets, M, P, mu, out, prec, s, symmetric, ws, ws_bytes, stream);
 }
 
 // ============================================================================ membrane force
@@ -538,7 +627,7 @@ extern "C" int vesnet_farfield_stokeslet_nearmasked(const double* targets, const
   if (P > 0) {
     if ((rc = vesnet_farfield_prepare(sources, f, w, off, M, P, prec, ws, ws_bytes, stream))) return rc;
     char* cur = aligned_base(ws);
-    pv = carve_prepared(cur, P, M, prec);
+    pv = carve_prepared(cur, P, M, prec, fwd_forces(prec));
     partial = s.splits > 1 ? reinterpret_cast<double*>(cur) : nullptr;
   }
   const double scale = 1.0 / (4.0 * kPi * mu);

@@ -37,6 +37,16 @@ struct PreparedView {
   double4* vtab;   // [M]   (c_x, c_y, B_x, B_y): reference point and net weighted vector
   double* hlen;    // [M]   mean arclength spacing sum_j w_j / N_v
   void* rec;       // [P]   streamed records: float4 (P32C, P32N) or double4 (P64)
+  double2* f64;    // [P]   forward P32C only: w_j f_j in float64 (the symmetric form's corrections)
+  double2* vaux;   // [M]   forward P32C only: (sum_j |w_j f_j|_1, max_j |y_j - c_v|^2) per vesicle
+};
+
+// Device views of the symmetric form's region (after the prepared region).
+struct SymmetricView {
+  int4* cyc;                 // [P/16 + M + 1] cycles: (first point, count <= 16, vesicle, 0)
+  int32_t* meta;             // [0] number of cycles, [1] fixed-point exponent S, [2] number of blocks
+  double2* fcyc;             // [P/16 + M + 1] float64 net force w f of each cycle
+  unsigned long long* acc;   // [2][P] fixed-point sums (two's complement int64 at 2^-S)
 };
 
 // Device views of the batched work plan.
@@ -52,6 +62,13 @@ hipError_t launch_prepare(int prec, const double* pts, const double* vec, const 
                           int M, int P, const PreparedView& pv, void* stream);
 hipError_t launch_forward(int prec, int T, int B, bool lds, bool mf, int splits, const double* tg, int P, int M,
                           const PreparedView& pv, double scale, double* out, double* partial, void* stream);
+// Symmetric form (float32-compensated, targets = sources): sizes of its tables and the launch.
+int sym_cycles_per_block(int T);
+int64_t sym_max_cycles(int P, int M);
+int64_t sym_max_blocks(int P, int M, int T);
+int64_t sym_units(int64_t nb);
+hipError_t launch_forward_symmetric(int T, int P, int M, const PreparedView& pv, const SymmetricView& sv,
+                                    double scale, double* out, void* stream);
 hipError_t launch_forward_near(int prec, int T, bool lds, int splits, const double* tg, int P, int M,
                                const PreparedView& pv, double scale, double* out, double* partial, int32_t* count,
                                int32_t* pairs, int32_t capacity, void* stream);

@@ -46,24 +46,29 @@ __device__ __forceinline__ double wave_sum(double x) {
 // Output per vesicle: range (j0, j1) clamped into [0, P], vtab = (c_x, c_y, B_x, B_y) with
 // c = mean of the points and B = sum of weighted vectors (float64, fixed-order wave tree);
 // per point: vid and the record: P32C (y - c, w vec) float32, P32N (y, w vec) float32,
-// P64 (y, w vec) float64.
+// P64 (y, w vec) float64.  When f64 / vaux are given: w vec per point in float64, and per
+// vesicle the sum of |w vec|_1 (fixed-order wave tree) and the largest squared distance of a
+// point from c.
 template <int PREC>
 __global__ __launch_bounds__(64) void k_prepare(const double* __restrict__ pts, const double* __restrict__ vec,
                                                 const double* __restrict__ wts, const int32_t* __restrict__ off_in,
                                                 int M, int P, int2* __restrict__ vrange, int32_t* __restrict__ vid,
                                                 double4* __restrict__ vtab, double* __restrict__ hlen,
-                                                void* __restrict__ rec) {
+                                                void* __restrict__ rec, double2* __restrict__ f64,
+                                                double2* __restrict__ vaux) {
   const int lane = threadIdx.x;
   for (int v = blockIdx.x; v < M; v += gridDim.x) {
     const int j0 = clampi(off_in[v], 0, P);
     const int j1 = max(j0, clampi(off_in[v + 1], 0, P));
-    double sx = 0.0, sy = 0.0, bx = 0.0, by = 0.0, sw = 0.0;
+    double sx = 0.0, sy = 0.0, bx = 0.0, by = 0.0, sw = 0.0, sa = 0.0;
     for (int j = j0 + lane; j < j1; j += 64) {
       const double wj = wts ? wts[j] : 1.0;
       sx += pts[j];
       sy += pts[P + j];
-      bx += wj * vec[j];
-      by += wj * vec[P + j];
+      const double ex = wj * vec[j], ey = wj * vec[P + j];
+      bx += ex;
+      by += ey;
+      sa += fabs(ex) + fabs(ey);
       sw += wj;
     }
     sx = wave_sum(sx);
@@ -71,6 +76,7 @@ __global__ __launch_bounds__(64) void k_prepare(const double* __restrict__ pts, 
     bx = wave_sum(bx);
     by = wave_sum(by);
     sw = wave_sum(sw);
+    if (vaux) sa = wave_sum(sa);
     const int n = j1 - j0;
     const double cx = n > 0 ? sx / n : 0.0;
     const double cy = n > 0 ? sy / n : 0.0;
@@ -79,11 +85,14 @@ __global__ __launch_bounds__(64) void k_prepare(const double* __restrict__ pts, 
       vtab[v] = make_double4(cx, cy, bx, by);
       hlen[v] = n > 0 ? sw / n : 0.0;
     }
+    double r2 = 0.0;
     for (int j = j0 + lane; j < j1; j += 64) {
       const double wj = wts ? wts[j] : 1.0;
       const double x = pts[j], y = pts[P + j];
       const double ex = wj * vec[j], ey = wj * vec[P + j];
       vid[j] = v;
+      if (f64) f64[j] = make_double2(ex, ey);
+      r2 = fmax(r2, (x - cx) * (x - cx) + (y - cy) * (y - cy));
       if constexpr (PREC == P32C) {
         static_cast<float4*>(rec)[j] = make_float4((float)(x - cx), (float)(y - cy), (float)ex, (float)ey);
       } else if constexpr (PREC == P32N) {
@@ -91,6 +100,11 @@ __global__ __launch_bounds__(64) void k_prepare(const double* __restrict__ pts, 
       } else {
         static_cast<double4*>(rec)[j] = make_double4(x, y, ex, ey);
       }
+    }
+    if (vaux) {
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) r2 = fmax(r2, __shfl_xor(r2, m, 64));
+      if (lane == 0) vaux[v] = make_double2(sa, r2);
     }
   }
 }
@@ -700,11 +714,11 @@ hipError_t launch_prepare(int prec, const double* pts, const double* vec, const 
   const int grid = M < 65535 ? M : 65535;
   switch (prec) {
     case P64: hipLaunchKernelGGL(k_prepare<P64>, dim3(grid), dim3(64), 0, S_(stream), pts, vec, wts, off, M, P,
-                                 pv.vrange, pv.vid, pv.vtab, pv.hlen, pv.rec); break;
+                                 pv.vrange, pv.vid, pv.vtab, pv.hlen, pv.rec, pv.f64, pv.vaux); break;
     case P32C: hipLaunchKernelGGL(k_prepare<P32C>, dim3(grid), dim3(64), 0, S_(stream), pts, vec, wts, off, M, P,
-                                  pv.vrange, pv.vid, pv.vtab, pv.hlen, pv.rec); break;
+                                  pv.vrange, pv.vid, pv.vtab, pv.hlen, pv.rec, pv.f64, pv.vaux); break;
     case P32N: hipLaunchKernelGGL(k_prepare<P32N>, dim3(grid), dim3(64), 0, S_(stream), pts, vec, wts, off, M, P,
-                                  pv.vrange, pv.vid, pv.vtab, pv.hlen, pv.rec); break;
+                                  pv.vrange, pv.vid, pv.vtab, pv.hlen, pv.rec, pv.f64, pv.vaux); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

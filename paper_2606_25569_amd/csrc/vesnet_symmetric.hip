@@ -1,0 +1,476 @@
+// Symmetric far-field kernel for gfx950: each unordered cross-vesicle pair is evaluated once.
+//
+// The Stokeslet of eq. (Stokeslet), read as -ln|r| I + r r^T/|r|^2, is even in r, and the
+// trapezoid sum of eq. (single_layer) (Section 2.2.1) taken at the discretisation points
+// themselves uses every point as target and as source.  One evaluation of r, |r|^2, its
+// logarithm and its reciprocal therefore serves both ordered pairs (i <- j and j <- i), which
+// halves the transcendental instructions of the direct gather (26 issue slots per unordered pair,
+// 13 per ordered pair, against 19.6).  Only the float32-compensated precision uses this form.
+//
+// Work decomposition
+//  * Points are cut into "cycles" of at most 16 consecutive points of one vesicle (a vesicle of
+//    N points gives ceil(N/16) cycles); CB = 32 T consecutive cycles form a block.
+//  * A unit is an unordered pair of blocks {bx, by}, by = bx + d (mod nb), d = 0 .. nb/2 (the
+//    circulant schedule visits every unordered pair of blocks once; for even nb the pairs at
+//    d = nb/2 are taken by bx < nb/2 only).  One workgroup of 512 threads (8 wavefronts, 32 rows
+//    of 16 lanes) evaluates a unit: row r holds target cycles r, r + 32, ... of block bx (T of
+//    them, one point per lane), and the source cycles of block by stream through LDS in chunks
+//    of 16 cycles.
+//  * Each row is a ring: at step s lane p pairs its T targets with source (p + s) mod 16 of the
+//    current source cycle, read from LDS (each cycle is stored twice so that the address is the
+//    lane's base plus an immediate offset).  The source's column sum travels with it around the
+//    ring, by a DPP row rotation folded into the add that closes each step.  After 16 steps two
+//    lane swaps (v_permlane32_swap, v_permlane16_swap) add the four rows of a wavefront, the
+//    column sums go to LDS, and after each chunk the workgroup adds its 8 wavefronts in a fixed
+//    order.
+//  * Own vesicle and the diagonal unit (d = 0): a (target cycle, source vesicle) pair is active
+//    when the vesicles differ and, for d = 0, when the target's vesicle index is the smaller one,
+//    so every unordered cross-vesicle pair is evaluated once.  Inactive targets sit at a far
+//    point with zero force: their column contributions are exact zeros and their row partials
+//    are dropped by a select.  Slots of a cycle past its count hold a copy of the cycle's first
+//    point with zero force (exact zeros in the rows; their column sums are never read).
+//
+// Compensation (float32 pairs, float64 corrections)
+//  * For a target of vesicle A and a source vesicle B the pair loop runs on the rescaled
+//    difference r' = 2^-k (x_i - y_j) = 2^-k (xi_i + c_A - c_B) - 2^-k xi_j, with xi the float32
+//    local coordinates about each vesicle's point mean c and k = floor(e/2) for
+//    |c_A - c_B|^2 + R_A^2 + R_B^2 = m 2^e (R the largest |xi| of a vesicle): |r'| is of order one
+//    for distant vesicles and bounded for overlapping hulls.  Scaling by a power of two is exact,
+//    so ln|r|^2 = ln 2 (log2|r'|^2 + 2k) exactly, and the rr-term is unchanged.
+//  * Row (target, segment of B in the block): float32 partial of -1/2 ln2 log2|r'|^2 F_j + rr-term,
+//    then in float64  - k ln2 F_seg, F_seg the float64 net force of the segment (the sum of its
+//    cycles' float64 net forces).
+//  * Column (source j of B, from the targets of one wavefront): float32 partial of the same terms
+//    with the targets' forces; the log correction - ln2 sum_cycles k F_cycle (float64) is the same
+//    for every source of B and is formed once per (wavefront, B).
+//    A distant force-free vesicle's nearly constant log therefore never enters a float32 sum.
+//
+// Accumulation across workgroups is deterministic: every row and column partial is added in
+// float64, rounded to a 64-bit fixed-point integer at 2^-S (S from a bound on every partial sum,
+// 520 sum_j |F_j|_1 < 2^(62 - S)) and added with 64-bit integer atomics, whose result does not
+// depend on their order.  A last kernel converts the integers back and scales by 1/(4 pi mu).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "vesnet_internal.h"
+
+namespace vesnet {
+
+namespace {
+
+constexpr int kRing = 16;                          // sources per ring cycle (one DPP row)
+constexpr int kSymThreads = 512;                   // threads per unit (8 wavefronts)
+constexpr int kSymWaves = kSymThreads / 64;
+constexpr int kRows = kSymThreads / kRing;         // rows of 16 lanes per unit
+constexpr int kChunk = 16;                         // source cycles per LDS chunk
+constexpr double kLn2d = 0.69314718055994530942;
+constexpr float kHalfLn2f = -0.34657359027997265471f;  // -(1/2) ln 2: log2|r|^2 -> -ln|r|
+constexpr float kFar = 1152921504606846976.0f;         // 2^60: position of an inactive target
+constexpr int kMaxShift = 60;                          // |k| bound of the power-of-two rescaling
+
+__device__ __forceinline__ float bitsf(unsigned x) { return __builtin_bit_cast(float, x); }
+__device__ __forceinline__ unsigned bitsu(float x) { return __builtin_bit_cast(unsigned, x); }
+
+// x from the lane one position up in the same row of 16 lanes (lane p reads lane (p + 1) mod 16).
+__device__ __forceinline__ float ring_next(float x) {
+  return bitsf((unsigned)__builtin_amdgcn_update_dpp(0, (int)bitsu(x), 0x12F, 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+
+// Plan: the cycle table of every vesicle in point order, the number of blocks and the
+// fixed-point exponent.  One workgroup of 1024 threads; everything in a fixed order.
+__global__ __launch_bounds__(1024) void k_sym_plan(const int2* __restrict__ vrange, const double2* __restrict__ vaux,
+                                                   int M, int cb, int ncyc_max, int4* __restrict__ cyc,
+                                                   int32_t* __restrict__ meta) {
+  __shared__ int32_t s_wsum[16];
+  __shared__ double s_dsum[16];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int run = 0;
+  double fa = 0.0;
+  for (int base = 0; base < M; base += 1024) {
+    const int v = base + t;
+    const int2 r = v < M ? vrange[v] : make_int2(0, 0);
+    const int n = max(0, r.y - r.x);
+    const int cnt = (n + kRing - 1) / kRing;
+    if (v < M) fa += vaux[v].x;
+    int x = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_wsum[wv] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
+    for (int k = 0; k < 16; ++k) {
+      const int s = s_wsum[k];
+      pre += k < wv ? s : 0;
+      tot += s;
+    }
+    const int first = run + pre + x - cnt;
+    for (int c = 0; c < cnt; ++c) {
+      const int e = first + c;
+      if (e < ncyc_max) cyc[e] = make_int4(r.x + kRing * c, min(kRing, n - kRing * c), v, 0);
+    }
+    run += tot;
+    __syncthreads();
+  }
+  fa = wave_sum_d(fa);
+  if (lane == 0) s_dsum[wv] = fa;
+  __syncthreads();
+  if (t == 0) {
+    double tot = 0.0;
+    for (int k = 0; k < 16; ++k) tot += s_dsum[k];
+    const int ncyc = min(run, ncyc_max);
+    meta[0] = ncyc;
+    // Every term of every partial sum is at most (|ln q|/2 + 1) |F|_1 <= 520 |F|_1 in magnitude
+    // (log2|r'|^2 within the float32 range, |k| <= 60), so every partial sum of the fixed-point
+    // integers stays below 2^62.
+    const double bound = 520.0 * tot;
+    int S = 0;
+    if (bound > 0.0 && isfinite(bound)) {
+      int e;
+      frexp(bound, &e);  // bound < 2^e
+      S = 62 - e;
+    }
+    meta[1] = S;
+    meta[2] = (ncyc + cb - 1) / cb;
+  }
+}
+
+// Float64 net force of every cycle (its points in order), and the zeroed fixed-point
+// accumulator (grid-stride over all 2P entries).
+__global__ __launch_bounds__(256) void k_sym_cycles(const int4* __restrict__ cyc, const int32_t* __restrict__ meta,
+                                                    const double2* __restrict__ f64, int P,
+                                                    double2* __restrict__ fcyc, unsigned long long* __restrict__ acc) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t first = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int64_t e = first; e < 2 * (int64_t)P; e += stride) acc[e] = 0ull;
+  const int ncyc = meta[0];
+  for (int64_t c = first; c < ncyc; c += stride) {
+    const int4 cy = cyc[c];
+    double sx = 0.0, sy = 0.0;
+    for (int m = 0; m < cy.y; ++m) {
+      const double2 F = f64[cy.x + m];
+      sx += F.x;
+      sy += F.y;
+    }
+    fcyc[c] = make_double2(sx, sy);
+  }
+}
+
+// One unit {bx, by} per workgroup (see the file header).
+template <int T>
+__global__ __launch_bounds__(kSymThreads) void k_sym_main(
+    int P, const double4* __restrict__ vtab, const double2* __restrict__ vaux, const float4* __restrict__ rec,
+    const int4* __restrict__ cyc, const double2* __restrict__ fcyc, const int32_t* __restrict__ meta,
+    unsigned long long* __restrict__ acc) {
+  constexpr int CB = kRows * T;  // cycles per block
+  __shared__ float4 s_tx[CB][kRing];               // target records (local coordinates, w f)
+  __shared__ double4 s_tc[CB];                     // (c_A, F_cycle) of each target cycle
+  __shared__ double s_tr[CB];                      // R_A^2
+  __shared__ int4 s_ti[CB];                        // (vesicle or -1, count, first point, 0)
+  __shared__ float4 s_rec[2][kChunk][2 * kRing];   // source cycles, each stored twice
+  __shared__ float s_col[2][kSymWaves][kChunk][2][kRing];
+  __shared__ double2 s_E[2][kSymWaves][kChunk];
+
+  const int ncyc = meta[0];
+  const int S = meta[1];
+  const int nb = meta[2];
+  if (nb <= 0) return;
+  const int Dh = nb >> 1;
+  const int units = (nb & 1) ? nb * (Dh + 1) : nb * Dh + Dh;
+  const int u = blockIdx.x;
+  if (u >= units) return;
+  const int d = u / nb;
+  const int bx = u - d * nb;
+  int by = bx + d;
+  if (by >= nb) by -= nb;
+  const bool diag = d == 0;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, p = lane & 15;
+  const int row = tid >> 4;
+  const int tc0 = bx * CB, tc1 = min(ncyc, tc0 + CB);
+  const int sc0 = by * CB, sc1 = min(ncyc, sc0 + CB);
+
+  // Target block into LDS.
+  for (int e = tid; e < CB * kRing; e += kSymThreads) {
+    const int t = e / kRing, m = e % kRing;
+    const int c = tc0 + t;
+    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (c < tc1) {
+      const int4 cy = cyc[c];
+      if (m < cy.y) r = rec[cy.x + m];
+    }
+    s_tx[t][m] = r;
+  }
+  for (int t = tid; t < CB; t += kSymThreads) {
+    const int c = tc0 + t;
+    if (c < tc1) {
+      const int4 cy = cyc[c];
+      const double4 vt = vtab[cy.z];
+      const double2 F = fcyc[c];
+      s_tc[t] = make_double4(vt.x, vt.y, F.x, F.y);
+      s_tr[t] = vaux[cy.z].y;
+      s_ti[t] = make_int4(cy.z, cy.y, cy.x, 0);
+    } else {
+      s_tc[t] = make_double4(0.0, 0.0, 0.0, 0.0);
+      s_tr[t] = 0.0;
+      s_ti[t] = make_int4(-1, 0, 0, 0);
+    }
+  }
+
+  // State of the current source segment, per target slot k (target cycle k * 32 + row).
+  float dx[T], dy[T], ns[T], fcx[T], fcy[T], fhx[T], fhy[T], lx[T], ly[T], rvx[T], rvy[T];
+  double ax[T], ay[T];
+  int kq[T];
+  int actm = 0;
+  double Ex = 0.0, Ey = 0.0, Fsx = 0.0, Fsy = 0.0;
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    dx[k] = dy[k] = ns[k] = fcx[k] = fcy[k] = fhx[k] = fhy[k] = 0.f;
+    lx[k] = ly[k] = rvx[k] = rvy[k] = 0.f;
+    ax[k] = ay[k] = 0.0;
+    kq[k] = 0;
+  }
+
+  auto setup = [&](int B) {
+    const double4 vb = vtab[B];
+    const double rb2 = vaux[B].y;
+    double ex = 0.0, ey = 0.0;
+    actm = 0;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const int t = k * kRows + row;
+      const int4 ti = s_ti[t];
+      const double4 tc = s_tc[t];
+      const float4 tx = s_tx[t][p];
+      const double Dx = tc.x - vb.x, Dy = tc.y - vb.y;
+      const double D = fma(Dy, Dy, fma(Dx, Dx, s_tr[t] + rb2));
+      int e;
+      frexp(D, &e);
+      const int kk = min(kMaxShift, max(-kMaxShift, e >> 1));
+      const bool rowact = ti.x >= 0 && ti.x != B && (!diag || ti.x < B);
+      const bool act = rowact && p < ti.y;
+      actm |= act ? (1 << k) : 0;
+      const float sc = ldexpf(1.0f, -kk);
+      dx[k] = act ? fmaf(tx.x, sc, (float)ldexp(Dx, -kk)) : kFar;
+      dy[k] = act ? fmaf(tx.y, sc, (float)ldexp(Dy, -kk)) : 0.f;
+      ns[k] = -sc;
+      fcx[k] = act ? tx.z : 0.f;
+      fcy[k] = act ? tx.w : 0.f;
+      fhx[k] = kHalfLn2f * fcx[k];
+      fhy[k] = kHalfLn2f * fcy[k];
+      kq[k] = kk;
+      lx[k] = ly[k] = rvx[k] = rvy[k] = 0.f;
+      ex += rowact ? (double)kk * tc.z : 0.0;
+      ey += rowact ? (double)kk * tc.w : 0.0;
+    }
+    // the 16 lanes of a row hold the same value: add the four rows of the wavefront
+    ex += __shfl_xor(ex, 16, 64);
+    ey += __shfl_xor(ey, 16, 64);
+    ex += __shfl_xor(ex, 32, 64);
+    ey += __shfl_xor(ey, 32, 64);
+    Ex = -kLn2d * ex;
+    Ey = -kLn2d * ey;
+    Fsx = Fsy = 0.0;
+  };
+
+  auto flush = [&]() {
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const float pvx = fmaf(kHalfLn2f, lx[k], rvx[k]);
+      const float pvy = fmaf(kHalfLn2f, ly[k], rvy[k]);
+      const double c = -kLn2d * (double)kq[k];
+      const bool act = (actm >> k) & 1;
+      ax[k] += act ? fma(c, Fsx, (double)pvx) : 0.0;
+      ay[k] += act ? fma(c, Fsy, (double)pvy) : 0.0;
+    }
+  };
+
+  // One ring cycle over the 16 sources of LDS cycle slot cc.
+  auto ring = [&](int buf, int cc) {
+    const float4* rb = &s_rec[buf][cc][p];
+    float cax = 0.f, cay = 0.f;
+#pragma unroll 2
+    for (int s = 0; s < kRing; ++s) {
+      const float4 sr = rb[s];
+      float lcx = 0.f, lcy = 0.f;
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const float rx = fmaf(sr.x, ns[k], dx[k]);
+        const float ry = fmaf(sr.y, ns[k], dy[k]);
+        const float q = fmaf(ry, ry, rx * rx);
+        const float L = __builtin_amdgcn_logf(q);
+        const float rho = __builtin_amdgcn_rcpf(q);
+        const float rxr = rx * rho, ryr = ry * rho;
+        const float b = fmaf(ryr, sr.w, rxr * sr.z);       // (r . F_j)/q
+        lx[k] = fmaf(L, sr.z, lx[k]);
+        ly[k] = fmaf(L, sr.w, ly[k]);
+        rvx[k] = fmaf(b, rx, rvx[k]);
+        rvy[k] = fmaf(b, ry, rvy[k]);
+        const float b2 = fmaf(ryr, fcy[k], rxr * fcx[k]);  // (r . F_i)/q
+        if (k == 0) {
+          lcx = L * fhx[k];
+          lcy = L * fhy[k];
+        } else {
+          lcx = fmaf(L, fhx[k], lcx);
+          lcy = fmaf(L, fhy[k], lcy);
+        }
+        lcx = fmaf(b2, rx, lcx);
+        lcy = fmaf(b2, ry, lcy);
+      }
+      cax = ring_next(cax) + lcx;
+      cay = ring_next(cay) + lcy;
+    }
+    // lane p now holds source (p + 15) mod 16 of its row; add the four rows: x sums end in lanes
+    // 0-31, y sums in lanes 32-63, then every row of a half holds the half's total
+    const auto h = __builtin_amdgcn_permlane32_swap(bitsu(cax), bitsu(cay), false, false);
+    const float z = bitsf(h[0]) + bitsf(h[1]);
+    const auto r16 = __builtin_amdgcn_permlane16_swap(bitsu(z), bitsu(z), false, false);
+    const float tot = bitsf(r16[0]) + bitsf(r16[1]);
+    if ((lane & 16) == 0) s_col[buf][wv][cc][lane >> 5][(p + kRing - 1) & (kRing - 1)] = tot;
+  };
+
+  // Records of source chunk g: slots 0..15 and again 16..31; slots past the cycle's count repeat
+  // its first point with zero force.
+  const int nchunks = (sc1 - sc0 + kChunk - 1) / kChunk;
+  const int st_cc = tid >> 5, st_q = tid & 31, st_m = st_q & (kRing - 1);
+  auto stage_load = [&](int g) {
+    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int c = sc0 + g * kChunk + st_cc;
+    if (c < sc1) {
+      const int4 cy = cyc[c];
+      r = rec[cy.x + (st_m < cy.y ? st_m : 0)];
+      if (st_m >= cy.y) r.z = r.w = 0.f;
+    }
+    return r;
+  };
+  auto stage_store = [&](int buf, const float4& r) { s_rec[buf][st_cc][st_q] = r; };
+
+  // Column sums of chunk g: the wavefronts and their log corrections added in a fixed order,
+  // then one fixed-point integer per (source, component).
+  auto reduce = [&](int g, int buf) {
+    const int cc = tid >> 5, comp = (tid >> 4) & 1, m = tid & (kRing - 1);
+    const int c = sc0 + g * kChunk + cc;
+    if (c >= sc1) return;
+    const int4 cy = cyc[c];
+    if (m >= cy.y) return;
+    double s = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < kSymWaves; ++w2) s += (double)s_col[buf][w2][cc][comp][m];
+    double e = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < kSymWaves; ++w2) {
+      const double2 E = s_E[buf][w2][cc];
+      e += comp ? E.y : E.x;
+    }
+    const long long X = (long long)rint(ldexp(s + e, S));
+    atomicAdd(&acc[(size_t)comp * P + cy.x + m], (unsigned long long)X);
+  };
+
+  int curB = -1;
+  stage_store(0, stage_load(0));
+  __syncthreads();
+  for (int g = 0; g < nchunks; ++g) {
+    const int buf = g & 1;
+    const float4 nxt = stage_load(g + 1);
+    if (g > 0) reduce(g - 1, buf ^ 1);
+    const int cbase = sc0 + g * kChunk;
+    const int ncc = min(kChunk, sc1 - cbase);
+    for (int cc = 0; cc < ncc; ++cc) {
+      const int4 cy = cyc[cbase + cc];
+      if (cy.z != curB) {
+        if (curB >= 0) flush();
+        setup(cy.z);
+        curB = cy.z;
+      }
+      const double2 Fc = fcyc[cbase + cc];
+      Fsx += Fc.x;
+      Fsy += Fc.y;
+      ring(buf, cc);
+      if (lane == 0) s_E[buf][wv][cc] = make_double2(Ex, Ey);
+    }
+    stage_store(buf ^ 1, nxt);
+    __syncthreads();
+  }
+  if (nchunks > 0) {
+    reduce(nchunks - 1, (nchunks - 1) & 1);
+    flush();
+  }
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    const int4 ti = s_ti[k * kRows + row];
+    if (ti.x >= 0 && p < ti.y) {
+      const int i = ti.z + p;
+      atomicAdd(&acc[i], (unsigned long long)(long long)rint(ldexp(ax[k], S)));
+      atomicAdd(&acc[(size_t)P + i], (unsigned long long)(long long)rint(ldexp(ay[k], S)));
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sym_finish(const unsigned long long* __restrict__ acc,
+                                                    const int32_t* __restrict__ meta, int P, double scale,
+                                                    double* __restrict__ out) {
+  const int S = meta[1];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 2 * (int64_t)P;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = ldexp((double)(long long)acc[e] * scale, -S);
+}
+
+}  // namespace
+
+static inline hipStream_t Sx_(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int sym_cycles_per_block(int T) { return kRows * T; }
+
+int64_t sym_max_cycles(int P, int M) { return (int64_t)P / kRing + (int64_t)M + 1; }
+
+int64_t sym_max_blocks(int P, int M, int T) {
+  const int cb = sym_cycles_per_block(T);
+  return (sym_max_cycles(P, M) + cb - 1) / cb;
+}
+
+int64_t sym_units(int64_t nb) {
+  if (nb <= 0) return 0;
+  const int64_t h = nb / 2;
+  return (nb & 1) ? nb * (h + 1) : nb * h + h;
+}
+
+hipError_t launch_forward_symmetric(int T, int P, int M, const PreparedView& pv, const SymmetricView& sv,
+                                    double scale, double* out, void* stream) {
+  if (P == 0) return hipSuccess;
+  hipStream_t st = Sx_(stream);
+  const int cb = sym_cycles_per_block(T);
+  const int ncyc_max = (int)sym_max_cycles(P, M);
+  const int nb_max = (int)sym_max_blocks(P, M, T);
+  hipLaunchKernelGGL(k_sym_plan, dim3(1), dim3(1024), 0, st, pv.vrange, pv.vaux, M, cb, ncyc_max, sv.cyc, sv.meta);
+  const int cgrid = (int)std::min<int64_t>((2 * (int64_t)P + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_sym_cycles, dim3(cgrid), dim3(256), 0, st, sv.cyc, sv.meta, pv.f64, P, sv.fcyc, sv.acc);
+  const dim3 grid((unsigned)sym_units(nb_max));
+  const float4* rec = static_cast<const float4*>(pv.rec);
+  switch (T) {
+#define VESNET_SYM_CASE(TT)                                                                                    \
+  case TT:                                                                                                     \
+    hipLaunchKernelGGL(k_sym_main<TT>, grid, dim3(kSymThreads), 0, st, P, pv.vtab, pv.vaux, rec, sv.cyc,      \
+                       sv.fcyc, sv.meta, sv.acc);                                                               \
+    break;
+    VESNET_SYM_CASE(1) VESNET_SYM_CASE(2) VESNET_SYM_CASE(4) VESNET_SYM_CASE(8)
+#undef VESNET_SYM_CASE
+    default: return hipErrorInvalidValue;
+  }
+  const int64_t n = 2 * (int64_t)P;
+  const int fgrid = (int)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
+  hipLaunchKernelGGL(k_sym_finish, dim3(fgrid), dim3(256), 0, st, sv.acc, sv.meta, P, scale, out);
+  return hipGetLastError();
+}
+
+}  // namespace vesnet

@@ -324,7 +324,7 @@ class _FarField(torch.autograd.Function):
         out = farfield_forward(targets, sources, force_density, arc_weights, part, mu, precision, config)
         ctx.save_for_backward(targets, sources, force_density, arc_weights)
         ctx.part, ctx.mu = part, mu
-        ctx.precision = "fp64" if L.precision_code(precision) == L.FP64 else "fp32c"
+        ctx.precision = L.precision_code(precision)
         return out
 
     @staticmethod
@@ -333,6 +333,8 @@ class _FarField(torch.autograd.Function):
         need = ctx.needs_input_grad[:4]
         if not any(need):
             return (None,) * 8
+        if ctx.precision == L.FP32_NAIVE:
+            raise L.VesnetError(L.ERR_UNSUPPORTED, "the naive float32 control has no backward; use 'fp32c' or 'fp64'")
         g = grad_out.contiguous()
         gt, gs, gf, gw = farfield_backward(targets, sources, f, w, ctx.part, ctx.mu, g, ctx.precision, need)
         return gt, gs, gf, gw, None, None, None, None

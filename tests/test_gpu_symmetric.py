@@ -1,0 +1,171 @@
+"""GPU parity of the symmetric float32-compensated forward (each unordered pair evaluated once)
+against the CPU oracle, through the C-ABI.
+
+The symmetric form runs when targets and sources are one array: pair_form 2 forces it, and the
+automatic choice takes it for large problems.  Bar: <= 1e-5 in max-norm error relative to
+max |u| (component-wise), as for the direct compensated form.  Its partial sums are added as
+fixed-point integers, so repeated calls must agree bit for bit.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import suspension as S
+from tests.gpu_util import dev_inputs, rel_err, say
+
+pytestmark = pytest.mark.gpu
+
+BAR = 1e-5
+
+
+@pytest.fixture(scope="module")
+def V():
+    import paper_2606_25569_amd as V
+    return V
+
+
+def _sym(V, s, T=None, X=None):
+    import torch
+    Xd, f, w = dev_inputs(s)
+    if X is not None:
+        Xd = X
+    cfg = {"pair_form": 2}
+    if T:
+        cfg["targets_per_thread"] = T
+    out = V.farfield_forward(Xd, Xd, f, w, s.offsets, s.mu, precision="fp32c", config=cfg)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _ragged_suspension(seed=77, sizes=None, spacing=4.0):
+    """Uneven vesicle sizes (0 .. 130 points), P not a multiple of any tile."""
+    rng = np.random.default_rng(seed)
+    if sizes is None:
+        sizes = [1, 3, 17, 0, 33, 64, 100, 130, 5, 47, 63, 65, 129, 2, 31, 96]
+    m = len(sizes)
+    side = int(np.ceil(np.sqrt(m)))
+    centers = np.array([[spacing * (k % side) + rng.uniform(-0.3, 0.3), spacing * (k // side) + rng.uniform(-0.3, 0.3)]
+                        for k in range(m)])
+    axes = np.tile(S.ellipse_axes(0.7), (m, 1))
+    angles = rng.uniform(0, 2 * np.pi, m)
+    return S._assemble(rng, centers, axes, angles, np.array(sizes), "k4", 0.05, 1.3, spacing * side)
+
+
+@pytest.mark.parametrize("T", [1, 2, 4, 8])
+def test_config0(V, T):
+    s = S.make_config(0)
+    ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    err, rms = rel_err(_sym(V, s, T), ref)
+    say(f"symmetric cfg0 T={T}: {err:.3e} rms {rms:.3e}")
+    assert err <= BAR
+
+
+@pytest.mark.parametrize("T", [1, 2, 4, 8])
+def test_ragged_partition(V, T):
+    """Empty, single-point and odd-sized vesicles; one block holds the whole suspension."""
+    s = _ragged_suspension()
+    ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    err, _ = rel_err(_sym(V, s, T), ref)
+    say(f"symmetric ragged T={T}: {err:.3e}")
+    assert err <= BAR
+
+
+@pytest.mark.parametrize("m", [90, 131])
+def test_many_blocks_odd_and_even(V, m):
+    """Enough points for several blocks at one target per thread (512 points per block): vesicles
+    straddle block boundaries, and both parities of the block count run (the circulant schedule
+    takes the opposite blocks once when their count is even)."""
+    rng = np.random.default_rng(m)
+    sizes = list(rng.integers(1, 90, size=m))
+    s = _ragged_suspension(seed=m, sizes=sizes, spacing=4.5)
+    ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    cycles = int(sum((n + 15) // 16 for n in sizes))
+    say(f"symmetric many blocks: P={s.n_points} cycles={cycles} blocks(T=1)={(cycles + 31) // 32}")
+    for T in (1, 2):
+        err, _ = rel_err(_sym(V, s, T), ref)
+        say(f"  T={T}: {err:.3e}")
+        assert err <= BAR
+
+
+def test_vesicle_larger_than_block(V):
+    """A vesicle of 2500 points covers several blocks of 512 points (T = 1)."""
+    rng = np.random.default_rng(8)
+    sizes = np.array([2500, 7, 1030, 33])
+    centers = np.array([[0.0, 0.0], [30.0, 0.0], [0.0, 30.0], [30.0, 30.0]])
+    axes = np.array([[10.0, 4.0], [1.2, 0.5], [6.0, 3.0], [1.3, 0.4]])
+    s = S._assemble(rng, centers, axes, rng.uniform(0, 6.28, 4), sizes, "k4", 0.2, 1.0, 40.0)
+    ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    for T in (1, 4):
+        err, _ = rel_err(_sym(V, s, T), ref)
+        say(f"symmetric large vesicle T={T}: {err:.3e}")
+        assert err <= BAR
+
+
+def test_large_translation(V):
+    """Every point shifted by (+1000, -1000): local coordinates keep float32 accurate."""
+    s = _ragged_suspension()
+    s.X = s.X + np.array([[1000.0], [-1000.0]])
+    ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    err, _ = rel_err(_sym(V, s, 2), ref)
+    say(f"symmetric +1000: {err:.3e}")
+    assert err <= BAR
+
+
+def test_single_vesicle_and_zero_force(V):
+    a, b = S.ellipse_axes(0.65)
+    X, w, th = S.ellipse_curve((0.0, 0.0), a, b, 0.0, 40)
+    s = S.Suspension(X=X, f=np.stack([np.cos(th), np.sin(th)]), w=w, offsets=np.array([0, 40], np.int32), mu=1.0,
+                     box=4.0, centers=np.zeros((1, 2)), axes=np.array([[a, b]]), angles=np.zeros(1))
+    assert np.all(_sym(V, s, 1) == 0.0)
+    s2 = S.make_config(0)
+    s2.f = np.zeros_like(s2.f)
+    assert np.all(_sym(V, s2, 2) == 0.0)
+
+
+def test_bitwise_repeatable(V):
+    """Fixed-point accumulation: the result does not depend on the order of the atomics."""
+    s = _ragged_suspension(seed=3, sizes=list(np.random.default_rng(3).integers(1, 90, size=120)), spacing=4.5)
+    a = _sym(V, s, 1)
+    for _ in range(3):
+        assert np.array_equal(_sym(V, s, 1), a)
+
+
+def test_automatic_choice_and_errors(V):
+    """The automatic form equals the forced symmetric form where it is chosen; the symmetric form
+    refuses separate target and source arrays and the other precisions."""
+    import torch
+    s = S.make_config(0)
+    X, f, w = dev_inputs(s)
+    T = X.clone()
+    with pytest.raises(V.VesnetError):
+        V.farfield_forward(T, X, f, w, s.offsets, s.mu, precision="fp32c", config={"pair_form": 2})
+    for prec in ("fp64", "fp32"):
+        with pytest.raises(V.VesnetError):
+            V.farfield_forward(X, X, f, w, s.offsets, s.mu, precision=prec, config={"pair_form": 2})
+    # separate arrays with the automatic form take the direct form
+    out = V.farfield_forward(T, X, f, w, s.offsets, s.mu, precision="fp32c")
+    torch.cuda.synchronize()
+    ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    assert rel_err(out.cpu().numpy(), ref)[0] <= BAR
+
+
+def test_config1_sampled_full_size(V):
+    """2000 x 128 (256,000 points) in the benchmark's launch shape, on the seeded 1% sample."""
+    s = S.load_config(1)
+    sel = S.sample_targets(s.n_points, 0.01, 101)
+    say(f"cfg1 symmetric: oracle on {sel.size} targets x {s.n_points} sources")
+    ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu, select=sel)
+    err, rms = rel_err(_sym(V, s)[:, sel], ref)
+    say(f"cfg1 symmetric: max rel err {err:.3e}  rms {rms:.3e}")
+    assert err <= BAR
+
+
+@pytest.mark.parametrize("variant", ["force_free", "net_force"])
+def test_config2_precision_study(V, variant):
+    """8000 x 64 at 35% on a 1% target sample: the symmetric form within the bar."""
+    s = S.load_config(2, variant)
+    sel = S.sample_targets(s.n_points, 0.01, 202)
+    ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu, select=sel)
+    err, rms = rel_err(_sym(V, s)[:, sel], ref)
+    say(f"cfg2 {variant} symmetric: max rel err {err:.3e}  rms {rms:.3e}")
+    assert err <= BAR
