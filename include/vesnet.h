@@ -152,6 +152,28 @@ VESNET_API int vesnet_farfield_stokeslet(const double* targets, const double* so
                               const vesnet_tile_config* cfg, void* workspace, size_t workspace_bytes,
                               void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+   that forbid hipMalloc): vesnet_farfield_stokeslet without a workspace argument.  Its workspace is
+   a device array inside the library, VESNET_NOALLOC_SCRATCH_BYTES (64 MiB) on each GPU, held from
+   the library's load on that GPU until the process ends; the call itself allocates nothing.
+   Its address on the current device is looked up on the first call on that device (the stream
+   must belong to the current device).
+     - Arguments, layouts, launch shapes, forms and results as vesnet_farfield_stokeslet, except
+       that when cfg leaves source_splits at 0 the direct form's split count is halved until the
+       workspace fits.
+     - Sizes whose workspace exceeds the array are refused with VESNET_ERR_WORKSPACE before
+       anything is enqueued.  The symmetric form (float32-compensated, targets == sources) needs
+       about 54 bytes per point and 96 per vesicle: about 1.1 million points fit.
+     - Every call on one GPU uses that GPU's one array: calls that overlap on a GPU (on different
+       streams, or from different threads without ordering) race and give wrong results.  Every
+       part that must start at zero is cleared by a kernel of the call itself. */
+#define VESNET_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+VESNET_API int vesnet_farfield_stokeslet_noalloc(const double* targets, const double* sources,
+                                                 const double* force_density, const double* arc_weights,
+                                                 const int32_t* vesicle_offsets, int32_t n_vesicles,
+                                                 int32_t n_points, double mu, double* out, int precision,
+                                                 const vesnet_tile_config* cfg, void* stream);
+
 /* ------------------------------------------------------------------ membrane force */
 
 /* The step before the sum, on the device: the elastic force density of

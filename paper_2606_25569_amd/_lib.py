@@ -28,7 +28,10 @@ EXPORTED = (
     "vesnet_rbf_workspace_bytes", "vesnet_rbf_fit", "vesnet_rbf_eval_near", "vesnet_treecode_default_depth",
     "vesnet_treecode_workspace_bytes", "vesnet_farfield_treecode", "vesnet_fmm_default_depth", "vesnet_fmm_workspace_bytes",
     "vesnet_farfield_fmm", "vesnet_fmm_nearmasked_workspace_bytes", "vesnet_farfield_fmm_nearmasked",
+    "vesnet_farfield_stokeslet_noalloc",
 )
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # VESNET_NOALLOC_SCRATCH_BYTES of include/vesnet.h
 
 
 class VesnetError(RuntimeError):
@@ -74,6 +77,7 @@ def lib():
         "vesnet_farfield_prepare": ([P, P, P, P, I32, I32, INT, P, SZ, P], INT),
         "vesnet_farfield_evaluate": ([P, P, I32, I32, D, P, INT, CFG, P, SZ, P], INT),
         "vesnet_farfield_stokeslet": ([P, P, P, P, P, I32, I32, D, P, INT, CFG, P, SZ, P], INT),
+        "vesnet_farfield_stokeslet_noalloc": ([P, P, P, P, P, I32, I32, D, P, INT, CFG, P], INT),
         "vesnet_batched_workspace_bytes": ([I32, I32, I32, INT], SZ),
         "vesnet_farfield_stokeslet_batched": ([P, P, P, P, P, I32, I32, P, I32, P, P, INT, CFG, P, SZ, P], INT),
         "vesnet_graph_create_batched": ([P, P, P, P, P, I32, I32, P, I32, P, P, INT, CFG, P, SZ,

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "vesnet.h"
@@ -942,4 +943,74 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
   *best = best_c;
   if (best_ms) *best_ms = best_t;
   return ok();
+}
+
+// ============================================================================ no allocation
+
+namespace {
+
+// The scratch memory of vesnet_farfield_stokeslet_noalloc: a device array of this library, one
+// copy per GPU (loaded with the library's code object on each device).  Host code never passes
+// its name to a kernel: the name is a host-side stand-in, and each device's address comes from
+// hipGetSymbolAddress on that device.
+static __device__ __align__(256) unsigned char scratch[VESNET_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's copy of the scratch array (looked up once per device).
+int scratch_on_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(VESNET_ERR_UNSUPPORTED, "device %d is beyond the %d devices the scratch table holds", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the scratch array");
+    if (!p) return fail(VESNET_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return VESNET_OK;
+}
+
+}  // namespace
+
+extern "C" int vesnet_farfield_stokeslet_noalloc(const double* targets, const double* sources, const double* f,
+                                                 const double* w, const int32_t* off, int32_t M, int32_t P, double mu,
+                                                 double* out, int prec, const vesnet_tile_config* cfg, void* stream) {
+  int rc = check_forward_args(targets, sources, f, w, off, M, P, out, prec, nullptr, 0, true, true);
+  if (rc) return rc;
+  if ((rc = check_mu(mu))) return rc;
+  if (P == 0) return ok();
+  if (!out) return fail(VESNET_ERR_INVALID_ARGUMENT, "out is NULL");
+  Shape s;
+  if ((rc = resolve_shape(cfg, P, M, prec, &s))) return rc;
+  if (s.pair == 2 && targets != sources)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "the symmetric pair form needs targets == sources (one point array)");
+  const bool symmetric =
+      s.pair == 2 || (s.pair == 0 && targets == sources && prec == P32C && s.accumulate == 1 && s.symT > 0);
+  // the workspace of the chosen form only; the direct form's split partials shrink until it fits
+  // unless the caller fixed source_splits
+  s.pair = symmetric ? 2 : 1;
+  const size_t cap = VESNET_NOALLOC_SCRATCH_BYTES;
+  size_t need = forward_bytes(P, M, prec, s);
+  if (!(cfg && cfg->source_splits))
+    while (need > cap && s.splits > 1) {
+      s.splits /= 2;
+      need = forward_bytes(P, M, prec, s);
+    }
+  if (need > cap)
+    return fail(VESNET_ERR_WORKSPACE,
+                "n_points=%d, n_vesicles=%d need %zu bytes of scratch; the no-allocation entry point has %zu "
+                "(use vesnet_farfield_stokeslet with a workspace)",
+                P, M, need, cap);
+  void* ws = nullptr;
+  if ((rc = scratch_on_current_device(&ws))) return rc;
+  if ((rc = vesnet_farfield_prepare(sources, f, w, off, M, P, prec, ws, cap, stream))) return rc;
+  return evaluate_resolved(targets, M, P, mu, out, prec, s, symmetric, ws, cap, stream);
 }

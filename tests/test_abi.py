@@ -24,7 +24,7 @@ def _declared():
 def test_every_declared_symbol_is_exported(L):
     lib = L.lib()
     names = _declared()
-    assert len(names) == 30, names
+    assert len(names) == 31, names
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(L.EXPORTED)
@@ -319,3 +319,17 @@ def test_symmetric_form_rejects(L):
     cfg.pair_form = 3
     assert _fwd(L, cfg=ctypes.byref(cfg)) == L.ERR_INVALID_ARGUMENT
     assert lib.vesnet_farfield_workspace_bytes(10, 2, 1, ctypes.byref(cfg)) == 0
+
+
+def test_noalloc_rejects_before_any_device_call(L):
+    """The no-allocation entry point refuses problems whose workspace exceeds its fixed scratch
+    array, and bad arguments, on the host (these calls never reach a device)."""
+    lib = L.lib()
+    P, M = 4_000_000, 10
+    args = [_p(FAKE), _p(FAKE), _p(FAKE + 0x2000000 * 8), _p(FAKE + 0x4000000 * 8), _p(FAKE + 0x6000000 * 8), M, P,
+            1.0, _p(FAKE + 0x8000000 * 8), 1, None, None]
+    assert lib.vesnet_farfield_stokeslet_noalloc(*args) == L.ERR_WORKSPACE
+    assert b"scratch" in lib.vesnet_last_error()
+    args[7] = 0.0
+    assert lib.vesnet_farfield_stokeslet_noalloc(*args) == L.ERR_INVALID_ARGUMENT
+    assert lib.vesnet_farfield_stokeslet_noalloc(None, None, None, None, None, 0, 0, 1.0, None, 1, None, None) == 0
