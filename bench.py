@@ -28,24 +28,59 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(tile):
-    """HBM bytes per launch of the pair kernel from the committed rocprofv3 counter summary,
-    or None when the kernel source or the launch shape differs from the one measured."""
+def measured_counters(tile, symmetric):
+    """Figures of the committed rocprofv3 counter summary of the pair kernel (HBM bytes per launch,
+    achieved shader clock, issue slots per pair), or {} when the kernel source or the launch shape
+    differs from the one measured."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_forward_fp32c_2000x128_counters.txt")
-    src = os.path.join(ROOT, "paper_2606_25569_amd", "csrc", "vesnet_kernels.hip")
+    name = "k_sym_main_fp32c_2000x128_counters.txt" if symmetric else "k_forward_fp32c_2000x128_counters.txt"
+    src = "vesnet_symmetric.hip" if symmetric else "vesnet_kernels.hip"
     try:
         fields = {}
-        for line in open(path):
+        for line in open(os.path.join(ROOT, "profiles", name)):
             if ":" in line:
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+        sha = hashlib.sha1(open(os.path.join(ROOT, "paper_2606_25569_amd", "csrc", src), "rb").read()).hexdigest()
         if fields.get("kernel_source_sha1") != sha or fields.get("tile") != tile:
-            return None
-        return float(fields["traffic_bytes_per_launch"])
+            return {}
+        out = {"profile": "profiles/" + name}
+        for key in ("traffic_bytes_per_launch", "sclk_ghz", "slots_per_pair"):
+            if key in fields:
+                out[key] = float(fields[key])
+        return out
     except (OSError, KeyError, ValueError):
+        return {}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_one_core(frac, seed):
+    """The oracle on one thread, in a child process (OMP_NUM_THREADS=1) that never touches the
+    GPU, on a seeded target sample of the 2000 x 128 workload: (pairs/s, targets, seconds)."""
+    import subprocess
+    code = ("import json, sys, time; sys.path.insert(0, %r)\n"
+            "from oracle import oracle as O\nfrom synth import suspension as S\n"
+            "s = S.load_config(1); sel = S.sample_targets(s.n_points, %r, %r)\n"
+            "t = time.perf_counter(); O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu, select=sel)\n"
+            "dt = time.perf_counter() - t\n"
+            "n = int(sum(s.n_points - (s.offsets[v + 1] - s.offsets[v]) for v in O.vesicle_ids(s.offsets)[sel]))\n"
+            "print(json.dumps({'pairs': n, 'targets': int(sel.size), 's': dt, 'threads': O.num_threads()}))\n"
+            % (ROOT, frac, seed))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        log(f"[bench] one-core oracle failed: {r.stderr[-500:]}")
         return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def main():
@@ -58,6 +93,9 @@ def main():
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape instead of the library default")
     ap.add_argument("--tile", default=None,
                     help="T,B,splits[,staging]: fixed launch shape instead of the tuned one (staging 1 = SGPR, 2 = LDS)")
+    ap.add_argument("--form", default="symmetric", choices=["symmetric", "direct"],
+                    help="pair form of the FP32-compensated sum: symmetric (one evaluation per unordered pair, the "
+                         "default) or direct (one gather per target)")
     ap.add_argument("--cpu-sample", type=float, default=0.03, help="fraction of targets the oracle evaluates")
     ap.add_argument("--workload", default="dense",
                     choices=["dense", "batched", "adjoint", "nearfield", "treecode", "force"],
@@ -125,6 +163,10 @@ def main():
         log(f"[bench] autotuned {cfg.as_dict()} ({tms:.3f} ms) in {time.time() - t1:.1f}s")
     if cfg is None:
         cfg = V.default_config(P, M, "fp32c")
+    symmetric = args.form == "symmetric"
+    cfg.pair_form = 2 if symmetric else 1
+    if symmetric and not args.tile:
+        cfg.targets_per_thread = 0  # the symmetric form's own default (two targets per thread)
     log(f"[bench] launch shape {cfg.as_dict()}")
     import ctypes
     cfg_ref = ctypes.byref(cfg)
@@ -202,17 +244,38 @@ def main():
             d = u[:, sel] - ref
             errs[name] = {"max_rel": float(np.abs(d).max() / scale),
                           "rms_rel": float(np.sqrt(np.mean(d * d)) / np.sqrt(np.mean(ref * ref)))}
-        cpu = {"value": sample_pairs / tcpu, "unit": "pairs/s", "cores": O.num_threads(), "kind": "oracle",
-               "sample": f"seeded {100 * args.cpu_sample:g}% target sample: {sel.size} targets x all {P} sources of the same workload "
-                         f"({sample_pairs:.3e} pairs, {tcpu:.2f} s wall)"}
-        log(f"[bench] errors {errs}; oracle {cpu['value']:.3e} pairs/s on {cpu['cores']} threads")
+        rate = sample_pairs / tcpu
+        cpu = {"value": rate, "unit": "pairs/s", "cores": O.num_threads(), "kind": "oracle",
+               "sample": f"seeded {100 * args.cpu_sample:g}% target sample: {sel.size} targets x all {P} sources of the "
+                         f"same workload ({sample_pairs:.3e} pairs, {tcpu:.2f} s wall)",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+               "extrapolated_full_config_s": pairs / rate,
+               "extrapolated_note": "the full 2000 x 128 sum at the sampled rate (extrapolated, not run)"}
+        log(f"[bench] errors {errs}; oracle {rate:.3e} pairs/s on {cpu['cores']} threads")
+        one = oracle_one_core(args.cpu_sample / 8, 103)
+        if one:
+            r1 = one["pairs"] / one["s"]
+            cpu["one_core"] = {"value": r1, "unit": "pairs/s", "threads": one["threads"],
+                               "sample": f"seeded {100 * args.cpu_sample / 8:g}% target sample: {one['targets']} targets "
+                                         f"({one['pairs']:.3e} pairs, {one['s']:.2f} s wall)",
+                               "extrapolated_full_config_s": pairs / r1}
+            log(f"[bench] oracle on one thread: {r1:.3e} pairs/s")
 
     t_kernel = float(eval_ms.mean()) * 1e-3
     achieved = FLOPS_PER_PAIR * pairs / t_kernel / 1e12
     d = cfg.as_dict()
     tile_key = ",".join(str(d[k]) for k in ("targets_per_thread", "block_threads", "source_splits", "source_staging",
-                                            "accumulate"))
-    traffic = measured_traffic(tile_key)
+                                            "accumulate", "pair_form"))
+    prof = measured_counters(tile_key, symmetric)
+    traffic = prof.get("traffic_bytes_per_launch")
+    mix = None
+    if "slots_per_pair" in prof:
+        # the instruction-mix ceiling: every SIMD issues 32 FP32 lanes per cycle at the measured shader
+        # clock, a transcendental takes four issue slots (counter basis in the profile summary)
+        sclk = prof.get("sclk_ghz", 2.4)
+        ceiling = 256 * 4 * 32 * sclk * 1e9 / prof["slots_per_pair"]
+        mix = {"ceiling_pairs_per_s": ceiling, "frac": (pairs / t_kernel) / ceiling,
+               "slots_per_pair": prof["slots_per_pair"], "sclk_ghz": sclk, "profile": prof["profile"]}
     rec = {
         "metric": METRIC,
         "value": value,
@@ -231,11 +294,14 @@ def main():
                                "Fourier forces k<=4, mu=1",
                    "n_points": P, "n_vesicles": M, "cross_vesicle_pairs": pairs,
                    "precision": "fp32-compensated (float32 pairs, float64 per-vesicle flush)",
+                   "pair_form": args.form,
                    "tile": cfg.as_dict()},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "kernel": "k_forward (pair sum)", "kernel_ms": float(eval_ms.mean()),
-                     "flops_per_pair": FLOPS_PER_PAIR},
+                     "kernel": "k_sym_main (symmetric pair sum)" if symmetric else "k_forward (pair sum)",
+                     "kernel_ms": float(eval_ms.mean()), "flops_per_pair": FLOPS_PER_PAIR,
+                     "mix_ceiling_frac": mix["frac"] if mix else None, "mix_ceiling": mix,
+                     "sclk_ghz": prof.get("sclk_ghz")},
         "cpu_baseline": cpu,
         "fp64": {"pairs_per_s": pairs / (ms64 * 1e-3), "ms_per_step": ms64,
                  "tflops": FLOPS_PER_PAIR * pairs / (ms64 * 1e-3) / 1e12,

@@ -98,8 +98,10 @@ typedef struct {
                                     (the Stokeslet is even), halving the logarithms and reciprocals;
                                     the targets must be the points the workspace was prepared with
                                     (vesnet_farfield_stokeslet requires targets == sources).
-                                    targets_per_thread (1, 2, 4) sets its block of 1024 T targets;
-                                    block_threads, source_splits and source_staging are unused.
+                                    targets_per_thread (1, 2, 4 or 8; 0 = the default 2) sets its
+                                    blocks of 256 T points (one 256-thread workgroup per pair of
+                                    blocks); block_threads, source_splits and source_staging are
+                                    unused.  The automatic choice always uses the default.
                                     Its partial sums are added as 64-bit fixed-point integers, so
                                     the result is bitwise reproducible.                            */
 } vesnet_tile_config;

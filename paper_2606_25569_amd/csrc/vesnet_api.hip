@@ -112,12 +112,12 @@ struct Shape {
   int symT;  // targets per thread of the symmetric form (0: too few units for it)
 };
 
-// Targets per thread of the symmetric form: the largest T in {8, 4, 2, 1} that still gives at
-// least four units per compute unit (a unit is one workgroup of 512 threads on one pair of blocks
-// of 512 T points), estimated with vesicles of a multiple of 16 points; 0 when even T = 1 gives
-// fewer.
+// Targets per thread of the symmetric form: 2 (the fastest measured on the 2000 x 128 suspension:
+// 15.7 ms against 17.1 ms at 4 and 17.7 ms at 1), or 1 when 2 gives fewer than four units per
+// compute unit (a unit is one workgroup of 256 threads on one pair of blocks of 256 T points),
+// estimated with vesicles of a multiple of 16 points; 0 when even 1 gives fewer (direct form).
 int sym_default_T(int32_t P) {
-  for (int T : {8, 4, 2, 1}) {
+  for (int T : {2, 1}) {
     const int64_t cyc = (int64_t)P / 16;
     const int cb = sym_cycles_per_block(T);
     if (sym_units((cyc + cb - 1) / cb) >= 1024) return T;
@@ -156,7 +156,9 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     if (cfg->source_staging) s.staging = cfg->source_staging;
     if (cfg->accumulate) s.accumulate = cfg->accumulate;
     if (cfg->pair_form) s.pair = cfg->pair_form;
-    if (cfg->targets_per_thread) s.symT = cfg->targets_per_thread;
+    // the symmetric form takes the caller's targets_per_thread only when it is asked for explicitly;
+    // the automatic choice keeps its own default
+    if (cfg->targets_per_thread && cfg->pair_form == 2) s.symT = cfg->targets_per_thread;
   }
   if (s.T != 1 && s.T != 2 && s.T != 4 && !(s.T == 8 && s.pair == 2))
     return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread must be 1, 2 or 4 (8 for the symmetric form; got %d)",

@@ -8,7 +8,9 @@
 // d/dalpha exact on the band-limited interpolant of the N points alpha_k = 2 pi k / N.
 // On the grid that operator is the circulant matrix with first column
 //   d_0 = 0,  d_m = (1/2) (-1)^m cot(pi m / N)  (N even),  (1/2) (-1)^m csc(pi m / N)  (N odd),
-// which equals multiplying Fourier mode k by i k with the even-N Nyquist mode dropped.  It is applied as
+// which equals multiplying Fourier mode k by i k with the even-N Nyquist mode dropped.  The weights sum
+// to zero, so the points enter it relative to the vesicle's first point: rounding then scales with the
+// vesicle's extent, not with its distance from the origin.  It is applied as
 // a direct O(N^2) sum from LDS in float64 (the fourth derivative amplifies rounding by up to (N/2)^4):
 // one wavefront per vesicle of up to 64, 128 or 256 points (k_elastic_wave), one workgroup per larger
 // vesicle of up to 1024 points (k_elastic), tens of microseconds for a whole suspension.
@@ -118,8 +120,8 @@ __global__ __launch_bounds__(64) void k_elastic_wave(const double* __restrict__ 
         c = (n & 1) ? sg / s : sg * co / s;
       }
       d[m] = c;
-      ux[pad8(m)] = ux[pad8(m + n)] = X[j0 + m];
-      uy[pad8(m)] = uy[pad8(m + n)] = X[P + j0 + m];
+      ux[pad8(m)] = ux[pad8(m + n)] = X[j0 + m] - X[j0];
+      uy[pad8(m)] = uy[pad8(m + n)] = X[P + j0 + m] - X[P + j0];
     }
     wave_sync();
     double ax[R], ay[R], jinv[R], sx[R], sy[R], tx[R], ty[R], bx[R], by[R];
@@ -222,8 +224,8 @@ __global__ __launch_bounds__(kB) void k_elastic(const double* __restrict__ X, co
         c = (n & 1) ? sg / s : sg * co / s;
       }
       d[m] = c;
-      ux[m] = X[j0 + m];
-      uy[m] = X[P + j0 + m];
+      ux[m] = X[j0 + m] - X[j0];
+      uy[m] = X[P + j0 + m] - X[P + j0];
     }
     __syncthreads();
 
@@ -340,8 +342,8 @@ __global__ __launch_bounds__(kB) void k_near_layers(const double* __restrict__ X
         c = (n & 1) ? sg / s : sg * co / s;
       }
       d[m] = c;
-      ux[m] = X[j0 + m];
-      uy[m] = X[P + j0 + m];
+      ux[m] = X[j0 + m] - X[j0];  // relative to the first point (derivative and signed area)
+      uy[m] = X[P + j0 + m] - X[P + j0];
     }
     __syncthreads();
     double ax[kPer], ay[kPer];
@@ -364,8 +366,8 @@ __global__ __launch_bounds__(kB) void k_near_layers(const double* __restrict__ X
 #pragma unroll
         for (int l = 0; l < 5; ++l) {
           const double dl = 0.5 * (double)(l - 2) * h;
-          lx[l * n + i] = fma(dl, nx, ux[i]);
-          ly[l * n + i] = fma(dl, ny, uy[i]);
+          lx[l * n + i] = fma(dl, nx, X[j0 + i]);
+          ly[l * n + i] = fma(dl, ny, X[P + j0 + i]);
         }
       }
     }

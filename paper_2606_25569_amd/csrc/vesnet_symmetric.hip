@@ -9,19 +9,20 @@
 //
 // Work decomposition
 //  * Points are cut into "cycles" of at most 16 consecutive points of one vesicle (a vesicle of
-//    N points gives ceil(N/16) cycles); CB = 32 T consecutive cycles form a block.
+//    N points gives ceil(N/16) cycles); CB = 16 T consecutive cycles form a block.
 //  * A unit is an unordered pair of blocks {bx, by}, by = bx + d (mod nb), d = 0 .. nb/2 (the
 //    circulant schedule visits every unordered pair of blocks once; for even nb the pairs at
-//    d = nb/2 are taken by bx < nb/2 only).  One workgroup of 512 threads (8 wavefronts, 32 rows
-//    of 16 lanes) evaluates a unit: row r holds target cycles r, r + 32, ... of block bx (T of
+//    d = nb/2 are taken by bx < nb/2 only).  One workgroup of 256 threads (4 wavefronts, 16 rows
+//    of 16 lanes) evaluates a unit: row r holds target cycles r, r + 16, ... of block bx (T of
 //    them, one point per lane), and the source cycles of block by stream through LDS in chunks
-//    of 16 cycles.
+//    of 8 cycles.  With T = 2 (the default: 512-point blocks, 94 VGPRs, 27 KB of LDS) five units
+//    share a compute unit.
 //  * Each row is a ring: at step s lane p pairs its T targets with source (p + s) mod 16 of the
 //    current source cycle, read from LDS (each cycle is stored twice so that the address is the
 //    lane's base plus an immediate offset).  The source's column sum travels with it around the
 //    ring, by a DPP row rotation folded into the add that closes each step.  After 16 steps two
 //    lane swaps (v_permlane32_swap, v_permlane16_swap) add the four rows of a wavefront, the
-//    column sums go to LDS, and after each chunk the workgroup adds its 8 wavefronts in a fixed
+//    column sums go to LDS, and after each chunk the workgroup adds its 4 wavefronts in a fixed
 //    order.
 //  * Own vesicle and the diagonal unit (d = 0): a (target cycle, source vesicle) pair is active
 //    when the vesicles differ and, for d = 0, when the target's vesicle index is the smaller one,
@@ -33,10 +34,12 @@
 // Compensation (float32 pairs, float64 corrections)
 //  * For a target of vesicle A and a source vesicle B the pair loop runs on the rescaled
 //    difference r' = 2^-k (x_i - y_j) = 2^-k (xi_i + c_A - c_B) - 2^-k xi_j, with xi the float32
-//    local coordinates about each vesicle's point mean c and k = floor(e/2) for
-//    |c_A - c_B|^2 + R_A^2 + R_B^2 = m 2^e (R the largest |xi| of a vesicle): |r'| is of order one
-//    for distant vesicles and bounded for overlapping hulls.  Scaling by a power of two is exact,
-//    so ln|r|^2 = ln 2 (log2|r'|^2 + 2k) exactly, and the rr-term is unchanged.
+//    local coordinates about each vesicle's point mean c (c_A - c_B rounded once from float64) and
+//    k = floor(e/2) for |c_A - c_B|^2 + R_A^2 + R_B^2 = m 2^e (R the largest |xi| of a vesicle):
+//    |r'| is of order one for distant vesicles and bounded for overlapping hulls.  Scaling by a
+//    power of two is exact, so ln|r|^2 = ln 2 (log2|r'|^2 + 2k) exactly, and the rr-term is
+//    unchanged.  (Plain subtractions on unscaled coordinates with the scale applied to |r|^2 give
+//    the same bits but one more instruction per pair, and measured 4% slower.)
 //  * Row (target, segment of B in the block): float32 partial of -1/2 ln2 log2|r'|^2 F_j + rr-term,
 //    then in float64  - k ln2 F_seg, F_seg the float64 net force of the segment (the sum of its
 //    cycles' float64 net forces).
@@ -62,10 +65,11 @@ namespace vesnet {
 namespace {
 
 constexpr int kRing = 16;                          // sources per ring cycle (one DPP row)
-constexpr int kSymThreads = 512;                   // threads per unit (8 wavefronts)
+constexpr int kSymThreads = 256;                   // threads per unit (4 wavefronts, one per SIMD)
 constexpr int kSymWaves = kSymThreads / 64;
 constexpr int kRows = kSymThreads / kRing;         // rows of 16 lanes per unit
-constexpr int kChunk = 16;                         // source cycles per LDS chunk
+constexpr int kChunk = 8;                          // source cycles per LDS chunk
+static_assert(kChunk * 2 * kRing <= kSymThreads, "one thread per staged record and per column sum of a chunk");
 constexpr double kLn2d = 0.69314718055994530942;
 constexpr float kHalfLn2f = -0.34657359027997265471f;  // -(1/2) ln 2: log2|r|^2 -> -ln|r|
 constexpr float kFar = 1152921504606846976.0f;         // 2^60: position of an inactive target
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_main(
     }
   }
 
-  // State of the current source segment, per target slot k (target cycle k * 32 + row).
+  // State of the current source segment, per target slot k (target cycle k * 16 + row).
   float dx[T], dy[T], ns[T], fcx[T], fcy[T], fhx[T], fhy[T], lx[T], ly[T], rvx[T], rvy[T];
   double ax[T], ay[T];
   int kq[T];
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_main(
   auto ring = [&](int buf, int cc) {
     const float4* rb = &s_rec[buf][cc][p];
     float cax = 0.f, cay = 0.f;
-#pragma unroll 2
+#pragma unroll 1
     for (int s = 0; s < kRing; ++s) {
       const float4 sr = rb[s];
       float lcx = 0.f, lcy = 0.f;
@@ -343,22 +347,26 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_main(
   // Records of source chunk g: slots 0..15 and again 16..31; slots past the cycle's count repeat
   // its first point with zero force.
   const int nchunks = (sc1 - sc0 + kChunk - 1) / kChunk;
+  const bool stager = tid < kChunk * 2 * kRing;
   const int st_cc = tid >> 5, st_q = tid & 31, st_m = st_q & (kRing - 1);
   auto stage_load = [&](int g) {
     float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
     const int c = sc0 + g * kChunk + st_cc;
-    if (c < sc1) {
+    if (stager && c < sc1) {
       const int4 cy = cyc[c];
       r = rec[cy.x + (st_m < cy.y ? st_m : 0)];
       if (st_m >= cy.y) r.z = r.w = 0.f;
     }
     return r;
   };
-  auto stage_store = [&](int buf, const float4& r) { s_rec[buf][st_cc][st_q] = r; };
+  auto stage_store = [&](int buf, const float4& r) {
+    if (stager) s_rec[buf][st_cc][st_q] = r;
+  };
 
   // Column sums of chunk g: the wavefronts and their log corrections added in a fixed order,
   // then one fixed-point integer per (source, component).
   auto reduce = [&](int g, int buf) {
+    if (tid >= kChunk * 2 * kRing) return;
     const int cc = tid >> 5, comp = (tid >> 4) & 1, m = tid & (kRing - 1);
     const int c = sc0 + g * kChunk + cc;
     if (c >= sc1) return;

@@ -29,28 +29,76 @@ def _curves(sizes, seed):
     return np.concatenate(X, axis=1), np.asarray(off, np.int32)
 
 
-def test_elastic_force_parity_across_sizes():
+def _exact_shift(X, off, shift):
+    """Points that are exactly representable both as given and translated by shift: each coordinate
+    is rounded to the grid of x + shift first, so the translated curve is the same curve."""
+    Xr = (X + shift) - shift
+    return Xr, Xr + shift
+
+
+def _centred_reference(X, sigma, kappa_b, off):
+    """The oracle on every curve moved to its own first point (f and w do not depend on the
+    translation), so the reference's rounding scales with the curve's extent only."""
+    f = np.empty_like(X)
+    w = np.empty(X.shape[1])
+    for v in range(len(off) - 1):
+        a, b = off[v], off[v + 1]
+        if b > a:
+            fv, wv = SP.elastic_force(X[:, a:b] - X[:, a:a + 1], sigma[a:b], kappa_b, np.array([0, b - a]))
+            f[:, a:b], w[a:b] = fv, wv
+    return f, w
+
+
+def _check_force(V, X, off, sizes, sigma, kappa_b, label):
+    """GPU force and weights against the centred oracle.  Bars: the rounding of the points relative to
+    the first point (size e = extent of the curve) amplified by at most N/2 per derivative, four of
+    them, for f; and e N log2 N 2 pi / N for |X_alpha| 2 pi / N: neither grows with the translation."""
     import torch
-    import paper_2606_25569_amd as V
-    sizes = [4, 7, 8, 31, 32, 64, 128, 255, 1000, 1024]
-    X, off = _curves(sizes, 5)
-    rng = np.random.default_rng(6)
-    sigma = rng.normal(size=X.shape[1])
-    ref_f, ref_w = SP.elastic_force(X, sigma, 0.7, off)
-    f, w = V.elastic_force(torch.tensor(X, device="cuda"), off, 0.7, torch.tensor(sigma, device="cuda"))
+    ref_f, ref_w = _centred_reference(X, sigma, kappa_b, off)
+    f, w = V.elastic_force(torch.tensor(X, device="cuda"), off, kappa_b, torch.tensor(sigma, device="cuda"))
     torch.cuda.synchronize()
     f, w = f.cpu().numpy(), w.cpu().numpy()
     for v, n in enumerate(sizes):
         a, b = off[v], off[v + 1]
-        # rounding of the points, amplified by at most N/2 per derivative (four of them)
-        tol = 64 * EPS * np.abs(X[:, a:b]).max() * (n / 2) ** 4 + 64 * EPS * np.abs(ref_f[:, a:b]).max()
+        if n < 3:
+            continue
+        ext = np.abs(X[:, a:b] - X[:, a:a + 1]).max()
+        tol = 64 * EPS * ext * (n / 2) ** 4 + 64 * EPS * np.abs(ref_f[:, a:b]).max()
         df = np.abs(f[:, a:b] - ref_f[:, a:b]).max()
-        say(f"elastic N={n}: max |df| {df:.3e} (bound {tol:.3e}), rel {df / np.abs(ref_f[:, a:b]).max():.3e}")
+        say(f"{label} N={n}: max |df| {df:.3e} (bound {tol:.3e}), rel {df / np.abs(ref_f[:, a:b]).max():.3e}")
         assert df <= tol
-        # |X_alpha| is a sum of N terms of size up to |X| (global coordinates): rounding of order
-        # eps |X| N log2(N), times 2 pi / N for the weight
-        atol_w = 16 * EPS * np.abs(X[:, a:b]).max() * n * max(1.0, np.log2(n)) * (2 * np.pi / n)
+        atol_w = 16 * EPS * ext * n * max(1.0, np.log2(n)) * (2 * np.pi / n)
         np.testing.assert_allclose(w[a:b], ref_w[a:b], rtol=0, atol=atol_w)
+
+
+@pytest.mark.parametrize("shift", [0.0, 1000.0])
+def test_elastic_force_parity_across_sizes(shift):
+    """N = 4 .. 1024 (one wavefront per vesicle and the workgroup kernel), in place and translated
+    by +1000: the bar depends on each curve's extent, not on its distance from the origin."""
+    import paper_2606_25569_amd as V
+    sizes = [4, 7, 8, 31, 32, 64, 128, 255, 1000, 1024]
+    X, off = _curves(sizes, 5)
+    X0, X1 = _exact_shift(X, off, shift)
+    rng = np.random.default_rng(6)
+    sigma = rng.normal(size=X.shape[1])
+    _check_force(V, X1, off, sizes, sigma, 0.7, f"elastic +{shift:g}")
+
+
+@pytest.mark.parametrize("sizes", [
+    [3, 17, 33, 63, 64, 65, 5, 40, 1, 64],        # mean <= 64: one point per lane (R = 1), 65 -> workgroup kernel
+    [65, 100, 127, 128, 129, 70, 99, 101],        # mean in (64, 128]: two points per lane (R = 2)
+    [129, 200, 255, 256, 257, 130, 203, 131],     # mean in (128, 256]: four points per lane (R = 4)
+])
+def test_elastic_force_wavefront_forms(sizes):
+    """Partitions whose mean size selects each one-wavefront form: sizes that are not multiples of the
+    points per lane, lanes past the last point, and vesicles just above the wavefront capacity that
+    fall to the workgroup kernel (the 2000 x 128 workload takes the R = 2 form)."""
+    import paper_2606_25569_amd as V
+    X, off = _curves(sizes, 31 + len(sizes))
+    X0, X1 = _exact_shift(X, off, 1000.0)
+    rng = np.random.default_rng(7)
+    sigma = rng.normal(size=X.shape[1])
+    _check_force(V, X1, off, sizes, sigma, 1.1, f"wavefront mean {int(np.mean(sizes))}")
 
 
 def test_elastic_force_zero_tension_and_degenerate_sizes():

@@ -72,7 +72,7 @@ def test_ragged_partition(V, T):
 
 @pytest.mark.parametrize("m", [90, 131])
 def test_many_blocks_odd_and_even(V, m):
-    """Enough points for several blocks at one target per thread (512 points per block): vesicles
+    """Enough points for several blocks at one target per thread (256 points per block): vesicles
     straddle block boundaries, and both parities of the block count run (the circulant schedule
     takes the opposite blocks once when their count is even)."""
     rng = np.random.default_rng(m)
@@ -80,7 +80,7 @@ def test_many_blocks_odd_and_even(V, m):
     s = _ragged_suspension(seed=m, sizes=sizes, spacing=4.5)
     ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
     cycles = int(sum((n + 15) // 16 for n in sizes))
-    say(f"symmetric many blocks: P={s.n_points} cycles={cycles} blocks(T=1)={(cycles + 31) // 32}")
+    say(f"symmetric many blocks: P={s.n_points} cycles={cycles} blocks(T=1)={(cycles + 15) // 16}")
     for T in (1, 2):
         err, _ = rel_err(_sym(V, s, T), ref)
         say(f"  T={T}: {err:.3e}")
@@ -88,7 +88,7 @@ def test_many_blocks_odd_and_even(V, m):
 
 
 def test_vesicle_larger_than_block(V):
-    """A vesicle of 2500 points covers several blocks of 512 points (T = 1)."""
+    """A vesicle of 2500 points covers several blocks of 256 points (T = 1)."""
     rng = np.random.default_rng(8)
     sizes = np.array([2500, 7, 1030, 33])
     centers = np.array([[0.0, 0.0], [30.0, 0.0], [0.0, 30.0], [30.0, 30.0]])
