@@ -18,6 +18,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOPS_PER_PAIR = 19          # sub x2, q: mul+fma, log, rcp, r.F: mul+fma, scale, 2 x (2 fma)
+ADJOINT_FLOPS_PER_PAIR = 68  # per ordered pair: r, q, rcp, log shared (7), v (12), position gradient (49)
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32
 PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64
 PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
@@ -401,12 +402,19 @@ def bench_adjoint(args):
     part = V.Partition(s.offsets, dev)
     rec = {"workload": "adjoint: 512 vesicles x 64 points at 30% area fraction, dL/du = u - u*",
            "n_points": s.n_points, "cross_vesicle_pairs": pairs}
+    rec["flops_per_pair"] = ADJOINT_FLOPS_PER_PAIR
     for prec in ("fp32c", "fp64"):
         tf = _time(lambda: V.farfield_forward(X, X, f, w, part, s.mu, prec), args.steps, stream)
-        tb = _time(lambda: V.farfield_backward(X, X, f, w, part, s.mu, g, prec), args.steps, stream)
-        rec[prec] = {"forward_ms": tf, "backward_ms": tb, "forward_pairs_per_s": pairs / (tf * 1e-3),
-                     "backward_pairs_per_s": pairs / (tb * 1e-3)}
-        log(f"[bench] adjoint {prec}: forward {tf:.3f} ms, backward {tb:.3f} ms")
+        # the points form (one pass over unordered pairs under fp32c) and the two gathers
+        tb = _time(lambda: V.farfield_backward_points(X, f, w, part, s.mu, g, prec), args.steps, stream)
+        t2 = _time(lambda: V.farfield_backward(X, X, f, w, part, s.mu, g, prec), args.steps, stream)
+        tfl = ADJOINT_FLOPS_PER_PAIR * pairs / (tb * 1e-3) / 1e12
+        peak = PEAK_FP32_TFLOPS if prec == "fp32c" else PEAK_FP64_TFLOPS
+        rec[prec] = {"forward_ms": tf, "backward_ms": tb, "backward_two_gathers_ms": t2,
+                     "forward_pairs_per_s": pairs / (tf * 1e-3), "backward_pairs_per_s": pairs / (tb * 1e-3),
+                     "backward_tflops": tfl, "backward_frac_peak": tfl / peak}
+        log(f"[bench] adjoint {prec}: forward {tf:.3f} ms, backward {tb:.3f} ms (two gathers {t2:.3f} ms), "
+            f"{tfl:.1f} TFLOP/s at {ADJOINT_FLOPS_PER_PAIR} flops per pair")
     print(json.dumps(rec), flush=True)
 
 

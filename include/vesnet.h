@@ -407,6 +407,34 @@ VESNET_API int vesnet_farfield_stokeslet_backward(const double* targets, const d
                                        double* grad_weights, int precision, void* workspace,
                                        size_t workspace_bytes, void* stream);
 
+/* The same adjoint for one point array that serves as targets and sources
+   (u_i = sum_{j not in ves(i)} G(X_i - X_j) F_j), with the positions
+   differentiated in both roles:
+     grad_points_k = sum_{m not in ves(k)} [ grad_r phi(X_k - X_m; g_k, F_m)
+                                            + grad_r phi(X_k - X_m; F_k, g_m) ]
+   and grad_force, grad_weights as above.  Both terms of one pair (k, m) share
+   r, |r|^2, its reciprocal and logarithm, and grad_r phi is odd in r, so under
+   VESNET_FP32_COMPENSATED each unordered pair of points in different vesicles
+   is evaluated once (the symmetric form of the forward, with float64 atomic
+   sums: the last bits may differ from call to call).  Under VESNET_FP64 the
+   two gathers of vesnet_farfield_stokeslet_backward run and their position
+   gradients are added.
+     points                       : device [2][P] float64
+     grad_out                     : device [2][P] float64
+     grad_points, grad_force      : device [2][P] float64 or NULL (skipped)
+     grad_weights                 : device [P] float64 or NULL
+     workspace                    : device, vesnet_backward_points_workspace_bytes(P, M, precision)
+   Outputs are overwritten and must not overlap inputs or each other; errors as
+   for vesnet_farfield_stokeslet_backward. */
+VESNET_API size_t vesnet_backward_points_workspace_bytes(int32_t n_points, int32_t n_vesicles, int precision);
+
+VESNET_API int vesnet_farfield_stokeslet_backward_points(const double* points, const double* force_density,
+                                              const double* arc_weights, const int32_t* vesicle_offsets,
+                                              int32_t n_vesicles, int32_t n_points, double mu,
+                                              const double* grad_out, double* grad_points, double* grad_force,
+                                              double* grad_weights, int precision, void* workspace,
+                                              size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------ tuning */
 
 /* Times every supported launch shape on the given (prepared inside) problem

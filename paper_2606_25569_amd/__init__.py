@@ -7,12 +7,12 @@ from ._lib import FP32_COMPENSATED, FP32_NAIVE, FP64, TileConfig, VesnetError
 _lib.lib()  # load now: no CPU fallback exists
 
 from .farfield import (BatchedProblem, Partition, autotune, default_config, elastic_force,  # noqa: E402
-                       farfield_backward, farfield_fmm, farfield_fmm_nearmasked, farfield_forward,
+                       farfield_backward, farfield_backward_points, farfield_fmm, farfield_fmm_nearmasked, farfield_forward,
                        farfield_nearmasked, farfield_stokeslet,
                        farfield_treecode, load_tuned, near_layers, rbf_eval_near, rbf_fit, workspace_bytes)
 
 __all__ = ["BatchedProblem", "Partition", "TileConfig", "VesnetError", "autotune", "default_config", "elastic_force",
-           "farfield_backward", "farfield_fmm", "farfield_fmm_nearmasked", "farfield_forward", "farfield_nearmasked",
+           "farfield_backward", "farfield_backward_points", "farfield_fmm", "farfield_fmm_nearmasked", "farfield_forward", "farfield_nearmasked",
            "farfield_stokeslet",
            "farfield_treecode",
            "load_tuned",

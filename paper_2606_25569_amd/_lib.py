@@ -23,7 +23,8 @@ EXPORTED = (
     "vesnet_farfield_workspace_bytes", "vesnet_farfield_prepare", "vesnet_farfield_evaluate",
     "vesnet_farfield_stokeslet", "vesnet_batched_workspace_bytes", "vesnet_farfield_stokeslet_batched",
     "vesnet_graph_create_batched", "vesnet_graph_launch", "vesnet_graph_destroy",
-    "vesnet_backward_workspace_bytes", "vesnet_farfield_stokeslet_backward", "vesnet_autotune",
+    "vesnet_backward_workspace_bytes", "vesnet_farfield_stokeslet_backward", "vesnet_backward_points_workspace_bytes",
+    "vesnet_farfield_stokeslet_backward_points", "vesnet_autotune",
     "vesnet_farfield_stokeslet_nearmasked", "vesnet_elastic_force", "vesnet_near_layers",
     "vesnet_rbf_workspace_bytes", "vesnet_rbf_fit", "vesnet_rbf_eval_near", "vesnet_treecode_default_depth",
     "vesnet_treecode_workspace_bytes", "vesnet_farfield_treecode", "vesnet_fmm_default_depth", "vesnet_fmm_workspace_bytes",
@@ -86,6 +87,8 @@ def lib():
         "vesnet_graph_destroy": ([P], INT),
         "vesnet_backward_workspace_bytes": ([I32, I32, INT], SZ),
         "vesnet_farfield_stokeslet_backward": ([P, P, P, P, P, I32, I32, D, P, P, P, P, P, INT, P, SZ, P], INT),
+        "vesnet_backward_points_workspace_bytes": ([I32, I32, INT], SZ),
+        "vesnet_farfield_stokeslet_backward_points": ([P, P, P, P, I32, I32, D, P, P, P, P, INT, P, SZ, P], INT),
         "vesnet_farfield_stokeslet_nearmasked": ([P, P, P, P, P, I32, I32, D, P, P, I32, P, INT, CFG, P, SZ, P], INT),
         "vesnet_elastic_force": ([P, P, D, P, I32, I32, P, P, P], INT),
         "vesnet_near_layers": ([P, P, P, I32, I32, P, P], INT),

@@ -861,6 +861,94 @@ extern "C" int vesnet_farfield_stokeslet_backward(const double* targets, const d
   return ok();
 }
 
+// Adjoint for one point array (targets = sources = points, positions differentiated in both roles).
+namespace {
+
+// Targets per thread of the symmetric adjoint: the forward's choice, one when the problem is small.
+int sym_bwd_T(int32_t P) {
+  const int T = sym_default_T(P);
+  return T ? T : 1;
+}
+
+size_t backward_points_bytes(int32_t P, int32_t M, int prec) {
+  if (prec == VESNET_FP32_COMPENSATED)
+    return kAlign + 2 * prepared_bytes(P, M, prec, true) + symmetric_bytes(P, M);
+  return backward_bytes(P, M, prec) + align_up((size_t)2 * P * sizeof(double));
+}
+
+}  // namespace
+
+extern "C" size_t vesnet_backward_points_workspace_bytes(int32_t P, int32_t M, int prec) {
+  if (check_sizes(P, M) || (prec != VESNET_FP64 && prec != VESNET_FP32_COMPENSATED)) return 0;
+  return backward_points_bytes(P, M, prec);
+}
+
+extern "C" int vesnet_farfield_stokeslet_backward_points(const double* points, const double* f, const double* w,
+                                                         const int32_t* off, int32_t M, int32_t P, double mu,
+                                                         const double* gout, double* grad_points, double* grad_f,
+                                                         double* grad_w, int prec, void* ws, size_t ws_bytes,
+                                                         void* stream) {
+  int rc = check_forward_args(points, points, f, w, off, M, P, nullptr, prec, ws, ws_bytes, true, true);
+  if (rc) return rc;
+  if (prec == VESNET_FP32_NAIVE)
+    return fail(VESNET_ERR_UNSUPPORTED, "the backward pass supports VESNET_FP64 and VESNET_FP32_COMPENSATED only");
+  if ((rc = check_mu(mu))) return rc;
+  if (P == 0) return ok();
+  if (!gout) return fail(VESNET_ERR_INVALID_ARGUMENT, "grad_out is NULL");
+  const size_t vb = (size_t)2 * P * sizeof(double), sb = (size_t)P * sizeof(double);
+  const void* ins[] = {points, f, gout, off, ws, w};
+  const size_t inb[] = {vb, vb, vb, (size_t)(M + 1) * sizeof(int32_t), ws_bytes, sb};
+  const void* outs[] = {grad_points, grad_f, grad_w};
+  const size_t outb[] = {vb, vb, sb};
+  for (int a = 0; a < 3; ++a) {
+    if (!outs[a]) continue;
+    for (int b = 0; b < 6; ++b)
+      if (overlaps(outs[a], outb[a], ins[b], inb[b]))
+        return fail(VESNET_ERR_INVALID_ARGUMENT, "gradient output %d overlaps an input or the workspace", a);
+    for (int b = a + 1; b < 3; ++b)
+      if (overlaps(outs[a], outb[a], outs[b], outb[b]))
+        return fail(VESNET_ERR_INVALID_ARGUMENT, "gradient outputs %d and %d overlap", a, b);
+  }
+  if (!grad_points && !grad_f && !grad_w) return ok();
+  if ((rc = check_workspace(ws, ws_bytes, backward_points_bytes(P, M, prec)))) return rc;
+  const double scale = 1.0 / (4.0 * kPi * mu);
+  char* cur = aligned_base(ws);
+  hipError_t e = hipSuccess;
+  if (prec == VESNET_FP32_COMPENSATED && grad_points) {
+    // one symmetric pass: (points, w f) and (points, g) records, cycles and their sums of g
+    PreparedView pvF = carve_prepared(cur, P, M, prec, true);
+    PreparedView pvG = carve_prepared(cur, P, M, prec, true);
+    SymmetricView sv = carve_symmetric(cur, P, M);
+    e = launch_prepare(prec, points, f, w, off, M, P, pvF, stream);
+    if (e == hipSuccess) e = launch_prepare(prec, points, gout, nullptr, off, M, P, pvG, stream);
+    if (e != hipSuccess) return hip_fail(e, "backward prepare launch");
+    e = launch_backward_symmetric(sym_bwd_T(P), P, M, pvF, pvG, sv, reinterpret_cast<double*>(sv.acc), f, w, scale,
+                                  grad_points, grad_f, grad_w, stream);
+    if (e != hipSuccess) return hip_fail(e, "symmetric backward launch");
+    return ok();
+  }
+  // two gathers (targets, then sources), whose position gradients are added
+  PreparedView pvS = carve_prepared(cur, P, M, prec);
+  PreparedView pvT = carve_prepared(cur, P, M, prec);
+  const Shape sh = backward_shape(P, M, prec);
+  double* part_t = nullptr;
+  double* part_s = nullptr;
+  if (sh.splits > 1) {
+    part_t = reinterpret_cast<double*>(cur);
+    part_s = part_t + (size_t)2 * sh.splits * P;
+    cur += align_up((size_t)6 * sh.splits * P * sizeof(double));
+  }
+  double* grad_s = grad_points ? reinterpret_cast<double*>(cur) : nullptr;
+  if (grad_points) e = launch_prepare(prec, points, f, w, off, M, P, pvS, stream);
+  if (e == hipSuccess) e = launch_prepare(prec, points, gout, nullptr, off, M, P, pvT, stream);
+  if (e != hipSuccess) return hip_fail(e, "backward prepare launch");
+  e = launch_backward(prec, sh.T, sh.splits, points, points, f, w, gout, P, M, pvS, pvT, scale, grad_points, grad_s,
+                      grad_f, grad_w, part_t, part_s, stream);
+  if (e == hipSuccess && grad_points) e = launch_add_f64(grad_points, grad_s, (int64_t)2 * P, stream);
+  if (e != hipSuccess) return hip_fail(e, "backward launch");
+  return ok();
+}
+
 // ============================================================================ tuning
 
 extern "C" int vesnet_autotune(const double* targets, const double* sources, const double* f, const double* w,

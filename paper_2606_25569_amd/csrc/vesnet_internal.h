@@ -69,6 +69,14 @@ int64_t sym_max_blocks(int P, int M, int T);
 int64_t sym_units(int64_t nb);
 hipError_t launch_forward_symmetric(int T, int P, int M, const PreparedView& pv, const SymmetricView& sv,
                                     double scale, double* out, void* stream);
+// a[e] += b[e] for e < n (float64)
+hipError_t launch_add_f64(double* a, const double* b, int64_t n, void* stream);
+// Its adjoint for targets = sources: pvF prepared from (points, f, w), pvG from (points, dL/du, no
+// weights); vsum is a [2][P] float64 scratch; grad_points is required, grad_f and grad_w may be null.
+hipError_t launch_backward_symmetric(int T, int P, int M, const PreparedView& pvF, const PreparedView& pvG,
+                                     const SymmetricView& sv, double* vsum, const double* f, const double* w,
+                                     double scale, double* grad_points, double* grad_f, double* grad_w,
+                                     void* stream);
 hipError_t launch_forward_near(int prec, int T, bool lds, int splits, const double* tg, int P, int M,
                                const PreparedView& pv, double scale, double* out, double* partial, int32_t* count,
                                int32_t* pairs, int32_t capacity, void* stream);

@@ -425,6 +425,353 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_main(
   }
 }
 
+// Adjoint of the symmetric form, for targets = sources = X (the positions differentiated in both
+// roles, w and f held fixed).  With c = 1/(4 pi mu), g = dL/du and phi(r; a, b) = a^T G(r) b:
+//   v_k      = sum_{m not in ves(k)} G(X_k - X_m) g_m                (then dL/df = c w v, dL/dw = c f . v)
+//   dL/dX_k  = c sum_{m not in ves(k)} H(X_k - X_m),  H(r) = grad phi(r; g_k, F_m) + grad phi(r; F_k, g_m),
+//   grad phi(r; a, b) = [ -(a . b) r + a (r . b) + b (a . r) ] / |r|^2 - 2 (a . r)(r . b) r / |r|^4.
+// G is even and grad phi odd in r (and symmetric in a, b), so the pair (k, m) adds H to k and -H to m,
+// and G(r) g_k to v_m: one evaluation of r, |r|^2, its logarithm and reciprocal serves all four.
+// The ring, units and compensation are those of k_sym_main, with g in place of F for v; H is of degree
+// -1 in r, so on the rescaled r' = 2^-k r it is computed as H' = 2^k H and scaled back by 2^-k (rows at
+// the flush, columns per pair inside the column sum).  Sums are added with float64 atomics.
+template <int T>
+__global__ __launch_bounds__(kSymThreads) void k_sym_bwd(
+    const double4* __restrict__ vtab, const double2* __restrict__ vaux, const float4* __restrict__ recF,
+    const float4* __restrict__ recG, const int4* __restrict__ cyc, const double2* __restrict__ gcyc,
+    const int32_t* __restrict__ meta, int P, double* __restrict__ gsum, double* __restrict__ vsum) {
+  constexpr int CB = kRows * T;
+  __shared__ float4 s_tx[CB][kRing];               // target records (local coordinates, w f)
+  __shared__ float2 s_tg[CB][kRing];               // target g
+  __shared__ double4 s_tc[CB];                     // (c_A, G_cycle) of each target cycle
+  __shared__ double s_tr[CB];                      // R_A^2
+  __shared__ int4 s_ti[CB];                        // (vesicle or -1, count, first point, 0)
+  __shared__ float4 s_rec[2][kChunk][2 * kRing];   // source cycles (local coordinates, w f), twice
+  __shared__ float2 s_reg[2][kChunk][2 * kRing];   // source g, twice
+  __shared__ float s_col[2][kSymWaves][kChunk][4][kRing];
+  __shared__ double2 s_E[2][kSymWaves][kChunk];
+
+  const int ncyc = meta[0];
+  const int nb = meta[2];
+  if (nb <= 0) return;
+  const int Dh = nb >> 1;
+  const int units = (nb & 1) ? nb * (Dh + 1) : nb * Dh + Dh;
+  const int u = blockIdx.x;
+  if (u >= units) return;
+  const int d = u / nb;
+  const int bx = u - d * nb;
+  int by = bx + d;
+  if (by >= nb) by -= nb;
+  const bool diag = d == 0;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, p = lane & 15;
+  const int row = tid >> 4;
+  const int tc0 = bx * CB, tc1 = min(ncyc, tc0 + CB);
+  const int sc0 = by * CB, sc1 = min(ncyc, sc0 + CB);
+
+  for (int e = tid; e < CB * kRing; e += kSymThreads) {
+    const int t = e / kRing, m = e % kRing;
+    const int c = tc0 + t;
+    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+    float2 g = make_float2(0.f, 0.f);
+    if (c < tc1) {
+      const int4 cy = cyc[c];
+      if (m < cy.y) {
+        r = recF[cy.x + m];
+        const float4 rg = recG[cy.x + m];
+        g = make_float2(rg.z, rg.w);
+      }
+    }
+    s_tx[t][m] = r;
+    s_tg[t][m] = g;
+  }
+  for (int t = tid; t < CB; t += kSymThreads) {
+    const int c = tc0 + t;
+    if (c < tc1) {
+      const int4 cy = cyc[c];
+      const double4 vt = vtab[cy.z];
+      const double2 G = gcyc[c];
+      s_tc[t] = make_double4(vt.x, vt.y, G.x, G.y);
+      s_tr[t] = vaux[cy.z].y;
+      s_ti[t] = make_int4(cy.z, cy.y, cy.x, 0);
+    } else {
+      s_tc[t] = make_double4(0.0, 0.0, 0.0, 0.0);
+      s_tr[t] = 0.0;
+      s_ti[t] = make_int4(-1, 0, 0, 0);
+    }
+  }
+
+  // per target slot k: rescaled position d and -2^-k, the target's F and g (zero when inactive),
+  // -1/2 ln2 g, -2^-k for the column gradient, float32 partials of the segment, float64 sums
+  float dx[T], dy[T], ns[T], fix[T], fiy[T], gix[T], giy[T], ghx[T], ghy[T];
+  float lvx[T], lvy[T], rvx[T], rvy[T], gax[T], gay[T];
+  double avx[T], avy[T], agx[T], agy[T];
+  int kq[T];
+  int actm = 0;
+  double Ex = 0.0, Ey = 0.0, Gsx = 0.0, Gsy = 0.0;
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    dx[k] = dy[k] = ns[k] = fix[k] = fiy[k] = gix[k] = giy[k] = ghx[k] = ghy[k] = 0.f;
+    lvx[k] = lvy[k] = rvx[k] = rvy[k] = gax[k] = gay[k] = 0.f;
+    avx[k] = avy[k] = agx[k] = agy[k] = 0.0;
+    kq[k] = 0;
+  }
+
+  auto setup = [&](int B) {
+    const double4 vb = vtab[B];
+    const double rb2 = vaux[B].y;
+    double ex = 0.0, ey = 0.0;
+    actm = 0;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const int t = k * kRows + row;
+      const int4 ti = s_ti[t];
+      const double4 tc = s_tc[t];
+      const float4 tx = s_tx[t][p];
+      const float2 tg = s_tg[t][p];
+      const double Dx = tc.x - vb.x, Dy = tc.y - vb.y;
+      const double D = fma(Dy, Dy, fma(Dx, Dx, s_tr[t] + rb2));
+      int e;
+      frexp(D, &e);
+      const int kk = min(kMaxShift, max(-kMaxShift, e >> 1));
+      const bool rowact = ti.x >= 0 && ti.x != B && (!diag || ti.x < B);
+      const bool act = rowact && p < ti.y;
+      actm |= act ? (1 << k) : 0;
+      const float sc = ldexpf(1.0f, -kk);
+      dx[k] = act ? fmaf(tx.x, sc, (float)ldexp(Dx, -kk)) : kFar;
+      dy[k] = act ? fmaf(tx.y, sc, (float)ldexp(Dy, -kk)) : 0.f;
+      ns[k] = -sc;
+      fix[k] = act ? tx.z : 0.f;
+      fiy[k] = act ? tx.w : 0.f;
+      gix[k] = act ? tg.x : 0.f;
+      giy[k] = act ? tg.y : 0.f;
+      ghx[k] = kHalfLn2f * gix[k];
+      ghy[k] = kHalfLn2f * giy[k];
+      kq[k] = kk;
+      lvx[k] = lvy[k] = rvx[k] = rvy[k] = gax[k] = gay[k] = 0.f;
+      ex += rowact ? (double)kk * tc.z : 0.0;
+      ey += rowact ? (double)kk * tc.w : 0.0;
+    }
+    ex += __shfl_xor(ex, 16, 64);
+    ey += __shfl_xor(ey, 16, 64);
+    ex += __shfl_xor(ex, 32, 64);
+    ey += __shfl_xor(ey, 32, 64);
+    Ex = -kLn2d * ex;
+    Ey = -kLn2d * ey;
+    Gsx = Gsy = 0.0;
+  };
+
+  auto flush = [&]() {
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const bool act = (actm >> k) & 1;
+      const float pvx = fmaf(kHalfLn2f, lvx[k], rvx[k]);
+      const float pvy = fmaf(kHalfLn2f, lvy[k], rvy[k]);
+      const double c = -kLn2d * (double)kq[k];
+      const double sg = ldexp(1.0, -kq[k]);
+      avx[k] += act ? fma(c, Gsx, (double)pvx) : 0.0;
+      avy[k] += act ? fma(c, Gsy, (double)pvy) : 0.0;
+      agx[k] += act ? sg * (double)gax[k] : 0.0;
+      agy[k] += act ? sg * (double)gay[k] : 0.0;
+    }
+  };
+
+  auto ring = [&](int buf, int cc) {
+    const float4* rb = &s_rec[buf][cc][p];
+    const float2* gb = &s_reg[buf][cc][p];
+    float cvx = 0.f, cvy = 0.f, cgx = 0.f, cgy = 0.f;
+#pragma unroll 1
+    for (int s = 0; s < kRing; ++s) {
+      const float4 sr = rb[s];
+      const float2 sg = gb[s];
+      float lvcx = 0.f, lvcy = 0.f, lgcx = 0.f, lgcy = 0.f;
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const float rx = fmaf(sr.x, ns[k], dx[k]);
+        const float ry = fmaf(sr.y, ns[k], dy[k]);
+        const float q = fmaf(ry, ry, rx * rx);
+        const float L = __builtin_amdgcn_logf(q);
+        const float rho = __builtin_amdgcn_rcpf(q);
+        const float ux = rx * rho, uy = ry * rho;
+        const float p3 = fmaf(uy, sg.y, ux * sg.x);        // (r . g_j)/q
+        const float p2 = fmaf(uy, giy[k], ux * gix[k]);    // (r . g_i)/q
+        const float p1 = fmaf(uy, sr.w, ux * sr.z);        // (r . F_j)/q
+        const float p4 = fmaf(uy, fiy[k], ux * fix[k]);    // (r . F_i)/q
+        // v: G(r) g_j into the row, G(r) g_i into the column
+        lvx[k] = fmaf(L, sg.x, lvx[k]);
+        lvy[k] = fmaf(L, sg.y, lvy[k]);
+        rvx[k] = fmaf(p3, rx, rvx[k]);
+        rvy[k] = fmaf(p3, ry, rvy[k]);
+        // H' = -(rho (g_i . F_j + F_i . g_j) + 2 (p1 p2 + p3 p4)) r + g_i p1 + F_j p2 + F_i p3 + g_j p4
+        const float ab = fmaf(gix[k], sr.z, fmaf(giy[k], sr.w, fmaf(fix[k], sg.x, fiy[k] * sg.y)));
+        const float m = fmaf(2.0f, fmaf(p1, p2, p3 * p4), rho * ab);
+        const float hx = fmaf(sg.x, p4, fmaf(fix[k], p3, fmaf(sr.z, p2, fmaf(gix[k], p1, -m * rx))));
+        const float hy = fmaf(sg.y, p4, fmaf(fiy[k], p3, fmaf(sr.w, p2, fmaf(giy[k], p1, -m * ry))));
+        gax[k] += hx;
+        gay[k] += hy;
+        if (k == 0) {
+          lvcx = L * ghx[k];
+          lvcy = L * ghy[k];
+          lgcx = ns[k] * hx;
+          lgcy = ns[k] * hy;
+        } else {
+          lvcx = fmaf(L, ghx[k], lvcx);
+          lvcy = fmaf(L, ghy[k], lvcy);
+          lgcx = fmaf(ns[k], hx, lgcx);
+          lgcy = fmaf(ns[k], hy, lgcy);
+        }
+        lvcx = fmaf(p2, rx, lvcx);
+        lvcy = fmaf(p2, ry, lvcy);
+      }
+      cvx = ring_next(cvx) + lvcx;
+      cvy = ring_next(cvy) + lvcy;
+      cgx = ring_next(cgx) + lgcx;
+      cgy = ring_next(cgy) + lgcy;
+    }
+    // add the four rows: v in the first swap, the gradient in the second
+    const auto hv = __builtin_amdgcn_permlane32_swap(bitsu(cvx), bitsu(cvy), false, false);
+    const float zv = bitsf(hv[0]) + bitsf(hv[1]);
+    const auto rv16 = __builtin_amdgcn_permlane16_swap(bitsu(zv), bitsu(zv), false, false);
+    const float totv = bitsf(rv16[0]) + bitsf(rv16[1]);
+    const auto hg = __builtin_amdgcn_permlane32_swap(bitsu(cgx), bitsu(cgy), false, false);
+    const float zg = bitsf(hg[0]) + bitsf(hg[1]);
+    const auto rg16 = __builtin_amdgcn_permlane16_swap(bitsu(zg), bitsu(zg), false, false);
+    const float totg = bitsf(rg16[0]) + bitsf(rg16[1]);
+    if ((lane & 16) == 0) {
+      const int slot = (p + kRing - 1) & (kRing - 1);
+      s_col[buf][wv][cc][lane >> 5][slot] = totv;
+      s_col[buf][wv][cc][2 + (lane >> 5)][slot] = totg;
+    }
+  };
+
+  const int nchunks = (sc1 - sc0 + kChunk - 1) / kChunk;
+  const bool stager = tid < kChunk * 2 * kRing;
+  const int st_cc = tid >> 5, st_q = tid & 31, st_m = st_q & (kRing - 1);
+  auto stage_load = [&](int g, float2& gg) {
+    float4 r = make_float4(0.f, 0.f, 0.f, 0.f);
+    gg = make_float2(0.f, 0.f);
+    const int c = sc0 + g * kChunk + st_cc;
+    if (stager && c < sc1) {
+      const int4 cy = cyc[c];
+      const int j = cy.x + (st_m < cy.y ? st_m : 0);
+      r = recF[j];
+      const float4 rg = recG[j];
+      if (st_m >= cy.y) {
+        r.z = r.w = 0.f;
+      } else {
+        gg = make_float2(rg.z, rg.w);
+      }
+    }
+    return r;
+  };
+  auto stage_store = [&](int buf, const float4& r, const float2& gg) {
+    if (stager) {
+      s_rec[buf][st_cc][st_q] = r;
+      s_reg[buf][st_cc][st_q] = gg;
+    }
+  };
+
+  // Column sums of chunk g: v (with its log correction) and the gradient, added over the
+  // wavefronts in a fixed order, then one float64 atomic addition per (source, component).
+  auto reduce = [&](int g, int buf) {
+    for (int e = tid; e < kChunk * 4 * kRing; e += kSymThreads) {
+      const int cc = e / (4 * kRing), comp = (e / kRing) & 3, m = e & (kRing - 1);
+      const int c = sc0 + g * kChunk + cc;
+      if (c >= sc1) continue;
+      const int4 cy = cyc[c];
+      if (m >= cy.y) continue;
+      double s = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < kSymWaves; ++w2) s += (double)s_col[buf][w2][cc][comp][m];
+      if (comp < 2) {
+#pragma unroll
+        for (int w2 = 0; w2 < kSymWaves; ++w2) {
+          const double2 E = s_E[buf][w2][cc];
+          s += comp ? E.y : E.x;
+        }
+        atomicAdd(&vsum[(size_t)comp * P + cy.x + m], s);
+      } else {
+        atomicAdd(&gsum[(size_t)(comp - 2) * P + cy.x + m], s);
+      }
+    }
+  };
+
+  int curB = -1;
+  {
+    float2 gg;
+    const float4 r = stage_load(0, gg);
+    stage_store(0, r, gg);
+  }
+  __syncthreads();
+  for (int g = 0; g < nchunks; ++g) {
+    const int buf = g & 1;
+    float2 ngg;
+    const float4 nxt = stage_load(g + 1, ngg);
+    if (g > 0) reduce(g - 1, buf ^ 1);
+    const int cbase = sc0 + g * kChunk;
+    const int ncc = min(kChunk, sc1 - cbase);
+    for (int cc = 0; cc < ncc; ++cc) {
+      const int4 cy = cyc[cbase + cc];
+      if (cy.z != curB) {
+        if (curB >= 0) flush();
+        setup(cy.z);
+        curB = cy.z;
+      }
+      const double2 Gc = gcyc[cbase + cc];
+      Gsx += Gc.x;
+      Gsy += Gc.y;
+      ring(buf, cc);
+      if (lane == 0) s_E[buf][wv][cc] = make_double2(Ex, Ey);
+    }
+    stage_store(buf ^ 1, nxt, ngg);
+    __syncthreads();
+  }
+  if (nchunks > 0) {
+    reduce(nchunks - 1, (nchunks - 1) & 1);
+    flush();
+  }
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    const int4 ti = s_ti[k * kRows + row];
+    if (ti.x >= 0 && p < ti.y) {
+      const int i = ti.z + p;
+      atomicAdd(&vsum[i], avx[k]);
+      atomicAdd(&vsum[(size_t)P + i], avy[k]);
+      atomicAdd(&gsum[i], agx[k]);
+      atomicAdd(&gsum[(size_t)P + i], agy[k]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ a, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    a[e] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_add_f64(double* __restrict__ a, const double* __restrict__ b, int64_t n) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    a[e] += b[e];
+}
+
+// dL/dX = c gsum (in place), dL/df = c w v, dL/dw = c f . v
+__global__ __launch_bounds__(256) void k_sym_bwd_finish(const double* __restrict__ vsum, const double* __restrict__ f,
+                                                        const double* __restrict__ w, int P, double scale,
+                                                        double* __restrict__ gX, double* __restrict__ gf,
+                                                        double* __restrict__ gw) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < P; j += gridDim.x * blockDim.x) {
+    if (gX) {
+      gX[j] *= scale;
+      gX[P + j] *= scale;
+    }
+    const double vx = scale * vsum[j], vy = scale * vsum[P + j];
+    if (gf) {
+      gf[j] = w[j] * vx;
+      gf[P + j] = w[j] * vy;
+    }
+    if (gw) gw[j] = f[j] * vx + f[P + j] * vy;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_sym_finish(const unsigned long long* __restrict__ acc,
                                                     const int32_t* __restrict__ meta, int P, double scale,
                                                     double* __restrict__ out) {
@@ -451,6 +798,48 @@ int64_t sym_units(int64_t nb) {
   if (nb <= 0) return 0;
   const int64_t h = nb / 2;
   return (nb & 1) ? nb * (h + 1) : nb * h + h;
+}
+
+hipError_t launch_backward_symmetric(int T, int P, int M, const PreparedView& pvF, const PreparedView& pvG,
+                                     const SymmetricView& sv, double* vsum, const double* f, const double* w,
+                                     double scale, double* grad_points, double* grad_f, double* grad_w,
+                                     void* stream) {
+  if (P == 0) return hipSuccess;
+  if (!grad_points || !vsum) return hipErrorInvalidValue;
+  hipStream_t st = Sx_(stream);
+  const int cb = sym_cycles_per_block(T);
+  const int ncyc_max = (int)sym_max_cycles(P, M);
+  const int nb_max = (int)sym_max_blocks(P, M, T);
+  hipLaunchKernelGGL(k_sym_plan, dim3(1), dim3(1024), 0, st, pvF.vrange, pvF.vaux, M, cb, ncyc_max, sv.cyc, sv.meta);
+  const int cgrid = (int)std::min<int64_t>((2 * (int64_t)P + 255) / 256, 4096);
+  // cycle sums of g (its float64 copy is the f64 array of the g-prepared region)
+  hipLaunchKernelGGL(k_sym_cycles, dim3(cgrid), dim3(256), 0, st, sv.cyc, sv.meta, pvG.f64, P, sv.fcyc, sv.acc);
+  hipLaunchKernelGGL(k_zero_f64, dim3(cgrid), dim3(256), 0, st, grad_points, 2 * (int64_t)P);
+  hipLaunchKernelGGL(k_zero_f64, dim3(cgrid), dim3(256), 0, st, vsum, 2 * (int64_t)P);
+  const dim3 grid((unsigned)sym_units(nb_max));
+  const float4* recF = static_cast<const float4*>(pvF.rec);
+  const float4* recG = static_cast<const float4*>(pvG.rec);
+  switch (T) {
+#define VESNET_SYMB_CASE(TT)                                                                                   \
+  case TT:                                                                                                     \
+    hipLaunchKernelGGL(k_sym_bwd<TT>, grid, dim3(kSymThreads), 0, st, pvF.vtab, pvF.vaux, recF, recG, sv.cyc,  \
+                       sv.fcyc, sv.meta, P, grad_points, vsum);                                                 \
+    break;
+    VESNET_SYMB_CASE(1) VESNET_SYMB_CASE(2) VESNET_SYMB_CASE(4)
+#undef VESNET_SYMB_CASE
+    default: return hipErrorInvalidValue;
+  }
+  const int fgrid = (P + 255) / 256 < 16384 ? (P + 255) / 256 : 16384;
+  hipLaunchKernelGGL(k_sym_bwd_finish, dim3(fgrid), dim3(256), 0, st, vsum, f, w, P, scale, grad_points, grad_f,
+                     grad_w);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_f64(double* a, const double* b, int64_t n, void* stream) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_add_f64, dim3(grid), dim3(256), 0, Sx_(stream), a, b, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_forward_symmetric(int T, int P, int M, const PreparedView& pv, const SymmetricView& sv,

@@ -318,13 +318,33 @@ def farfield_backward(targets, sources, force_density, arc_weights, partition, m
     return gt, gs, gf, gw
 
 
+def farfield_backward_points(points, force_density, arc_weights, partition, mu, grad_out, precision="fp32c",
+                             need=(True, True, True)):
+    """Reverse mode for one point array used as targets and sources: returns (grad_points,
+    grad_force, grad_weights), None where not needed.  grad_points holds both roles of each point."""
+    part = as_partition(partition)
+    P, M = part.n_points, part.n_vesicles
+    _check_vec("grad_out", grad_out, P)
+    prec = L.precision_code(precision)
+    dev = points.device
+    gx = torch.empty((2, P), dtype=torch.float64, device=dev) if need[0] else None
+    gf = torch.empty((2, P), dtype=torch.float64, device=dev) if need[1] else None
+    gw = torch.empty((P,), dtype=torch.float64, device=dev) if need[2] else None
+    ws = _workspace(L.lib().vesnet_backward_points_workspace_bytes(P, M, prec), dev)
+    L.check(L.lib().vesnet_farfield_stokeslet_backward_points(
+        _ptr(points), _ptr(force_density), _ptr(arc_weights), _ptr(part.device), M, P, float(mu), _ptr(grad_out),
+        _ptr(gx), _ptr(gf), _ptr(gw), prec, _ptr(ws), ws.numel(), _stream()))
+    return gx, gf, gw
+
+
 class _FarField(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, targets, sources, force_density, arc_weights, part, mu, precision, config):
+    def forward(ctx, targets, sources, force_density, arc_weights, part, mu, precision, config, same=False):
         out = farfield_forward(targets, sources, force_density, arc_weights, part, mu, precision, config)
         ctx.save_for_backward(targets, sources, force_density, arc_weights)
         ctx.part, ctx.mu = part, mu
         ctx.precision = L.precision_code(precision)
+        ctx.same = same
         return out
 
     @staticmethod
@@ -332,12 +352,17 @@ class _FarField(torch.autograd.Function):
         targets, sources, f, w = ctx.saved_tensors
         need = ctx.needs_input_grad[:4]
         if not any(need):
-            return (None,) * 8
+            return (None,) * 9
         if ctx.precision == L.FP32_NAIVE:
             raise L.VesnetError(L.ERR_UNSUPPORTED, "the naive float32 control has no backward; use 'fp32c' or 'fp64'")
         g = grad_out.contiguous()
+        if ctx.same and need[0] and need[1]:
+            # one tensor in both roles: its gradient is the sum of the two, computed in one pass
+            gx, gf, gw = farfield_backward_points(targets, f, w, ctx.part, ctx.mu, g, ctx.precision,
+                                                  (True, need[2], need[3]))
+            return gx, None, gf, gw, None, None, None, None, None
         gt, gs, gf, gw = farfield_backward(targets, sources, f, w, ctx.part, ctx.mu, g, ctx.precision, need)
-        return gt, gs, gf, gw, None, None, None, None
+        return gt, gs, gf, gw, None, None, None, None, None
 
 
 def farfield_stokeslet(targets, sources, force_density, arc_weights, vesicle_offsets, mu=1.0, precision="fp32c",
@@ -346,7 +371,8 @@ def farfield_stokeslet(targets, sources, force_density, arc_weights, vesicle_off
     force_density and arc_weights (the backward runs the hand-written adjoint
     kernels; the naive float32 form has no backward)."""
     part = as_partition(vesicle_offsets)
-    return _FarField.apply(targets, sources, force_density, arc_weights, part, float(mu), precision, config)
+    return _FarField.apply(targets, sources, force_density, arc_weights, part, float(mu), precision, config,
+                           targets is sources)
 
 
 # ----------------------------------------------------------------------------- batched

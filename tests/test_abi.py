@@ -24,7 +24,7 @@ def _declared():
 def test_every_declared_symbol_is_exported(L):
     lib = L.lib()
     names = _declared()
-    assert len(names) == 31, names
+    assert len(names) == 33, names
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(L.EXPORTED)
@@ -144,6 +144,37 @@ def test_backward_rejects(L):
     # workspace too small
     assert lib.vesnet_farfield_stokeslet_backward(*args, _p(FAKE + 0x700000), None, None, None, 1, _p(FAKE + 0x600000),
                                                   8, None) == -3
+
+
+def test_backward_points_rejects(L):
+    lib = L.lib()
+    # points, force_density, arc_weights, offsets, M, P, mu, grad_out
+    args = [_p(FAKE), _p(FAKE + 0x100000), _p(FAKE + 0x200000), _p(FAKE + 0x300000), 2, 10, 1.0, _p(FAKE + 0x500000)]
+    ws = [_p(FAKE + 0x600000), 1 << 30, None]
+    assert lib.vesnet_farfield_stokeslet_backward_points(*args, _p(FAKE + 0x700000), None, None, 2, *ws) == -2
+    assert lib.vesnet_farfield_stokeslet_backward_points(*args, _p(FAKE + 0x700000), _p(FAKE + 0x700000 + 8), None, 1,
+                                                         *ws) == -1
+    assert lib.vesnet_farfield_stokeslet_backward_points(*args, _p(FAKE + 0x500000), None, None, 1, *ws) == -1
+    assert lib.vesnet_farfield_stokeslet_backward_points(*args, None, None, _p(FAKE + 0x200000), 1, *ws) == -1
+    a2 = list(args)
+    a2[7] = None
+    assert lib.vesnet_farfield_stokeslet_backward_points(*a2, _p(FAKE + 0x700000), None, None, 1, *ws) == -1
+    a2 = list(args)
+    a2[6] = -1.0
+    assert lib.vesnet_farfield_stokeslet_backward_points(*a2, _p(FAKE + 0x700000), None, None, 1, *ws) == -1
+    assert lib.vesnet_farfield_stokeslet_backward_points(*args, _p(FAKE + 0x700000), None, None, 1,
+                                                         _p(FAKE + 0x600000), 8, None) == -3
+    # nothing requested, and the empty problem: no-ops
+    assert lib.vesnet_farfield_stokeslet_backward_points(*args, None, None, None, 1, *ws) == 0
+    assert lib.vesnet_farfield_stokeslet_backward_points(None, None, None, None, 0, 0, 1.0, None, None, None, None, 1,
+                                                         None, 0, None) == 0
+    # workspace sizes: the symmetric (fp32c) form needs less than the gathers plus their sum buffer
+    for P, M in ((512, 16), (256000, 2000)):
+        b32 = lib.vesnet_backward_points_workspace_bytes(P, M, 1)
+        b64 = lib.vesnet_backward_points_workspace_bytes(P, M, 0)
+        assert 0 < b32 and 0 < b64
+        assert b64 >= lib.vesnet_backward_workspace_bytes(P, M, 0) + 16 * P
+    assert lib.vesnet_backward_points_workspace_bytes(512, 16, 2) == 0
 
 
 def test_batched_rejects(L):
