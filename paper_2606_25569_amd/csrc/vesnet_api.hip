@@ -184,6 +184,12 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
   if (s.pair == 2 && s.accumulate == 2)
     return fail(VESNET_ERR_UNSUPPORTED, "the symmetric pair form accumulates on the VALU only");
   if (s.pair == 2 && s.symT == 0) s.symT = 1;
+  if (s.symT && !sym_fits(P, M, s.symT)) {
+    if (s.pair == 2)
+      return fail(VESNET_ERR_UNSUPPORTED, "too many points for the symmetric form at %d targets per thread (its "
+                  "units exceed one launch); use more targets per thread or the direct form", s.symT);
+    s.symT = sym_fits(P, M, 4) ? 4 : sym_fits(P, M, 8) ? 8 : 0;
+  }
   *out = s;
   return VESNET_OK;
 }
@@ -864,16 +870,22 @@ extern "C" int vesnet_farfield_stokeslet_backward(const double* targets, const d
 // Adjoint for one point array (targets = sources = points, positions differentiated in both roles).
 namespace {
 
-// Targets per thread of the symmetric adjoint: the forward's choice, one when the problem is small.
-int sym_bwd_T(int32_t P) {
+// Targets per thread of the symmetric adjoint: the forward's choice, one when the problem is small,
+// four when the units of the smaller choice would not fit one launch; 0 when none fits (the gathers).
+int sym_bwd_T(int32_t P, int32_t M) {
   const int T = sym_default_T(P);
-  return T ? T : 1;
+  if (sym_fits(P, M, T ? T : 1)) return T ? T : 1;
+  return sym_fits(P, M, 4) ? 4 : 0;
 }
 
+// The symmetric pass (FP32-compensated): two prepared regions with forces, the cycle tables and a
+// [2][P] buffer for the position gradient when the caller does not ask for it; otherwise the
+// gathers' workspace and a [2][P] buffer for the source-role gradient.
 size_t backward_points_bytes(int32_t P, int32_t M, int prec) {
-  if (prec == VESNET_FP32_COMPENSATED)
-    return kAlign + 2 * prepared_bytes(P, M, prec, true) + symmetric_bytes(P, M);
-  return backward_bytes(P, M, prec) + align_up((size_t)2 * P * sizeof(double));
+  const size_t vec = align_up((size_t)2 * P * sizeof(double));
+  if (prec == VESNET_FP32_COMPENSATED && sym_bwd_T(P, M))
+    return kAlign + 2 * prepared_bytes(P, M, prec, true) + symmetric_bytes(P, M) + vec;
+  return backward_bytes(P, M, prec) + vec;
 }
 
 }  // namespace
@@ -914,16 +926,18 @@ extern "C" int vesnet_farfield_stokeslet_backward_points(const double* points, c
   const double scale = 1.0 / (4.0 * kPi * mu);
   char* cur = aligned_base(ws);
   hipError_t e = hipSuccess;
-  if (prec == VESNET_FP32_COMPENSATED && grad_points) {
+  const int symT = prec == VESNET_FP32_COMPENSATED ? sym_bwd_T(P, M) : 0;
+  if (symT) {
     // one symmetric pass: (points, w f) and (points, g) records, cycles and their sums of g
     PreparedView pvF = carve_prepared(cur, P, M, prec, true);
     PreparedView pvG = carve_prepared(cur, P, M, prec, true);
     SymmetricView sv = carve_symmetric(cur, P, M);
+    double* gx = grad_points ? grad_points : reinterpret_cast<double*>(cur);
     e = launch_prepare(prec, points, f, w, off, M, P, pvF, stream);
     if (e == hipSuccess) e = launch_prepare(prec, points, gout, nullptr, off, M, P, pvG, stream);
     if (e != hipSuccess) return hip_fail(e, "backward prepare launch");
-    e = launch_backward_symmetric(sym_bwd_T(P), P, M, pvF, pvG, sv, reinterpret_cast<double*>(sv.acc), f, w, scale,
-                                  grad_points, grad_f, grad_w, stream);
+    e = launch_backward_symmetric(symT, P, M, pvF, pvG, sv, reinterpret_cast<double*>(sv.acc), f, w, scale, gx,
+                                  grad_f, grad_w, stream);
     if (e != hipSuccess) return hip_fail(e, "symmetric backward launch");
     return ok();
   }

@@ -67,6 +67,8 @@ int sym_cycles_per_block(int T);
 int64_t sym_max_cycles(int P, int M);
 int64_t sym_max_blocks(int P, int M, int T);
 int64_t sym_units(int64_t nb);
+// whether the unit count of the symmetric form at T targets per thread fits one launch (2^31 - 1)
+bool sym_fits(int P, int M, int T);
 hipError_t launch_forward_symmetric(int T, int P, int M, const PreparedView& pv, const SymmetricView& sv,
                                     double scale, double* out, void* stream);
 // a[e] += b[e] for e < n (float64)

@@ -65,6 +65,7 @@ namespace vesnet {
 namespace {
 
 constexpr int kRing = 16;                          // sources per ring cycle (one DPP row)
+constexpr int kXcds = 8;                           // XCDs of the MI355X (workgroups are dealt to them in turn)
 constexpr int kSymThreads = 256;                   // threads per unit (4 wavefronts, one per SIMD)
 constexpr int kSymWaves = kSymThreads / 64;
 constexpr int kRows = kSymThreads / kRing;         // rows of 16 lanes per unit
@@ -171,6 +172,33 @@ __global__ __launch_bounds__(256) void k_sym_cycles(const int4* __restrict__ cyc
   }
 }
 
+// The unit (row block bx, column block by) of this workgroup, false when it has none.  Units are the
+// pairs {bx, bx + d mod nb}, d = 0 .. nb/2 (for even nb, d = nb/2 only for bx < nb/2), numbered row
+// block by row block.  Workgroups are handed to the eight XCDs in turn (workgroup g to XCD g mod 8), so
+// each XCD is given one contiguous range of that numbering: its concurrent units share a row block and
+// a window of about nb/2 consecutive column blocks, which stays in the XCD's own L2.
+__device__ __forceinline__ bool sym_unit(int nb, int& bx, int& by) {
+  const int h = nb >> 1;
+  const int units = (nb & 1) ? nb * (h + 1) : nb * h + h;
+  const int g = blockIdx.x;
+  if (g >= units) return false;
+  const int q = units / kXcds, r = units % kXcds;
+  const int x = g % kXcds;
+  const int L = x * q + min(x, r) + g / kXcds;
+  int d;
+  if (L < h * (h + 1) || (nb & 1)) {
+    bx = L / (h + 1);
+    d = L - bx * (h + 1);
+  } else {
+    const int L2 = L - h * (h + 1);
+    bx = h + L2 / h;
+    d = L2 - (bx - h) * h;
+  }
+  by = bx + d;
+  if (by >= nb) by -= nb;
+  return true;
+}
+
 // One unit {bx, by} per workgroup (see the file header).
 template <int T>
 __global__ __launch_bounds__(kSymThreads) void k_sym_main(
@@ -190,15 +218,9 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_main(
   const int S = meta[1];
   const int nb = meta[2];
   if (nb <= 0) return;
-  const int Dh = nb >> 1;
-  const int units = (nb & 1) ? nb * (Dh + 1) : nb * Dh + Dh;
-  const int u = blockIdx.x;
-  if (u >= units) return;
-  const int d = u / nb;
-  const int bx = u - d * nb;
-  int by = bx + d;
-  if (by >= nb) by -= nb;
-  const bool diag = d == 0;
+  int bx, by;
+  if (!sym_unit(nb, bx, by)) return;
+  const bool diag = bx == by;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, p = lane & 15;
   const int row = tid >> 4;
@@ -454,15 +476,9 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_bwd(
   const int ncyc = meta[0];
   const int nb = meta[2];
   if (nb <= 0) return;
-  const int Dh = nb >> 1;
-  const int units = (nb & 1) ? nb * (Dh + 1) : nb * Dh + Dh;
-  const int u = blockIdx.x;
-  if (u >= units) return;
-  const int d = u / nb;
-  const int bx = u - d * nb;
-  int by = bx + d;
-  if (by >= nb) by -= nb;
-  const bool diag = d == 0;
+  int bx, by;
+  if (!sym_unit(nb, bx, by)) return;
+  const bool diag = bx == by;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, p = lane & 15;
   const int row = tid >> 4;
@@ -799,6 +815,8 @@ int64_t sym_units(int64_t nb) {
   const int64_t h = nb / 2;
   return (nb & 1) ? nb * (h + 1) : nb * h + h;
 }
+
+bool sym_fits(int P, int M, int T) { return sym_units(sym_max_blocks(P, M, T)) <= (int64_t)INT32_MAX; }
 
 hipError_t launch_backward_symmetric(int T, int P, int M, const PreparedView& pvF, const PreparedView& pvG,
                                      const SymmetricView& sv, double* vsum, const double* f, const double* w,

@@ -111,8 +111,8 @@ def test_config4_sampled(V, prec):
 
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
 def test_partial_requests_agree(V, prec):
-    """grad_force and grad_weights alone, or with the positions, give the same values (without the
-    positions the fp32c call takes the gathers' v pass, so the two differ only by rounding)."""
+    """grad_force and grad_weights alone, or with the positions, give the same values up to the order
+    of the float64 atomic additions (fp32c: the position gradient then goes to the workspace)."""
     s = _ragged_suspension(seed=5)
     g = _g(s, 15)
     full = _points(V, s, g, prec)

@@ -143,13 +143,15 @@ def test_config1_sampled_full_size(V):
 
 @pytest.mark.parametrize("variant", ["force_free", "net_force"])
 def test_config2_precision_study(V, variant):
-    """8000 x 64 at 35%: naive float32, compensated float32 and float64 against the oracle."""
+    """8000 x 64 at 35%: naive float32, compensated float32 (direct form; the symmetric form has its
+    own test) and float64 against the oracle on the seeded 1% target sample."""
     s = S.load_config(2, variant)
-    sel = S.sample_targets(s.n_points, 0.002, 202)
+    sel = S.sample_targets(s.n_points, 0.01, 202)
+    say(f"cfg2 {variant}: oracle on {sel.size} targets x {s.n_points} sources")
     ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu, select=sel)
     res = {}
     for prec in ("fp32", "fp32c", "fp64"):
-        res[prec] = rel_err(_run(V, s, prec)[:, sel], ref)
+        res[prec] = rel_err(_run(V, s, prec, {"pair_form": 1} if prec == "fp32c" else None)[:, sel], ref)
         say(f"cfg2 {variant} {prec}: max rel err {res[prec][0]:.3e}  rms {res[prec][1]:.3e}")
     assert res["fp64"][0] <= 1e-12
     assert res["fp32c"][0] <= 1e-5
