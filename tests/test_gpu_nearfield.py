@@ -45,8 +45,12 @@ def test_no_near_pairs_equals_plain_far_field():
     import paper_2606_25569_amd as V
     s = S.load_config(4)
     X, f, w = dev_inputs(s)
-    plain = V.farfield_forward(X, X, f, w, s.offsets, s.mu, "fp32c")
+    # the masked kernel extends the direct gather, so it is compared with the direct form; the default
+    # (symmetric) form rounds its float32 terms in another order and agrees to the float32 bar
+    plain = V.farfield_forward(X, X, f, w, s.offsets, s.mu, "fp32c", config={"pair_form": 1})
+    sym = V.farfield_forward(X, X, f, w, s.offsets, s.mu, "fp32c")
     out, pairs = V.farfield_nearmasked(X, X, f, w, s.offsets, s.mu, "fp32c")
     torch.cuda.synchronize()
     assert pairs.shape[0] == 0
     assert torch.equal(out, plain) or rel_err(out.cpu().numpy(), plain.cpu().numpy())[0] < 1e-14
+    assert rel_err(out.cpu().numpy(), sym.cpu().numpy())[0] < 1e-5
