@@ -345,13 +345,26 @@ def bench_batched(args):
     X = torch.tensor(b.X, device=dev)
     f = torch.tensor(b.f, device=dev)
     w = torch.tensor(b.w, device=dev)
-    bp = V.BatchedProblem(X, X, f, w, b.vesicle_offsets, b.suspension_offsets, b.mu, precision="fp32c")
-    best, tms = V.autotune(None, None, None, None, None, batched=bp, repeats=2)
-    log(f"[bench] batched autotune: {best.as_dict()} {tms:.3f} ms")
-    bp.config = best
-    t_eager = _time(bp.run, args.steps, stream)
-    bp.capture()
-    t_graph = _time(bp.replay, args.steps, stream)
+    # the library's default shape (the batched symmetric form), the direct persistent form, and the
+    # autotuner's choice, each eager and as a HIP graph
+    forms = {}
+    for name, cfg in (("symmetric_default", None), ("direct_default", {"pair_form": 1}), ("tuned", "tune")):
+        bp = V.BatchedProblem(X, X, f, w, b.vesicle_offsets, b.suspension_offsets, b.mu, precision="fp32c",
+                              config=None if cfg == "tune" else cfg)
+        if cfg == "tune":
+            best, tms = V.autotune(None, None, None, None, None, batched=bp, repeats=2)
+            log(f"[bench] batched autotune: {best.as_dict()} {tms:.3f} ms")
+            bp.config = best
+        te = _time(bp.run, args.steps, stream)
+        bp.capture()
+        tg = _time(bp.replay, args.steps, stream)
+        bp.close()
+        forms[name] = {"eager_ms": te, "graph_ms": tg, "pairs_per_s_graph": pairs / (tg * 1e-3),
+                       "tflops_graph": FLOPS_PER_PAIR * pairs / (tg * 1e-3) / 1e12,
+                       "frac_fp32_peak_graph": FLOPS_PER_PAIR * pairs / (tg * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
+                       "tile": (bp.config.as_dict() if bp.config is not None else "library default")}
+        log(f"[bench] batched {name}: eager {te:.3f} ms, graph {tg:.3f} ms -> {pairs / (tg * 1e-3):.4e} pairs/s")
+    t_eager, t_graph = forms["tuned"]["eager_ms"], forms["tuned"]["graph_ms"]
     # one prepare+evaluate per suspension, each with its own tuned-by-default shape
     parts, slices, wss, outs = [], [], [], []
     base = 0
@@ -375,7 +388,7 @@ def bench_batched(args):
     t_loop_graph = _time(g.replay, args.steps, stream)
     rec = {"workload": "batched: 64 independent suspensions, M log-uniform in [10,1500], N in {32,64,128}, "
                        "area fraction U[0.20,0.35], FP32-compensated",
-           "n_points": b.n_points, "cross_vesicle_pairs": pairs, "tile": best.as_dict(),
+           "n_points": b.n_points, "cross_vesicle_pairs": pairs, "tile": best.as_dict(), "forms": forms,
            "ms": {"persistent_eager": t_eager, "persistent_graph": t_graph, "loop_eager": t_loop,
                   "loop_graph": t_loop_graph},
            "pairs_per_s": {"persistent_graph": pairs / (t_graph * 1e-3), "loop_graph": pairs / (t_loop_graph * 1e-3)},

@@ -77,7 +77,8 @@ typedef struct {
   int32_t block_threads;      /* 64, 128 or 256                                               */
   int32_t source_splits;      /* >= 1: source vesicles split into this many chunks, reduced in
                                  a fixed order by a second kernel (bitwise deterministic)      */
-  int32_t blocks_per_cu;      /* batched persistent grid: workgroups per compute unit (1..16) */
+  int32_t blocks_per_cu;      /* batched persistent grid: workgroups per compute unit (1..16;
+                                 0: 4 for the direct form, as many as fit for the symmetric form) */
   int32_t source_staging;     /* 1: source records read at wave-uniform addresses into SGPRs;
                                  2: records staged through LDS tiles of 1024 and read back with
                                     broadcast LDS loads into VGPRs                               */
@@ -358,9 +359,26 @@ VESNET_API int vesnet_farfield_fmm_nearmasked(const double* points, const double
    Suspension s owns vesicles suspension_offsets[s] .. suspension_offsets[s+1]-1
    (device int32 [S+1], suspension_offsets[0] = 0, [S] = V) and has viscosity
    mu[s] (device float64 [S], each > 0).  No interaction crosses suspensions.
-   One persistent launch: work items (suspension, block of targets) are ordered
-   largest suspension first on the device and handed out through a counter in
-   the workspace, so the call needs no host-side copy of the tables. */
+   Each suspension's result is the single call's (vesnet_farfield_stokeslet) on
+   its own points; the call needs no host-side copy of the tables (they are
+   read on the device, so the call can be captured once and replayed).
+   Two forms, chosen as in the single call (cfg->pair_form):
+   * symmetric (VESNET_FP32_COMPENSATED, targets == sources, pair_form 0 or 2):
+     the single call's symmetric form for every suspension in one persistent
+     launch.  A plan kernel cuts each suspension into blocks of 256 T points
+     (T = targets_per_thread: 1, 2 or 4 when pair_form is 2, else the single
+     call's default for the total point count) that never reach into another
+     suspension; the unordered pairs of a suspension's blocks are its units,
+     numbered suspension by suspension and split into eight contiguous queues,
+     one per XCD, drained through counters in the workspace by
+     blocks_per_cu workgroups per compute unit (0: as many as fit).  Every
+     suspension's output equals that of a single symmetric call with the same
+     T bit for bit (the fixed-point sums do not depend on the order).
+   * direct (every other call, or pair_form 1): work items (suspension, block
+     of targets) ordered largest suspension first on the device and handed
+     out through a counter in the workspace.
+   Errors: VESNET_ERR_UNSUPPORTED when the symmetric form's units could exceed
+   one launch (about 2^31; use pair_form 1), else as the single call. */
 VESNET_API size_t vesnet_batched_workspace_bytes(int32_t n_points, int32_t n_vesicles, int32_t n_suspensions, int precision);
 
 VESNET_API int vesnet_farfield_stokeslet_batched(const double* targets, const double* sources, const double* force_density,
@@ -440,9 +458,12 @@ VESNET_API int vesnet_farfield_stokeslet_backward_points(const double* points, c
 /* Times every supported launch shape on the given (prepared inside) problem
    with HIP events and returns the fastest in *best and its time in *best_ms.
    batched != 0 tunes the batched call (then suspension_offsets, n_suspensions
-   and mu_device are used; otherwise mu_host).  Host-synchronous; the
-   workspace must hold the largest shape tried (shapes that do not fit are
-   skipped). */
+   and mu_device are used; otherwise mu_host).  The candidates are the direct
+   form's shapes (pair_form 1 where the symmetric form could also run) and, for
+   one compensated point array, the symmetric form at 1, 2, 4 (and, single
+   call, 8) targets per thread (batched: with 0, 2, 4 or 8 workgroups per
+   compute unit).  Host-synchronous; the workspace must hold the largest shape
+   tried (shapes that do not fit are skipped). */
 VESNET_API int vesnet_autotune(const double* targets, const double* sources, const double* force_density,
                     const double* arc_weights, const int32_t* vesicle_offsets, int32_t n_vesicles,
                     int32_t n_points, int batched, const int32_t* suspension_offsets, int32_t n_suspensions,

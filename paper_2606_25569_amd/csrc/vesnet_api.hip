@@ -652,6 +652,22 @@ namespace {
 
 size_t plan_bytes(int32_t S) { return align_up((size_t)(4 * (size_t)S + 2) * sizeof(int32_t)); }
 
+// The batched symmetric form's tables: per-suspension (cycles, blocks, exponent), first units and points.
+size_t symb_bytes(int32_t S) {
+  return align_up((size_t)S * sizeof(int4)) + 2 * align_up((size_t)(S + 1) * sizeof(int32_t));
+}
+
+SymBatchView carve_symb(char*& cur, int32_t S) {
+  SymBatchView bv;
+  bv.stab = reinterpret_cast<int4*>(cur);
+  cur += align_up((size_t)S * sizeof(int4));
+  bv.ustart = reinterpret_cast<int32_t*>(cur);
+  cur += align_up((size_t)(S + 1) * sizeof(int32_t));
+  bv.pstart = reinterpret_cast<int32_t*>(cur);
+  cur += align_up((size_t)(S + 1) * sizeof(int32_t));
+  return bv;
+}
+
 PlanView carve_plan(char*& cur, int32_t S) {
   PlanView pl;
   int32_t* p = reinterpret_cast<int32_t*>(cur);
@@ -685,14 +701,49 @@ int check_batched_args(const double* targets, const double* sources, const doubl
   return VESNET_OK;
 }
 
+// The batched call takes the symmetric form when the precision is compensated, targets and sources are
+// one array and the call does not ask for the direct form (or matrix-core accumulation).
+bool batched_symmetric(const double* targets, const double* sources, int prec, const Shape& s) {
+  return prec == P32C && targets == sources && s.accumulate == 1 && s.pair != 1;
+}
+
+// Targets per thread and workgroups of the batched symmetric form: the caller's targets_per_thread when
+// pair_form 2 asks for it (1, 2 or 4), else the single-suspension default for the total point count;
+// blocks_per_cu when the caller sets it, else as many units as one compute unit holds.
+int batched_symmetric_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int32_t S, const Shape& s,
+                            int* T, int* grid) {
+  int t = s.symT ? s.symT : 1;
+  if (t == 8) t = 4;
+  if (cfg && cfg->pair_form == 2 && cfg->targets_per_thread) t = cfg->targets_per_thread;
+  if (t != 1 && t != 2 && t != 4)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread of the batched symmetric form must be 1, 2 or 4");
+  while (t < 4 && symb_max_units(P, M, S, t) > (int64_t)INT32_MAX) t *= 2;
+  if (symb_max_units(P, M, S, t) > (int64_t)INT32_MAX)
+    return fail(VESNET_ERR_UNSUPPORTED, "too many points for the batched symmetric form; use pair_form 1");
+  const int bpc = cfg && cfg->blocks_per_cu ? cfg->blocks_per_cu : symb_units_per_cu(t);
+  *T = t;
+  *grid = num_cus() * bpc;
+  return VESNET_OK;
+}
+
 int enqueue_batched(const double* targets, const double* sources, const double* f, const double* w,
                     const int32_t* off, int32_t M, int32_t P, const int32_t* sus_off, int32_t S, const double* mu,
-                    double* out, int prec, const Shape& s, void* ws, void* stream) {
+                    double* out, int prec, const Shape& s, const vesnet_tile_config* cfg, void* ws, void* stream) {
   char* cur = aligned_base(ws);
-  PreparedView pv = carve_prepared(cur, P, M, prec);
+  PreparedView pv = carve_prepared(cur, P, M, prec, fwd_forces(prec));
   PlanView pl = carve_plan(cur, S);
   hipError_t e = launch_prepare(prec, sources, f, w, off, M, P, pv, stream);
   if (e != hipSuccess) return hip_fail(e, "prepare launch");
+  if (batched_symmetric(targets, sources, prec, s)) {
+    int T = 0, grid = 0;
+    int rc = batched_symmetric_shape(cfg, P, M, S, s, &T, &grid);
+    if (rc) return rc;
+    SymmetricView sv = carve_symmetric(cur, P, M);
+    SymBatchView bv = carve_symb(cur, S);
+    e = launch_batched_symmetric(T, grid, P, M, pv, sv, bv, sus_off, off, S, mu, out, stream);
+    if (e != hipSuccess) return hip_fail(e, "batched symmetric launch");
+    return VESNET_OK;
+  }
   e = launch_plan(sus_off, S, M, pv, s.T * s.B, pl, stream);
   if (e != hipSuccess) return hip_fail(e, "plan launch");
   const int grid = num_cus() * s.bpc;
@@ -705,7 +756,9 @@ int enqueue_batched(const double* targets, const double* sources, const double* 
 
 extern "C" size_t vesnet_batched_workspace_bytes(int32_t P, int32_t M, int32_t S, int prec) {
   if (check_sizes(P, M) || !valid_precision(prec) || S < 0) return 0;
-  return kAlign + prepared_bytes(P, M, prec) + plan_bytes(S);
+  size_t b = kAlign + prepared_bytes(P, M, prec, fwd_forces(prec)) + plan_bytes(S);
+  if (prec == P32C) b += symmetric_bytes(P, M) + symb_bytes(S);
+  return b;
 }
 
 extern "C" int vesnet_farfield_stokeslet_batched(const double* targets, const double* sources, const double* f,
@@ -719,7 +772,8 @@ extern "C" int vesnet_farfield_stokeslet_batched(const double* targets, const do
   Shape s;
   if ((rc = resolve_shape(cfg, P, M, prec, &s))) return rc;
   if ((rc = check_workspace(ws, ws_bytes, vesnet_batched_workspace_bytes(P, M, S, prec)))) return rc;
-  if ((rc = enqueue_batched(targets, sources, f, w, off, M, P, sus_off, S, mu, out, prec, s, ws, stream))) return rc;
+  if ((rc = enqueue_batched(targets, sources, f, w, off, M, P, sus_off, S, mu, out, prec, s, cfg, ws, stream)))
+    return rc;
   return ok();
 }
 
@@ -741,6 +795,11 @@ extern "C" int vesnet_graph_create_batched(const double* targets, const double* 
   Shape s;
   if ((rc = resolve_shape(cfg, P, M, prec, &s))) return rc;
   if ((rc = check_workspace(ws, ws_bytes, vesnet_batched_workspace_bytes(P, M, S, prec)))) return rc;
+  if (batched_symmetric(targets, sources, prec, s)) {
+    // resolve the symmetric shape (and its occupancy query) before the capture begins
+    int T = 0, grid = 0;
+    if ((rc = batched_symmetric_shape(cfg, P, M, S, s, &T, &grid))) return rc;
+  }
   hipStream_t st = nullptr;
   hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
@@ -749,7 +808,7 @@ extern "C" int vesnet_graph_create_batched(const double* targets, const double* 
     (void)hipStreamDestroy(st);
     return hip_fail(e, "hipStreamBeginCapture");
   }
-  rc = enqueue_batched(targets, sources, f, w, off, M, P, sus_off, S, mu, out, prec, s, ws, st);
+  rc = enqueue_batched(targets, sources, f, w, off, M, P, sus_off, S, mu, out, prec, s, cfg, ws, st);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(st, &g);
   if (rc) {
@@ -980,6 +1039,11 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
   if (repeats < 1) repeats = 1;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
 
+  // Direct-form shapes (pair_form 1 where the symmetric form could run, so that each candidate is the
+  // shape it names) and, for one compensated point array, the symmetric form's targets per thread
+  // (batched: also its workgroups per compute unit, 0 = as many as fit).
+  const bool sym_ok = prec == VESNET_FP32_COMPENSATED && targets == sources;
+  const int direct = sym_ok ? 1 : 0;
   std::vector<vesnet_tile_config> cands;
   for (int acc : {1, 2}) {
     if (acc == 2 && (batched || prec != VESNET_FP32_COMPENSATED)) continue;
@@ -987,16 +1051,29 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
       for (int T : {1, 2, 4})
         for (int B : {64, 128, 256}) {
           if (batched) {
-            for (int bpc : {1, 2, 4, 8}) cands.push_back({T, B, 1, bpc, stg, acc});
+            for (int bpc : {1, 2, 4, 8}) cands.push_back({T, B, 1, bpc, stg, acc, direct});
           } else {
             for (int sp : {1, 2, 4, 8, 16}) {
               if (sp > std::max(1, M)) continue;
-              const Shape sh{T, B, sp, 1, stg, acc};
+              const Shape sh{T, B, sp, 1, stg, acc, direct};
               if (forward_bytes(P, M, prec, sh) > ws_bytes) continue;
-              cands.push_back({T, B, sp, 1, stg, acc});
+              cands.push_back({T, B, sp, 1, stg, acc, direct});
             }
           }
         }
+  }
+  if (sym_ok) {
+    for (int T : {1, 2, 4, 8}) {
+      if (batched) {
+        if (T == 8) continue;
+        for (int bpc : {0, 2, 4, 8}) cands.push_back({T, 0, 0, bpc, 0, 1, 2});
+      } else {
+        if (!sym_fits(P, M, T)) continue;
+        const Shape sh{T, 256, 1, 1, 2, 1, 2, T};
+        if (forward_bytes(P, M, prec, sh) > ws_bytes) continue;
+        cands.push_back({T, 0, 0, 0, 0, 1, 2});
+      }
+    }
   }
   if (batched && (rc = check_workspace(ws, ws_bytes, vesnet_batched_workspace_bytes(P, M, S, prec)))) return rc;
   if (cands.empty()) return fail(VESNET_ERR_WORKSPACE, "workspace too small for any launch shape");

@@ -44,9 +44,18 @@ struct PreparedView {
 // Device views of the symmetric form's region (after the prepared region).
 struct SymmetricView {
   int4* cyc;                 // [P/16 + M + 1] cycles: (first point, count <= 16, vesicle, 0)
-  int32_t* meta;             // [0] number of cycles, [1] fixed-point exponent S, [2] number of blocks
+  int32_t* meta;             // [64] plan values: [0] number of cycles, [1] fixed-point exponent S, [2] number of
+                             // blocks (one suspension) or of units (batched; then [4..12] the XCD queues and
+                             // [16..23] their counters)
   double2* fcyc;             // [P/16 + M + 1] float64 net force w f of each cycle
   unsigned long long* acc;   // [2][P] fixed-point sums (two's complement int64 at 2^-S)
+};
+
+// Device views of the batched symmetric form's plan (after the symmetric region).
+struct SymBatchView {
+  int4* stab;       // [S]   per suspension: (first cycle, end cycle, blocks, fixed-point exponent)
+  int32_t* ustart;  // [S+1] first unit of each suspension
+  int32_t* pstart;  // [S+1] first point of each suspension
 };
 
 // Device views of the batched work plan.
@@ -71,6 +80,14 @@ int64_t sym_units(int64_t nb);
 bool sym_fits(int P, int M, int T);
 hipError_t launch_forward_symmetric(int T, int P, int M, const PreparedView& pv, const SymmetricView& sv,
                                     double scale, double* out, void* stream);
+// Batched symmetric form (float32-compensated, targets = sources, S independent suspensions): a bound
+// of its unit count, the workgroups of its persistent kernel one compute unit holds, and the launch
+// (plan, cycle forces, persistent kernel on `grid` workgroups, conversion with each suspension's mu).
+int64_t symb_max_units(int P, int M, int S, int T);
+int symb_units_per_cu(int T);
+hipError_t launch_batched_symmetric(int T, int grid, int P, int M, const PreparedView& pv, const SymmetricView& sv,
+                                    const SymBatchView& bv, const int32_t* sus_off, const int32_t* off, int S,
+                                    const double* mu, double* out, void* stream);
 // a[e] += b[e] for e < n (float64)
 hipError_t launch_add_f64(double* a, const double* b, int64_t n, void* stream);
 // Its adjoint for targets = sources: pvF prepared from (points, f, w), pvG from (points, dL/du, no

@@ -57,6 +57,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "vesnet_internal.h"
 
@@ -72,6 +73,7 @@ constexpr int kRows = kSymThreads / kRing;         // rows of 16 lanes per unit
 constexpr int kChunk = 8;                          // source cycles per LDS chunk
 static_assert(kChunk * 2 * kRing <= kSymThreads, "one thread per staged record and per column sum of a chunk");
 constexpr double kLn2d = 0.69314718055994530942;
+constexpr double kPi = 3.14159265358979323846;
 constexpr float kHalfLn2f = -0.34657359027997265471f;  // -(1/2) ln 2: log2|r|^2 -> -ln|r|
 constexpr float kFar = 1152921504606846976.0f;         // 2^60: position of an inactive target
 constexpr int kMaxShift = 60;                          // |k| bound of the power-of-two rescaling
@@ -177,14 +179,9 @@ __global__ __launch_bounds__(256) void k_sym_cycles(const int4* __restrict__ cyc
 // block by row block.  Workgroups are handed to the eight XCDs in turn (workgroup g to XCD g mod 8), so
 // each XCD is given one contiguous range of that numbering: its concurrent units share a row block and
 // a window of about nb/2 consecutive column blocks, which stays in the XCD's own L2.
-__device__ __forceinline__ bool sym_unit(int nb, int& bx, int& by) {
+// Unit number L (0 <= L < nb (nb + 1) / 2) of nb blocks, row block by row block, as the pair {bx, by}.
+__device__ __forceinline__ void sym_unit_blocks(int nb, int L, int& bx, int& by) {
   const int h = nb >> 1;
-  const int units = (nb & 1) ? nb * (h + 1) : nb * h + h;
-  const int g = blockIdx.x;
-  if (g >= units) return false;
-  const int q = units / kXcds, r = units % kXcds;
-  const int x = g % kXcds;
-  const int L = x * q + min(x, r) + g / kXcds;
   int d;
   if (L < h * (h + 1) || (nb & 1)) {
     bx = L / (h + 1);
@@ -196,15 +193,27 @@ __device__ __forceinline__ bool sym_unit(int nb, int& bx, int& by) {
   }
   by = bx + d;
   if (by >= nb) by -= nb;
+}
+
+__device__ __forceinline__ bool sym_unit(int nb, int& bx, int& by) {
+  const int h = nb >> 1;
+  const int units = (nb & 1) ? nb * (h + 1) : nb * h + h;
+  const int g = blockIdx.x;
+  if (g >= units) return false;
+  const int q = units / kXcds, r = units % kXcds;
+  const int x = g % kXcds;
+  sym_unit_blocks(nb, x * q + min(x, r) + g / kXcds, bx, by);
   return true;
 }
 
-// One unit {bx, by} per workgroup (see the file header).
+// One unit: target cycles [tc0, tc1) against source cycles [sc0, sc1) (diag: the two blocks are one),
+// fixed-point exponent S (see the file header).  Called by the whole workgroup.
 template <int T>
-__global__ __launch_bounds__(kSymThreads) void k_sym_main(
-    int P, const double4* __restrict__ vtab, const double2* __restrict__ vaux, const float4* __restrict__ rec,
-    const int4* __restrict__ cyc, const double2* __restrict__ fcyc, const int32_t* __restrict__ meta,
-    unsigned long long* __restrict__ acc) {
+__device__ __forceinline__ void sym_eval_unit(int P, const double4* __restrict__ vtab,
+                                              const double2* __restrict__ vaux, const float4* __restrict__ rec,
+                                              const int4* __restrict__ cyc, const double2* __restrict__ fcyc, int S,
+                                              int tc0, int tc1, int sc0, int sc1, bool diag,
+                                              unsigned long long* __restrict__ acc) {
   constexpr int CB = kRows * T;  // cycles per block
   __shared__ float4 s_tx[CB][kRing];               // target records (local coordinates, w f)
   __shared__ double4 s_tc[CB];                     // (c_A, F_cycle) of each target cycle
@@ -214,18 +223,8 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_main(
   __shared__ float s_col[2][kSymWaves][kChunk][2][kRing];
   __shared__ double2 s_E[2][kSymWaves][kChunk];
 
-  const int ncyc = meta[0];
-  const int S = meta[1];
-  const int nb = meta[2];
-  if (nb <= 0) return;
-  int bx, by;
-  if (!sym_unit(nb, bx, by)) return;
-  const bool diag = bx == by;
-
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, p = lane & 15;
   const int row = tid >> 4;
-  const int tc0 = bx * CB, tc1 = min(ncyc, tc0 + CB);
-  const int sc0 = by * CB, sc1 = min(ncyc, sc0 + CB);
 
   // Target block into LDS.
   for (int e = tid; e < CB * kRing; e += kSymThreads) {
@@ -444,6 +443,217 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_main(
       atomicAdd(&acc[i], (unsigned long long)(long long)rint(ldexp(ax[k], S)));
       atomicAdd(&acc[(size_t)P + i], (unsigned long long)(long long)rint(ldexp(ay[k], S)));
     }
+  }
+}
+
+// One unit {bx, by} per workgroup (see the file header).
+template <int T>
+__global__ __launch_bounds__(kSymThreads) void k_sym_main(
+    int P, const double4* __restrict__ vtab, const double2* __restrict__ vaux, const float4* __restrict__ rec,
+    const int4* __restrict__ cyc, const double2* __restrict__ fcyc, const int32_t* __restrict__ meta,
+    unsigned long long* __restrict__ acc) {
+  constexpr int CB = kRows * T;
+  const int ncyc = meta[0];
+  const int S = meta[1];
+  const int nb = meta[2];
+  if (nb <= 0) return;
+  int bx, by;
+  if (!sym_unit(nb, bx, by)) return;
+  const int tc0 = bx * CB, sc0 = by * CB;
+  sym_eval_unit<T>(P, vtab, vaux, rec, cyc, fcyc, S, tc0, min(ncyc, tc0 + CB), sc0, min(ncyc, sc0 + CB), bx == by,
+                   acc);
+}
+
+// ------------------------------------------------------------------ batched symmetric form
+// Many independent suspensions in one persistent launch.  Each suspension's cycles are contiguous (its
+// vesicles in order), its blocks of CB cycles never reach into another suspension, and its units are the
+// circulant pairs of its own blocks, so no pair across suspensions is formed.  The units of all
+// suspensions are numbered suspension by suspension (row block by row block inside each), and that
+// numbering is cut into eight contiguous ranges, one queue per XCD: a workgroup takes units from its own
+// XCD's queue by an atomic counter and, once that queue is empty, from the next XCDs' in turn.
+// Every unit does the same work (up to the last block of a suspension), so the order needs no sorting.
+
+// Slots of the plan values in the symmetric region's meta array.
+constexpr int kMetaUnits = 2;    // total number of units
+constexpr int kMetaQueue = 4;    // [kXcds + 1] first unit of each XCD's queue
+constexpr int kMetaCount = 16;   // [kXcds] next position in each queue
+static_assert(kMetaCount + kXcds <= 64, "plan values fit the 256-byte meta slot");
+
+__device__ __forceinline__ int wave_scan_incl(int x, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// Plan: per suspension s, stab[s] = (first cycle, end cycle, blocks, fixed-point exponent), ustart[s] its
+// first unit, pstart[s] its first point (ustart[S], pstart[S]: totals); the cycle table; meta[0] the
+// number of cycles, the XCD queues and their zeroed counters.  One workgroup of 1024 threads, in a fixed
+// order; the exponent of a suspension is the one the single-suspension plan gives it.
+__global__ __launch_bounds__(1024) void k_symb_plan(const int2* __restrict__ vrange, const double2* __restrict__ vaux,
+                                                    const int32_t* __restrict__ sus_off,
+                                                    const int32_t* __restrict__ off, int nsus, int cb, int ncyc_max,
+                                                    int4* __restrict__ cyc, int4* __restrict__ stab,
+                                                    int32_t* __restrict__ ustart, int32_t* __restrict__ pstart,
+                                                    int32_t* __restrict__ meta) {
+  __shared__ int s_wc[16], s_wu[16];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  // cycles and the bound of the partial sums of each suspension, one wavefront per suspension
+  for (int s = wv; s < nsus; s += 16) {
+    const int v0 = sus_off[s], v1 = sus_off[s + 1];
+    int cnt = 0;
+    double fs = 0.0;
+    for (int v = v0 + lane; v < v1; v += 64) {
+      const int2 r = vrange[v];
+      cnt += (max(0, r.y - r.x) + kRing - 1) / kRing;
+      fs += vaux[v].x;
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
+    fs = wave_sum_d(fs);
+    if (lane == 0) {
+      const double bound = 520.0 * fs;  // as in k_sym_plan
+      int S = 0;
+      if (bound > 0.0 && isfinite(bound)) {
+        int e;
+        frexp(bound, &e);
+        S = 62 - e;
+      }
+      stab[s] = make_int4(cnt, 0, (cnt + cb - 1) / cb, S);
+    }
+  }
+  __syncthreads();
+  // exclusive scans over the suspensions: first cycle and first unit
+  int runc = 0, runu = 0;
+  for (int base = 0; base < nsus; base += 1024) {
+    const int s = base + t;
+    const int4 st = s < nsus ? stab[s] : make_int4(0, 0, 0, 0);
+    const int nu = (int)((int64_t)st.z * (st.z + 1) / 2);
+    const int xc = wave_scan_incl(st.x, lane), xu = wave_scan_incl(nu, lane);
+    if (lane == 63) {
+      s_wc[wv] = xc;
+      s_wu[wv] = xu;
+    }
+    __syncthreads();
+    int prec_ = 0, preu = 0, totc = 0, totu = 0;
+    for (int k = 0; k < 16; ++k) {
+      prec_ += k < wv ? s_wc[k] : 0;
+      preu += k < wv ? s_wu[k] : 0;
+      totc += s_wc[k];
+      totu += s_wu[k];
+    }
+    if (s < nsus) {
+      const int c0 = runc + prec_ + xc - st.x;
+      stab[s] = make_int4(c0, c0 + st.x, st.z, st.w);
+      ustart[s] = runu + preu + xu - nu;
+      pstart[s] = off[sus_off[s]];
+    }
+    runc += totc;
+    runu += totu;
+    __syncthreads();
+  }
+  if (t == 0) {
+    ustart[nsus] = runu;
+    pstart[nsus] = off[sus_off[nsus]];
+    meta[0] = min(runc, ncyc_max);
+    meta[kMetaUnits] = runu;
+    const int q = runu / kXcds, r = runu % kXcds;
+    for (int x = 0; x <= kXcds; ++x) meta[kMetaQueue + x] = x * q + min(x, r);
+  }
+  if (t < kXcds) meta[kMetaCount + t] = 0;
+  __syncthreads();
+  // the cycles of every vesicle, one wavefront per suspension
+  for (int s = wv; s < nsus; s += 16) {
+    const int v0 = sus_off[s], v1 = sus_off[s + 1];
+    int c = stab[s].x;
+    for (int vb = v0; vb < v1; vb += 64) {
+      const int v = vb + lane;
+      const int2 r = v < v1 ? vrange[v] : make_int2(0, 0);
+      const int n = max(0, r.y - r.x);
+      const int cnt = (n + kRing - 1) / kRing;
+      const int x = wave_scan_incl(cnt, lane);
+      const int first = c + x - cnt;
+      for (int k = 0; k < cnt; ++k)
+        if (first + k < ncyc_max) cyc[first + k] = make_int4(r.x + kRing * k, min(kRing, n - kRing * k), v, 0);
+      c += __shfl(x, 63, 64);
+    }
+  }
+}
+
+// Persistent batched kernel: units from the XCD queues until all are empty (see above).
+template <int T>
+__global__ __launch_bounds__(kSymThreads) void k_symb_main(
+    int P, const double4* __restrict__ vtab, const double2* __restrict__ vaux, const float4* __restrict__ rec,
+    const int4* __restrict__ cyc, const double2* __restrict__ fcyc, const int4* __restrict__ stab,
+    const int32_t* __restrict__ ustart, int nsus, int32_t* __restrict__ meta, unsigned long long* __restrict__ acc) {
+  constexpr int CB = kRows * T;
+  __shared__ int s_job[2];
+  const int xcd = blockIdx.x % kXcds;
+  int probe = 0;                    // thread 0: queues found empty so far
+  int slo = 0, shi = 0, scur = 0;   // thread 0: unit range of the last suspension found
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int u = -1;
+      while (probe < kXcds) {
+        const int q = xcd + probe < kXcds ? xcd + probe : xcd + probe - kXcds;
+        const int lo = meta[kMetaQueue + q], n = meta[kMetaQueue + q + 1] - lo;
+        const int k = atomicAdd(&meta[kMetaCount + q], 1);
+        if (k < n) {
+          u = lo + k;
+          break;
+        }
+        ++probe;
+      }
+      if (u >= 0 && (u < slo || u >= shi)) {
+        int lo = 0, hi = nsus;  // ustart[lo] <= u < ustart[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (ustart[mid] <= u)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        scur = lo;
+        slo = ustart[lo];
+        shi = ustart[lo + 1];
+      }
+      s_job[0] = u;
+      s_job[1] = scur;
+    }
+    __syncthreads();
+    const int u = s_job[0], sus = s_job[1];
+    __syncthreads();
+    if (u < 0) return;
+    const int4 st = stab[sus];
+    int bx, by;
+    sym_unit_blocks(st.z, u - ustart[sus], bx, by);
+    const int tc0 = st.x + bx * CB, sc0 = st.x + by * CB;
+    sym_eval_unit<T>(P, vtab, vaux, rec, cyc, fcyc, st.w, tc0, min(st.y, tc0 + CB), sc0, min(st.y, sc0 + CB),
+                     bx == by, acc);
+    __syncthreads();
+  }
+}
+
+// out = acc 2^-S_s / (4 pi mu_s) for the points of suspension s.
+__global__ __launch_bounds__(256) void k_symb_finish(const unsigned long long* __restrict__ acc,
+                                                     const int4* __restrict__ stab, const int32_t* __restrict__ pstart,
+                                                     const double* __restrict__ mu, int nsus, int P,
+                                                     double* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 2 * (int64_t)P;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e < P ? e : e - P);
+    int lo = 0, hi = nsus;  // pstart[lo] <= j < pstart[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pstart[mid] <= j)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const double scale = 1.0 / (4.0 * kPi * mu[lo]);
+    out[e] = ldexp((double)(long long)acc[e] * scale, -stab[lo].w);
   }
 }
 
@@ -857,6 +1067,57 @@ hipError_t launch_add_f64(double* a, const double* b, int64_t n, void* stream) {
   if (n <= 0) return hipSuccess;
   const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_add_f64, dim3(grid), dim3(256), 0, Sx_(stream), a, b, n);
+  return hipGetLastError();
+}
+
+int64_t symb_max_units(int P, int M, int S, int T) {
+  // the blocks of all suspensions number at most (cycles / CB) + S, and n (n + 1) / 2 is superadditive
+  return sym_units(sym_max_blocks(P, M, T) + S);
+}
+
+// Cached after the first query (every device this library runs on is a gfx950).
+int symb_units_per_cu(int T) {
+  static std::atomic<int> cache[5] = {};
+  if (T != 1 && T != 2 && T != 4) return 1;
+  int n = cache[T].load(std::memory_order_relaxed);
+  if (n > 0) return n;
+  hipError_t e = hipErrorInvalidValue;
+  switch (T) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_symb_main<1>, kSymThreads, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_symb_main<2>, kSymThreads, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_symb_main<4>, kSymThreads, 0); break;
+  }
+  if (e != hipSuccess || n <= 0) return 1;
+  cache[T].store(n, std::memory_order_relaxed);
+  return n;
+}
+
+hipError_t launch_batched_symmetric(int T, int grid, int P, int M, const PreparedView& pv, const SymmetricView& sv,
+                                    const SymBatchView& bv, const int32_t* sus_off, const int32_t* off, int S,
+                                    const double* mu, double* out, void* stream) {
+  if (P == 0 || S == 0) return hipSuccess;
+  if (grid < 1) return hipErrorInvalidValue;
+  hipStream_t st = Sx_(stream);
+  const int cb = sym_cycles_per_block(T);
+  const int ncyc_max = (int)sym_max_cycles(P, M);
+  hipLaunchKernelGGL(k_symb_plan, dim3(1), dim3(1024), 0, st, pv.vrange, pv.vaux, sus_off, off, S, cb, ncyc_max,
+                     sv.cyc, bv.stab, bv.ustart, bv.pstart, sv.meta);
+  const int cgrid = (int)std::min<int64_t>((2 * (int64_t)P + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_sym_cycles, dim3(cgrid), dim3(256), 0, st, sv.cyc, sv.meta, pv.f64, P, sv.fcyc, sv.acc);
+  const float4* rec = static_cast<const float4*>(pv.rec);
+  switch (T) {
+#define VESNET_SYMB_MAIN(TT)                                                                                     \
+  case TT:                                                                                                       \
+    hipLaunchKernelGGL(k_symb_main<TT>, dim3(grid), dim3(kSymThreads), 0, st, P, pv.vtab, pv.vaux, rec, sv.cyc, \
+                       sv.fcyc, bv.stab, bv.ustart, S, sv.meta, sv.acc);                                          \
+    break;
+    VESNET_SYMB_MAIN(1) VESNET_SYMB_MAIN(2) VESNET_SYMB_MAIN(4)
+#undef VESNET_SYMB_MAIN
+    default: return hipErrorInvalidValue;
+  }
+  const int64_t n = 2 * (int64_t)P;
+  const int fgrid = (int)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
+  hipLaunchKernelGGL(k_symb_finish, dim3(fgrid), dim3(256), 0, st, sv.acc, bv.stab, bv.pstart, mu, S, P, out);
   return hipGetLastError();
 }
 
