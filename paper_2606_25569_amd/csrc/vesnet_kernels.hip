@@ -193,6 +193,12 @@ __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int 
   using Rec = typename Real<PREC>::R;
   __shared__ Rec tile[LDS ? kTile : 1];
   int tile_lo = 0, tile_hi = 0;
+  // float64: the logarithm's table (one entry per lane of the first wavefront)
+  __shared__ double2 ltab[PREC == P64 ? kLogTab : 1];
+  if constexpr (PREC == P64) {
+    if (threadIdx.x < kLogTab) ltab[threadIdx.x] = log_tab_entry(threadIdx.x);
+    __syncthreads();
+  }
 
   for (int v = v_begin; v < v_end; ++v) {
     if constexpr (!LDS) {
@@ -269,12 +275,12 @@ __device__ __forceinline__ void gather(int i_begin, int i_end, int v_begin, int 
         const real q = ry * ry + rx * rx;
         if constexpr (NEAR) qmin[k] = q < qmin[k] ? q : qmin[k];
         real rho;
-        if constexpr (PREC == P64) rho = 1.0 / q;
+        if constexpr (PREC == P64) rho = recip(q);
         else rho = __builtin_amdgcn_rcpf(q);
         const real beta = ry * s.w + rx * s.z;  // r . b
         if constexpr (NEED_V) {
           real L;
-          if constexpr (PREC == P64) L = log(q);
+          if constexpr (PREC == P64) L = log_reduced(q, ltab);
           else L = __builtin_amdgcn_logf(q);
           const real t = beta * rho;
           if constexpr (MF) {

@@ -61,76 +61,6 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 t, double2 c) {
   return make_double2(fma(a.x, t.x, fma(-a.y, t.y, c.x)), fma(a.x, t.y, fma(a.y, t.x, c.y)));
 }
 
-// 1 / x for finite x != 0: the hardware estimate refined by two Newton steps (each doubles the correct
-// bits; the result is within an ulp or so of the correctly rounded quotient).
-__device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
-}
-
-// Natural log of a finite q > 0, in about 20 FP64 operations: q = m 2^e with m in [1/sqrt 2, sqrt 2),
-// ln m = 2 atanh(s) = 2 sum_k s^(2k+1) / (2k+1), s = (m - 1) / (m + 1), |s| <= 0.1716; the terms
-// after s^21 are below 3e-17 of ln m.  ln 2 is split into a 32-bit high part (exact products with e)
-// and a low part.  Against 40-digit references the series with an exact quotient stays within 2 ulp;
-// the refined reciprocal adds at most about one more.
-__device__ __forceinline__ double log_pos(double q) {
-  constexpr double kLn2Hi = 6.93147180369123816490e-01;
-  constexpr double kLn2Lo = 1.90821492927058770002e-10;
-  int e;
-  double m = frexp(q, &e);
-  if (m < 0.70710678118654752440) {
-    m *= 2.0;
-    --e;
-  }
-  const double s = (m - 1.0) * recip(m + 1.0);
-  const double s2 = s * s;
-  double pol = 1.0 / 21.0;
-  pol = fma(pol, s2, 1.0 / 19.0);
-  pol = fma(pol, s2, 1.0 / 17.0);
-  pol = fma(pol, s2, 1.0 / 15.0);
-  pol = fma(pol, s2, 1.0 / 13.0);
-  pol = fma(pol, s2, 1.0 / 11.0);
-  pol = fma(pol, s2, 1.0 / 9.0);
-  pol = fma(pol, s2, 1.0 / 7.0);
-  pol = fma(pol, s2, 1.0 / 5.0);
-  pol = fma(pol, s2, 1.0 / 3.0);
-  pol = fma(pol, s2, 1.0);
-  return fma((double)e, kLn2Hi, fma((double)e, kLn2Lo, 2.0 * s * pol));
-}
-
-// Table of the reduced log below: entry i (mantissa interval [1 + i/64, 1 + (i+1)/64)) holds a 10-bit
-// approximation a of 1 / (1 + (i + 0.5) / 64) and -ln a (from log_pos).  One entry per lane.
-constexpr int kLogTab = 64;
-__device__ __forceinline__ double2 log_tab_entry(int i) {
-  const double c = 1.0 + ((double)i + 0.5) / 64.0;
-  const double a = rint(512.0 / c) / 512.0;
-  return make_double2(a, -log_pos(a));
-}
-
-// Natural log of a finite q > 0 with the table: q = m 2^e, m in [1, 2); r = m a - 1 (exact product, one
-// rounding), |r| < 0.009, ln m = -ln a + log1p(r), log1p by its series through r^7 (the next term is
-// below 5e-18); ln 2 in a high and a low part as in log_pos.  About 20 operations, no division.
-__device__ __forceinline__ double log_reduced(double q, const double2* __restrict__ tab) {
-  constexpr double kLn2Hi = 6.93147180369123816490e-01;
-  constexpr double kLn2Lo = 1.90821492927058770002e-10;
-  int e;
-  const double mant = frexp(q, &e);  // [0.5, 1): the top six mantissa bits are bits 19..14 of the high word
-  const double m = 2.0 * mant;
-  const int i = (__double2hiint(mant) >> 14) & (kLogTab - 1);  // in range for every input
-  const double2 t = tab[i];
-  const double r = fma(m, t.x, -1.0);
-  double pol = 1.0 / 7.0;
-  pol = fma(pol, r, -1.0 / 6.0);
-  pol = fma(pol, r, 1.0 / 5.0);
-  pol = fma(pol, r, -1.0 / 4.0);
-  pol = fma(pol, r, 1.0 / 3.0);
-  pol = fma(pol, r, -0.5);
-  pol = fma(pol, r, 1.0);
-  const double ed = (double)(e - 1);
-  return fma(ed, kLn2Hi, fma(ed, kLn2Lo, fma(r, pol, t.y)));
-}
-
 // Box centre at a level with n boxes per side (contraction off: the same bits as the plain formula).
 __device__ __forceinline__ double2 box_center(const Geom& g, int n, int bx, int by) {
 #pragma clang fp contract(off)
