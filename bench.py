@@ -210,24 +210,30 @@ def main():
     log(f"[bench] fp32c: {ms_step:.3f} ms/step, pair kernel {eval_ms.mean():.3f} ms (min {eval_ms.min():.3f}), "
         f"prepare {prep_ms.mean() * 1e3:.1f} us -> {value:.4e} pairs/s")
 
-    # FP64 GPU kernel on the same inputs
+    # FP64 GPU kernels on the same inputs: the plain direct gather (the baseline), then the symmetric form
     prec64 = V.FP64
-    cfg64 = V.default_config(P, M, "fp64")
-    ws64 = torch.empty(lib.vesnet_farfield_workspace_bytes(P, M, prec64, ctypes.byref(cfg64)), dtype=torch.uint8,
-                       device=dev)
-    prepare(prec64, ctypes.byref(cfg64), ws64)
-    evaluate(prec64, ctypes.byref(cfg64), ws64)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.fp64_steps):
+
+    def time64(pair_form):
+        cfg64 = V.default_config(P, M, "fp64")
+        cfg64.pair_form = pair_form
+        ws64 = torch.empty(lib.vesnet_farfield_workspace_bytes(P, M, prec64, ctypes.byref(cfg64)), dtype=torch.uint8,
+                           device=dev)
         prepare(prec64, ctypes.byref(cfg64), ws64)
         evaluate(prec64, ctypes.byref(cfg64), ws64)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms64 = e0.elapsed_time(e1) / args.fp64_steps
-    u64 = out.cpu().numpy()
-    log(f"[bench] fp64: {ms64:.3f} ms/step -> {pairs / (ms64 * 1e-3):.4e} pairs/s")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.fp64_steps):
+            prepare(prec64, ctypes.byref(cfg64), ws64)
+            evaluate(prec64, ctypes.byref(cfg64), ws64)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.fp64_steps, out.cpu().numpy()
+
+    ms64, u64 = time64(1)
+    log(f"[bench] fp64 (direct): {ms64:.3f} ms/step -> {pairs / (ms64 * 1e-3):.4e} pairs/s")
+    ms64s, u64s = time64(2)
+    log(f"[bench] fp64 (symmetric): {ms64s:.3f} ms/step -> {pairs / (ms64s * 1e-3):.4e} pairs/s")
 
     # accuracy on a seeded target sample, and the CPU baseline on the same sample
     sel = S.sample_targets(P, args.cpu_sample, 101)
@@ -241,7 +247,7 @@ def main():
         tcpu = time.perf_counter() - tc
         sample_pairs = int(sum(P - (s.offsets[v + 1] - s.offsets[v]) for v in O.vesicle_ids(s.offsets)[sel]))
         scale = np.abs(ref).max()
-        for name, u in (("fp32c", u32), ("fp64", u64)):
+        for name, u in (("fp32c", u32), ("fp64", u64), ("fp64_symmetric", u64s)):
             d = u[:, sel] - ref
             errs[name] = {"max_rel": float(np.abs(d).max() / scale),
                           "rms_rel": float(np.sqrt(np.mean(d * d)) / np.sqrt(np.mean(ref * ref)))}
@@ -304,10 +310,16 @@ def main():
                      "mix_ceiling_frac": mix["frac"] if mix else None, "mix_ceiling": mix,
                      "sclk_ghz": prof.get("sclk_ghz")},
         "cpu_baseline": cpu,
-        "fp64": {"pairs_per_s": pairs / (ms64 * 1e-3), "ms_per_step": ms64,
+        "fp64": {"kernel": "k_forward<FP64> (plain direct gather, the baseline)",
+                 "pairs_per_s": pairs / (ms64 * 1e-3), "ms_per_step": ms64,
                  "tflops": FLOPS_PER_PAIR * pairs / (ms64 * 1e-3) / 1e12,
                  "frac_fp64_peak": FLOPS_PER_PAIR * pairs / (ms64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
                  "speedup_fp32c_over_fp64": ms64 / ms_step},
+        "fp64_symmetric": {"kernel": "k_sym64_main (each unordered pair once, two-word fixed-point sums)",
+                           "pairs_per_s": pairs / (ms64s * 1e-3), "ms_per_step": ms64s,
+                           "tflops": FLOPS_PER_PAIR * pairs / (ms64s * 1e-3) / 1e12,
+                           "frac_fp64_peak": FLOPS_PER_PAIR * pairs / (ms64s * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                           "speedup_fp32c_over_fp64_symmetric": ms64s / ms_step},
         "max_rel_err": errs or None,
         "prepare_us": float(prep_ms.mean() * 1e3),
     }

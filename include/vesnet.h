@@ -90,21 +90,22 @@ typedef struct {
                                     and does not overlap the VALU work; kept for comparison)      */
   int32_t pair_form;          /* 0: automatic - vesnet_farfield_stokeslet takes the symmetric form
                                     when targets == sources (the same pointer), the precision is
-                                    VESNET_FP32_COMPENSATED, accumulate is 1 and the problem is
-                                    large enough (at least four units per compute unit); every
-                                    other call takes the direct form;
+                                    VESNET_FP32_COMPENSATED or VESNET_FP64, accumulate is 1 and the
+                                    problem is large enough (at least four units per compute
+                                    unit); every other call takes the direct form;
                                  1: direct form - one gather per target over all source vesicles;
-                                 2: symmetric form (compensated only) - each unordered pair of
-                                    points of different vesicles is evaluated once and serves both
-                                    (the Stokeslet is even), halving the logarithms and reciprocals;
-                                    the targets must be the points the workspace was prepared with
-                                    (vesnet_farfield_stokeslet requires targets == sources).
-                                    targets_per_thread (1, 2, 4 or 8; 0 = the default 2) sets its
-                                    blocks of 256 T points (one 256-thread workgroup per pair of
-                                    blocks); block_threads, source_splits and source_staging are
-                                    unused.  The automatic choice always uses the default.
-                                    Its partial sums are added as 64-bit fixed-point integers, so
-                                    the result is bitwise reproducible.                            */
+                                 2: symmetric form (compensated and float64) - each unordered pair
+                                    of points of different vesicles is evaluated once and serves
+                                    both (the Stokeslet is even), halving the logarithms and
+                                    reciprocals; the targets must be the points the workspace was
+                                    prepared with (vesnet_farfield_stokeslet requires targets ==
+                                    sources).  targets_per_thread (compensated 1, 2, 4 or 8, float64
+                                    1 or 2; 0 = the default 2) sets its blocks of 256 T points (one
+                                    256-thread workgroup per pair of blocks); block_threads,
+                                    source_splits and source_staging are unused.  The automatic
+                                    choice always uses the default.  Its partial sums are added as
+                                    64-bit fixed-point integers (float64: a high and a low word,
+                                    40 bits finer), so the result is bitwise reproducible.         */
 } vesnet_tile_config;
 
 /* Library version string and the thread-local description of the last error. */

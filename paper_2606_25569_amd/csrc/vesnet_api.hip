@@ -47,7 +47,12 @@ size_t rec_bytes(int prec) { return prec == P64 ? sizeof(double4) : sizeof(float
 
 // The forward calls' prepared region of the compensated form also holds the float64 weighted
 // forces and the per-vesicle |F|_1 sums that the symmetric form needs.
-bool fwd_forces(int prec) { return prec == P32C; }
+bool fwd_forces(int prec) { return prec == P32C || prec == P64; }
+
+// The precisions with a symmetric form (one evaluation per unordered pair), and the 64-bit accumulator
+// words it needs per point and component (float64: a high and a low fixed-point word).
+bool has_symmetric(int prec) { return prec == P32C || prec == P64; }
+int acc_words(int prec) { return prec == P64 ? 2 : 1; }
 
 size_t prepared_bytes(int32_t P, int32_t M, int prec, bool forces = false) {
   size_t b = align_up((size_t)M * sizeof(int2)) + align_up((size_t)P * sizeof(int32_t)) +
@@ -80,13 +85,13 @@ PreparedView carve_prepared(char*& cursor, int32_t P, int32_t M, int prec, bool 
 }
 
 // The symmetric form's region: cycle table, plan values, cycle net forces, fixed-point sums.
-size_t symmetric_bytes(int32_t P, int32_t M) {
+size_t symmetric_bytes(int32_t P, int32_t M, int words = 1) {
   return align_up((size_t)sym_max_cycles(P, M) * sizeof(int4)) + align_up(4 * sizeof(int32_t)) +
          align_up((size_t)sym_max_cycles(P, M) * sizeof(double2)) +
-         align_up((size_t)2 * P * sizeof(unsigned long long));
+         align_up((size_t)2 * words * P * sizeof(unsigned long long));
 }
 
-SymmetricView carve_symmetric(char*& cursor, int32_t P, int32_t M) {
+SymmetricView carve_symmetric(char*& cursor, int32_t P, int32_t M, int words = 1) {
   SymmetricView sv;
   sv.cyc = reinterpret_cast<int4*>(cursor);
   cursor += align_up((size_t)sym_max_cycles(P, M) * sizeof(int4));
@@ -95,7 +100,7 @@ SymmetricView carve_symmetric(char*& cursor, int32_t P, int32_t M) {
   sv.fcyc = reinterpret_cast<double2*>(cursor);
   cursor += align_up((size_t)sym_max_cycles(P, M) * sizeof(double2));
   sv.acc = reinterpret_cast<unsigned long long*>(cursor);
-  cursor += align_up((size_t)2 * P * sizeof(unsigned long long));
+  cursor += align_up((size_t)2 * words * P * sizeof(unsigned long long));
   return sv;
 }
 
@@ -142,7 +147,7 @@ Shape default_shape(int32_t P, int32_t M, int prec) {
   while (waves * splits < want && splits < 16) splits *= 2;
   s.splits = std::max(1, std::min<int>(splits, std::max(1, M)));
   s.pair = 0;
-  s.symT = prec == P32C ? sym_default_T(P) : 0;
+  s.symT = has_symmetric(prec) ? sym_default_T(P) : 0;
   return s;
 }
 
@@ -179,8 +184,10 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     return fail(VESNET_ERR_UNSUPPORTED, "matrix-core accumulation exists for the compensated form only");
   if (s.pair < 0 || s.pair > 2)
     return fail(VESNET_ERR_INVALID_ARGUMENT, "pair_form must be 0, 1 or 2 (got %d)", s.pair);
-  if (s.pair == 2 && prec != VESNET_FP32_COMPENSATED)
-    return fail(VESNET_ERR_UNSUPPORTED, "the symmetric pair form exists for the compensated form only");
+  if (s.pair == 2 && !has_symmetric(prec))
+    return fail(VESNET_ERR_UNSUPPORTED, "the symmetric pair form exists for the compensated and float64 forms only");
+  if (s.pair == 2 && prec == P64 && s.symT > 2)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread of the float64 symmetric form must be 1 or 2");
   if (s.pair == 2 && s.accumulate == 2)
     return fail(VESNET_ERR_UNSUPPORTED, "the symmetric pair form accumulates on the VALU only");
   if (s.pair == 2 && s.symT == 0) s.symT = 1;
@@ -188,7 +195,7 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     if (s.pair == 2)
       return fail(VESNET_ERR_UNSUPPORTED, "too many points for the symmetric form at %d targets per thread (its "
                   "units exceed one launch); use more targets per thread or the direct form", s.symT);
-    s.symT = sym_fits(P, M, 4) ? 4 : sym_fits(P, M, 8) ? 8 : 0;
+    s.symT = prec == P64 ? 0 : sym_fits(P, M, 4) ? 4 : sym_fits(P, M, 8) ? 8 : 0;
   }
   *out = s;
   return VESNET_OK;
@@ -199,7 +206,7 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
 size_t forward_bytes(int32_t P, int32_t M, int prec, const Shape& s) {
   size_t b = kAlign + prepared_bytes(P, M, prec, fwd_forces(prec));
   if (s.pair != 2 && s.splits > 1) b += align_up((size_t)2 * s.splits * P * sizeof(double));
-  if (prec == P32C && s.pair != 1) b += symmetric_bytes(P, M);
+  if (has_symmetric(prec) && s.pair != 1) b += symmetric_bytes(P, M, acc_words(prec));
   return b;
 }
 
@@ -323,8 +330,9 @@ int evaluate_resolved(const double* targets, int32_t M, int32_t P, double mu, do
   hipError_t e;
   if (symmetric) {
     if (s.pair != 2 && s.splits > 1) cur += align_up((size_t)2 * s.splits * P * sizeof(double));
-    SymmetricView sv = carve_symmetric(cur, P, M);
-    e = launch_forward_symmetric(s.symT, P, M, pv, sv, scale, out, stream);
+    SymmetricView sv = carve_symmetric(cur, P, M, acc_words(prec));
+    e = prec == P64 ? launch_forward_symmetric64(s.symT, P, M, pv, sv, scale, out, stream)
+                    : launch_forward_symmetric(s.symT, P, M, pv, sv, scale, out, stream);
     if (e != hipSuccess) return hip_fail(e, "symmetric forward launch");
   } else {
     double* partial = s.splits > 1 ? reinterpret_cast<double*>(cur) : nullptr;
@@ -364,7 +372,7 @@ extern "C" int vesnet_farfield_stokeslet(const double* targets, const double* so
   if (s.pair == 2 && targets != sources)
     return fail(VESNET_ERR_INVALID_ARGUMENT, "the symmetric pair form needs targets == sources (one point array)");
   const bool symmetric =
-      s.pair == 2 || (s.pair == 0 && targets == sources && prec == P32C && s.accumulate == 1 && s.symT > 0);
+      s.pair == 2 || (s.pair == 0 && targets == sources && has_symmetric(prec) && s.accumulate == 1 && s.symT > 0);
   if ((rc = check_workspace(ws, ws_bytes, forward_bytes(P, M, prec, s)))) return rc;
   if ((rc = vesnet_farfield_prepare(sources, f, w, off, M, P, prec, ws, ws_bytes, stream))) return rc;
   return evaluate_resolved(targets, M, P, mu, out, prec, s, symmetric, ws, ws_bytes, stream);
@@ -1042,7 +1050,7 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
   // Direct-form shapes (pair_form 1 where the symmetric form could run, so that each candidate is the
   // shape it names) and, for one compensated point array, the symmetric form's targets per thread
   // (batched: also its workgroups per compute unit, 0 = as many as fit).
-  const bool sym_ok = prec == VESNET_FP32_COMPENSATED && targets == sources;
+  const bool sym_ok = (prec == VESNET_FP32_COMPENSATED || (prec == VESNET_FP64 && !batched)) && targets == sources;
   const int direct = sym_ok ? 1 : 0;
   std::vector<vesnet_tile_config> cands;
   for (int acc : {1, 2}) {
@@ -1068,6 +1076,7 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
         if (T == 8) continue;
         for (int bpc : {0, 2, 4, 8}) cands.push_back({T, 0, 0, bpc, 0, 1, 2});
       } else {
+        if (prec == VESNET_FP64 && T > 2) continue;
         if (!sym_fits(P, M, T)) continue;
         const Shape sh{T, 256, 1, 1, 2, 1, 2, T};
         if (forward_bytes(P, M, prec, sh) > ws_bytes) continue;
@@ -1174,7 +1183,7 @@ extern "C" int vesnet_farfield_stokeslet_noalloc(const double* targets, const do
   if (s.pair == 2 && targets != sources)
     return fail(VESNET_ERR_INVALID_ARGUMENT, "the symmetric pair form needs targets == sources (one point array)");
   const bool symmetric =
-      s.pair == 2 || (s.pair == 0 && targets == sources && prec == P32C && s.accumulate == 1 && s.symT > 0);
+      s.pair == 2 || (s.pair == 0 && targets == sources && has_symmetric(prec) && s.accumulate == 1 && s.symT > 0);
   // the workspace of the chosen form only; the direct form's split partials shrink until it fits
   // unless the caller fixed source_splits
   s.pair = symmetric ? 2 : 1;

@@ -120,7 +120,8 @@ struct SymmetricView {
                              // blocks (one suspension) or of units (batched; then [4..12] the XCD queues and
                              // [16..23] their counters)
   double2* fcyc;             // [P/16 + M + 1] float64 net force w f of each cycle
-  unsigned long long* acc;   // [2][P] fixed-point sums (two's complement int64 at 2^-S)
+  unsigned long long* acc;   // [2][P] fixed-point sums (two's complement int64 at 2^-S); float64 form:
+                             // [2][2][P], the high words then the low words at 2^-(S + 40)
 };
 
 // Device views of the batched symmetric form's plan (after the symmetric region).
@@ -152,6 +153,10 @@ int64_t sym_units(int64_t nb);
 bool sym_fits(int P, int M, int T);
 hipError_t launch_forward_symmetric(int T, int P, int M, const PreparedView& pv, const SymmetricView& sv,
                                     double scale, double* out, void* stream);
+// The float64 symmetric form (T = 1 or 2; sv.acc holds 4P words: the high words of both components, then
+// the low words).
+hipError_t launch_forward_symmetric64(int T, int P, int M, const PreparedView& pv, const SymmetricView& sv,
+                                      double scale, double* out, void* stream);
 // Batched symmetric form (float32-compensated, targets = sources, S independent suspensions): a bound
 // of its unit count, the workgroups of its persistent kernel one compute unit holds, and the launch
 // (plan, cycle forces, persistent kernel on `grid` workgroups, conversion with each suspension's mu).

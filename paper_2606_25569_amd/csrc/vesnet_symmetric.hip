@@ -464,6 +464,241 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_main(
                    acc);
 }
 
+// ------------------------------------------------------------------ float64 symmetric form
+// The same schedule (cycles, blocks, circulant units, rings of 16 lanes) in float64 on global coordinates:
+// float64 needs no compensation, so a segment's set-up only selects the target or a far point with zero
+// force, and its rows are flushed without a log correction.  The logarithm and reciprocal are the table
+// logarithm and Newton reciprocal shared with the direct float64 kernel; column sums travel around the ring
+// by DPP moves of both halves of each double.  Sums leave the workgroup as two 64-bit fixed-point words:
+// hi = rint(x 2^S) and lo = rint((x - hi 2^-S) 2^(S + kLoBits)) (the first difference is exact), each added
+// by an integer atomic, so the result is again independent of the order of the atomics while the
+// resolution is 2^-(S + kLoBits), far below float64 rounding of the sum.  |lo| <= 2^(kLoBits - 1), so up to
+// 2^(62 - kLoBits + 1) partials per point stay exact.
+constexpr int kLoBits = 40;
+constexpr int kChunk64 = 4;                         // source cycles per LDS chunk
+constexpr double kFar64 = 3.2733906078961419e150;   // 2^500: position of an inactive target
+static_assert(kChunk64 * 2 * kRing <= kSymThreads, "one thread per staged record and per column sum of a chunk");
+
+// x from lane (p + 1) mod 16 of the same row (both halves of the double moved by DPP).
+__device__ __forceinline__ double ring_next64(double x) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x12F, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x12F, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ unsigned long long dlo(double x) { return __builtin_bit_cast(unsigned long long, x); }
+__device__ __forceinline__ double dfrom(unsigned lo, unsigned hi) {
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Adds x to the two fixed-point words of one accumulator entry (hi at a, lo at a + 2P).
+__device__ __forceinline__ void fixed_add2(unsigned long long* __restrict__ a, size_t two_p, double x, int S) {
+  const double h = rint(ldexp(x, S));
+  const double r = x - ldexp(h, -S);  // exact
+  atomicAdd(a, (unsigned long long)(long long)h);
+  atomicAdd(a + two_p, (unsigned long long)(long long)rint(ldexp(r, S + kLoBits)));
+}
+
+template <int T>
+__global__ __launch_bounds__(kSymThreads) void k_sym64_main(
+    int P, const double4* __restrict__ rec, const int4* __restrict__ cyc, const int32_t* __restrict__ meta,
+    unsigned long long* __restrict__ acc) {
+  constexpr int CB = kRows * T;
+  __shared__ int4 s_ti[CB];                          // (vesicle or -1, count, first point, 0)
+  __shared__ double4 s_rec[2][kChunk64][2 * kRing];  // source cycles (x, y, F_x, F_y), each stored twice
+  __shared__ double s_col[2][kSymWaves][kChunk64][2][kRing];
+  __shared__ double2 ltab[kLogTab];
+
+  const int ncyc = meta[0];
+  const int S = meta[1];
+  const int nb = meta[2];
+  if (nb <= 0) return;
+  int bx, by;
+  if (!sym_unit(nb, bx, by)) return;
+  const bool diag = bx == by;
+  const int tc0 = bx * CB, tc1 = min(ncyc, tc0 + CB);
+  const int sc0 = by * CB, sc1 = min(ncyc, sc0 + CB);
+  const size_t two_p = 2 * (size_t)P;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, p = lane & 15;
+  const int row = tid >> 4;
+  if (tid < kLogTab) ltab[tid] = log_tab_entry(tid);
+  for (int t = tid; t < CB; t += kSymThreads) {
+    const int c = tc0 + t;
+    if (c < tc1) {
+      const int4 cy = cyc[c];
+      s_ti[t] = make_int4(cy.z, cy.y, cy.x, 0);
+    } else {
+      s_ti[t] = make_int4(-1, 0, 0, 0);
+    }
+  }
+  __syncthreads();
+
+  // this lane's targets (slot k: target cycle k * 16 + row, point p of it)
+  double4 tr[T];
+  int4 ti[T];
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    ti[k] = s_ti[k * kRows + row];
+    tr[k] = ti[k].x >= 0 && p < ti[k].y ? rec[ti[k].z + p] : make_double4(0.0, 0.0, 0.0, 0.0);
+  }
+  double dx[T], dy[T], fcx[T], fcy[T], fhx[T], fhy[T], lx[T], ly[T], rvx[T], rvy[T], ax[T], ay[T];
+  int actm = 0;
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    dx[k] = dy[k] = fcx[k] = fcy[k] = fhx[k] = fhy[k] = 0.0;
+    lx[k] = ly[k] = rvx[k] = rvy[k] = ax[k] = ay[k] = 0.0;
+  }
+
+  auto setup = [&](int B) {
+    actm = 0;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const bool act = ti[k].x >= 0 && ti[k].x != B && (!diag || ti[k].x < B) && p < ti[k].y;
+      actm |= act ? (1 << k) : 0;
+      dx[k] = act ? tr[k].x : kFar64;
+      dy[k] = act ? tr[k].y : 0.0;
+      fcx[k] = act ? tr[k].z : 0.0;
+      fcy[k] = act ? tr[k].w : 0.0;
+      fhx[k] = -0.5 * fcx[k];
+      fhy[k] = -0.5 * fcy[k];
+      lx[k] = ly[k] = rvx[k] = rvy[k] = 0.0;
+    }
+  };
+
+  auto flush = [&]() {
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const bool act = (actm >> k) & 1;
+      ax[k] += act ? fma(-0.5, lx[k], rvx[k]) : 0.0;
+      ay[k] += act ? fma(-0.5, ly[k], rvy[k]) : 0.0;
+    }
+  };
+
+  auto ring = [&](int buf, int cc) {
+    const double4* rb = &s_rec[buf][cc][p];
+    double cax = 0.0, cay = 0.0;
+#pragma unroll 1
+    for (int s = 0; s < kRing; ++s) {
+      const double4 sr = rb[s];
+      double lcx = 0.0, lcy = 0.0;
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const double rx = dx[k] - sr.x;
+        const double ry = dy[k] - sr.y;
+        const double q = fma(ry, ry, rx * rx);
+        const double L = log_reduced(q, ltab);
+        const double rho = recip(q);
+        const double rxr = rx * rho, ryr = ry * rho;
+        const double b = fma(ryr, sr.w, rxr * sr.z);       // (r . F_j)/q
+        lx[k] = fma(L, sr.z, lx[k]);
+        ly[k] = fma(L, sr.w, ly[k]);
+        rvx[k] = fma(b, rx, rvx[k]);
+        rvy[k] = fma(b, ry, rvy[k]);
+        const double b2 = fma(ryr, fcy[k], rxr * fcx[k]);  // (r . F_i)/q
+        if (k == 0) {
+          lcx = L * fhx[k];
+          lcy = L * fhy[k];
+        } else {
+          lcx = fma(L, fhx[k], lcx);
+          lcy = fma(L, fhy[k], lcy);
+        }
+        lcx = fma(b2, rx, lcx);
+        lcy = fma(b2, ry, lcy);
+      }
+      cax = ring_next64(cax) + lcx;
+      cay = ring_next64(cay) + lcy;
+    }
+    // lane p holds source (p + 15) mod 16 of its row; add the four rows: x sums end in lanes 0-31, y sums
+    // in lanes 32-63 (both halves of each double swapped alike), then every row of a half holds the total
+    const unsigned long long bx_ = dlo(cax), by_ = dlo(cay);
+    const auto hl = __builtin_amdgcn_permlane32_swap((unsigned)bx_, (unsigned)by_, false, false);
+    const auto hh = __builtin_amdgcn_permlane32_swap((unsigned)(bx_ >> 32), (unsigned)(by_ >> 32), false, false);
+    const double z = dfrom(hl[0], hh[0]) + dfrom(hl[1], hh[1]);
+    const unsigned long long bz = dlo(z);
+    const auto gl = __builtin_amdgcn_permlane16_swap((unsigned)bz, (unsigned)bz, false, false);
+    const auto gh = __builtin_amdgcn_permlane16_swap((unsigned)(bz >> 32), (unsigned)(bz >> 32), false, false);
+    const double tot = dfrom(gl[0], gh[0]) + dfrom(gl[1], gh[1]);
+    if ((lane & 16) == 0) s_col[buf][wv][cc][lane >> 5][(p + kRing - 1) & (kRing - 1)] = tot;
+  };
+
+  const int nchunks = (sc1 - sc0 + kChunk64 - 1) / kChunk64;
+  const bool stager = tid < kChunk64 * 2 * kRing;
+  const int st_cc = tid >> 5, st_q = tid & 31, st_m = st_q & (kRing - 1);
+  auto stage_load = [&](int g) {
+    double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
+    const int c = sc0 + g * kChunk64 + st_cc;
+    if (stager && c < sc1) {
+      const int4 cy = cyc[c];
+      r = rec[cy.x + (st_m < cy.y ? st_m : 0)];
+      if (st_m >= cy.y) r.z = r.w = 0.0;
+    }
+    return r;
+  };
+  auto stage_store = [&](int buf, const double4& r) {
+    if (stager) s_rec[buf][st_cc][st_q] = r;
+  };
+  // column sums of chunk g: the four wavefronts added in a fixed order, then two fixed-point words
+  auto reduce = [&](int g, int buf) {
+    if (tid >= kChunk64 * 2 * kRing) return;
+    const int cc = tid >> 5, comp = (tid >> 4) & 1, m = tid & (kRing - 1);
+    const int c = sc0 + g * kChunk64 + cc;
+    if (c >= sc1) return;
+    const int4 cy = cyc[c];
+    if (m >= cy.y) return;
+    const double v = ((s_col[buf][0][cc][comp][m] + s_col[buf][1][cc][comp][m]) + s_col[buf][2][cc][comp][m]) +
+                     s_col[buf][3][cc][comp][m];
+    fixed_add2(&acc[(size_t)comp * P + cy.x + m], two_p, v, S);
+  };
+
+  int curB = -1;
+  stage_store(0, stage_load(0));
+  __syncthreads();
+  for (int g = 0; g < nchunks; ++g) {
+    const int buf = g & 1;
+    const double4 nxt = stage_load(g + 1);
+    if (g > 0) reduce(g - 1, buf ^ 1);
+    const int cbase = sc0 + g * kChunk64;
+    const int ncc = min(kChunk64, sc1 - cbase);
+    for (int cc = 0; cc < ncc; ++cc) {
+      const int4 cy = cyc[cbase + cc];
+      if (cy.z != curB) {
+        if (curB >= 0) flush();
+        setup(cy.z);
+        curB = cy.z;
+      }
+      ring(buf, cc);
+    }
+    stage_store(buf ^ 1, nxt);
+    __syncthreads();
+  }
+  if (nchunks > 0) {
+    reduce(nchunks - 1, (nchunks - 1) & 1);
+    flush();
+  }
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    if (ti[k].x >= 0 && p < ti[k].y) {
+      const int i = ti[k].z + p;
+      fixed_add2(&acc[i], two_p, ax[k], S);
+      fixed_add2(&acc[(size_t)P + i], two_p, ay[k], S);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sym64_finish(const unsigned long long* __restrict__ acc,
+                                                      const int32_t* __restrict__ meta, int P, double scale,
+                                                      double* __restrict__ out) {
+  const int S = meta[1];
+  const int64_t n = 2 * (int64_t)P;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const double hi = (double)(long long)acc[e];
+    const double lo = (double)(long long)acc[n + e];
+    out[e] = ldexp(fma(lo, ldexp(1.0, -kLoBits), hi) * scale, -S);
+  }
+}
+
 // ------------------------------------------------------------------ batched symmetric form
 // Many independent suspensions in one persistent launch.  Each suspension's cycles are contiguous (its
 // vesicles in order), its blocks of CB cycles never reach into another suspension, and its units are the
@@ -1118,6 +1353,32 @@ hipError_t launch_batched_symmetric(int T, int grid, int P, int M, const Prepare
   const int64_t n = 2 * (int64_t)P;
   const int fgrid = (int)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
   hipLaunchKernelGGL(k_symb_finish, dim3(fgrid), dim3(256), 0, st, sv.acc, bv.stab, bv.pstart, mu, S, P, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_symmetric64(int T, int P, int M, const PreparedView& pv, const SymmetricView& sv,
+                                      double scale, double* out, void* stream) {
+  if (P == 0) return hipSuccess;
+  hipStream_t st = Sx_(stream);
+  const int cb = sym_cycles_per_block(T);
+  const int ncyc_max = (int)sym_max_cycles(P, M);
+  const int nb_max = (int)sym_max_blocks(P, M, T);
+  hipLaunchKernelGGL(k_sym_plan, dim3(1), dim3(1024), 0, st, pv.vrange, pv.vaux, M, cb, ncyc_max, sv.cyc, sv.meta);
+  // cycle forces (unused here) and the first 2P accumulator words; the low words are zeroed below
+  const int cgrid = (int)std::min<int64_t>((2 * (int64_t)P + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_sym_cycles, dim3(cgrid), dim3(256), 0, st, sv.cyc, sv.meta, pv.f64, P, sv.fcyc, sv.acc);
+  hipLaunchKernelGGL(k_zero_f64, dim3(cgrid), dim3(256), 0, st, reinterpret_cast<double*>(sv.acc + 2 * (size_t)P),
+                     2 * (int64_t)P);
+  const dim3 grid((unsigned)sym_units(nb_max));
+  const double4* rec = static_cast<const double4*>(pv.rec);
+  switch (T) {
+    case 1: hipLaunchKernelGGL(k_sym64_main<1>, grid, dim3(kSymThreads), 0, st, P, rec, sv.cyc, sv.meta, sv.acc); break;
+    case 2: hipLaunchKernelGGL(k_sym64_main<2>, grid, dim3(kSymThreads), 0, st, P, rec, sv.cyc, sv.meta, sv.acc); break;
+    default: return hipErrorInvalidValue;
+  }
+  const int64_t n = 2 * (int64_t)P;
+  const int fgrid = (int)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
+  hipLaunchKernelGGL(k_sym64_finish, dim3(fgrid), dim3(256), 0, st, sv.acc, sv.meta, P, scale, out);
   return hipGetLastError();
 }
 

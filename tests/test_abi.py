@@ -340,13 +340,19 @@ def test_naive_precision_has_no_backward(L):
 
 
 def test_symmetric_form_rejects(L):
-    """pair_form 2 (one evaluation per unordered pair) needs targets == sources and the
-    compensated precision; bad pair_form values are refused."""
+    """pair_form 2 (one evaluation per unordered pair) needs targets == sources and the compensated or
+    float64 precision (float64: one or two targets per thread); bad pair_form values are refused."""
     lib = L.lib()
     cfg = L.TileConfig()
     cfg.pair_form = 2
     assert _fwd(L, cfg=ctypes.byref(cfg)) == L.ERR_INVALID_ARGUMENT          # targets != sources
-    assert _fwd(L, cfg=ctypes.byref(cfg), prec=0, sources=FAKE) == L.ERR_UNSUPPORTED
+    assert _fwd(L, cfg=ctypes.byref(cfg), prec=2, sources=FAKE) == L.ERR_UNSUPPORTED
+    cfg.targets_per_thread = 4
+    assert _fwd(L, cfg=ctypes.byref(cfg), prec=0, sources=FAKE) == L.ERR_INVALID_ARGUMENT
+    assert lib.vesnet_farfield_workspace_bytes(10, 2, 0, ctypes.byref(cfg)) == 0
+    cfg.targets_per_thread = 2
+    assert lib.vesnet_farfield_workspace_bytes(10, 2, 0, ctypes.byref(cfg)) > 0
+    cfg.targets_per_thread = 0
     cfg.pair_form = 3
     assert _fwd(L, cfg=ctypes.byref(cfg)) == L.ERR_INVALID_ARGUMENT
     assert lib.vesnet_farfield_workspace_bytes(10, 2, 1, ctypes.byref(cfg)) == 0
