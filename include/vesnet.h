@@ -432,12 +432,14 @@ VESNET_API int vesnet_farfield_stokeslet_backward(const double* targets, const d
      grad_points_k = sum_{m not in ves(k)} [ grad_r phi(X_k - X_m; g_k, F_m)
                                             + grad_r phi(X_k - X_m; F_k, g_m) ]
    and grad_force, grad_weights as above.  Both terms of one pair (k, m) share
-   r, |r|^2, its reciprocal and logarithm, and grad_r phi is odd in r, so under
-   VESNET_FP32_COMPENSATED each unordered pair of points in different vesicles
-   is evaluated once (the symmetric form of the forward, with float64 atomic
-   sums: the last bits may differ from call to call).  Under VESNET_FP64 the
-   two gathers of vesnet_farfield_stokeslet_backward run and their position
-   gradients are added.
+   r, |r|^2, its reciprocal and logarithm, and grad_r phi is odd in r, so each
+   unordered pair of points in different vesicles is evaluated once (the
+   symmetric forms of the forward: VESNET_FP32_COMPENSATED on rescaled local
+   coordinates, VESNET_FP64 on global coordinates), with float64 atomic sums:
+   the last bits may differ from call to call.  (Should the units of the
+   symmetric form not fit one launch, about 33 million points, the two gathers
+   of vesnet_farfield_stokeslet_backward run and their position gradients are
+   added.)
      points                       : device [2][P] float64
      grad_out                     : device [2][P] float64
      grad_points, grad_force      : device [2][P] float64 or NULL (skipped)

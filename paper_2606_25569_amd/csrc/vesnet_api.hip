@@ -945,12 +945,20 @@ int sym_bwd_T(int32_t P, int32_t M) {
   return sym_fits(P, M, 4) ? 4 : 0;
 }
 
-// The symmetric pass (FP32-compensated): two prepared regions with forces, the cycle tables and a
-// [2][P] buffer for the position gradient when the caller does not ask for it; otherwise the
+// Targets per thread of the float64 symmetric adjoint: one (126 VGPRs, four wavefronts per SIMD; two
+// need 200), two when the units of one would not fit a launch; 0: the gathers.
+int sym64_bwd_T(int32_t P, int32_t M) { return sym_fits(P, M, 1) ? 1 : sym_fits(P, M, 2) ? 2 : 0; }
+
+int points_bwd_T(int32_t P, int32_t M, int prec) {
+  return prec == VESNET_FP32_COMPENSATED ? sym_bwd_T(P, M) : prec == VESNET_FP64 ? sym64_bwd_T(P, M) : 0;
+}
+
+// The symmetric pass (FP32-compensated and FP64): two prepared regions with forces, the cycle tables
+// and a [2][P] buffer for the position gradient when the caller does not ask for it; otherwise the
 // gathers' workspace and a [2][P] buffer for the source-role gradient.
 size_t backward_points_bytes(int32_t P, int32_t M, int prec) {
   const size_t vec = align_up((size_t)2 * P * sizeof(double));
-  if (prec == VESNET_FP32_COMPENSATED && sym_bwd_T(P, M))
+  if (points_bwd_T(P, M, prec))
     return kAlign + 2 * prepared_bytes(P, M, prec, true) + symmetric_bytes(P, M) + vec;
   return backward_bytes(P, M, prec) + vec;
 }
@@ -993,7 +1001,7 @@ extern "C" int vesnet_farfield_stokeslet_backward_points(const double* points, c
   const double scale = 1.0 / (4.0 * kPi * mu);
   char* cur = aligned_base(ws);
   hipError_t e = hipSuccess;
-  const int symT = prec == VESNET_FP32_COMPENSATED ? sym_bwd_T(P, M) : 0;
+  const int symT = points_bwd_T(P, M, prec);
   if (symT) {
     // one symmetric pass: (points, w f) and (points, g) records, cycles and their sums of g
     PreparedView pvF = carve_prepared(cur, P, M, prec, true);
@@ -1003,8 +1011,11 @@ extern "C" int vesnet_farfield_stokeslet_backward_points(const double* points, c
     e = launch_prepare(prec, points, f, w, off, M, P, pvF, stream);
     if (e == hipSuccess) e = launch_prepare(prec, points, gout, nullptr, off, M, P, pvG, stream);
     if (e != hipSuccess) return hip_fail(e, "backward prepare launch");
-    e = launch_backward_symmetric(symT, P, M, pvF, pvG, sv, reinterpret_cast<double*>(sv.acc), f, w, scale, gx,
-                                  grad_f, grad_w, stream);
+    e = prec == VESNET_FP64
+            ? launch_backward_symmetric64(symT, P, M, pvF, pvG, sv, reinterpret_cast<double*>(sv.acc), f, w, scale,
+                                          gx, grad_f, grad_w, stream)
+            : launch_backward_symmetric(symT, P, M, pvF, pvG, sv, reinterpret_cast<double*>(sv.acc), f, w, scale, gx,
+                                        grad_f, grad_w, stream);
     if (e != hipSuccess) return hip_fail(e, "symmetric backward launch");
     return ok();
   }

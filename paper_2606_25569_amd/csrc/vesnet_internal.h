@@ -173,6 +173,11 @@ hipError_t launch_backward_symmetric(int T, int P, int M, const PreparedView& pv
                                      const SymmetricView& sv, double* vsum, const double* f, const double* w,
                                      double scale, double* grad_points, double* grad_f, double* grad_w,
                                      void* stream);
+// The same in float64 (T = 1 or 2; pvF and pvG prepared in float64 with forces).
+hipError_t launch_backward_symmetric64(int T, int P, int M, const PreparedView& pvF, const PreparedView& pvG,
+                                       const SymmetricView& sv, double* vsum, const double* f, const double* w,
+                                       double scale, double* grad_points, double* grad_f, double* grad_w,
+                                       void* stream);
 hipError_t launch_forward_near(int prec, int T, bool lds, int splits, const double* tg, int P, int M,
                                const PreparedView& pv, double scale, double* out, double* partial, int32_t* count,
                                int32_t* pairs, int32_t capacity, void* stream);

@@ -1204,6 +1204,250 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_bwd(
   }
 }
 
+// Float64 adjoint for targets = sources, on the schedule of k_sym64_main: per pair the same v (G(r) g_j to
+// the row, G(r) g_i to the column) and H (+H to the row, -H to the column) as k_sym_bwd, on global
+// coordinates without compensation; four float64 sums travel around the ring.  Sums are added with float64
+// atomics, as in k_sym_bwd.
+template <int T>
+__global__ __launch_bounds__(kSymThreads) void k_sym64_bwd(const double4* __restrict__ recF,
+                                                           const double4* __restrict__ recG,
+                                                           const int4* __restrict__ cyc,
+                                                           const int32_t* __restrict__ meta, int P,
+                                                           double* __restrict__ gsum, double* __restrict__ vsum) {
+  constexpr int CB = kRows * T;
+  __shared__ int4 s_ti[CB];                          // (vesicle or -1, count, first point, 0)
+  __shared__ double4 s_rec[2][kChunk64][2 * kRing];  // source cycles (x, y, F_x, F_y), twice
+  __shared__ double2 s_reg[2][kChunk64][2 * kRing];  // source g, twice
+  __shared__ double s_col[2][kSymWaves][kChunk64][4][kRing];
+  __shared__ double2 ltab[kLogTab];
+
+  const int ncyc = meta[0];
+  const int nb = meta[2];
+  if (nb <= 0) return;
+  int bx, by;
+  if (!sym_unit(nb, bx, by)) return;
+  const bool diag = bx == by;
+  const int tc0 = bx * CB, tc1 = min(ncyc, tc0 + CB);
+  const int sc0 = by * CB, sc1 = min(ncyc, sc0 + CB);
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, p = lane & 15;
+  const int row = tid >> 4;
+  if (tid < kLogTab) ltab[tid] = log_tab_entry(tid);
+  for (int t = tid; t < CB; t += kSymThreads) {
+    const int c = tc0 + t;
+    if (c < tc1) {
+      const int4 cy = cyc[c];
+      s_ti[t] = make_int4(cy.z, cy.y, cy.x, 0);
+    } else {
+      s_ti[t] = make_int4(-1, 0, 0, 0);
+    }
+  }
+  __syncthreads();
+
+  double4 tf[T];
+  double2 tg[T];
+  int4 ti[T];
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    ti[k] = s_ti[k * kRows + row];
+    const bool in = ti[k].x >= 0 && p < ti[k].y;
+    tf[k] = in ? recF[ti[k].z + p] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const double4 g4 = in ? recG[ti[k].z + p] : make_double4(0.0, 0.0, 0.0, 0.0);
+    tg[k] = make_double2(g4.z, g4.w);
+  }
+  // per target slot k: position (or a far point), F and g (zero when inactive), -1/2 g, the segment's
+  // partials (log and rr parts of v, H) and the unit's sums
+  double dx[T], dy[T], fix[T], fiy[T], gix[T], giy[T], ghx[T], ghy[T];
+  double lvx[T], lvy[T], rvx[T], rvy[T], gax[T], gay[T], avx[T], avy[T], agx[T], agy[T];
+  int actm = 0;
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    dx[k] = dy[k] = fix[k] = fiy[k] = gix[k] = giy[k] = ghx[k] = ghy[k] = 0.0;
+    lvx[k] = lvy[k] = rvx[k] = rvy[k] = gax[k] = gay[k] = avx[k] = avy[k] = agx[k] = agy[k] = 0.0;
+  }
+
+  auto setup = [&](int B) {
+    actm = 0;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const bool act = ti[k].x >= 0 && ti[k].x != B && (!diag || ti[k].x < B) && p < ti[k].y;
+      actm |= act ? (1 << k) : 0;
+      dx[k] = act ? tf[k].x : kFar64;
+      dy[k] = act ? tf[k].y : 0.0;
+      fix[k] = act ? tf[k].z : 0.0;
+      fiy[k] = act ? tf[k].w : 0.0;
+      gix[k] = act ? tg[k].x : 0.0;
+      giy[k] = act ? tg[k].y : 0.0;
+      ghx[k] = -0.5 * gix[k];
+      ghy[k] = -0.5 * giy[k];
+      lvx[k] = lvy[k] = rvx[k] = rvy[k] = gax[k] = gay[k] = 0.0;
+    }
+  };
+
+  auto flush = [&]() {
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+      const bool act = (actm >> k) & 1;
+      avx[k] += act ? fma(-0.5, lvx[k], rvx[k]) : 0.0;
+      avy[k] += act ? fma(-0.5, lvy[k], rvy[k]) : 0.0;
+      agx[k] += act ? gax[k] : 0.0;
+      agy[k] += act ? gay[k] : 0.0;
+    }
+  };
+
+  auto ring = [&](int buf, int cc) {
+    const double4* rb = &s_rec[buf][cc][p];
+    const double2* gb = &s_reg[buf][cc][p];
+    double cvx = 0.0, cvy = 0.0, cgx = 0.0, cgy = 0.0;
+#pragma unroll 1
+    for (int s = 0; s < kRing; ++s) {
+      const double4 sr = rb[s];
+      const double2 sg = gb[s];
+      double lvcx = 0.0, lvcy = 0.0, lgcx = 0.0, lgcy = 0.0;
+#pragma unroll
+      for (int k = 0; k < T; ++k) {
+        const double rx = dx[k] - sr.x;
+        const double ry = dy[k] - sr.y;
+        const double q = fma(ry, ry, rx * rx);
+        const double L = log_reduced(q, ltab);
+        const double rho = recip(q);
+        const double ux = rx * rho, uy = ry * rho;
+        const double p3 = fma(uy, sg.y, ux * sg.x);        // (r . g_j)/q
+        const double p2 = fma(uy, giy[k], ux * gix[k]);    // (r . g_i)/q
+        const double p1 = fma(uy, sr.w, ux * sr.z);        // (r . F_j)/q
+        const double p4 = fma(uy, fiy[k], ux * fix[k]);    // (r . F_i)/q
+        lvx[k] = fma(L, sg.x, lvx[k]);
+        lvy[k] = fma(L, sg.y, lvy[k]);
+        rvx[k] = fma(p3, rx, rvx[k]);
+        rvy[k] = fma(p3, ry, rvy[k]);
+        // H = -(rho (g_i . F_j + F_i . g_j) + 2 (p1 p2 + p3 p4)) r + g_i p1 + F_j p2 + F_i p3 + g_j p4
+        const double ab = fma(gix[k], sr.z, fma(giy[k], sr.w, fma(fix[k], sg.x, fiy[k] * sg.y)));
+        const double m = fma(2.0, fma(p1, p2, p3 * p4), rho * ab);
+        const double hx = fma(sg.x, p4, fma(fix[k], p3, fma(sr.z, p2, fma(gix[k], p1, -m * rx))));
+        const double hy = fma(sg.y, p4, fma(fiy[k], p3, fma(sr.w, p2, fma(giy[k], p1, -m * ry))));
+        gax[k] += hx;
+        gay[k] += hy;
+        if (k == 0) {
+          lvcx = L * ghx[k];
+          lvcy = L * ghy[k];
+          lgcx = -hx;
+          lgcy = -hy;
+        } else {
+          lvcx = fma(L, ghx[k], lvcx);
+          lvcy = fma(L, ghy[k], lvcy);
+          lgcx -= hx;
+          lgcy -= hy;
+        }
+        lvcx = fma(p2, rx, lvcx);
+        lvcy = fma(p2, ry, lvcy);
+      }
+      cvx = ring_next64(cvx) + lvcx;
+      cvy = ring_next64(cvy) + lvcy;
+      cgx = ring_next64(cgx) + lgcx;
+      cgy = ring_next64(cgy) + lgcy;
+    }
+    // add the four rows of the wavefront (both halves of each double swapped alike): v, then H
+    auto rows4 = [&](double a, double b) {
+      const unsigned long long ba = dlo(a), bb = dlo(b);
+      const auto hl = __builtin_amdgcn_permlane32_swap((unsigned)ba, (unsigned)bb, false, false);
+      const auto hh = __builtin_amdgcn_permlane32_swap((unsigned)(ba >> 32), (unsigned)(bb >> 32), false, false);
+      const double z = dfrom(hl[0], hh[0]) + dfrom(hl[1], hh[1]);
+      const unsigned long long bz = dlo(z);
+      const auto gl = __builtin_amdgcn_permlane16_swap((unsigned)bz, (unsigned)bz, false, false);
+      const auto gh = __builtin_amdgcn_permlane16_swap((unsigned)(bz >> 32), (unsigned)(bz >> 32), false, false);
+      return dfrom(gl[0], gh[0]) + dfrom(gl[1], gh[1]);
+    };
+    const double totv = rows4(cvx, cvy);
+    const double totg = rows4(cgx, cgy);
+    if ((lane & 16) == 0) {
+      const int slot = (p + kRing - 1) & (kRing - 1);
+      s_col[buf][wv][cc][lane >> 5][slot] = totv;
+      s_col[buf][wv][cc][2 + (lane >> 5)][slot] = totg;
+    }
+  };
+
+  const int nchunks = (sc1 - sc0 + kChunk64 - 1) / kChunk64;
+  const bool stager = tid < kChunk64 * 2 * kRing;
+  const int st_cc = tid >> 5, st_q = tid & 31, st_m = st_q & (kRing - 1);
+  auto stage_load = [&](int g, double2& gg) {
+    double4 r = make_double4(0.0, 0.0, 0.0, 0.0);
+    gg = make_double2(0.0, 0.0);
+    const int c = sc0 + g * kChunk64 + st_cc;
+    if (stager && c < sc1) {
+      const int4 cy = cyc[c];
+      const int j = cy.x + (st_m < cy.y ? st_m : 0);
+      r = recF[j];
+      const double4 rg = recG[j];
+      if (st_m >= cy.y) {
+        r.z = r.w = 0.0;
+      } else {
+        gg = make_double2(rg.z, rg.w);
+      }
+    }
+    return r;
+  };
+  auto stage_store = [&](int buf, const double4& r, const double2& gg) {
+    if (stager) {
+      s_rec[buf][st_cc][st_q] = r;
+      s_reg[buf][st_cc][st_q] = gg;
+    }
+  };
+  // column sums of chunk g: v and H added over the wavefronts in a fixed order, one float64 atomic
+  // addition per (source, quantity, component)
+  auto reduce = [&](int g, int buf) {
+    const int cc = tid >> 6, comp = (tid >> 4) & 3, m = tid & (kRing - 1);
+    const int c = sc0 + g * kChunk64 + cc;
+    if (cc >= kChunk64 || c >= sc1) return;
+    const int4 cy = cyc[c];
+    if (m >= cy.y) return;
+    const double v = ((s_col[buf][0][cc][comp][m] + s_col[buf][1][cc][comp][m]) + s_col[buf][2][cc][comp][m]) +
+                     s_col[buf][3][cc][comp][m];
+    double* dst = comp < 2 ? vsum : gsum;
+    atomicAdd(&dst[(size_t)(comp & 1) * P + cy.x + m], v);
+  };
+
+  int curB = -1;
+  {
+    double2 g0;
+    const double4 r0 = stage_load(0, g0);
+    stage_store(0, r0, g0);
+  }
+  __syncthreads();
+  for (int g = 0; g < nchunks; ++g) {
+    const int buf = g & 1;
+    double2 ng;
+    const double4 nxt = stage_load(g + 1, ng);
+    if (g > 0) reduce(g - 1, buf ^ 1);
+    const int cbase = sc0 + g * kChunk64;
+    const int ncc = min(kChunk64, sc1 - cbase);
+    for (int cc = 0; cc < ncc; ++cc) {
+      const int4 cy = cyc[cbase + cc];
+      if (cy.z != curB) {
+        if (curB >= 0) flush();
+        setup(cy.z);
+        curB = cy.z;
+      }
+      ring(buf, cc);
+    }
+    stage_store(buf ^ 1, nxt, ng);
+    __syncthreads();
+  }
+  if (nchunks > 0) {
+    reduce(nchunks - 1, (nchunks - 1) & 1);
+    flush();
+  }
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    if (ti[k].x >= 0 && p < ti[k].y) {
+      const int i = ti[k].z + p;
+      atomicAdd(&vsum[i], avx[k]);
+      atomicAdd(&vsum[(size_t)P + i], avy[k]);
+      atomicAdd(&gsum[i], agx[k]);
+      atomicAdd(&gsum[(size_t)P + i], agy[k]);
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ a, int64_t n) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
     a[e] = 0.0;
@@ -1290,6 +1534,36 @@ hipError_t launch_backward_symmetric(int T, int P, int M, const PreparedView& pv
     break;
     VESNET_SYMB_CASE(1) VESNET_SYMB_CASE(2) VESNET_SYMB_CASE(4)
 #undef VESNET_SYMB_CASE
+    default: return hipErrorInvalidValue;
+  }
+  const int fgrid = (P + 255) / 256 < 16384 ? (P + 255) / 256 : 16384;
+  hipLaunchKernelGGL(k_sym_bwd_finish, dim3(fgrid), dim3(256), 0, st, vsum, f, w, P, scale, grad_points, grad_f,
+                     grad_w);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward_symmetric64(int T, int P, int M, const PreparedView& pvF, const PreparedView& pvG,
+                                       const SymmetricView& sv, double* vsum, const double* f, const double* w,
+                                       double scale, double* grad_points, double* grad_f, double* grad_w,
+                                       void* stream) {
+  if (P == 0) return hipSuccess;
+  if (!grad_points || !vsum) return hipErrorInvalidValue;
+  hipStream_t st = Sx_(stream);
+  const int cb = sym_cycles_per_block(T);
+  const int ncyc_max = (int)sym_max_cycles(P, M);
+  const int nb_max = (int)sym_max_blocks(P, M, T);
+  hipLaunchKernelGGL(k_sym_plan, dim3(1), dim3(1024), 0, st, pvF.vrange, pvF.vaux, M, cb, ncyc_max, sv.cyc, sv.meta);
+  const int cgrid = (int)std::min<int64_t>((2 * (int64_t)P + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero_f64, dim3(cgrid), dim3(256), 0, st, grad_points, 2 * (int64_t)P);
+  hipLaunchKernelGGL(k_zero_f64, dim3(cgrid), dim3(256), 0, st, vsum, 2 * (int64_t)P);
+  const dim3 grid((unsigned)sym_units(nb_max));
+  const double4* recF = static_cast<const double4*>(pvF.rec);
+  const double4* recG = static_cast<const double4*>(pvG.rec);
+  switch (T) {
+    case 1: hipLaunchKernelGGL(k_sym64_bwd<1>, grid, dim3(kSymThreads), 0, st, recF, recG, sv.cyc, sv.meta, P,
+                               grad_points, vsum); break;
+    case 2: hipLaunchKernelGGL(k_sym64_bwd<2>, grid, dim3(kSymThreads), 0, st, recF, recG, sv.cyc, sv.meta, P,
+                               grad_points, vsum); break;
     default: return hipErrorInvalidValue;
   }
   const int fgrid = (P + 255) / 256 < 16384 ? (P + 255) / 256 : 16384;

@@ -168,12 +168,15 @@ def test_backward_points_rejects(L):
     assert lib.vesnet_farfield_stokeslet_backward_points(*args, None, None, None, 1, *ws) == 0
     assert lib.vesnet_farfield_stokeslet_backward_points(None, None, None, None, 0, 0, 1.0, None, None, None, None, 1,
                                                          None, 0, None) == 0
-    # workspace sizes: the symmetric (fp32c) form needs less than the gathers plus their sum buffer
+    # workspace sizes: the symmetric forms (fp32c and fp64) need less than the gathers plus their sum
+    # buffer, and at least two prepared regions, the cycle table, the [2][P] sums and a [2][P] buffer
     for P, M in ((512, 16), (256000, 2000)):
         b32 = lib.vesnet_backward_points_workspace_bytes(P, M, 1)
         b64 = lib.vesnet_backward_points_workspace_bytes(P, M, 0)
         assert 0 < b32 and 0 < b64
-        assert b64 >= lib.vesnet_backward_workspace_bytes(P, M, 0) + 16 * P
+        assert b32 < lib.vesnet_backward_workspace_bytes(P, M, 1) + 16 * P
+        assert b64 < lib.vesnet_backward_workspace_bytes(P, M, 0) + 16 * P
+        assert b64 >= 2 * P * (32 + 16 + 4) + 16 * P + 16 * P
     assert lib.vesnet_backward_points_workspace_bytes(512, 16, 2) == 0
 
 

@@ -1,8 +1,9 @@
 """GPU parity of the adjoint for one point array (targets = sources) through the C-ABI entry
 vesnet_farfield_stokeslet_backward_points, against the oracle's gradient.
 
-Under fp32c each unordered pair of points in different vesicles is evaluated once (the symmetric
-form of the forward); under fp64 the two gathers run and their position gradients are added.
+Under fp32c and fp64 each unordered pair of points in different vesicles is evaluated once (the
+symmetric forms of the forward; float64 on global coordinates); the two gathers remain for separate
+target and source arrays (tests/test_gpu_backward.py).
 Bars: 1e-5 (fp32c) and 1e-12 (fp64) in max-norm error relative to the largest component, per
 output.  The cases cover one and two targets per thread (small problems take one), ragged and
 empty vesicles, vesicles longer than a block, several blocks of both parities, a translated
@@ -70,17 +71,19 @@ def test_ragged_partition(V, prec):
     _check(s, _points(V, s, g, prec), ref, prec, "ragged")
 
 
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
 @pytest.mark.parametrize("m", [90, 131])
-def test_many_blocks_odd_and_even(V, m):
+def test_many_blocks_odd_and_even(V, m, prec):
     rng = np.random.default_rng(m)
     s = _ragged_suspension(seed=m, sizes=list(rng.integers(1, 90, size=m)), spacing=4.5)
     g = _g(s, m)
     sel = S.sample_targets(s.n_points, 0.25, m)
     ref = O.grad_suspension(s.X, s.f, s.w, s.offsets, s.mu, g, select=sel)
-    _check(s, _points(V, s, g, "fp32c"), ref, "fp32c", f"many blocks m={m}", sel)
+    _check(s, _points(V, s, g, prec), ref, prec, f"many blocks m={m}", sel)
 
 
-def test_vesicle_larger_than_block(V):
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_vesicle_larger_than_block(V, prec):
     rng = np.random.default_rng(8)
     sizes = np.array([2500, 7, 1030, 33])
     centers = np.array([[0.0, 0.0], [30.0, 0.0], [0.0, 30.0], [30.0, 30.0]])
@@ -88,15 +91,16 @@ def test_vesicle_larger_than_block(V):
     s = S._assemble(rng, centers, axes, rng.uniform(0, 6.28, 4), sizes, "k4", 0.2, 1.0, 40.0)
     g = _g(s, 12)
     ref = O.grad_suspension(s.X, s.f, s.w, s.offsets, s.mu, g)
-    _check(s, _points(V, s, g, "fp32c"), ref, "fp32c", "large vesicle")
+    _check(s, _points(V, s, g, prec), ref, prec, "large vesicle")
 
 
-def test_large_translation(V):
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_large_translation(V, prec):
     s = _ragged_suspension()
     s.X = s.X + np.array([[1000.0], [-1000.0]])
     g = _g(s, 13)
     ref = O.grad_suspension(s.X, s.f, s.w, s.offsets, s.mu, g)
-    _check(s, _points(V, s, g, "fp32c"), ref, "fp32c", "+1000")
+    _check(s, _points(V, s, g, prec), ref, prec, "+1000")
 
 
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
@@ -123,16 +127,17 @@ def test_partial_requests_agree(V, prec):
     assert rel_err(only_w[2], full[2])[0] <= BARS[prec]
 
 
-def test_zero_cases(V):
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_zero_cases(V, prec):
     """Zero dL/du gives zero gradients; one vesicle has no cross pairs at all."""
     s = S.make_config(0)
-    for a in _points(V, s, np.zeros((2, s.n_points)), "fp32c"):
+    for a in _points(V, s, np.zeros((2, s.n_points)), prec):
         assert np.all(a == 0.0)
     a, b = S.ellipse_axes(0.65)
     X, w, th = S.ellipse_curve((0.0, 0.0), a, b, 0.0, 40)
     s1 = S.Suspension(X=X, f=np.stack([np.cos(th), np.sin(th)]), w=w, offsets=np.array([0, 40], np.int32), mu=1.0,
                       box=4.0, centers=np.zeros((1, 2)), axes=np.array([[a, b]]), angles=np.zeros(1))
-    for a in _points(V, s1, _g(s1, 16), "fp32c"):
+    for a in _points(V, s1, _g(s1, 16), prec):
         assert np.all(a == 0.0)
 
 
@@ -148,11 +153,14 @@ def test_autograd_takes_the_points_form_for_one_tensor(V):
         X = torch.tensor(s.X, device="cuda", requires_grad=True)
         f = torch.tensor(s.f, device="cuda", requires_grad=True)
         w = torch.tensor(s.w, device="cuda")
-        Y = X if same else X * 1.0
-        out = V.farfield_stokeslet(X, Y, f, w, s.offsets, s.mu, precision="fp32c")
-        (0.5 * ((out - torch.tensor(ustar, device="cuda")) ** 2).sum()).backward()
-        torch.cuda.synchronize()
-        for name, a in (("grad_X", X.grad), ("grad_f", f.grad)):
-            err, _ = rel_err(a.cpu().numpy(), ref[name])
-            say(f"autograd same={same} {name}: {err:.3e}")
-            assert err <= BARS["fp32c"], (same, name, err)
+        for prec in ("fp32c", "fp64"):
+            X.grad = None
+            f.grad = None
+            Y = X if same else X * 1.0
+            out = V.farfield_stokeslet(X, Y, f, w, s.offsets, s.mu, precision=prec)
+            (0.5 * ((out - torch.tensor(ustar, device="cuda")) ** 2).sum()).backward()
+            torch.cuda.synchronize()
+            for name, a in (("grad_X", X.grad), ("grad_f", f.grad)):
+                err, _ = rel_err(a.cpu().numpy(), ref[name])
+                say(f"autograd same={same} {prec} {name}: {err:.3e}")
+                assert err <= BARS[prec], (same, prec, name, err)
