@@ -1,11 +1,15 @@
-// Symmetric far-field kernel for gfx950: each unordered cross-vesicle pair is evaluated once.
+// Symmetric far-field kernels for gfx950: each unordered cross-vesicle pair is evaluated once.
 //
 // The Stokeslet of eq. (Stokeslet), read as -ln|r| I + r r^T/|r|^2, is even in r, and the
 // trapezoid sum of eq. (single_layer) (Section 2.2.1) taken at the discretisation points
 // themselves uses every point as target and as source.  One evaluation of r, |r|^2, its
 // logarithm and its reciprocal therefore serves both ordered pairs (i <- j and j <- i), which
 // halves the transcendental instructions of the direct gather (26 issue slots per unordered pair,
-// 13 per ordered pair, against 19.6).  Only the float32-compensated precision uses this form.
+// 13 per ordered pair, against 19.6).
+// This file holds, on one schedule: the float32-compensated forward (k_sym_main) and its batched
+// persistent form (k_symb_*), the float64 forward (k_sym64_main), and the adjoints of one point
+// array in float32-compensated (k_sym_bwd) and float64 (k_sym64_bwd) form.  The description below is
+// the float32-compensated forward's; the other kernels state where they differ.
 //
 // Work decomposition
 //  * Points are cut into "cycles" of at most 16 consecutive points of one vesicle (a vesicle of
