@@ -216,6 +216,8 @@ def main():
     def time64(pair_form):
         cfg64 = V.default_config(P, M, "fp64")
         cfg64.pair_form = pair_form
+        if pair_form == 2:
+            cfg64.targets_per_thread = 0  # the symmetric form's own default
         ws64 = torch.empty(lib.vesnet_farfield_workspace_bytes(P, M, prec64, ctypes.byref(cfg64)), dtype=torch.uint8,
                            device=dev)
         prepare(prec64, ctypes.byref(cfg64), ws64)

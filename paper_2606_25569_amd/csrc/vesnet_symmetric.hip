@@ -823,7 +823,7 @@ __global__ __launch_bounds__(1024) void k_symb_plan(const int2* __restrict__ vra
 
 // Persistent batched kernel: units from the XCD queues until all are empty (see above).
 template <int T>
-__global__ __launch_bounds__(kSymThreads) void k_symb_main(
+__global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(T == 2 ? 5 : 1))) void k_symb_main(
     int P, const double4* __restrict__ vtab, const double2* __restrict__ vaux, const float4* __restrict__ rec,
     const int4* __restrict__ cyc, const double2* __restrict__ fcyc, const int4* __restrict__ stab,
     const int32_t* __restrict__ ustart, int nsus, int32_t* __restrict__ meta, unsigned long long* __restrict__ acc) {
