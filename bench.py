@@ -29,12 +29,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_counters(tile, symmetric):
+def measured_counters(tile, symmetric, name=None):
     """Figures of the committed rocprofv3 counter summary of the pair kernel (HBM bytes per launch,
     achieved shader clock, issue slots per pair), or {} when the kernel source or the launch shape
     differs from the one measured."""
     import hashlib
-    name = "k_sym_main_fp32c_2000x128_counters.txt" if symmetric else "k_forward_fp32c_2000x128_counters.txt"
+    if name is None:
+        name = "k_sym_main_fp32c_2000x128_counters.txt" if symmetric else "k_forward_fp32c_2000x128_counters.txt"
     src = "vesnet_symmetric.hip" if symmetric else "vesnet_kernels.hip"
     try:
         fields = {}
@@ -276,6 +277,7 @@ def main():
     tile_key = ",".join(str(d[k]) for k in ("targets_per_thread", "block_threads", "source_splits", "source_staging",
                                             "accumulate", "pair_form"))
     prof = measured_counters(tile_key, symmetric)
+    prof64 = measured_counters("0,256,16,2,1,2", True, "k_sym64_main_fp64_2000x128_counters.txt")
     traffic = prof.get("traffic_bytes_per_launch")
     mix = None
     if "slots_per_pair" in prof:
@@ -318,6 +320,8 @@ def main():
                  "frac_fp64_peak": FLOPS_PER_PAIR * pairs / (ms64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
                  "speedup_fp32c_over_fp64": ms64 / ms_step},
         "fp64_symmetric": {"kernel": "k_sym64_main (each unordered pair once, two-word fixed-point sums)",
+                           "traffic": prof64.get("traffic_bytes_per_launch"), "sclk_ghz": prof64.get("sclk_ghz"),
+                           "profile": prof64.get("profile"),
                            "pairs_per_s": pairs / (ms64s * 1e-3), "ms_per_step": ms64s,
                            "tflops": FLOPS_PER_PAIR * pairs / (ms64s * 1e-3) / 1e12,
                            "frac_fp64_peak": FLOPS_PER_PAIR * pairs / (ms64s * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
