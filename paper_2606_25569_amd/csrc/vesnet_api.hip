@@ -662,7 +662,8 @@ size_t plan_bytes(int32_t S) { return align_up((size_t)(4 * (size_t)S + 2) * siz
 
 // The batched symmetric form's tables: per-suspension (cycles, blocks, exponent), first units and points.
 size_t symb_bytes(int32_t S) {
-  return align_up((size_t)S * sizeof(int4)) + 2 * align_up((size_t)(S + 1) * sizeof(int32_t));
+  return align_up((size_t)S * sizeof(int4)) + 2 * align_up((size_t)(S + 1) * sizeof(int32_t)) +
+         align_up((size_t)S * sizeof(int2));
 }
 
 SymBatchView carve_symb(char*& cur, int32_t S) {
@@ -673,6 +674,8 @@ SymBatchView carve_symb(char*& cur, int32_t S) {
   cur += align_up((size_t)(S + 1) * sizeof(int32_t));
   bv.pstart = reinterpret_cast<int32_t*>(cur);
   cur += align_up((size_t)(S + 1) * sizeof(int32_t));
+  bv.vr = reinterpret_cast<int2*>(cur);
+  cur += align_up((size_t)S * sizeof(int2));
   return bv;
 }
 

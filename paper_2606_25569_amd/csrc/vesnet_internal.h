@@ -129,6 +129,7 @@ struct SymBatchView {
   int4* stab;       // [S]   per suspension: (first cycle, end cycle, blocks, fixed-point exponent)
   int32_t* ustart;  // [S+1] first unit of each suspension
   int32_t* pstart;  // [S+1] first point of each suspension
+  int2* vr;         // [S]   vesicle range of each suspension, clamped, disjoint and non-decreasing
 };
 
 // Device views of the batched work plan.

@@ -731,17 +731,50 @@ __device__ __forceinline__ int wave_scan_incl(int x, int lane) {
 // first unit, pstart[s] its first point (ustart[S], pstart[S]: totals); the cycle table; meta[0] the
 // number of cycles, the XCD queues and their zeroed counters.  One workgroup of 1024 threads, in a fixed
 // order; the exponent of a suspension is the one the single-suspension plan gives it.
+// The suspensions' vesicle ranges are first clamped to [0, M] and made disjoint and non-decreasing
+// (vr[s] = (v0, v1), v0 = max(offset s, every earlier end), v1 = max(offset s + 1, v0)): valid offsets are
+// unchanged, and no input can make the cycles outrun their table.
 __global__ __launch_bounds__(1024) void k_symb_plan(const int2* __restrict__ vrange, const double2* __restrict__ vaux,
-                                                    const int32_t* __restrict__ sus_off,
-                                                    const int32_t* __restrict__ off, int nsus, int cb, int ncyc_max,
-                                                    int4* __restrict__ cyc, int4* __restrict__ stab,
-                                                    int32_t* __restrict__ ustart, int32_t* __restrict__ pstart,
+                                                    const int32_t* __restrict__ sus_off, int M, int P, int nsus,
+                                                    int cb, int ncyc_max, int4* __restrict__ cyc,
+                                                    int4* __restrict__ stab, int32_t* __restrict__ ustart,
+                                                    int32_t* __restrict__ pstart, int2* __restrict__ vr,
                                                     int32_t* __restrict__ meta) {
   __shared__ int s_wc[16], s_wu[16];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  // disjoint, non-decreasing vesicle ranges (a running maximum of the clamped ends)
+  int pm = 0;
+  for (int base = 0; base < nsus; base += 1024) {
+    const int s = base + t;
+    const int a = s < nsus ? min(max(sus_off[s], 0), M) : 0;
+    const int b = s < nsus ? min(max(sus_off[s + 1], 0), M) : 0;
+    int x = b;  // inclusive running maximum of the ends within the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x = max(x, y);
+    }
+    if (lane == 63) s_wc[wv] = x;
+    __syncthreads();
+    int pre = pm, tot = pm;
+    for (int k = 0; k < 16; ++k) {
+      pre = k < wv ? max(pre, s_wc[k]) : pre;
+      tot = max(tot, s_wc[k]);
+    }
+    int ex = __shfl_up(x, 1, 64);  // the maximum over the earlier lanes of this wavefront
+    ex = lane == 0 ? pre : max(pre, ex);
+    if (s < nsus) {
+      const int v0 = max(a, ex);
+      vr[s] = make_int2(v0, max(b, v0));
+    }
+    pm = tot;
+    __syncthreads();
+  }
+  __syncthreads();
   // cycles and the bound of the partial sums of each suspension, one wavefront per suspension
   for (int s = wv; s < nsus; s += 16) {
-    const int v0 = sus_off[s], v1 = sus_off[s + 1];
+    const int2 rs = vr[s];
+    const int v0 = rs.x, v1 = rs.y;
     int cnt = 0;
     double fs = 0.0;
     for (int v = v0 + lane; v < v1; v += 64) {
@@ -787,7 +820,8 @@ __global__ __launch_bounds__(1024) void k_symb_plan(const int2* __restrict__ vra
       const int c0 = runc + prec_ + xc - st.x;
       stab[s] = make_int4(c0, c0 + st.x, st.z, st.w);
       ustart[s] = runu + preu + xu - nu;
-      pstart[s] = off[sus_off[s]];
+      const int v0 = vr[s].x;
+      pstart[s] = v0 < M ? vrange[v0].x : P;
     }
     runc += totc;
     runu += totu;
@@ -795,7 +829,7 @@ __global__ __launch_bounds__(1024) void k_symb_plan(const int2* __restrict__ vra
   }
   if (t == 0) {
     ustart[nsus] = runu;
-    pstart[nsus] = off[sus_off[nsus]];
+    pstart[nsus] = P;
     meta[0] = min(runc, ncyc_max);
     meta[kMetaUnits] = runu;
     const int q = runu / kXcds, r = runu % kXcds;
@@ -805,7 +839,8 @@ __global__ __launch_bounds__(1024) void k_symb_plan(const int2* __restrict__ vra
   __syncthreads();
   // the cycles of every vesicle, one wavefront per suspension
   for (int s = wv; s < nsus; s += 16) {
-    const int v0 = sus_off[s], v1 = sus_off[s + 1];
+    const int2 rs = vr[s];
+    const int v0 = rs.x, v1 = rs.y;
     int c = stab[s].x;
     for (int vb = v0; vb < v1; vb += 64) {
       const int v = vb + lane;
@@ -1613,8 +1648,8 @@ hipError_t launch_batched_symmetric(int T, int grid, int P, int M, const Prepare
   hipStream_t st = Sx_(stream);
   const int cb = sym_cycles_per_block(T);
   const int ncyc_max = (int)sym_max_cycles(P, M);
-  hipLaunchKernelGGL(k_symb_plan, dim3(1), dim3(1024), 0, st, pv.vrange, pv.vaux, sus_off, off, S, cb, ncyc_max,
-                     sv.cyc, bv.stab, bv.ustart, bv.pstart, sv.meta);
+  hipLaunchKernelGGL(k_symb_plan, dim3(1), dim3(1024), 0, st, pv.vrange, pv.vaux, sus_off, M, P, S, cb, ncyc_max,
+                     sv.cyc, bv.stab, bv.ustart, bv.pstart, bv.vr, sv.meta);
   const int cgrid = (int)std::min<int64_t>((2 * (int64_t)P + 255) / 256, 4096);
   hipLaunchKernelGGL(k_sym_cycles, dim3(cgrid), dim3(256), 0, st, sv.cyc, sv.meta, pv.f64, P, sv.fcyc, sv.acc);
   const float4* rec = static_cast<const float4*>(pv.rec);
