@@ -49,8 +49,9 @@ def test_noalloc_matches_workspace_entry_two_calls():
         err, _ = rel_err(_noalloc(V, X, T, f, w, part, s.mu, "fp32c"), ref)
         say(f"noalloc P={s.n_points} separate targets: {err:.3e}")
         assert err <= BARS["fp32c"]
-        cfg = {"pair_form": 2, "targets_per_thread": 1}
-        ref = V.farfield_forward(X, X, f, w, part, s.mu, precision="fp32c", config=cfg).cpu().numpy()
-        got = _noalloc(V, X, X, f, w, part, s.mu, "fp32c", cfg)
-        say(f"noalloc P={s.n_points} symmetric: bitwise {np.array_equal(got, ref)}")
-        assert np.array_equal(got, ref)
+        for prec in ("fp32c", "fp64"):  # the symmetric forms add fixed-point integers: equal bit for bit
+            cfg = {"pair_form": 2, "targets_per_thread": 1}
+            ref = V.farfield_forward(X, X, f, w, part, s.mu, precision=prec, config=cfg).cpu().numpy()
+            got = _noalloc(V, X, X, f, w, part, s.mu, prec, cfg)
+            say(f"noalloc P={s.n_points} symmetric {prec}: bitwise {np.array_equal(got, ref)}")
+            assert np.array_equal(got, ref)
