@@ -168,7 +168,7 @@ def main():
     symmetric = args.form == "symmetric"
     cfg.pair_form = 2 if symmetric else 1
     if symmetric and not args.tile:
-        cfg.targets_per_thread = 0  # the symmetric form's own default (two targets per thread)
+        cfg.targets_per_thread = 0  # the symmetric form's own default
     log(f"[bench] launch shape {cfg.as_dict()}")
     import ctypes
     cfg_ref = ctypes.byref(cfg)

@@ -73,7 +73,7 @@ typedef enum {
 
 /* Launch shape of the pair kernels.  A zero field selects the built-in default. */
 typedef struct {
-  int32_t targets_per_thread; /* 1, 2 or 4                                                    */
+  int32_t targets_per_thread; /* 1, 2 or 4 (symmetric form: see pair_form)                    */
   int32_t block_threads;      /* 64, 128 or 256                                               */
   int32_t source_splits;      /* >= 1: source vesicles split into this many chunks, reduced in
                                  a fixed order by a second kernel (bitwise deterministic)      */
@@ -99,8 +99,10 @@ typedef struct {
                                     both (the Stokeslet is even), halving the logarithms and
                                     reciprocals; the targets must be the points the workspace was
                                     prepared with (vesnet_farfield_stokeslet requires targets ==
-                                    sources).  targets_per_thread (compensated 1, 2, 4 or 8, float64
-                                    1 or 2; 0 = the default 2) sets its blocks of 256 T points (one
+                                    sources).  targets_per_thread (compensated 1, 2, 3, 4 or 8,
+                                    default 3; float64 1 or 2, default 2; the default drops to 2,
+                                    then 1, for problems too small for four units per compute
+                                    unit) sets its blocks of 256 T points (one
                                     256-thread workgroup per pair of blocks); block_threads,
                                     source_splits and source_staging are unused.  The automatic
                                     choice always uses the default.  Its partial sums are added as
@@ -367,7 +369,7 @@ VESNET_API int vesnet_farfield_fmm_nearmasked(const double* points, const double
    * symmetric (VESNET_FP32_COMPENSATED, targets == sources, pair_form 0 or 2):
      the single call's symmetric form for every suspension in one persistent
      launch.  A plan kernel cuts each suspension into blocks of 256 T points
-     (T = targets_per_thread: 1, 2 or 4 when pair_form is 2, else the single
+     (T = targets_per_thread: 1, 2, 3 or 4 when pair_form is 2, else the single
      call's default for the total point count) that never reach into another
      suspension; the unordered pairs of a suspension's blocks are its units,
      numbered suspension by suspension and split into eight contiguous queues,

@@ -117,12 +117,13 @@ struct Shape {
   int symT;  // targets per thread of the symmetric form (0: too few units for it)
 };
 
-// Targets per thread of the symmetric form: 2 (the fastest measured on the 2000 x 128 suspension:
-// 15.7 ms against 17.1 ms at 4 and 17.7 ms at 1), or 1 when 2 gives fewer than four units per
-// compute unit (a unit is one workgroup of 256 threads on one pair of blocks of 256 T points),
-// estimated with vesicles of a multiple of 16 points; 0 when even 1 gives fewer (direct form).
-int sym_default_T(int32_t P) {
-  for (int T : {2, 1}) {
+// Targets per thread of the symmetric form: the largest of `top`, 2 and 1 that gives at least four units
+// per compute unit (a unit is one workgroup of 256 threads on one pair of blocks of 256 T points),
+// estimated with vesicles of a multiple of 16 points; 0 when even 1 gives fewer (direct form).  `top` is
+// 3 for the compensated forward (the fastest measured on the 2000 x 128 suspension: 14.9 ms against
+// 15.7 ms at 2, 17.1 ms at 4 and 17.7 ms at 1) and 2 for the float64 forward and the adjoints.
+int sym_default_T(int32_t P, int top) {
+  for (int T : {top, 2, 1}) {
     const int64_t cyc = (int64_t)P / 16;
     const int cb = sym_cycles_per_block(T);
     if (sym_units((cyc + cb - 1) / cb) >= 1024) return T;
@@ -147,7 +148,7 @@ Shape default_shape(int32_t P, int32_t M, int prec) {
   while (waves * splits < want && splits < 16) splits *= 2;
   s.splits = std::max(1, std::min<int>(splits, std::max(1, M)));
   s.pair = 0;
-  s.symT = has_symmetric(prec) ? sym_default_T(P) : 0;
+  s.symT = has_symmetric(prec) ? sym_default_T(P, prec == P32C ? 3 : 2) : 0;
   return s;
 }
 
@@ -165,11 +166,11 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     // the automatic choice keeps its own default
     if (cfg->targets_per_thread && cfg->pair_form == 2) s.symT = cfg->targets_per_thread;
   }
-  if (s.T != 1 && s.T != 2 && s.T != 4 && !(s.T == 8 && s.pair == 2))
-    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread must be 1, 2 or 4 (8 for the symmetric form; got %d)",
-                s.T);
-  if (s.symT != 1 && s.symT != 2 && s.symT != 4 && s.symT != 8 && s.symT != 0)
-    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread of the symmetric form must be 1, 2, 4 or 8");
+  if (s.T != 1 && s.T != 2 && s.T != 4 && !((s.T == 3 || s.T == 8) && s.pair == 2))
+    return fail(VESNET_ERR_INVALID_ARGUMENT,
+                "targets_per_thread must be 1, 2 or 4 (3 or 8 for the symmetric form; got %d)", s.T);
+  if (s.symT < 0 || s.symT > 8 || (s.symT > 4 && s.symT != 8))
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread of the symmetric form must be 1, 2, 3, 4 or 8");
   if (s.B != 64 && s.B != 128 && s.B != 256)
     return fail(VESNET_ERR_INVALID_ARGUMENT, "block_threads must be 64, 128 or 256 (got %d)", s.B);
   if (s.splits < 1 || s.splits > kMaxSplits)
@@ -719,16 +720,16 @@ bool batched_symmetric(const double* targets, const double* sources, int prec, c
 }
 
 // Targets per thread and workgroups of the batched symmetric form: the caller's targets_per_thread when
-// pair_form 2 asks for it (1, 2 or 4), else the single-suspension default for the total point count;
+// pair_form 2 asks for it (1, 2, 3 or 4), else the single-suspension default for the total point count;
 // blocks_per_cu when the caller sets it, else as many units as one compute unit holds.
 int batched_symmetric_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int32_t S, const Shape& s,
                             int* T, int* grid) {
   int t = s.symT ? s.symT : 1;
   if (t == 8) t = 4;
   if (cfg && cfg->pair_form == 2 && cfg->targets_per_thread) t = cfg->targets_per_thread;
-  if (t != 1 && t != 2 && t != 4)
-    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread of the batched symmetric form must be 1, 2 or 4");
-  while (t < 4 && symb_max_units(P, M, S, t) > (int64_t)INT32_MAX) t *= 2;
+  if (t < 1 || t > 4)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread of the batched symmetric form must be 1, 2, 3 or 4");
+  while (t < 4 && symb_max_units(P, M, S, t) > (int64_t)INT32_MAX) ++t;
   if (symb_max_units(P, M, S, t) > (int64_t)INT32_MAX)
     return fail(VESNET_ERR_UNSUPPORTED, "too many points for the batched symmetric form; use pair_form 1");
   const int bpc = cfg && cfg->blocks_per_cu ? cfg->blocks_per_cu : symb_units_per_cu(t);
@@ -943,7 +944,7 @@ namespace {
 // Targets per thread of the symmetric adjoint: the forward's choice, one when the problem is small,
 // four when the units of the smaller choice would not fit one launch; 0 when none fits (the gathers).
 int sym_bwd_T(int32_t P, int32_t M) {
-  const int T = sym_default_T(P);
+  const int T = sym_default_T(P, 2);
   if (sym_fits(P, M, T ? T : 1)) return T ? T : 1;
   return sym_fits(P, M, 4) ? 4 : 0;
 }
@@ -1085,7 +1086,7 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
         }
   }
   if (sym_ok) {
-    for (int T : {1, 2, 4, 8}) {
+    for (int T : {1, 2, 3, 4, 8}) {
       if (batched) {
         if (T == 8) continue;
         for (int bpc : {0, 2, 4, 8}) cands.push_back({T, 0, 0, bpc, 0, 1, 2});

@@ -19,8 +19,8 @@
 //    d = nb/2 are taken by bx < nb/2 only).  One workgroup of 256 threads (4 wavefronts, 16 rows
 //    of 16 lanes) evaluates a unit: row r holds target cycles r, r + 16, ... of block bx (T of
 //    them, one point per lane), and the source cycles of block by stream through LDS in chunks
-//    of 8 cycles.  With T = 2 (the default: 512-point blocks, 94 VGPRs, 27 KB of LDS) five units
-//    share a compute unit.
+//    of 8 cycles.  With T = 3 (the float32-compensated default: 768-point blocks, 112 VGPRs, 32 KB of
+//    LDS) four units share a compute unit; with T = 2 (512-point blocks, 94 VGPRs, 27 KB) five.
 //  * Each row is a ring: at step s lane p pairs its T targets with source (p + s) mod 16 of the
 //    current source cycle, read from LDS (each cycle is stored twice so that the address is the
 //    lane's base plus an immediate offset).  The source's column sum travels with it around the
@@ -858,7 +858,7 @@ __global__ __launch_bounds__(1024) void k_symb_plan(const int2* __restrict__ vra
 
 // Persistent batched kernel: units from the XCD queues until all are empty (see above).
 template <int T>
-__global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(T == 2 ? 5 : 1))) void k_symb_main(
+__global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(T == 2 ? 5 : T == 3 ? 4 : 1))) void k_symb_main(
     int P, const double4* __restrict__ vtab, const double2* __restrict__ vaux, const float4* __restrict__ rec,
     const int4* __restrict__ cyc, const double2* __restrict__ fcyc, const int4* __restrict__ stab,
     const int32_t* __restrict__ ustart, int nsus, int32_t* __restrict__ meta, unsigned long long* __restrict__ acc) {
@@ -1626,13 +1626,14 @@ int64_t symb_max_units(int P, int M, int S, int T) {
 // Cached after the first query (every device this library runs on is a gfx950).
 int symb_units_per_cu(int T) {
   static std::atomic<int> cache[5] = {};
-  if (T != 1 && T != 2 && T != 4) return 1;
+  if (T < 1 || T > 4) return 1;
   int n = cache[T].load(std::memory_order_relaxed);
   if (n > 0) return n;
   hipError_t e = hipErrorInvalidValue;
   switch (T) {
     case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_symb_main<1>, kSymThreads, 0); break;
     case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_symb_main<2>, kSymThreads, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_symb_main<3>, kSymThreads, 0); break;
     default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_symb_main<4>, kSymThreads, 0); break;
   }
   if (e != hipSuccess || n <= 0) return 1;
@@ -1659,7 +1660,7 @@ hipError_t launch_batched_symmetric(int T, int grid, int P, int M, const Prepare
     hipLaunchKernelGGL(k_symb_main<TT>, dim3(grid), dim3(kSymThreads), 0, st, P, pv.vtab, pv.vaux, rec, sv.cyc, \
                        sv.fcyc, bv.stab, bv.ustart, S, sv.meta, sv.acc);                                          \
     break;
-    VESNET_SYMB_MAIN(1) VESNET_SYMB_MAIN(2) VESNET_SYMB_MAIN(4)
+    VESNET_SYMB_MAIN(1) VESNET_SYMB_MAIN(2) VESNET_SYMB_MAIN(3) VESNET_SYMB_MAIN(4)
 #undef VESNET_SYMB_MAIN
     default: return hipErrorInvalidValue;
   }
@@ -1713,7 +1714,7 @@ hipError_t launch_forward_symmetric(int T, int P, int M, const PreparedView& pv,
     hipLaunchKernelGGL(k_sym_main<TT>, grid, dim3(kSymThreads), 0, st, P, pv.vtab, pv.vaux, rec, sv.cyc,      \
                        sv.fcyc, sv.meta, sv.acc);                                                               \
     break;
-    VESNET_SYM_CASE(1) VESNET_SYM_CASE(2) VESNET_SYM_CASE(4) VESNET_SYM_CASE(8)
+    VESNET_SYM_CASE(1) VESNET_SYM_CASE(2) VESNET_SYM_CASE(3) VESNET_SYM_CASE(4) VESNET_SYM_CASE(8)
 #undef VESNET_SYM_CASE
     default: return hipErrorInvalidValue;
   }

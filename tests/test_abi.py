@@ -353,6 +353,12 @@ def test_symmetric_form_rejects(L):
     cfg.targets_per_thread = 4
     assert _fwd(L, cfg=ctypes.byref(cfg), prec=0, sources=FAKE) == L.ERR_INVALID_ARGUMENT
     assert lib.vesnet_farfield_workspace_bytes(10, 2, 0, ctypes.byref(cfg)) == 0
+    cfg.targets_per_thread = 3                                                # compensated only
+    assert lib.vesnet_farfield_workspace_bytes(10, 2, 0, ctypes.byref(cfg)) == 0
+    assert lib.vesnet_farfield_workspace_bytes(10, 2, 1, ctypes.byref(cfg)) > 0
+    for bad in (5, 6, 7, 9, -1):
+        cfg.targets_per_thread = bad
+        assert lib.vesnet_farfield_workspace_bytes(10, 2, 1, ctypes.byref(cfg)) == 0
     cfg.targets_per_thread = 2
     assert lib.vesnet_farfield_workspace_bytes(10, 2, 0, ctypes.byref(cfg)) > 0
     cfg.targets_per_thread = 0

@@ -137,7 +137,7 @@ def _ragged_batch():
     return members
 
 
-@pytest.mark.parametrize("T", [1, 2, 4])
+@pytest.mark.parametrize("T", [1, 2, 3, 4])
 def test_symmetric_batch_equals_single_symmetric_calls(V, T):
     """The batched symmetric form (the default for one compensated point array) on a small batch: the
     oracle per suspension, and one symmetric call per suspension of the same T bit for bit (fixed-point
@@ -162,7 +162,7 @@ def test_symmetric_batch_ragged(V):
     mus = [0.5 + 0.01 * (k % 50) for k in range(len(members))]
     b = S.batch_of(members, mus)
     X, f, w = _dev(b)
-    for T in (1, 2):
+    for T in (1, 2, 3):
         bp = V.BatchedProblem(X, X, f, w, b.vesicle_offsets, b.suspension_offsets, b.mu, precision="fp32c",
                               config={"pair_form": 2, "targets_per_thread": T})
         out = bp.run().cpu().numpy()
@@ -197,8 +197,9 @@ def test_config3_batched_vs_loop(V):
     refs = _per_suspension_oracle(b, frac=0.01, seed=3000)
     worst = _check_against(b, out, refs, 1e-5)
     say(f"cfg3 batched fp32c worst rel err {worst:.3e}")
-    # the default batched form takes two targets per thread at this size, as a single call would
-    np.testing.assert_array_equal(out, _single_symmetric(V, X, f, w, b, 2))
+    # the default batched form takes three targets per thread at this size (the single call's default for
+    # the total point count)
+    np.testing.assert_array_equal(out, _single_symmetric(V, X, f, w, b, 3))
     say("cfg3 batched equals the per-suspension loop bit for bit")
     bp.capture()
     for r in range(3):
@@ -226,7 +227,7 @@ def test_autotune_returns_valid_shape(V):
     best, ms = V.autotune(X, X, f, w, s.offsets, 1.0, "fp32c", repeats=2, store=False)
     d = best.as_dict()
     if d["pair_form"] == 2:  # the symmetric form: targets per thread only
-        assert d["targets_per_thread"] in (1, 2, 4, 8) and ms > 0
+        assert d["targets_per_thread"] in (1, 2, 3, 4, 8) and ms > 0
     else:
         assert d["targets_per_thread"] in (1, 2, 4) and d["block_threads"] in (64, 128, 256) and ms > 0
     ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, 1.0)

@@ -51,7 +51,7 @@ def _ragged_suspension(seed=77, sizes=None, spacing=4.0):
     return S._assemble(rng, centers, axes, angles, np.array(sizes), "k4", 0.05, 1.3, spacing * side)
 
 
-@pytest.mark.parametrize("T", [1, 2, 4, 8])
+@pytest.mark.parametrize("T", [1, 2, 3, 4, 8])
 def test_config0(V, T):
     s = S.make_config(0)
     ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
@@ -60,7 +60,7 @@ def test_config0(V, T):
     assert err <= BAR
 
 
-@pytest.mark.parametrize("T", [1, 2, 4, 8])
+@pytest.mark.parametrize("T", [1, 2, 3, 4, 8])
 def test_ragged_partition(V, T):
     """Empty, single-point and odd-sized vesicles; one block holds the whole suspension."""
     s = _ragged_suspension()
@@ -81,7 +81,7 @@ def test_many_blocks_odd_and_even(V, m):
     ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
     cycles = int(sum((n + 15) // 16 for n in sizes))
     say(f"symmetric many blocks: P={s.n_points} cycles={cycles} blocks(T=1)={(cycles + 15) // 16}")
-    for T in (1, 2):
+    for T in (1, 2, 3):
         err, _ = rel_err(_sym(V, s, T), ref)
         say(f"  T={T}: {err:.3e}")
         assert err <= BAR
@@ -95,7 +95,7 @@ def test_vesicle_larger_than_block(V):
     axes = np.array([[10.0, 4.0], [1.2, 0.5], [6.0, 3.0], [1.3, 0.4]])
     s = S._assemble(rng, centers, axes, rng.uniform(0, 6.28, 4), sizes, "k4", 0.2, 1.0, 40.0)
     ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
-    for T in (1, 4):
+    for T in (1, 3, 4):
         err, _ = rel_err(_sym(V, s, T), ref)
         say(f"symmetric large vesicle T={T}: {err:.3e}")
         assert err <= BAR
