@@ -100,7 +100,7 @@ typedef struct {
                                     reciprocals; the targets must be the points the workspace was
                                     prepared with (vesnet_farfield_stokeslet requires targets ==
                                     sources).  targets_per_thread (compensated 1, 2, 3, 4 or 8,
-                                    default 3; float64 1 or 2, default 2; the default drops to 2,
+                                    default 3; float64 1, 2, 3 or 4, default 4; the default drops to 2,
                                     then 1, for problems too small for four units per compute
                                     unit) sets its blocks of 256 T points (one
                                     256-thread workgroup per pair of blocks); block_threads,

@@ -120,8 +120,9 @@ struct Shape {
 // Targets per thread of the symmetric form: the largest of `top`, 2 and 1 that gives at least four units
 // per compute unit (a unit is one workgroup of 256 threads on one pair of blocks of 256 T points),
 // estimated with vesicles of a multiple of 16 points; 0 when even 1 gives fewer (direct form).  `top` is
-// 3 for the compensated forward (the fastest measured on the 2000 x 128 suspension: 14.9 ms against
-// 15.7 ms at 2, 17.1 ms at 4 and 17.7 ms at 1) and 2 for the float64 forward and the adjoints.
+// the fastest measured on the 2000 x 128 suspension: 3 for the compensated forward (14.9 ms against
+// 15.7 ms at 2, 17.1 ms at 4 and 17.7 ms at 1), 4 for the float64 forward (41.7 ms against 42.3 ms at 3
+// and 43.4 ms at 2), and 2 for the adjoints.
 int sym_default_T(int32_t P, int top) {
   for (int T : {top, 2, 1}) {
     const int64_t cyc = (int64_t)P / 16;
@@ -148,7 +149,7 @@ Shape default_shape(int32_t P, int32_t M, int prec) {
   while (waves * splits < want && splits < 16) splits *= 2;
   s.splits = std::max(1, std::min<int>(splits, std::max(1, M)));
   s.pair = 0;
-  s.symT = has_symmetric(prec) ? sym_default_T(P, prec == P32C ? 3 : 2) : 0;
+  s.symT = has_symmetric(prec) ? sym_default_T(P, prec == P32C ? 3 : 4) : 0;
   return s;
 }
 
@@ -187,8 +188,8 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     return fail(VESNET_ERR_INVALID_ARGUMENT, "pair_form must be 0, 1 or 2 (got %d)", s.pair);
   if (s.pair == 2 && !has_symmetric(prec))
     return fail(VESNET_ERR_UNSUPPORTED, "the symmetric pair form exists for the compensated and float64 forms only");
-  if (s.pair == 2 && prec == P64 && s.symT > 2)
-    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread of the float64 symmetric form must be 1 or 2");
+  if (s.pair == 2 && prec == P64 && s.symT > 4)
+    return fail(VESNET_ERR_INVALID_ARGUMENT, "targets_per_thread of the float64 symmetric form must be 1, 2, 3 or 4");
   if (s.pair == 2 && s.accumulate == 2)
     return fail(VESNET_ERR_UNSUPPORTED, "the symmetric pair form accumulates on the VALU only");
   if (s.pair == 2 && s.symT == 0) s.symT = 1;
@@ -196,7 +197,7 @@ int resolve_shape(const vesnet_tile_config* cfg, int32_t P, int32_t M, int prec,
     if (s.pair == 2)
       return fail(VESNET_ERR_UNSUPPORTED, "too many points for the symmetric form at %d targets per thread (its "
                   "units exceed one launch); use more targets per thread or the direct form", s.symT);
-    s.symT = prec == P64 ? 0 : sym_fits(P, M, 4) ? 4 : sym_fits(P, M, 8) ? 8 : 0;
+    s.symT = sym_fits(P, M, 4) ? 4 : prec != P64 && sym_fits(P, M, 8) ? 8 : 0;
   }
   *out = s;
   return VESNET_OK;
@@ -1091,7 +1092,7 @@ extern "C" int vesnet_autotune(const double* targets, const double* sources, con
         if (T == 8) continue;
         for (int bpc : {0, 2, 4, 8}) cands.push_back({T, 0, 0, bpc, 0, 1, 2});
       } else {
-        if (prec == VESNET_FP64 && T > 2) continue;
+        if (prec == VESNET_FP64 && T > 4) continue;
         if (!sym_fits(P, M, T)) continue;
         const Shape sh{T, 256, 1, 1, 2, 1, 2, T};
         if (forward_bytes(P, M, prec, sh) > ws_bytes) continue;

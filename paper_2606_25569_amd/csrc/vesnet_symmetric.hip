@@ -1688,6 +1688,8 @@ hipError_t launch_forward_symmetric64(int T, int P, int M, const PreparedView& p
   switch (T) {
     case 1: hipLaunchKernelGGL(k_sym64_main<1>, grid, dim3(kSymThreads), 0, st, P, rec, sv.cyc, sv.meta, sv.acc); break;
     case 2: hipLaunchKernelGGL(k_sym64_main<2>, grid, dim3(kSymThreads), 0, st, P, rec, sv.cyc, sv.meta, sv.acc); break;
+    case 3: hipLaunchKernelGGL(k_sym64_main<3>, grid, dim3(kSymThreads), 0, st, P, rec, sv.cyc, sv.meta, sv.acc); break;
+    case 4: hipLaunchKernelGGL(k_sym64_main<4>, grid, dim3(kSymThreads), 0, st, P, rec, sv.cyc, sv.meta, sv.acc); break;
     default: return hipErrorInvalidValue;
   }
   const int64_t n = 2 * (int64_t)P;

@@ -344,18 +344,20 @@ def test_naive_precision_has_no_backward(L):
 
 def test_symmetric_form_rejects(L):
     """pair_form 2 (one evaluation per unordered pair) needs targets == sources and the compensated or
-    float64 precision (float64: one or two targets per thread); bad pair_form values are refused."""
+    float64 precision (float64: one to four targets per thread); bad pair_form values are refused."""
     lib = L.lib()
     cfg = L.TileConfig()
     cfg.pair_form = 2
     assert _fwd(L, cfg=ctypes.byref(cfg)) == L.ERR_INVALID_ARGUMENT          # targets != sources
     assert _fwd(L, cfg=ctypes.byref(cfg), prec=2, sources=FAKE) == L.ERR_UNSUPPORTED
-    cfg.targets_per_thread = 4
+    cfg.targets_per_thread = 8                                                # compensated only
     assert _fwd(L, cfg=ctypes.byref(cfg), prec=0, sources=FAKE) == L.ERR_INVALID_ARGUMENT
     assert lib.vesnet_farfield_workspace_bytes(10, 2, 0, ctypes.byref(cfg)) == 0
-    cfg.targets_per_thread = 3                                                # compensated only
-    assert lib.vesnet_farfield_workspace_bytes(10, 2, 0, ctypes.byref(cfg)) == 0
     assert lib.vesnet_farfield_workspace_bytes(10, 2, 1, ctypes.byref(cfg)) > 0
+    for t in (3, 4):
+        cfg.targets_per_thread = t
+        assert lib.vesnet_farfield_workspace_bytes(10, 2, 0, ctypes.byref(cfg)) > 0
+        assert lib.vesnet_farfield_workspace_bytes(10, 2, 1, ctypes.byref(cfg)) > 0
     for bad in (5, 6, 7, 9, -1):
         cfg.targets_per_thread = bad
         assert lib.vesnet_farfield_workspace_bytes(10, 2, 1, ctypes.byref(cfg)) == 0

@@ -132,7 +132,7 @@ def test_bitwise_repeatable(V):
 
 def test_automatic_choice_and_errors(V):
     """The automatic form equals the forced symmetric form where it is chosen; the symmetric form
-    refuses separate target and source arrays, the naive precision, and more than two targets per
+    refuses separate target and source arrays, the naive precision, and more than four targets per
     thread in float64."""
     import torch
     s = S.make_config(0)
@@ -144,7 +144,7 @@ def test_automatic_choice_and_errors(V):
         V.farfield_forward(X, X, f, w, s.offsets, s.mu, precision="fp32", config={"pair_form": 2})
     with pytest.raises(V.VesnetError):
         V.farfield_forward(X, X, f, w, s.offsets, s.mu, precision="fp64",
-                           config={"pair_form": 2, "targets_per_thread": 4})
+                           config={"pair_form": 2, "targets_per_thread": 8})
     # separate arrays with the automatic form take the direct form
     out = V.farfield_forward(T, X, f, w, s.offsets, s.mu, precision="fp32c")
     torch.cuda.synchronize()

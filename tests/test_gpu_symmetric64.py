@@ -36,7 +36,7 @@ def _sym64(V, s, T=None):
     return out.cpu().numpy()
 
 
-@pytest.mark.parametrize("T", [1, 2])
+@pytest.mark.parametrize("T", [1, 2, 3, 4])
 def test_config0(V, T):
     s = S.make_config(0)
     ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
@@ -45,7 +45,7 @@ def test_config0(V, T):
     assert err <= BAR
 
 
-@pytest.mark.parametrize("T", [1, 2])
+@pytest.mark.parametrize("T", [1, 2, 3, 4])
 def test_ragged_partition(V, T):
     """Empty, single-point and odd-sized vesicles; one block holds the whole suspension."""
     s = _ragged_suspension()
@@ -62,21 +62,21 @@ def test_many_blocks_odd_and_even(V, m):
     sizes = list(rng.integers(1, 90, size=m))
     s = _ragged_suspension(seed=m, sizes=sizes, spacing=4.5)
     ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
-    for T in (1, 2):
+    for T in (1, 2, 3, 4):
         err, _ = rel_err(_sym64(V, s, T), ref)
         say(f"symmetric fp64 many blocks m={m} T={T}: {err:.3e}")
         assert err <= BAR
 
 
 def test_vesicle_larger_than_block(V):
-    """A vesicle of 2500 points covers several blocks of 256 and 512 points."""
+    """A vesicle of 2500 points covers several blocks of 256, 512 and 1024 points."""
     rng = np.random.default_rng(8)
     sizes = np.array([2500, 7, 1030, 33])
     centers = np.array([[0.0, 0.0], [30.0, 0.0], [0.0, 30.0], [30.0, 30.0]])
     axes = np.array([[10.0, 4.0], [1.2, 0.5], [6.0, 3.0], [1.3, 0.4]])
     s = S._assemble(rng, centers, axes, rng.uniform(0, 6.28, 4), sizes, "k4", 0.2, 1.0, 40.0)
     ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
-    for T in (1, 2):
+    for T in (1, 2, 4):
         err, _ = rel_err(_sym64(V, s, T), ref)
         say(f"symmetric fp64 large vesicle T={T}: {err:.3e}")
         assert err <= BAR
