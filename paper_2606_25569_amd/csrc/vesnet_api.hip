@@ -121,8 +121,8 @@ struct Shape {
 // per compute unit (a unit is one workgroup of 256 threads on one pair of blocks of 256 T points),
 // estimated with vesicles of a multiple of 16 points; 0 when even 1 gives fewer (direct form).  `top` is
 // the fastest measured on the 2000 x 128 suspension: 3 for the compensated forward (14.9 ms against
-// 15.7 ms at 2, 17.1 ms at 4 and 17.7 ms at 1), 4 for the float64 forward (41.7 ms against 42.3 ms at 3
-// and 43.4 ms at 2), and 2 for the adjoints.
+// 15.7 ms at 2, 17.1 ms at 4 and 17.7 ms at 1) and adjoint (31.3 ms against 32.2 ms at 2 and 36.6 ms at
+// 4), 4 for the float64 forward (41.7 ms against 42.3 ms at 3 and 43.4 ms at 2).
 int sym_default_T(int32_t P, int top) {
   for (int T : {top, 2, 1}) {
     const int64_t cyc = (int64_t)P / 16;
@@ -942,10 +942,10 @@ extern "C" int vesnet_farfield_stokeslet_backward(const double* targets, const d
 // Adjoint for one point array (targets = sources = points, positions differentiated in both roles).
 namespace {
 
-// Targets per thread of the symmetric adjoint: the forward's choice, one when the problem is small,
+// Targets per thread of the symmetric adjoint: the forward's rule, one when the problem is small,
 // four when the units of the smaller choice would not fit one launch; 0 when none fits (the gathers).
 int sym_bwd_T(int32_t P, int32_t M) {
-  const int T = sym_default_T(P, 2);
+  const int T = sym_default_T(P, 3);
   if (sym_fits(P, M, T ? T : 1)) return T ? T : 1;
   return sym_fits(P, M, 4) ? 4 : 0;
 }

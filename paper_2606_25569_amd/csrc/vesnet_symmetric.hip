@@ -1571,7 +1571,7 @@ hipError_t launch_backward_symmetric(int T, int P, int M, const PreparedView& pv
     hipLaunchKernelGGL(k_sym_bwd<TT>, grid, dim3(kSymThreads), 0, st, pvF.vtab, pvF.vaux, recF, recG, sv.cyc,  \
                        sv.fcyc, sv.meta, P, grad_points, vsum);                                                 \
     break;
-    VESNET_SYMB_CASE(1) VESNET_SYMB_CASE(2) VESNET_SYMB_CASE(4)
+    VESNET_SYMB_CASE(1) VESNET_SYMB_CASE(2) VESNET_SYMB_CASE(3) VESNET_SYMB_CASE(4)
 #undef VESNET_SYMB_CASE
     default: return hipErrorInvalidValue;
   }

@@ -5,7 +5,7 @@ Under fp32c and fp64 each unordered pair of points in different vesicles is eval
 symmetric forms of the forward; float64 on global coordinates); the two gathers remain for separate
 target and source arrays (tests/test_gpu_backward.py).
 Bars: 1e-5 (fp32c) and 1e-12 (fp64) in max-norm error relative to the largest component, per
-output.  The cases cover one and two targets per thread (small problems take one), ragged and
+output.  The cases cover one, two and three targets per thread (small problems take one), ragged and
 empty vesicles, vesicles longer than a block, several blocks of both parities, a translated
 suspension, the partial requests and the zero cases.
 """
@@ -111,6 +111,19 @@ def test_config4_sampled(V, prec):
     sel = S.sample_targets(s.n_points, 400 / s.n_points, 4141)
     ref = O.grad_suspension(s.X, s.f, s.w, s.offsets, s.mu, g, select=sel)
     _check(s, _points(V, s, g, prec), ref, prec, "cfg4", sel)
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_default_shape_of_large_problems(V, prec):
+    """About 38,000 points in 400 vesicles of 60 .. 129 points: large enough for the compensated adjoint's
+    three targets per thread (768-point blocks, at least four units per compute unit), 400 sampled points."""
+    rng = np.random.default_rng(21)
+    s = _ragged_suspension(seed=21, sizes=list(rng.integers(60, 130, size=400)), spacing=4.5)
+    g = _g(s, 21)
+    sel = S.sample_targets(s.n_points, 400 / s.n_points, 2121)
+    ref = O.grad_suspension(s.X, s.f, s.w, s.offsets, s.mu, g, select=sel)
+    say(f"large adjoint: P={s.n_points}")
+    _check(s, _points(V, s, g, prec), ref, prec, "large", sel)
 
 
 @pytest.mark.parametrize("prec", ["fp32c", "fp64"])
