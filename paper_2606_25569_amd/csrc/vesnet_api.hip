@@ -950,9 +950,14 @@ int sym_bwd_T(int32_t P, int32_t M) {
   return sym_fits(P, M, 4) ? 4 : 0;
 }
 
-// Targets per thread of the float64 symmetric adjoint: one (126 VGPRs, four wavefronts per SIMD; two
-// need 200), two when the units of one would not fit a launch; 0: the gathers.
-int sym64_bwd_T(int32_t P, int32_t M) { return sym_fits(P, M, 1) ? 1 : sym_fits(P, M, 2) ? 2 : 0; }
+// Targets per thread of the float64 symmetric adjoint: two where they give at least four units per compute
+// unit (200 VGPRs, two wavefronts per SIMD: 69.4 ms against 74.6 ms at one on 2000 x 128, equal at
+// 512 x 64), else one (126 VGPRs); two when the units of one would not fit a launch; 0: the gathers.
+int sym64_bwd_T(int32_t P, int32_t M) {
+  const int T = sym_default_T(P, 2);
+  if (sym_fits(P, M, T ? T : 1)) return T ? T : 1;
+  return sym_fits(P, M, 2) ? 2 : 0;
+}
 
 int points_bwd_T(int32_t P, int32_t M, int prec) {
   return prec == VESNET_FP32_COMPENSATED ? sym_bwd_T(P, M) : prec == VESNET_FP64 ? sym64_bwd_T(P, M) : 0;
