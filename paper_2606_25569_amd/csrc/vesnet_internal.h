@@ -32,12 +32,14 @@ __device__ inline double wave_mean_spacing(const double* __restrict__ w, int n) 
 
 // ---- float64 reciprocal and logarithm without division (used by the float64 pair loops and the trees)
 
-// 1 / x for finite x != 0: the hardware estimate refined by two Newton steps (each doubles the correct
-// bits; the result is within an ulp or so of the correctly rounded quotient).
+// 1 / x for finite x != 0 whose reciprocal is a normal number: the hardware estimate r0 (relative error
+// measured below 5e-8 on gfx950) refined by one third-order step, r0 (1 + e + e^2) with e = 1 - x r0 (the
+// exact reciprocal is r0 / (1 - e)): three FMAs leave a truncation of order e^3 < 1e-22 and about one
+// rounding, within an ulp or so of the correctly rounded quotient, as two Newton steps (four FMAs) do.
 __device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 
 // Natural log of a finite q > 0, in about 20 FP64 operations: q = m 2^e with m in [1/sqrt 2, sqrt 2),
@@ -70,27 +72,26 @@ __device__ __forceinline__ double log_pos(double q) {
   return fma((double)e, kLn2Hi, fma((double)e, kLn2Lo, 2.0 * s * pol));
 }
 
-// Table of the reduced log below: entry i (mantissa interval [1 + i/64, 1 + (i+1)/64)) holds a 10-bit
-// approximation a of 1 / (1 + (i + 0.5) / 64) and -ln a (from log_pos).  One entry per lane.
+// Table of the reduced log below: entry i (mantissa interval [1 + i/64, 1 + (i+1)/64)) holds 2a, with a
+// a 10-bit approximation of 1 / (1 + (i + 0.5) / 64), and -ln 2a (from log_pos).  One entry per lane.
 constexpr int kLogTab = 64;
 __device__ __forceinline__ double2 log_tab_entry(int i) {
   const double c = 1.0 + ((double)i + 0.5) / 64.0;
-  const double a = rint(512.0 / c) / 512.0;
-  return make_double2(a, -log_pos(a));
+  const double a2 = rint(512.0 / c) / 256.0;
+  return make_double2(a2, -log_pos(a2));
 }
 
-// Natural log of a finite q > 0 with the table: q = m 2^e, m in [1, 2); r = m a - 1 (exact product, one
-// rounding), |r| < 0.009, ln m = -ln a + log1p(r), log1p by its series through r^7 (the next term is
-// below 5e-18); ln 2 in a high and a low part as in log_pos.  About 20 operations, no division.
+// Natural log of a finite q > 0 with the table: q = mant 2^e, mant in [1/2, 1); r = mant (2a) - 1 (exact
+// product, one rounding), |r| < 0.009, ln mant = -ln 2a + log1p(r), log1p by its series through r^7 (the
+// next term is below 5e-18); ln 2 in a high and a low part as in log_pos.  About 18 operations, no division.
 __device__ __forceinline__ double log_reduced(double q, const double2* __restrict__ tab) {
   constexpr double kLn2Hi = 6.93147180369123816490e-01;
   constexpr double kLn2Lo = 1.90821492927058770002e-10;
   int e;
   const double mant = frexp(q, &e);  // [0.5, 1): the top six mantissa bits are bits 19..14 of the high word
-  const double m = 2.0 * mant;
   const int i = (__double2hiint(mant) >> 14) & (kLogTab - 1);  // in range for every input
   const double2 t = tab[i];
-  const double r = fma(m, t.x, -1.0);
+  const double r = fma(mant, t.x, -1.0);
   double pol = 1.0 / 7.0;
   pol = fma(pol, r, -1.0 / 6.0);
   pol = fma(pol, r, 1.0 / 5.0);
@@ -98,7 +99,7 @@ __device__ __forceinline__ double log_reduced(double q, const double2* __restric
   pol = fma(pol, r, 1.0 / 3.0);
   pol = fma(pol, r, -0.5);
   pol = fma(pol, r, 1.0);
-  const double ed = (double)(e - 1);
+  const double ed = (double)e;
   return fma(ed, kLn2Hi, fma(ed, kLn2Lo, fma(r, pol, t.y)));
 }
 
