@@ -31,8 +31,8 @@ def log(*a):
 
 def measured_counters(tile, symmetric, name=None):
     """Figures of the committed rocprofv3 counter summary of the pair kernel (HBM bytes per launch,
-    achieved shader clock, issue slots per pair), or {} when the kernel source or the launch shape
-    differs from the one measured."""
+    achieved shader clock, issue slots per pair), or {} when the kernel source (its file followed by the
+    shared device header vesnet_internal.h) or the launch shape differs from the one measured."""
     import hashlib
     if name is None:
         name = "k_sym_main_fp32c_2000x128_counters.txt" if symmetric else "k_forward_fp32c_2000x128_counters.txt"
@@ -43,7 +43,10 @@ def measured_counters(tile, symmetric, name=None):
             if ":" in line:
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-        sha = hashlib.sha1(open(os.path.join(ROOT, "paper_2606_25569_amd", "csrc", src), "rb").read()).hexdigest()
+        csrc = os.path.join(ROOT, "paper_2606_25569_amd", "csrc")
+        h = hashlib.sha1(open(os.path.join(csrc, src), "rb").read())
+        h.update(open(os.path.join(csrc, "vesnet_internal.h"), "rb").read())
+        sha = h.hexdigest()
         if fields.get("kernel_source_sha1") != sha or fields.get("tile") != tile:
             return {}
         out = {"profile": "profiles/" + name}

@@ -72,35 +72,52 @@ __device__ __forceinline__ double log_pos(double q) {
   return fma((double)e, kLn2Hi, fma((double)e, kLn2Lo, 2.0 * s * pol));
 }
 
-// Table of the reduced log below: entry i (mantissa interval [1 + i/64, 1 + (i+1)/64)) holds 2a, with a
-// a 10-bit approximation of 1 / (1 + (i + 0.5) / 64), and -ln 2a (from log_pos).  One entry per lane.
-constexpr int kLogTab = 64;
-__device__ __forceinline__ double2 log_tab_entry(int i) {
-  const double c = 1.0 + ((double)i + 0.5) / 64.0;
-  const double a2 = rint(512.0 / c) / 256.0;
+// Table of the reduced log below, N = 2^k entries: entry i (mantissa interval [1 + i/N, 1 + (i+1)/N)) holds
+// 2a, with a an approximation of 1 / (1 + (i + 0.5) / N) to 1/(16 N), and -ln 2a (from log_pos).
+template <int N>
+__device__ __forceinline__ double2 log_tab_entry_n(int i) {
+  const double c = 1.0 + ((double)i + 0.5) / N;
+  const double a2 = rint(8.0 * N / c) / (4.0 * N);
   return make_double2(a2, -log_pos(a2));
 }
 
-// Natural log of a finite q > 0 with the table: q = mant 2^e, mant in [1/2, 1); r = mant (2a) - 1 (exact
-// product, one rounding), |r| < 0.009, ln mant = -ln 2a + log1p(r), log1p by its series through r^7 (the
-// next term is below 5e-18); ln 2 in a high and a low part as in log_pos.  About 18 operations, no division.
-__device__ __forceinline__ double log_reduced(double q, const double2* __restrict__ tab) {
+// Natural log of a finite q > 0 with an N-entry table: q = mant 2^e, mant in [1/2, 1); r = mant (2a) - 1
+// (exact product, one rounding), |r| <= 1/(2Nc) + c/(16N) (c in [1, 2), to first order), ln mant =
+// -ln 2a + log1p(r), log1p by its series; ln 2 in a high and a low part as in log_pos.  The series stops
+// where the next term is below 5e-18: through r^7 for N = 64 (|r| < 0.0089), through r^5 for N = 512
+// (|r| < 0.0012).  About 18 (N = 64) or 16 (N = 512) operations, no division.
+template <int N>
+__device__ __forceinline__ double log_reduced_n(double q, const double2* __restrict__ tab) {
+  static_assert(N == 64 || N == 512, "series lengths are set for 64 and 512 entries");
+  constexpr int kShift = N == 64 ? 14 : 11;  // the top log2(N) mantissa bits end at bit 19 of the high word
   constexpr double kLn2Hi = 6.93147180369123816490e-01;
   constexpr double kLn2Lo = 1.90821492927058770002e-10;
   int e;
-  const double mant = frexp(q, &e);  // [0.5, 1): the top six mantissa bits are bits 19..14 of the high word
-  const int i = (__double2hiint(mant) >> 14) & (kLogTab - 1);  // in range for every input
+  const double mant = frexp(q, &e);
+  const int i = (__double2hiint(mant) >> kShift) & (N - 1);  // in range for every input
   const double2 t = tab[i];
   const double r = fma(mant, t.x, -1.0);
-  double pol = 1.0 / 7.0;
-  pol = fma(pol, r, -1.0 / 6.0);
-  pol = fma(pol, r, 1.0 / 5.0);
+  double pol;
+  if constexpr (N == 64) {
+    pol = 1.0 / 7.0;
+    pol = fma(pol, r, -1.0 / 6.0);
+    pol = fma(pol, r, 1.0 / 5.0);
+  } else {
+    pol = 1.0 / 5.0;
+  }
   pol = fma(pol, r, -1.0 / 4.0);
   pol = fma(pol, r, 1.0 / 3.0);
   pol = fma(pol, r, -0.5);
   pol = fma(pol, r, 1.0);
   const double ed = (double)e;
   return fma(ed, kLn2Hi, fma(ed, kLn2Lo, fma(r, pol, t.y)));
+}
+
+// The 64-entry form (one entry per lane of a wavefront), used by the direct float64 kernel and the trees.
+constexpr int kLogTab = 64;
+__device__ __forceinline__ double2 log_tab_entry(int i) { return log_tab_entry_n<kLogTab>(i); }
+__device__ __forceinline__ double log_reduced(double q, const double2* __restrict__ tab) {
+  return log_reduced_n<kLogTab>(q, tab);
 }
 
 // Device views of a prepared workspace region.

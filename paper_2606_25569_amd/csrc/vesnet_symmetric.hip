@@ -471,8 +471,9 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_main(
 // ------------------------------------------------------------------ float64 symmetric form
 // The same schedule (cycles, blocks, circulant units, rings of 16 lanes) in float64 on global coordinates:
 // float64 needs no compensation, so a segment's set-up only selects the target or a far point with zero
-// force, and its rows are flushed without a log correction.  The logarithm and reciprocal are the table
-// logarithm and Newton reciprocal shared with the direct float64 kernel; column sums travel around the ring
+// force, and its rows are flushed without a log correction.  The logarithm is the table logarithm of the
+// direct float64 kernel with a 512-entry table (two fewer series terms than its 64 entries), the reciprocal
+// that kernel's refined hardware estimate; column sums travel around the ring
 // by DPP moves of both halves of each double.  Sums leave the workgroup as two 64-bit fixed-point words:
 // hi = rint(x 2^S) and lo = rint((x - hi 2^-S) 2^(S + kLoBits)) (the first difference is exact), each added
 // by an integer atomic, so the result is again independent of the order of the atomics while the
@@ -480,6 +481,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym_main(
 // 2^(62 - kLoBits + 1) partials per point stay exact.
 constexpr int kLoBits = 40;
 constexpr int kChunk64 = 4;                         // source cycles per LDS chunk
+constexpr int kLogTab64 = 512;                     // entries of the float64 kernels' log table (8 KB of LDS)
 constexpr double kFar64 = 3.2733906078961419e150;   // 2^500: position of an inactive target
 static_assert(kChunk64 * 2 * kRing <= kSymThreads, "one thread per staged record and per column sum of a chunk");
 
@@ -512,7 +514,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym64_main(
   __shared__ int4 s_ti[CB];                          // (vesicle or -1, count, first point, 0)
   __shared__ double4 s_rec[2][kChunk64][2 * kRing];  // source cycles (x, y, F_x, F_y), each stored twice
   __shared__ double s_col[2][kSymWaves][kChunk64][2][kRing];
-  __shared__ double2 ltab[kLogTab];
+  __shared__ double2 ltab[kLogTab64];
 
   const int ncyc = meta[0];
   const int S = meta[1];
@@ -527,7 +529,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym64_main(
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, p = lane & 15;
   const int row = tid >> 4;
-  if (tid < kLogTab) ltab[tid] = log_tab_entry(tid);
+  for (int e = tid; e < kLogTab64; e += kSymThreads) ltab[e] = log_tab_entry_n<kLogTab64>(e);
   for (int t = tid; t < CB; t += kSymThreads) {
     const int c = tc0 + t;
     if (c < tc1) {
@@ -592,7 +594,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym64_main(
         const double rx = dx[k] - sr.x;
         const double ry = dy[k] - sr.y;
         const double q = fma(ry, ry, rx * rx);
-        const double L = log_reduced(q, ltab);
+        const double L = log_reduced_n<kLogTab64>(q, ltab);
         const double rho = recip(q);
         const double rxr = rx * rho, ryr = ry * rho;
         const double b = fma(ryr, sr.w, rxr * sr.z);       // (r . F_j)/q
@@ -1258,7 +1260,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym64_bwd(const double4* __rest
   __shared__ double4 s_rec[2][kChunk64][2 * kRing];  // source cycles (x, y, F_x, F_y), twice
   __shared__ double2 s_reg[2][kChunk64][2 * kRing];  // source g, twice
   __shared__ double s_col[2][kSymWaves][kChunk64][4][kRing];
-  __shared__ double2 ltab[kLogTab];
+  __shared__ double2 ltab[kLogTab64];
 
   const int ncyc = meta[0];
   const int nb = meta[2];
@@ -1271,7 +1273,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym64_bwd(const double4* __rest
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, p = lane & 15;
   const int row = tid >> 4;
-  if (tid < kLogTab) ltab[tid] = log_tab_entry(tid);
+  for (int e = tid; e < kLogTab64; e += kSymThreads) ltab[e] = log_tab_entry_n<kLogTab64>(e);
   for (int t = tid; t < CB; t += kSymThreads) {
     const int c = tc0 + t;
     if (c < tc1) {
@@ -1348,7 +1350,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym64_bwd(const double4* __rest
         const double rx = dx[k] - sr.x;
         const double ry = dy[k] - sr.y;
         const double q = fma(ry, ry, rx * rx);
-        const double L = log_reduced(q, ltab);
+        const double L = log_reduced_n<kLogTab64>(q, ltab);
         const double rho = recip(q);
         const double ux = rx * rho, uy = ry * rho;
         const double p3 = fma(uy, sg.y, ux * sg.x);        // (r . g_j)/q
