@@ -85,7 +85,9 @@ __device__ __forceinline__ double2 log_tab_entry_n(int i) {
 // (exact product, one rounding), |r| <= 1/(2Nc) + c/(16N) (c in [1, 2), to first order), ln mant =
 // -ln 2a + log1p(r), log1p by its series; ln 2 in a high and a low part as in log_pos.  The series stops
 // where the next term is below 5e-18: through r^7 for N = 64 (|r| < 0.0089), through r^5 for N = 512
-// (|r| < 0.0012).  About 18 (N = 64) or 16 (N = 512) operations, no division.
+// (|r| < 0.0012).  The 512-entry form adds e ln 2 with one FMA and ln 2 rounded to a double, an extra
+// error of at most |e| 2.3e-17 (a quarter ulp of the result for |e| <= 20).  About 18 (N = 64) or 15
+// (N = 512) operations, no division.
 template <int N>
 __device__ __forceinline__ double log_reduced_n(double q, const double2* __restrict__ tab) {
   static_assert(N == 64 || N == 512, "series lengths are set for 64 and 512 entries");
@@ -110,7 +112,8 @@ __device__ __forceinline__ double log_reduced_n(double q, const double2* __restr
   pol = fma(pol, r, -0.5);
   pol = fma(pol, r, 1.0);
   const double ed = (double)e;
-  return fma(ed, kLn2Hi, fma(ed, kLn2Lo, fma(r, pol, t.y)));
+  if constexpr (N == 64) return fma(ed, kLn2Hi, fma(ed, kLn2Lo, fma(r, pol, t.y)));
+  return fma(ed, 0.69314718055994530942, fma(r, pol, t.y));
 }
 
 // The 64-entry form (one entry per lane of a wavefront), used by the direct float64 kernel and the trees.
