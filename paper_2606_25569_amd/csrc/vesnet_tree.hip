@@ -842,8 +842,9 @@ __device__ __forceinline__ bool next_box(ListWalk& s, int depth, int ix, int iy,
 
 // Targets per wavefront of the evaluation: the treecode's far part costs the same per wavefront whatever
 // its target count, so it takes 64; the fast multipole method's is a short polynomial per target and
-// takes 32, twice the wavefronts to hide the direct part's latencies.
-template <bool kFmm> constexpr int eval_chunk_shift() { return kFmm ? 5 : 6; }
+// takes 16, four times the wavefronts to hide the direct part's latencies (at 2000 x 128, order 30:
+// 0.58 ms against 0.63 ms at 32 and 0.60 ms at 8 targets).
+template <bool kFmm> constexpr int eval_chunk_shift() { return kFmm ? 4 : 6; }
 
 // One wavefront per (leaf, chunk of kChunk of its points); every lane one target.  The far part is the
 // treecode's walk over the interaction lists (kFmm false: mom holds the finalised moments) or the leaf's
@@ -1116,11 +1117,11 @@ __global__ __launch_bounds__(kOwnThreads) void k_tc_own(const double* __restrict
 // Near-field masking of Algorithm 4 on the fast multipole result: vesicle v (not the target's own) is near
 // target i when min_j |x_i - x_j| <= h_v (the rule of the direct masked sum, decided here in FP64 on
 // squared distances).  With every h_v at most the leaf width, all such points lie in the 3 x 3 leaves around
-// the target's leaf.  One wavefront per (leaf, chunk of 32 targets) stages those leaves' points in LDS, up to
-// kNearStage at a time with every lane's loads issued together (a neighbourhood of that many points costs
-// three rounds of memory latency); lanes t and t + 32 scan alternate points for target t, each keeping the
-// distinct near vesicles it meets (at most kNearMax, else bit 0 of *flag), and lane t merges the two sets
-// and sorts them ascending.  One atomic per
+// the target's leaf.  One wavefront per (leaf, chunk of targets: the evaluation's work list) stages those
+// leaves' points in LDS, up to kNearStage at a time with every lane's loads issued together (a neighbourhood
+// of that many points costs three rounds of memory latency); the 64 / chunk lanes t, t + chunk, ... scan
+// interleaved points for target t, each keeping the distinct near vesicles it meets (at most kNearMax, else
+// bit 0 of *flag), and lane t merges the sets and sorts them ascending.  One atomic per
 // wavefront reserves the pair slots.  The whole wavefront then takes the near vesicles of each target in
 // turn, 64 points at a time, and subtracts their exact direct sum at x_i from out[i]: the FMM had included v
 // through the direct part or the expansions, and the difference leaves the masked far field with the FMM's
@@ -1153,12 +1154,13 @@ __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, c
                                                 int32_t* __restrict__ pairs, int capacity, int32_t* __restrict__ count,
                                                 int32_t* __restrict__ flag) {
   constexpr int kChunk = 1 << eval_chunk_shift<true>();
-  static_assert(kChunk == 32, "two lanes per target");
+  constexpr int kGroups = 64 / kChunk;  // lanes per target: group g scans every kGroups-th source from g on
+  static_assert(kGroups >= 2 && kGroups * kChunk == 64, "a power-of-two chunk of at most 32 targets");
   __shared__ double sx_[kNearStage], sy_[kNearStage], sh[kNearStage];
   __shared__ int32_t sv[kNearStage];
   __shared__ double2 ltab[kLogTab];
-  __shared__ int32_t mlist[kChunk][kNearMax + 1];
-  __shared__ int32_t mcount[kChunk];
+  __shared__ int32_t mlist[kGroups - 1][kChunk][kNearMax + 1];
+  __shared__ int32_t mcount[kGroups - 1][kChunk];
   const int n = 1 << depth;
   const int nleaf = n * n;
   const int item = blockIdx.x;
@@ -1170,7 +1172,7 @@ __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, c
   }
   const int leaf = lo;
   const int lane = threadIdx.x;
-  const int t = lane & (kChunk - 1), half = lane >> 5;
+  const int t = lane & (kChunk - 1), grp = lane / kChunk;
   ltab[lane] = log_tab_entry(lane);  // read after the barriers below
   const int s0 = starts[leaf], s1 = starts[leaf + 1];
   const int slot = s0 + (item - wstart[leaf]) * kChunk + t;
@@ -1223,24 +1225,26 @@ __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, c
     __syncthreads();
     if (!active) continue;
 #pragma unroll 4
-    for (int q = half; q < cnt; q += 2) {
+    for (int q = grp; q < cnt; q += kGroups) {
       const double rx = zx - sx_[q], ry = zy - sy_[q];
       const int vq = sv[q];
       if (!(rx * rx + ry * ry > sh[q]) && vq != vi) near_insert(nv, nn, over, vq);
     }
   }
-  // merge the upper half's sets into the lower half's
-  if (half == 1) {
+  // merge the other groups' sets into group 0's
+  if (grp > 0) {
 #pragma unroll
     for (int k = 0; k < kNearMax; ++k)
-      if (k < nn) mlist[t][k] = nv[k];
-    mcount[t] = nn;
+      if (k < nn) mlist[grp - 1][t][k] = nv[k];
+    mcount[grp - 1][t] = nn;
     nn = 0;
   }
   __syncthreads();
-  if (half == 0) {
-    const int m = mcount[t];
-    for (int k = 0; k < m; ++k) near_insert(nv, nn, over, mlist[t][k]);
+  if (grp == 0) {
+    for (int g2 = 0; g2 < kGroups - 1; ++g2) {
+      const int m = mcount[g2][t];
+      for (int k = 0; k < m; ++k) near_insert(nv, nn, over, mlist[g2][t][k]);
+    }
     // ascending vesicle order: the subtraction order, and so the result, does not depend on the scan
 #pragma unroll
     for (int a = 1; a < kNearMax; ++a)
@@ -1253,7 +1257,7 @@ __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, c
         }
   }
   if (__ballot(over) != 0 && lane == 0) atomicOr(flag, 1);
-  int incl = nn;  // inclusive prefix of the pair counts over the wavefront (zero in the upper half)
+  int incl = nn;  // inclusive prefix of the pair counts over the wavefront (zero outside group 0)
   for (int o = 1; o < 64; o <<= 1) {
     const int y = __shfl_up(incl, o);
     if (lane >= o) incl += y;
@@ -1263,7 +1267,7 @@ __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, c
   int base = 0;
   if (lane == 0) base = atomicAdd(count, total);
   base = __shfl(base, 0);
-  if (half == 0) {
+  if (grp == 0) {
     const int b0 = base + incl - nn;
 #pragma unroll
     for (int k = 0; k < kNearMax; ++k)
@@ -1272,21 +1276,21 @@ __global__ __launch_bounds__(64) void k_fmm_near(const double* __restrict__ X, c
           pairs[2 * (b0 + k)] = i;
           pairs[2 * (b0 + k) + 1] = nv[k];
         }
-        mlist[t][k] = nv[k];
+        mlist[0][t][k] = nv[k];
       }
-    mcount[t] = nn;
+    mcount[0][t] = nn;
   }
   __syncthreads();
-  unsigned long long todo = __ballot(half == 0 && nn > 0);
+  unsigned long long todo = __ballot(grp == 0 && nn > 0);
   while (todo) {
     const int tt = __ffsll(todo) - 1;
     todo &= todo - 1;
     const double tx = __shfl(zx, tt), ty = __shfl(zy, tt);
     const int it = __shfl(i, tt);
-    const int m = mcount[tt];
+    const int m = mcount[0][tt];
     double ux = 0.0, uy = 0.0;
     for (int k = 0; k < m; ++k) {
-      const int v = mlist[tt][k];
+      const int v = mlist[0][tt][k];
       const int v0 = clamp_i(off[v], 0, P), v1 = max(v0, clamp_i(off[v + 1], 0, P));
       for (int j = v0 + lane; j < v1; j += 64)
         direct_term(tx, ty, X[j], X[P + j], w[j] * f[j], w[j] * f[P + j], ltab, ux, uy);
