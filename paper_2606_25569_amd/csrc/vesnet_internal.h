@@ -85,9 +85,10 @@ __device__ __forceinline__ double2 log_tab_entry_n(int i) {
 // (exact product, one rounding), |r| <= 1/(2Nc) + c/(16N) (c in [1, 2), to first order), ln mant =
 // -ln 2a + log1p(r), log1p by its series; ln 2 in a high and a low part as in log_pos.  The series stops
 // where the next term is below 5e-18: through r^7 for N = 64 (|r| < 0.0089), through r^5 for N = 512
-// (|r| < 0.0012).  The 512-entry form adds e ln 2 with one FMA and ln 2 rounded to a double, an extra
-// error of at most |e| 2.3e-17 (a quarter ulp of the result for |e| <= 20).  About 18 (N = 64) or 15
-// (N = 512) operations, no division.
+// (|r| < 0.0012).  Both forms are accurate in absolute terms (near q = 1 the result is a difference of
+// terms of order ln 2, and the table entry alone carries up to about 5e-17).  The 512-entry form adds
+// e ln 2 with one FMA and ln 2 rounded to a double, an extra absolute error of at most |e| 2.3e-17 (a
+// quarter of an ulp of ln q at |e| = 20).  About 18 (N = 64) or 15 (N = 512) operations, no division.
 template <int N>
 __device__ __forceinline__ double log_reduced_n(double q, const double2* __restrict__ tab) {
   static_assert(N == 64 || N == 512, "series lengths are set for 64 and 512 entries");
