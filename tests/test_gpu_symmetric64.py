@@ -92,6 +92,25 @@ def test_large_translation(V):
     assert err <= BAR
 
 
+@pytest.mark.parametrize("scale", [1e-6, 1e6])
+def test_scaled_suspension(V, scale):
+    """Coordinates and weights scaled by 1e-6 and 1e6: |r|^2 spans exponents of about -40 and +40, where the
+    logarithm's e ln 2 term dominates; every float64 form (symmetric at T = 1 and the default, direct) within
+    the bar of the oracle."""
+    import torch
+    s = _ragged_suspension(seed=9)
+    s.X = s.X * scale
+    s.w = s.w * scale
+    ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    for cfg in ({"pair_form": 2, "targets_per_thread": 1}, {"pair_form": 2}, {"pair_form": 1}):
+        X, f, w = dev_inputs(s)
+        out = V.farfield_forward(X, X, f, w, s.offsets, s.mu, precision="fp64", config=cfg)
+        torch.cuda.synchronize()
+        err, _ = rel_err(out.cpu().numpy(), ref)
+        say(f"fp64 scaled x{scale:g} {cfg}: {err:.3e}")
+        assert err <= BAR
+
+
 def test_single_vesicle_and_zero_force(V):
     a, b = S.ellipse_axes(0.65)
     X, w, th = S.ellipse_curve((0.0, 0.0), a, b, 0.0, 40)
