@@ -111,6 +111,26 @@ def test_large_translation(V):
     assert err <= BAR
 
 
+@pytest.mark.parametrize("scale", [1e-6, 1e6])
+def test_scaled_suspension(V, scale):
+    """Coordinates and weights scaled by 1e-6 and 1e6: the power-of-two rescaling takes shifts of about -16
+    and +24 and the log corrections carry large multiples of ln 2; the symmetric form (T = 1 and 3) and the
+    direct form within the bar of the oracle."""
+    import torch
+    s = _ragged_suspension(seed=9)
+    s.X = s.X * scale
+    s.w = s.w * scale
+    ref = O.farfield_suspension(s.X, s.f, s.w, s.offsets, s.mu)
+    for cfg in ({"pair_form": 2, "targets_per_thread": 1}, {"pair_form": 2, "targets_per_thread": 3},
+                {"pair_form": 1}):
+        X, f, w = dev_inputs(s)
+        out = V.farfield_forward(X, X, f, w, s.offsets, s.mu, precision="fp32c", config=cfg)
+        torch.cuda.synchronize()
+        err, _ = rel_err(out.cpu().numpy(), ref)
+        say(f"fp32c scaled x{scale:g} {cfg}: {err:.3e}")
+        assert err <= BAR
+
+
 def test_single_vesicle_and_zero_force(V):
     a, b = S.ellipse_axes(0.65)
     X, w, th = S.ellipse_curve((0.0, 0.0), a, b, 0.0, 40)
