@@ -313,7 +313,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel": "k_sym_main (symmetric pair sum)" if symmetric else "k_forward (pair sum)",
-                     "kernel_ms": float(eval_ms.mean()), "flops_per_pair": FLOPS_PER_PAIR,
+                     "kernel_ms": float(eval_ms.mean()), "kernel_ms_median": float(np.median(eval_ms)),
+                     "kernel_ms_min": float(eval_ms.min()), "flops_per_pair": FLOPS_PER_PAIR,
                      "mix_ceiling_frac": mix["frac"] if mix else None, "mix_ceiling": mix,
                      "sclk_ghz": prof.get("sclk_ghz")},
         "cpu_baseline": cpu,
